@@ -1,0 +1,186 @@
+/*
+ * lcc.h -- C-ABI of the MI355X LambdaCC multilevel clustering library (pLouvain / Louvain+, pLeiden).
+ *
+ * The library clusters an undirected graph by maximising the LambdaCC objective (Eq. 1 of the paper):
+ *
+ *     lambdaCC(C) = sum over clusters C_i of sum over ordered pairs u != v in C_i of w(u,v) - lambda w(u) w(v)
+ *
+ * with the synchronous multilevel methods of the paper: Louvain / Louvain+ (Alg. 1, local move Alg. 2 with
+ * the afterburner filter Alg. 3, contraction Alg. 4) and pLeiden (Alg. 5, spanning-tree refinement Alg. 6,
+ * alternate local move Sec. V-A).  Modularity (w(v) = weighted degree, lambda = gamma / sum_v w(v)) and the
+ * Constant Potts Model (w(v) = 1) are special cases (Sec. II-A).
+ *
+ * All arithmetic is exact: integer weights, 64-bit sums, scores compared as exact integers.  Results are
+ * deterministic and independent of scheduling.
+ *
+ * Every entry point returns an lcc_status; on a negative status no output buffer is written and
+ * lcc_last_error() (thread-local) describes the failure.  No C++ exception crosses this boundary.
+ * Every computation runs on the GPU; there is no CPU fallback.
+ */
+#ifndef LCC_H
+#define LCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LCC_OK = 0,
+  LCC_ERR_INVALID = -1,       /* malformed arguments or CSR structure (offsets, index range, options) */
+  LCC_ERR_NOT_SYMMETRIC = -2, /* some edge (u,v) has no reverse (v,u) of equal weight */
+  LCC_ERR_SELF_LOOP = -3,     /* some row v contains v */
+  LCC_ERR_UNSORTED = -4,      /* a row is not strictly ascending (duplicates count as unsorted) */
+  LCC_ERR_WEIGHT = -5,        /* an edge weight <= 0 or a given vertex weight < 0 */
+  LCC_ERR_LAMBDA = -6,        /* lambda outside [0, 1] or undefined (zero denominator / zero total weight) */
+  LCC_ERR_OVERFLOW = -7,      /* exactness bound violated: total edge weight >= 2^31, or
+                                 q * W_E + p * W^2 >= 2^60 for lambda = p / q in lowest terms */
+  LCC_ERR_OOM = -8,           /* the allocator returned NULL */
+  LCC_ERR_DEVICE = -9,        /* a HIP runtime call failed */
+  LCC_ERR_BUSY = -10,         /* server: admission refused (footprint exceeds the free budget) */
+  LCC_ERR_NOT_FOUND = -11     /* server: unknown ticket */
+} lcc_status;
+
+/* Method variants.  LCC_PLOUVAIN is the paper's pLouvain (Louvain+ with the uncoarsening local move,
+ * Alg. 1 line 12); LCC_LOUVAIN omits the uncoarsening local move; LCC_PLEIDEN is Alg. 5; LCC_PLEIDEN_PLUS
+ * adds the uncoarsening local move to pLeiden (Sec. VI-A). */
+typedef enum { LCC_LOUVAIN = 0, LCC_PLOUVAIN = 1, LCC_PLEIDEN = 2, LCC_PLEIDEN_PLUS = 3 } lcc_variant;
+
+/* Vertex weights w(v): given by the caller, the weighted degree (modularity), or 1 (CPM). */
+typedef enum { LCC_VW_GIVEN = 0, LCC_VW_WEIGHTED_DEGREE = 1, LCC_VW_UNIT = 2 } lcc_vw_mode;
+
+/* Where the graph arrays and labels_out live. */
+typedef enum { LCC_MEM_HOST = 0, LCC_MEM_DEVICE = 1 } lcc_mem;
+
+/* Undirected graph in symmetric CSR (Sec. IV: both (u,v) and (v,u) are stored).  Row v lists the neighbours
+ * of v strictly ascending, without v itself.  Borrowed for the duration of a call.
+ *   n            vertices, 0 <= n < 2^31
+ *   nnz          stored (directed) entries = offsets[n]
+ *   offsets      n+1 entries, int32 (offsets_bits = 32) or int64 (offsets_bits = 64), offsets[0] = 0
+ *   indices      nnz int32 neighbour ids
+ *   edge_w       nnz int32 weights > 0, symmetric; NULL means every weight is 1
+ *   vertex_w     n int64 weights >= 0, read only when vw_mode = LCC_VW_GIVEN
+ *   mem          all arrays of this graph are host (LCC_MEM_HOST) or device (LCC_MEM_DEVICE) pointers */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const void* offsets;
+  int32_t offsets_bits;
+  const int32_t* indices;
+  const int32_t* edge_w;
+  const int64_t* vertex_w;
+  lcc_vw_mode vw_mode;
+  lcc_mem mem;
+} lcc_graph;
+
+/* lambda = num / den, or num / (den * W) when over_total_weight != 0, W = sum of the vertex weights.
+ * Modularity with resolution gamma = a / b: vw_mode = LCC_VW_WEIGHTED_DEGREE, {a, b, 1}.  CPM 1/20: {1, 20, 0}. */
+typedef struct {
+  uint64_t num;
+  uint64_t den;
+  int32_t over_total_weight;
+} lcc_lambda;
+
+/* Trace sink (optional): records of 8 int64 {kind, level, phase, pass, a, b, c, d}:
+ *   kind 1  local-move pass:     a = candidates |L|, b = kept moves |M|, c = objective numerator after the pass
+ *   kind 2  level summary:       pass = 0, a = n_l, b = nnz_l, c = clusters after the local move, d = numerator
+ *   kind 3  alternate local move: a = non-node-optimal vertices, b = committed prefix, c = numerator after
+ *   kind 4  refinement:          a = refined clusters, b = refinement call index, c = |U|, d = tree members
+ * phase 0 = coarsening, 1 = uncoarsening.  Numerators are level-local (constant offsets between levels). */
+typedef struct {
+  int64_t* records;  /* host array of 8 * capacity int64 */
+  int64_t capacity;
+  int64_t count;     /* set by the call: number of records produced (may exceed capacity) */
+} lcc_trace;
+
+/* Result-affecting options (lcc_default_options fills the paper's settings, Sec. VI-C):
+ *   pass_limit 6; temperature phi = 3/4 for passes 1-4 and 1/4 for passes 5-6 (phase k covers the passes
+ *   <= phi_until[k]); afterburner tie window epsilon = 1/10 on the objective change (Sec. IV-A);
+ *   seed for the refinement's random choices; max_levels 64 (a guard; hitting it sets LCC_FLAG_LEVEL_CAP);
+ *   validate != 0 checks the CSR on the device before clustering. */
+typedef struct {
+  int32_t pass_limit;
+  int32_t n_phi;
+  uint32_t phi_num[8], phi_den[8], phi_until[8];
+  uint32_t eps_num, eps_den;
+  uint64_t seed;
+  int32_t max_levels;
+  int32_t validate;
+  lcc_trace* trace;
+} lcc_options;
+
+enum { LCC_FLAG_LEVEL_CAP = 1, LCC_FLAG_REFINE_NO_PROGRESS = 2 };
+
+/* Result of a clustering.  objective = lambdaCC (Eq. 1) as FP64; the exact value is obj_num / obj_den with
+ * obj_num a signed 128-bit integer split into (obj_num_hi, obj_num_lo).  modularity is the Newman-Girvan
+ * modularity (with the requested resolution) when vw_mode = LCC_VW_WEIGHTED_DEGREE and lambda is over the
+ * total weight, NaN otherwise. */
+typedef struct {
+  int64_t num_clusters;
+  double objective;
+  double modularity;
+  int64_t obj_num_hi;
+  uint64_t obj_num_lo;
+  uint64_t obj_den;
+  int32_t levels;
+  uint32_t flags;
+} lcc_result;
+
+/* Device-memory allocator used for every device buffer the library needs (stream-ordered on the call's
+ * stream is not required: buffers are freed only after the stream is synchronised).  NULL functions select
+ * hipMalloc / hipFree. */
+typedef void* (*lcc_alloc_fn)(size_t bytes, void* user);
+typedef void (*lcc_free_fn)(void* ptr, void* user);
+
+typedef struct lcc_ctx lcc_ctx;
+typedef struct lcc_server lcc_server;
+
+/* Create a context on HIP device `device`.  The context owns its scratch workspace (grown on demand through
+ * the allocator, released by lcc_destroy).  A context runs one call at a time. */
+lcc_status lcc_create(int device, lcc_alloc_fn alloc, lcc_free_fn free_fn, void* user, lcc_ctx** out);
+lcc_status lcc_destroy(lcc_ctx* ctx);
+
+/* Fill *opts with the paper's settings (see lcc_options). */
+void lcc_default_options(lcc_options* opts);
+
+/* Upper bound of the device bytes one lcc_cluster call on a graph of n vertices and nnz entries may hold
+ * at once (workspace + coarse levels); used for admission control. */
+lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size_t* bytes);
+
+/* Cluster one graph (Alg. 1 or Alg. 5 with the setup of Sec. II).  labels_out: n int32, in the same memory
+ * space as the graph, receives compact labels 0..c-1 numbered in ascending order of the cluster's
+ * top-level id.  stream: hipStream_t (NULL = the default stream); the call returns after the stream has
+ * completed its work.  opts NULL = lcc_default_options. */
+lcc_status lcc_cluster(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                       const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res);
+
+/* Cluster `count` independent graphs (each with its own lambda and variant) in one call.  Results are
+ * identical to `count` separate lcc_cluster calls.  labels_out[i] and res[i] as for lcc_cluster. */
+lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lambdas,
+                             const lcc_variant* variants, int64_t count, const lcc_options* opts, void* stream,
+                             int32_t* const* labels_out, lcc_result* res);
+
+/* Exact objective (Eq. 1) of a given clustering `labels` (n int32 in [0, n), same memory as g), computed on
+ * the device. */
+lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, const int32_t* labels,
+                         void* stream, lcc_result* res);
+
+/* Continuous-batching server over one context: jobs are admitted while their footprint
+ * (lcc_workspace_bytes) fits in hbm_budget, their level state stays on the device, and the sweeps of
+ * concurrently admitted jobs are co-scheduled.  lcc_submit copies the graph before returning.
+ * lcc_poll: *done = 1 and outputs written once the job finished (labels_out on the host). */
+lcc_status lcc_server_create(lcc_ctx* ctx, size_t hbm_budget, lcc_server** out);
+lcc_status lcc_submit(lcc_server* s, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                      const lcc_options* opts, uint64_t* ticket);
+lcc_status lcc_poll(lcc_server* s, uint64_t ticket, int* done, int32_t* labels_out, lcc_result* res);
+lcc_status lcc_server_destroy(lcc_server* s);
+
+const char* lcc_status_string(lcc_status st);
+const char* lcc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LCC_H */

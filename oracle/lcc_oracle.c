@@ -79,7 +79,8 @@ static void put128(i128 x, int64_t* hl) {
 
 /* ---------------------------------------------------------------------------------------------------
  * Setup (Sec. II): validate the symmetric CSR, derive vertex weights, fix lambda = p / q.
- * Check order: structure, self-loops, sortedness, weights, symmetry, weight totals, lambda, bound.
+ * Check order: arguments, structure, self-loops, sortedness, weights, symmetry, weight totals (total edge
+ * weight < 2^31, given vertex weights < 2^31), lambda, exactness bound.
  * ------------------------------------------------------------------------------------------------- */
 static int64_t find_in_row(const ograph* g, int64_t row, int32_t key) {
   int64_t lo = g->off[row], hi = g->off[row + 1];
@@ -99,6 +100,8 @@ int orc_setup(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* 
               int vw_mode, uint64_t lam_num, uint64_t lam_den, int lam_over_total, int64_t* vw_out,
               uint64_t* pq) {
   if (n < 0 || n > 2147483647LL || !off) return ORC_ERR_INVALID;
+  if (vw_mode != ORC_VW_GIVEN && vw_mode != ORC_VW_WEIGHTED_DEGREE && vw_mode != ORC_VW_UNIT) return ORC_ERR_INVALID;
+  if (vw_mode == ORC_VW_GIVEN && n > 0 && !vw_in) return ORC_ERR_INVALID;
   if (off[0] != 0) return ORC_ERR_INVALID;
   for (int64_t v = 0; v < n; ++v)
     if (off[v + 1] < off[v]) return ORC_ERR_INVALID;
@@ -116,13 +119,9 @@ int orc_setup(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* 
       if (idx[j] <= idx[j - 1]) return ORC_ERR_UNSORTED;
   for (int64_t j = 0; j < nnz; ++j)
     if (EW(&g, j) <= 0) return ORC_ERR_WEIGHT;
-  if (vw_mode == ORC_VW_GIVEN) {
-    if (!vw_in) return ORC_ERR_INVALID;
+  if (vw_mode == ORC_VW_GIVEN)
     for (int64_t v = 0; v < n; ++v)
       if (vw_in[v] < 0) return ORC_ERR_WEIGHT;
-  } else if (vw_mode != ORC_VW_WEIGHTED_DEGREE && vw_mode != ORC_VW_UNIT) {
-    return ORC_ERR_INVALID;
-  }
   for (int64_t v = 0; v < n; ++v)
     for (int64_t j = off[v]; j < off[v + 1]; ++j) {
       int64_t r = find_in_row(&g, idx[j], (int32_t)v);
@@ -131,6 +130,9 @@ int orc_setup(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* 
   i128 WE = 0, W = 0;
   for (int64_t j = 0; j < nnz; ++j) WE += EW(&g, j);
   if (WE >= ((i128)1 << 31)) return ORC_ERR_OVERFLOW;
+  if (vw_mode == ORC_VW_GIVEN)
+    for (int64_t v = 0; v < n; ++v)
+      if (vw_in[v] >= ((int64_t)1 << 31)) return ORC_ERR_OVERFLOW;
   for (int64_t v = 0; v < n; ++v) {
     int64_t x;
     if (vw_mode == ORC_VW_GIVEN) x = vw_in[v];
@@ -139,7 +141,6 @@ int orc_setup(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* 
     vw_out[v] = x;
     W += x;
   }
-  if (W >= ((i128)1 << 62)) return ORC_ERR_OVERFLOW;
   if (lam_den == 0) return ORC_ERR_LAMBDA;
   i128 P = lam_num, Q = (i128)lam_den * (lam_over_total ? W : 1);
   if (Q <= 0 || P > Q) return ORC_ERR_LAMBDA;

@@ -1,0 +1,8 @@
+"""MI355X-native synchronous multilevel LambdaCC clustering (pLouvain / Louvain+, pLeiden, pLeiden+).
+
+The computation lives in the HIP library ``liblcc.so`` (hand-written gfx950 kernels behind the C-ABI of
+``include/lcc.h``); :mod:`paper_2608_01503_amd.lcc` is its thin ctypes binding.
+"""
+from .lcc import (LCC_LOUVAIN, LCC_PLEIDEN, LCC_PLEIDEN_PLUS, LCC_PLOUVAIN, LCC_VW_GIVEN, LCC_VW_UNIT,  # noqa: F401
+                  LCC_VW_WEIGHTED_DEGREE, Context, LccError, Result, Server, lcc_default_options,
+                  lcc_workspace_bytes, load, make_graph)

@@ -1,0 +1,240 @@
+// Internal header of the MI355X LambdaCC library: device helpers, control-block layout and the host-side
+// launchers each translation unit exports to the driver.  Not part of the public C-ABI (include/lcc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lcc {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int NBUCKET = 8;
+constexpr int MAX_PASSES = 32;
+constexpr int32_t D_NONE = -1;   // no destination
+constexpr int32_t D_EMPTY = -2;  // destination = a new singleton cluster
+
+// Degree buckets (upper bounds, inclusive).  Buckets 0-3 are handled by sub-wave groups of 4/8/16/32 lanes
+// (one neighbour per lane), 4-5 by one wavefront per vertex, 6-7 by one workgroup per vertex.  The local-move
+// kernels aggregate neighbour clusters with register shuffles (0-3), an LDS hash (4-6) or a global-memory
+// hash inside the edge arena (7).
+constexpr int64_t BUCKET_MAX[NBUCKET] = {4, 8, 16, 32, 128, 1024, 4096, INT64_MAX};
+constexpr int LDS_SLOTS_B4 = 256;
+constexpr int LDS_SLOTS_B5 = 2048;
+constexpr int LDS_SLOTS_B6 = 8192;
+
+__host__ __device__ inline int bucket_of(int64_t d) {
+  int b = 0;
+  while (b < NBUCKET - 1 && d > BUCKET_MAX[b]) ++b;
+  return b;
+}
+
+// splitmix64 output function (Steele, Lea & Flood, OOPSLA 2014)
+__host__ __device__ __forceinline__ uint64_t fmix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ULL;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+// MurmurHash3 32-bit finaliser (Appleby): a bijection on 32-bit words
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6BU;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35U;
+  return h ^ (h >> 16);
+}
+// t-th output (t = 0, 1, ...) of the splitmix64 generator seeded with `seed`
+__host__ __device__ __forceinline__ uint64_t seed_stream(uint64_t seed, uint64_t t) {
+  return fmix64(seed + (t + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+// Statistics of one LocalMovePasses call, written by the device.  State k = clustering after k passes.
+struct LMSlot {
+  int64_t nL[MAX_PASSES + 1];   // candidates of pass i
+  int64_t nM[MAX_PASSES + 1];   // kept moves of pass i
+  int64_t I[MAX_PASSES + 1];    // ordered internal edge weight of state k
+  int64_t SW2[MAX_PASSES + 1];  // sum over clusters of W_c^2 for state k
+  int32_t skip[MAX_PASSES + 2]; // pass i repeats pass i-1 exactly (no move, same temperature)
+  int32_t copy;                 // current best-so-far decision: copy C -> C_out
+  int32_t pad;
+  int64_t n_empty;              // movers to a new singleton in the current pass
+  int64_t Nbest;                // objective numerator of C_out
+  int64_t N0;                   // objective numerator of the starting clustering
+};
+
+// Scalars shared by the driver and the kernels.
+struct Ctrl {
+  uint32_t err_bits;            // validation errors (ERR_* bits)
+  uint32_t pad0;
+  int64_t bucket_count[NBUCKET];
+  int64_t bucket_off[NBUCKET + 1];
+  int64_t bucket_cursor[NBUCKET];
+  uint64_t sum_we;              // total edge weight W_E
+  uint64_t sum_w;               // total vertex weight W
+  uint64_t sum_w2;              // sum of w(v)^2
+  int64_t count0, count1, count2, count3;  // scratch counters (clusters, entries, ...)
+  int64_t obj_I;                // objective kernel: internal weight
+  int64_t obj_SW2;              // objective kernel: sum of squared cluster weights
+  int64_t lmalt_k, lmalt_best_k;
+  int64_t refine_U, refine_m;
+  int64_t lmalt_best;
+};
+
+enum : uint32_t {
+  ERRB_INVALID = 1u << 0,
+  ERRB_SELF_LOOP = 1u << 1,
+  ERRB_UNSORTED = 1u << 2,
+  ERRB_WEIGHT = 1u << 3,
+  ERRB_NOT_SYMMETRIC = 1u << 4,
+  ERRB_VW_TOO_BIG = 1u << 5,
+  ERRB_INTERNAL = 1u << 6,  // an internal invariant failed (reported as LCC_ERR_DEVICE)
+};
+
+// A level graph on the device.  off int64[n+1], idx int32[nnz], w int32[nnz], vw int64[n].
+struct DevGraph {
+  int64_t n = 0, nnz = 0;
+  const int64_t* off = nullptr;
+  const int32_t* idx = nullptr;
+  const int32_t* w = nullptr;
+  const int64_t* vw = nullptr;
+};
+
+// Vertex lists of the degree buckets of one level (all buckets in one array, bucket b at [off[b], off[b+1])).
+struct Buckets {
+  const int32_t* list = nullptr;
+  int64_t count[NBUCKET] = {};
+  int64_t off[NBUCKET + 1] = {};
+  // hub (last bucket) vertices are processed in fixed-size edge chunks: chunk range of hub k is
+  // [hub_chunk_off[k], hub_chunk_off[k+1]); per-chunk partial results and per-hub accumulators:
+  const int32_t* hub_chunk_off = nullptr;
+  int64_t hub_chunks = 0;
+  int64_t* hub_ps = nullptr;
+  int32_t* hub_pc = nullptr;
+  int64_t* hub_pown = nullptr;
+  int64_t* hub_acc = nullptr;
+};
+
+// Scoring parameters of a level: lambda = p / q; phi = phi_a / phi_b; tie window threshold on |delta_u -
+// delta_v| (see lm.hip).
+struct Score {
+  int64_t p, q;
+  int64_t tie;
+};
+
+// Packed per-vertex local-move state read by the afterburner: cluster, destination (D_NONE when v is not a
+// candidate), delta.  16 bytes, one load per neighbour.
+struct alignas(16) VState {
+  int32_t c;
+  int32_t d;
+  int64_t delta;
+};
+
+// ---------------------------------------------------------------------------------------------------------
+// Host-side launchers (all asynchronous on `st`)
+// ---------------------------------------------------------------------------------------------------------
+
+// prim.hip
+size_t scan_temp_bytes(int64_t n);
+// out[i] = sum_{j<i} in[j] for i in [0, n], out[n] = total.  If `cond` is not null the kernels do nothing
+// when *cond == 0.
+void scan_u8_i32(const uint8_t* in, int32_t* out, int64_t n, void* temp, const int64_t* cond, hipStream_t st);
+void scan_i32_i32(const int32_t* in, int32_t* out, int64_t n, void* temp, hipStream_t st);
+void scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st);
+void scan_i64_i64(const int64_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st);
+void scan_u32_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t st);
+// LSD radix sort of (key, val) pairs over the 8-bit digits starting at the given bit shifts (ascending);
+// stable.  Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is in (k0, v0), 1 otherwise.
+size_t radix_temp_bytes(int64_t m);
+int radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, const int* shifts,
+                     int npass, void* temp, hipStream_t st);
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
+void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
+void zero_bytes(void* p, size_t bytes, hipStream_t st);  // a fill kernel, safe inside captured graphs
+void iota_i32(int32_t* p, int64_t n, hipStream_t st);
+void copy_i32(int32_t* dst, const int32_t* src, int64_t n, hipStream_t st);
+void offsets32_to_64(const int32_t* in, int64_t* out, int64_t n1, hipStream_t st);
+
+// lm.hip: setup, buckets, local move, objective
+void launch_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* ctrl, hipStream_t st);
+void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, const int64_t* vw_given,
+                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st);
+void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st);
+// chunk offsets of the hubs (n7 entries of the last bucket): chunk_off[n7+1] via cnt[n7] scratch
+void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt, int32_t* chunk_off,
+                       void* temp, hipStream_t st);
+constexpr int64_t HUB_CHUNK_EDGES = 4096;
+void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st);
+
+struct LMBuffers {
+  int32_t* C;      // current clustering (labels in [0, n))
+  int32_t* Cout;   // best-so-far clustering
+  int64_t* W;      // cluster weights, indexed by cluster id
+  int32_t* sz;     // cluster sizes
+  VState* vs;      // packed (C, D, delta)
+  uint8_t* keep;   // afterburner verdict
+  uint8_t* empty;  // kept movers to a new singleton
+  int32_t* scan_a; // n+1
+  int32_t* scan_b; // n+1
+  int32_t* freelist;
+  uint32_t* arena; // 2 * nnz (key, value) slots for the global-memory hash
+  void* scan_temp;
+};
+
+struct LMParams {
+  Score sc;
+  int pass_limit;
+  uint32_t phi_num[MAX_PASSES + 1], phi_den[MAX_PASSES + 1];  // per pass (1-based)
+  int64_t sum_w2;  // sum of w(v)^2 of the level
+};
+
+// Runs LocalMovePasses (Alg. 2) on level graph g from the clustering in bufs.C (`singleton` = C is the
+// identity).  Leaves C_out in bufs.Cout.  Statistics in *slot.
+void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool singleton, LMBuffers& bufs,
+                LMSlot* slot, Ctrl* ctrl, hipStream_t st);
+// Destinations without the temperature rule (candidate iff the move strictly improves): used by
+// LocalMoveAlt.  Fills bufs.vs and bufs.keep (keep = non-node-optimal).
+void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
+                                LMSlot* slot, hipStream_t st);
+void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, int32_t* sz,
+                            hipStream_t st);
+// Exact objective pieces of clustering C: ctrl->obj_I and ctrl->obj_SW2 (W must hold C's cluster weights).
+void launch_objective(const DevGraph& g, const Buckets& b, const int32_t* C, const int64_t* W,
+                      Ctrl* ctrl, hipStream_t st);
+void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hipStream_t st);
+
+// contract.hip
+// used flags of labels -> rank (compact map) : rank[c] for c in [0, n), count at rank[n].
+void launch_label_rank(const int32_t* labels, int64_t n, uint8_t* used, int32_t* rank, void* temp,
+                       hipStream_t st);
+void launch_map_labels(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map, hipStream_t st);
+void launch_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t* cvw, hipStream_t st);
+void launch_cross_count(const DevGraph& g, const Buckets& b, const int32_t* map, int32_t* cnt,
+                        hipStream_t st);
+void launch_cross_emit(const DevGraph& g, const Buckets& b, const int32_t* map, int64_t* cursor,
+                       uint64_t* keys, uint32_t* vals, hipStream_t st);
+void launch_heads(const uint64_t* keys, int64_t m, uint8_t* head, hipStream_t st);
+void launch_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8_t* head, const int32_t* uid,
+                         int64_t m, int32_t* cidx, int32_t* cw, int32_t* cdeg, hipStream_t st);
+void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st);
+void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,
+                       hipStream_t st);
+
+// refine.hip: pLeidenR (Alg. 6)
+struct RefineBuffers {
+  int64_t* WB; int64_t* aB; int64_t* aX; uint8_t* inU; int32_t* H; int32_t* par; int32_t* root;
+  uint8_t* flip; uint8_t* has_child; int32_t* tsz; uint8_t* member; int32_t* mpos;
+  uint64_t* k0; uint32_t* v0; uint64_t* k1; uint32_t* v1;
+  int64_t* pw; int64_t* pc; int64_t* tmp64a; int64_t* tmp64b; int32_t* pos_of; int32_t* fail;
+  void* scan_temp; void* radix_temp;
+};
+void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t* B, uint64_t seed, uint64_t t,
+            int32_t* R, RefineBuffers& rb, Ctrl* ctrl, hipStream_t st);
+
+// lmalt.hip: LocalMoveAlt (Sec. V-A)
+void lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs, LMSlot* slot, Ctrl* ctrl,
+           int32_t* list, int64_t* gain, hipStream_t st);
+
+}  // namespace lcc

@@ -1,0 +1,261 @@
+// Graph contraction (Alg. 4) as relabel + sort + segmented reduce, and the projections between levels.
+//
+// Coarse vertex x = rank of cluster id among the ids in use (ascending compaction by prefix scan).  Every
+// fine entry (v, u, w) with map[v] != map[u] is emitted as key (map[v] << 32 | map[u]), value w; an LSD radix
+// sort over the used key bits brings equal keys together in (x, y) order; run heads become the coarse
+// entries (neighbours ascending, weights summed with integer atomics, self-loops dropped).  The result is
+// the canonical coarse CSR independent of scheduling.
+#include "common.h"
+
+namespace lcc {
+
+namespace {
+
+constexpr int HUB_BLOCK = 256;
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = cdiv(n, BLOCK);
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (unsigned)g;
+}
+inline unsigned grp_blocks(int64_t cnt, int G) { return (unsigned)cdiv(cnt, BLOCK / G); }
+
+__device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
+  int64_t lo = 0, hi = n7;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (chunk_off[mid] <= blk) lo = mid; else hi = mid;
+  }
+  return (int)lo;
+}
+
+__global__ void k_mark_used(const int32_t* labels, int64_t n, uint8_t* used) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    used[labels[v]] = 1;
+}
+
+__global__ void k_map(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    map[v] = rank[labels[v]];
+}
+
+__global__ void k_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t* cvw) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd((unsigned long long*)&cvw[map[v]], (unsigned long long)vw[v]);
+}
+
+// cross-cluster entries per fine vertex; G lanes per vertex (G = 64 also covers whole-block rows by
+// striding), hubs by chunks with atomics
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_cross_count_grp(const int32_t* list, int64_t cnt, DevGraph g,
+                                                           const int32_t* map, int32_t* out) {
+  const int gl = threadIdx.x % G;
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  if (gid >= cnt) return;
+  const int32_t v = list[gid];
+  const int32_t x = map[v];
+  int c = 0;
+  for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) c += map[g.idx[j]] != x;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, G);
+  if (gl == 0) out[v] = c;
+}
+
+__global__ __launch_bounds__(HUB_BLOCK) void k_cross_count_chunk(const int32_t* hubs, const int32_t* chunk_off,
+                                                                 int64_t n7, int64_t chunk, DevGraph g,
+                                                                 const int32_t* map, int32_t* out) {
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int32_t x = map[v];
+  const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * chunk;
+  const int64_t j1 = min(g.off[v + 1], j0 + chunk);
+  int c = 0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) c += map[g.idx[j]] != x;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, WAVE);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && c) atomicAdd(&out[v], c);
+}
+
+// Emit (x << 32 | y, w); positions claimed per group with one atomic on the vertex cursor (the cursor
+// starts at the vertex's exclusive prefix of cross entries).
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_cross_emit_grp(const int32_t* list, int64_t cnt, DevGraph g,
+                                                          const int32_t* map, int64_t* cursor, uint64_t* keys,
+                                                          uint32_t* vals) {
+  const int gl = threadIdx.x % G;
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  // groups past the end still execute the ballots (uniform control flow inside the wavefront)
+  const bool active = gid < cnt;
+  const int32_t v = active ? list[gid] : 0;
+  const int64_t j0 = active ? g.off[v] : 0, j1 = active ? g.off[v + 1] : 0;
+  // trip count must be uniform across the wavefront for the ballots: iterate to the wave's max degree
+  int64_t d = j1 - j0;
+  int64_t dmax = d;
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, WAVE));
+  const int32_t x = active ? map[v] : -1;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int gbase = lane - gl;
+  const uint64_t gmask = (G == WAVE) ? ~0ull : (((1ull << G) - 1) << gbase);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+  for (int64_t off = 0; off < dmax; off += G) {
+    int64_t j = j0 + off + gl;
+    bool in = active && j < j1;
+    int32_t y = in ? map[g.idx[j]] : -1;
+    bool cross = in && y != x;
+    uint64_t m = __ballot(cross) & gmask;
+    int64_t base = 0;
+    int leader = m ? __ffsll((unsigned long long)m) - 1 : gbase;
+    if (m && lane == leader)
+      base = (int64_t)atomicAdd((unsigned long long*)&cursor[v], (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (cross) {
+      int64_t p = base + __popcll(m & lt);
+      keys[p] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
+      vals[p] = (uint32_t)g.w[j];
+    }
+  }
+}
+
+// rows handled by whole workgroups (bucket 6) or hub chunks: each wavefront claims its own positions
+__global__ __launch_bounds__(HUB_BLOCK) void k_cross_emit_chunk(const int32_t* list, const int32_t* chunk_off,
+                                                                int64_t nv, int64_t chunk, DevGraph g,
+                                                                const int32_t* map, int64_t* cursor,
+                                                                uint64_t* keys, uint32_t* vals) {
+  int k;
+  int64_t j0, j1;
+  int32_t v;
+  if (chunk_off) {
+    k = find_chunk_owner(chunk_off, nv, blockIdx.x);
+    v = list[k];
+    j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * chunk;
+    j1 = min(g.off[v + 1], j0 + chunk);
+  } else {
+    v = list[blockIdx.x];
+    j0 = g.off[v];
+    j1 = g.off[v + 1];
+  }
+  const int32_t x = map[v];
+  const int lane = threadIdx.x & (WAVE - 1);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+  const int wv = threadIdx.x / WAVE;
+  for (int64_t jb = j0 + (int64_t)wv * WAVE; jb < j1; jb += HUB_BLOCK) {
+    int64_t j = jb + lane;
+    bool in = j < j1;
+    int32_t y = in ? map[g.idx[j]] : -1;
+    bool cross = in && y != x;
+    uint64_t m = __ballot(cross);
+    if (!m) continue;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int64_t base = 0;
+    if (lane == leader) base = (int64_t)atomicAdd((unsigned long long*)&cursor[v], (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (cross) {
+      int64_t p = base + __popcll(m & lt);
+      keys[p] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
+      vals[p] = (uint32_t)g.w[j];
+    }
+  }
+}
+
+__global__ void k_zero_hub_counts(const int32_t* hubs, int64_t n7, int32_t* cnt) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n7; k += (int64_t)gridDim.x * blockDim.x)
+    cnt[hubs[k]] = 0;
+}
+
+__global__ void k_heads(const uint64_t* keys, int64_t m, uint8_t* head) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    head[i] = (i == 0 || keys[i] != keys[i - 1]);
+}
+
+__global__ void k_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8_t* head, const int32_t* uid,
+                               int64_t m, int32_t* cidx, int32_t* cw, int32_t* cdeg) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t k = keys[i];
+    int32_t u = uid[i] + head[i] - 1;
+    if (head[i]) {
+      cidx[u] = (int32_t)(uint32_t)k;
+      atomicAdd(&cdeg[(int32_t)(k >> 32)], 1);
+    }
+    atomicAdd(&cw[u], (int32_t)vals[i]);
+  }
+}
+
+__global__ void k_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    fine_C[v] = coarse_C[map[v]];
+}
+
+__global__ void k_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    Cc[map[v]] = rankB[B[v]];
+}
+
+}  // namespace
+
+void launch_label_rank(const int32_t* labels, int64_t n, uint8_t* used, int32_t* rank, void* temp,
+                       hipStream_t st) {
+  fill_u8(used, 0, n, st);
+  k_mark_used<<<grid_for(n), BLOCK, 0, st>>>(labels, n, used);
+  scan_u8_i32(used, rank, n, temp, nullptr, st);
+}
+
+void launch_map_labels(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map, hipStream_t st) {
+  k_map<<<grid_for(n), BLOCK, 0, st>>>(labels, rank, n, map);
+}
+
+void launch_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t* cvw, hipStream_t st) {
+  k_coarse_vw<<<grid_for(n), BLOCK, 0, st>>>(map, vw, n, cvw);
+}
+
+void launch_cross_count(const DevGraph& g, const Buckets& b, const int32_t* map, int32_t* cnt, hipStream_t st) {
+  const int32_t* L = b.list;
+  if (b.count[0]) k_cross_count_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, map, cnt);
+  if (b.count[1]) k_cross_count_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, map, cnt);
+  if (b.count[2]) k_cross_count_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, map, cnt);
+  if (b.count[3]) k_cross_count_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, map, cnt);
+  int64_t nw = b.count[4] + b.count[5] + b.count[6];
+  if (nw) k_cross_count_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, map, cnt);
+  if (b.count[7]) {
+    const int32_t* hubs = L + b.off[7];
+    k_zero_hub_counts<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], cnt);
+    k_cross_count_chunk<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7],
+                                                                     HUB_CHUNK_EDGES, g, map, cnt);
+  }
+}
+
+void launch_cross_emit(const DevGraph& g, const Buckets& b, const int32_t* map, int64_t* cursor, uint64_t* keys,
+                       uint32_t* vals, hipStream_t st) {
+  const int32_t* L = b.list;
+  if (b.count[0]) k_cross_emit_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, map, cursor, keys, vals);
+  if (b.count[1]) k_cross_emit_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, map, cursor, keys, vals);
+  if (b.count[2]) k_cross_emit_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, map, cursor, keys, vals);
+  if (b.count[3]) k_cross_emit_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, map, cursor, keys, vals);
+  int64_t nw = b.count[4] + b.count[5];
+  if (nw) k_cross_emit_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, map, cursor, keys, vals);
+  if (b.count[6]) k_cross_emit_chunk<<<(unsigned)b.count[6], HUB_BLOCK, 0, st>>>(L + b.off[6], nullptr, b.count[6], 0, g, map, cursor, keys, vals);
+  if (b.count[7]) k_cross_emit_chunk<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], HUB_CHUNK_EDGES, g, map, cursor, keys, vals);
+}
+
+void launch_heads(const uint64_t* keys, int64_t m, uint8_t* head, hipStream_t st) {
+  k_heads<<<grid_for(m), BLOCK, 0, st>>>(keys, m, head);
+}
+
+void launch_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8_t* head, const int32_t* uid,
+                         int64_t m, int32_t* cidx, int32_t* cw, int32_t* cdeg, hipStream_t st) {
+  k_coarse_write<<<grid_for(m), BLOCK, 0, st>>>(keys, vals, head, uid, m, cidx, cw, cdeg);
+}
+
+void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st) {
+  k_project<<<grid_for(n), BLOCK, 0, st>>>(coarse_C, map, n, fine_C);
+}
+
+void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,
+                       hipStream_t st) {
+  k_downsample<<<grid_for(n), BLOCK, 0, st>>>(B, rankB, map, n, Cc);
+}
+
+}  // namespace lcc

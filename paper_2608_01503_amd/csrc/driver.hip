@@ -1,0 +1,904 @@
+// Host driver and C-ABI of the MI355X LambdaCC library (include/lcc.h).
+//
+// A context owns a workspace carved once per graph size (per-vertex state, degree buckets, the edge arena
+// shared by the hub hash tables, the contraction sort and the refinement sort) and a pool from which the
+// coarse level graphs are bump-allocated (reset at the end of every call, kept for the next).  All work of a
+// call is queued on the caller's stream; the host synchronises only where a size decides the next launch
+// (bucket counts, cluster counts, coarse entry counts) -- a handful of times per level.
+#include <algorithm>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/lcc.h"
+#include "common.h"
+
+using namespace lcc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Fail {
+  lcc_status st;
+};
+
+[[noreturn]] void fail(lcc_status st, const std::string& msg) {
+  g_last_error = msg;
+  throw Fail{st};
+}
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(LCC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t ALIGN = 256;
+constexpr int NSLOT = 4 * 1024 + 16;
+
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    size_t bytes = align_up((size_t)std::max<int64_t>(count, 1) * sizeof(T));
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+// Workspace buffers of one context, sized for a level-0 graph of n vertices and nnz entries.
+struct WS {
+  Ctrl* ctrl;
+  LMSlot* slots;
+  int64_t* in_off; int32_t* in_idx; int32_t* in_w; int64_t* in_vwg; int32_t* in_labels;
+  int64_t* vw0;
+  int32_t *C, *Cout, *sz, *scan_a, *scan_b, *freelist;
+  int64_t* W;
+  VState* vs;
+  uint8_t *keep, *empty, *used;
+  int32_t *rank, *cnt, *list0, *hub_cnt, *hub_off0;
+  int64_t* pos;
+  int64_t* hub_ps; int32_t* hub_pc; int64_t* hub_pown; int64_t* hub_acc;
+  uint64_t *k0, *k1; uint32_t *v0, *v1;
+  uint8_t* head; int32_t* uid;
+  int64_t *WB, *aB, *aX, *pw, *pc, *t64a, *t64b, *alt_gain;
+  uint8_t *inU, *flip, *has_child, *member;
+  int32_t *H, *par, *root, *tsz, *pos_of, *fail, *mpos, *alt_list;
+  void* scan_temp;
+  void* radix_temp;
+};
+
+size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
+  Carver c{base};
+  const int64_t M = std::max(n, nnz);
+  const int64_t nch = nnz / HUB_CHUNK_EDGES + n + 1;
+  w.ctrl = c.take<Ctrl>(1);
+  w.slots = c.take<LMSlot>(NSLOT);
+  w.in_off = c.take<int64_t>(n + 1);
+  w.in_idx = c.take<int32_t>(nnz);
+  w.in_w = c.take<int32_t>(nnz);
+  w.in_vwg = c.take<int64_t>(n);
+  w.in_labels = c.take<int32_t>(n);
+  w.vw0 = c.take<int64_t>(n);
+  w.C = c.take<int32_t>(n); w.Cout = c.take<int32_t>(n); w.sz = c.take<int32_t>(n);
+  w.scan_a = c.take<int32_t>(n + 1); w.scan_b = c.take<int32_t>(n + 1); w.freelist = c.take<int32_t>(n);
+  w.W = c.take<int64_t>(n);
+  w.vs = c.take<VState>(n);
+  w.keep = c.take<uint8_t>(n); w.empty = c.take<uint8_t>(n); w.used = c.take<uint8_t>(n);
+  w.rank = c.take<int32_t>(n + 1); w.cnt = c.take<int32_t>(n); w.list0 = c.take<int32_t>(n);
+  w.hub_cnt = c.take<int32_t>(n); w.hub_off0 = c.take<int32_t>(n + 1);
+  w.pos = c.take<int64_t>(n + 1);
+  w.hub_ps = c.take<int64_t>(nch); w.hub_pc = c.take<int32_t>(nch); w.hub_pown = c.take<int64_t>(nch);
+  w.hub_acc = c.take<int64_t>(n);
+  // k0 and k1 are adjacent: together they also hold the hub hash tables (2 nnz slots of 8 bytes)
+  w.k0 = c.take<uint64_t>(M); w.k1 = c.take<uint64_t>(M);
+  w.v0 = c.take<uint32_t>(M); w.v1 = c.take<uint32_t>(M);
+  w.head = c.take<uint8_t>(M); w.uid = c.take<int32_t>(M + 1);
+  w.WB = c.take<int64_t>(n); w.aB = c.take<int64_t>(n); w.aX = c.take<int64_t>(n);
+  w.pw = c.take<int64_t>(n + 1); w.pc = c.take<int64_t>(n + 1);
+  w.t64a = c.take<int64_t>(n); w.t64b = c.take<int64_t>(n); w.alt_gain = c.take<int64_t>(n);
+  w.inU = c.take<uint8_t>(n); w.flip = c.take<uint8_t>(n); w.has_child = c.take<uint8_t>(n);
+  w.member = c.take<uint8_t>(n);
+  w.H = c.take<int32_t>(n); w.par = c.take<int32_t>(n); w.root = c.take<int32_t>(n); w.tsz = c.take<int32_t>(n);
+  w.pos_of = c.take<int32_t>(n); w.fail = c.take<int32_t>(n); w.mpos = c.take<int32_t>(n + 1);
+  w.alt_list = c.take<int32_t>(n);
+  w.scan_temp = c.take<char>((int64_t)scan_temp_bytes(M + 1));
+  w.radix_temp = c.take<char>((int64_t)radix_temp_bytes(M));
+  return c.off;
+}
+
+// Level graphs: bump allocation from chunks of the caller's allocator, reset per call.
+struct Pool {
+  struct Chunk { char* p; size_t cap; };
+  std::vector<Chunk> chunks;
+  size_t cur = 0, off = 0;
+};
+
+// Footprint of the coarse levels (a generous geometric bound; the pool grows if a graph needs more).
+size_t level_bytes(int64_t n, int64_t nnz) {
+  return align_up((size_t)(n + 1) * 8) + align_up((size_t)nnz * 8) + align_up((size_t)n * 8) +
+         4 * align_up((size_t)n * 4) + align_up((size_t)(n + 2) * 4);
+}
+
+}  // namespace
+
+struct lcc_ctx {
+  int device = 0;
+  lcc_alloc_fn alloc = nullptr;
+  lcc_free_fn freef = nullptr;
+  void* user = nullptr;
+  char* ws_base = nullptr;
+  size_t ws_bytes = 0;
+  int64_t ws_n = -1, ws_nnz = -1;
+  WS w{};
+  Pool pool;
+  Ctrl* h_ctrl = nullptr;       // pinned mirror
+  LMSlot* h_slots = nullptr;    // pinned mirror
+  std::mutex mu;
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (alloc) p = alloc(bytes, user);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (!p) fail(LCC_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    if (freef) freef(p, user);
+    else (void)hipFree(p);
+  }
+  void ensure_ws(int64_t n, int64_t nnz) {
+    if (n <= ws_n && nnz <= ws_nnz) return;
+    int64_t nn = std::max(n, ws_n), ne = std::max(nnz, ws_nnz);
+    WS tmp{};
+    size_t need = carve(tmp, nullptr, nn, ne);
+    if (ws_base) { (void)hipDeviceSynchronize(); dfree(ws_base); ws_base = nullptr; }
+    ws_base = (char*)dalloc(need);
+    ws_bytes = need;
+    carve(w, ws_base, nn, ne);
+    ws_n = nn;
+    ws_nnz = ne;
+  }
+  void* pool_take(size_t bytes) {
+    bytes = align_up(bytes);
+    while (pool.cur < pool.chunks.size()) {
+      auto& c = pool.chunks[pool.cur];
+      if (pool.off + bytes <= c.cap) {
+        void* p = c.p + pool.off;
+        pool.off += bytes;
+        return p;
+      }
+      ++pool.cur;
+      pool.off = 0;
+    }
+    size_t cap = std::max(bytes, std::max((size_t)64 << 20, level_bytes(ws_n, ws_nnz)));
+    pool.chunks.push_back({(char*)dalloc(cap), cap});
+    pool.cur = pool.chunks.size() - 1;
+    pool.off = bytes;
+    return pool.chunks.back().p;
+  }
+  void pool_reset() { pool.cur = 0; pool.off = 0; }
+};
+
+namespace {
+
+template <typename T>
+T* take(lcc_ctx* ctx, int64_t count) {
+  return (T*)ctx->pool_take((size_t)std::max<int64_t>(count, 1) * sizeof(T));
+}
+
+struct Level {
+  DevGraph g;
+  Buckets b;
+  int32_t* map = nullptr;  // fine vertex -> coarse vertex of the next level
+  int32_t* C = nullptr;    // clustering of this level
+  int64_t sum_w2 = 0;
+};
+
+__global__ void k_reset_level_counters(Ctrl* c) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int b = 0; b < NBUCKET; ++b) { c->bucket_count[b] = 0; c->bucket_cursor[b] = 0; }
+  c->count3 = 0;
+  c->sum_w = 0;
+  c->sum_w2 = 0;
+}
+
+__global__ void k_ones(int32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 1;
+}
+
+__global__ void k_labels_in_range(const int32_t* lab, int64_t n, Ctrl* c) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (lab[i] < 0 || lab[i] >= n) atomicOr(&c->err_bits, ERRB_INVALID);
+}
+
+unsigned grid1(int64_t n) {
+  int64_t g = (n + BLOCK - 1) / BLOCK;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+struct Run {
+  lcc_ctx* ctx;
+  hipStream_t st;
+  WS& w;
+  lcc_options o;
+  Score sc{};
+  int64_t p = 0, q = 1;
+  std::vector<Level> lv;
+  std::vector<int64_t> trace;   // 8 int64 per record
+  int nslot = 0;
+  uint32_t flags = 0;
+  uint64_t W = 0;
+  uint64_t refine_calls = 0;
+
+  Run(lcc_ctx* c, hipStream_t s) : ctx(c), st(s), w(c->w) {}
+
+  void sync(const char* what) {
+    hip_check(hipGetLastError(), what);
+    hip_check(hipStreamSynchronize(st), what);
+  }
+  void read_ctrl(const char* what) {
+    hip_check(hipMemcpyAsync(ctx->h_ctrl, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), what);
+    sync(what);
+  }
+  void rec(int64_t kind, int64_t level, int64_t phase, int64_t pass, int64_t a, int64_t b, int64_t c,
+           int64_t d) {
+    int64_t r[8] = {kind, level, phase, pass, a, b, c, d};
+    trace.insert(trace.end(), r, r + 8);
+  }
+
+  // degree buckets of a level + hub chunk offsets + vertex weight sums
+  void prepare(Level& L, int32_t* list, int32_t* hub_off) {
+    const int64_t n = L.g.n;
+    k_reset_level_counters<<<1, 1, 0, st>>>(w.ctrl);
+    launch_buckets(L.g.off, n, list, w.ctrl, st);
+    launch_vertex_sums(L.g.vw, n, w.ctrl, st);
+    read_ctrl("buckets");
+    Buckets& b = L.b;
+    b.list = list;
+    for (int k = 0; k < NBUCKET; ++k) { b.count[k] = ctx->h_ctrl->bucket_count[k]; b.off[k] = ctx->h_ctrl->bucket_off[k]; }
+    b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
+    b.hub_chunks = ctx->h_ctrl->count3;
+    b.hub_chunk_off = hub_off;
+    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
+    if (b.count[NBUCKET - 1]) launch_hub_chunks(list + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, hub_off, w.scan_temp, st);
+  }
+
+  LMBuffers bufs() {
+    LMBuffers B{};
+    B.C = w.C; B.Cout = w.Cout; B.W = w.W; B.sz = w.sz; B.vs = w.vs; B.keep = w.keep; B.empty = w.empty;
+    B.scan_a = w.scan_a; B.scan_b = w.scan_b; B.freelist = w.freelist; B.arena = (uint32_t*)w.k0;
+    B.scan_temp = w.scan_temp;
+    return B;
+  }
+
+  LMParams lm_params(const Level& L) {
+    LMParams P{};
+    P.sc = sc;
+    P.pass_limit = o.pass_limit;
+    for (int i = 1; i <= o.pass_limit; ++i) {
+      int k = 0;
+      while (k < o.n_phi - 1 && (uint32_t)i > o.phi_until[k]) ++k;
+      P.phi_num[i] = o.phi_num[k];
+      P.phi_den[i] = o.phi_den[k];
+    }
+    P.sum_w2 = L.sum_w2;
+    return P;
+  }
+
+  // LocalMovePasses on level l from L.C (or singletons); result in L.C.  Returns the slot used.
+  int local_move_level(int l, bool singleton, int phase) {
+    Level& L = lv[l];
+    if (nslot >= NSLOT) fail(LCC_ERR_INVALID, "too many local-move calls");
+    int s = nslot++;
+    rec(-1, l, phase, 0, s, 0, 0, 0);  // marker: the pass records of slot s go here
+    LMBuffers B = bufs();
+    if (!singleton) copy_i32(w.C, L.C, L.g.n, st);
+    local_move(L.g, L.b, lm_params(L), singleton, B, w.slots + s, w.ctrl, st);
+    copy_i32(L.C, w.Cout, L.g.n, st);
+    return s;
+  }
+
+  LMSlot read_slot(int s) {
+    hip_check(hipMemcpyAsync(ctx->h_slots + s, w.slots + s, sizeof(LMSlot), hipMemcpyDeviceToHost, st), "slot");
+    sync("slot");
+    return ctx->h_slots[s];
+  }
+
+  int64_t count_labels(const int32_t* labels, int64_t n) {
+    launch_label_rank(labels, n, w.used, w.rank, w.scan_temp, st);
+    int32_t nc = 0;
+    hip_check(hipMemcpyAsync(&nc, w.rank + n, sizeof(int32_t), hipMemcpyDeviceToHost, st), "count");
+    sync("count");
+    return nc;
+  }
+
+  // Contract level l by `labels` (rank already in w.rank, nc clusters) into a new level l+1.
+  void contract(int l, const int32_t* labels, int64_t nc) {
+    Level& L = lv[l];
+    const int64_t n = L.g.n;
+    L.map = take<int32_t>(ctx, n);
+    launch_map_labels(labels, w.rank, n, L.map, st);
+    Level N;
+    int64_t* coff = take<int64_t>(ctx, nc + 1);
+    int64_t* cvw = take<int64_t>(ctx, nc);
+    fill_i64(cvw, 0, nc, st);
+    launch_coarse_vw(L.map, L.g.vw, n, cvw, st);
+    launch_cross_count(L.g, L.b, L.map, w.cnt, st);
+    scan_i32_i64(w.cnt, w.pos, n, w.scan_temp, st);
+    int64_t E = 0;
+    hip_check(hipMemcpyAsync(&E, w.pos + n, sizeof(int64_t), hipMemcpyDeviceToHost, st), "entries");
+    sync("entries");
+    int64_t nnzc = 0;
+    int32_t* cidx;
+    int32_t* cw;
+    int32_t* cdeg = take<int32_t>(ctx, nc);
+    fill_i32(cdeg, 0, nc, st);
+    if (E > 0) {
+      launch_cross_emit(L.g, L.b, L.map, w.pos, w.k0, w.v0, st);
+      int ybits = 1;
+      while (((int64_t)1 << ybits) < nc) ++ybits;
+      int shifts[8], np = 0;
+      for (int s = 0; s < ybits; s += 8) shifts[np++] = s;
+      for (int s = 0; s < ybits; s += 8) shifts[np++] = 32 + s;
+      int which = radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, E, shifts, np, w.radix_temp, st);
+      const uint64_t* ks = which ? w.k1 : w.k0;
+      const uint32_t* vs = which ? w.v1 : w.v0;
+      launch_heads(ks, E, w.head, st);
+      scan_u8_i32(w.head, w.uid, E, w.scan_temp, nullptr, st);
+      int32_t nz = 0;
+      hip_check(hipMemcpyAsync(&nz, w.uid + E, sizeof(int32_t), hipMemcpyDeviceToHost, st), "coarse nnz");
+      sync("coarse nnz");
+      nnzc = nz;
+      cidx = take<int32_t>(ctx, nnzc);
+      cw = take<int32_t>(ctx, nnzc);
+      fill_i32(cw, 0, nnzc, st);
+      launch_coarse_write(ks, vs, w.head, w.uid, E, cidx, cw, cdeg, st);
+    } else {
+      cidx = take<int32_t>(ctx, 1);
+      cw = take<int32_t>(ctx, 1);
+    }
+    scan_i32_i64(cdeg, coff, nc, w.scan_temp, st);
+    N.g.n = nc;
+    N.g.nnz = nnzc;
+    N.g.off = coff;
+    N.g.idx = cidx;
+    N.g.w = cw;
+    N.g.vw = cvw;
+    N.C = take<int32_t>(ctx, nc);
+    lv.push_back(N);
+    Level& NL = lv.back();
+    prepare(NL, take<int32_t>(ctx, nc), take<int32_t>(ctx, nc + 1));
+  }
+
+  // ---------------------------------------------------------------------------------------------------
+  // Alg. 1: Louvain / Louvain+
+  // ---------------------------------------------------------------------------------------------------
+  int louvain(bool plus) {
+    int l = 0;
+    for (;;) {
+      int s = local_move_level(l, true, 0);
+      Level& L = lv[l];
+      int64_t nc = count_labels(L.C, L.g.n);
+      LMSlot S = read_slot(s);
+      rec(2, l, 0, 0, L.g.n, L.g.nnz, nc, S.Nbest);
+      if (nc == L.g.n) break;
+      if (l + 1 >= o.max_levels) { flags |= LCC_FLAG_LEVEL_CAP; break; }
+      contract(l, lv[l].C, nc);
+      ++l;
+    }
+    int top = l;
+    for (int k = top - 1; k >= 0; --k) {
+      Level& L = lv[k];
+      launch_project(lv[k + 1].C, L.map, L.g.n, L.C, st);
+      if (plus) {
+        int s = local_move_level(k, false, 1);
+        int64_t nc = count_labels(L.C, L.g.n);
+        LMSlot S = read_slot(s);
+        rec(2, k, 1, 0, L.g.n, L.g.nnz, nc, S.Nbest);
+      }
+    }
+    return top;
+  }
+
+  // ---------------------------------------------------------------------------------------------------
+  // Alg. 5: pLeiden / pLeiden+
+  // ---------------------------------------------------------------------------------------------------
+  RefineBuffers rbufs() {
+    RefineBuffers r{};
+    r.WB = w.WB; r.aB = w.aB; r.aX = w.aX; r.inU = w.inU; r.H = w.H; r.par = w.par; r.root = w.root;
+    r.flip = w.flip; r.has_child = w.has_child; r.tsz = w.tsz; r.member = w.member; r.mpos = w.mpos;
+    r.k0 = w.k0; r.v0 = w.v0; r.k1 = w.k1; r.v1 = w.v1;
+    r.pw = w.pw; r.pc = w.pc; r.tmp64a = w.t64a; r.tmp64b = w.t64b; r.pos_of = w.pos_of; r.fail = w.fail;
+    r.scan_temp = w.scan_temp; r.radix_temp = w.radix_temp;
+    return r;
+  }
+
+  int leiden(bool plus, const int32_t* init) {
+    int l = 0;
+    int noprog = 0;
+    if (init) copy_i32(lv[0].C, init, lv[0].g.n, st);
+    bool singleton = init == nullptr;
+    for (;;) {
+      Level& L = lv[l];
+      const int64_t n = L.g.n;
+      int s = local_move_level(l, singleton, 0);
+      singleton = false;
+      LMSlot S = read_slot(s);
+      int64_t N = S.Nbest;
+      if (S.Nbest == S.N0) {
+        // C_l unchanged by the local move: the alternate local move (Sec. V-A) from C_l
+        LMBuffers B = bufs();
+        copy_i32(w.C, L.C, n, st);
+        launch_cluster_weights(w.C, L.g.vw, n, w.W, w.sz, st);
+        if (nslot >= NSLOT) fail(LCC_ERR_INVALID, "too many local-move calls");
+        int s2 = nslot++;
+        lmalt(L.g, L.b, sc, B, w.slots + s2, w.ctrl, w.alt_list, w.alt_gain, st);
+        copy_i32(L.C, w.C, n, st);
+        launch_cluster_weights(w.C, L.g.vw, n, w.W, nullptr, st);
+        launch_objective(L.g, L.b, w.C, w.W, w.ctrl, st);
+        read_ctrl("lmalt");
+        N = q * ctx->h_ctrl->obj_I - p * (ctx->h_ctrl->obj_SW2 - L.sum_w2);
+        rec(3, l, 0, 0, ctx->h_ctrl->lmalt_k, ctx->h_ctrl->lmalt_best_k, N, 0);
+      }
+      int64_t nc = count_labels(L.C, n);
+      rec(2, l, 0, 0, n, L.g.nnz, nc, N);
+      if (nc == n) break;
+      if (l + 1 >= o.max_levels) { flags |= LCC_FLAG_LEVEL_CAP; break; }
+      // refinement R of B = C_l; compaction of B for the downsampled clustering
+      int32_t* R = w.in_labels;
+      RefineBuffers rb = rbufs();
+      refine(L.g, L.b, sc, L.C, o.seed, refine_calls, R, rb, w.ctrl, st);
+      int64_t nR = count_labels(R, n);
+      read_ctrl("refine");
+      if (ctx->h_ctrl->err_bits & ERRB_INTERNAL) fail(LCC_ERR_DEVICE, "refinement produced a parent cycle");
+      rec(4, l, 0, 0, nR, (int64_t)refine_calls, ctx->h_ctrl->refine_U, ctx->h_ctrl->refine_m);
+      ++refine_calls;
+      if (nR == n) {
+        if (++noprog >= 3) { flags |= LCC_FLAG_REFINE_NO_PROGRESS; break; }
+        continue;  // the same level again with the next refinement seed
+      }
+      noprog = 0;
+      contract(l, R, nR);
+      // Downsample: C_{l+1}[x] = compact(C_l)[C_l[v]] for any v in x
+      Level& L2 = lv[l];
+      count_labels(L2.C, n);  // w.rank = compaction of C_l
+      launch_downsample(L2.C, w.rank, L2.map, n, lv[l + 1].C, st);
+      ++l;
+    }
+    int top = l;
+    for (int k = top - 1; k >= 0; --k) {
+      Level& L = lv[k];
+      launch_project(lv[k + 1].C, L.map, L.g.n, L.C, st);
+      if (plus) {
+        int s = local_move_level(k, false, 1);
+        int64_t nc = count_labels(L.C, L.g.n);
+        LMSlot S = read_slot(s);
+        rec(2, k, 1, 0, L.g.n, L.g.nnz, nc, S.Nbest);
+      }
+    }
+    return top;
+  }
+
+  void emit_pass_records() {
+    // local-move pass records are read back in one copy at the end
+    if (!nslot) return;
+    hip_check(hipMemcpyAsync(ctx->h_slots, w.slots, sizeof(LMSlot) * nslot, hipMemcpyDeviceToHost, st), "slots");
+    sync("slots");
+  }
+};
+
+void default_opts(lcc_options* o) {
+  memset(o, 0, sizeof(*o));
+  o->pass_limit = 6;
+  o->n_phi = 2;
+  o->phi_num[0] = 3; o->phi_den[0] = 4; o->phi_until[0] = 4;
+  o->phi_num[1] = 1; o->phi_den[1] = 4; o->phi_until[1] = 6;
+  o->eps_num = 1; o->eps_den = 10;
+  o->seed = 1;
+  o->max_levels = 64;
+  o->validate = 1;
+  o->trace = nullptr;
+}
+
+void check_opts(const lcc_options& o) {
+  if (o.pass_limit < 0 || o.pass_limit > MAX_PASSES) fail(LCC_ERR_INVALID, "pass_limit outside [0, 32]");
+  if (o.n_phi < 1 || o.n_phi > 8) fail(LCC_ERR_INVALID, "n_phi outside [1, 8]");
+  for (int k = 0; k < o.n_phi; ++k)
+    if (o.phi_den[k] == 0 || o.phi_num[k] > o.phi_den[k]) fail(LCC_ERR_INVALID, "temperature phi outside [0, 1]");
+  if (o.eps_den == 0) fail(LCC_ERR_INVALID, "eps_den = 0");
+  if (o.max_levels <= 0 || o.max_levels > 1024) fail(LCC_ERR_INVALID, "max_levels outside [1, 1024]");
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) { uint64_t t = a % b; a = b; b = t; }
+  return a;
+}
+
+// Setup (Sec. II): copy or adopt the input, validate it on the device, derive vertex weights, W, W_E,
+// lambda = p / q in lowest terms and the exactness bound.  Fills lv[0].
+void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_labels) {
+  lcc_ctx* ctx = R.ctx;
+  WS& w = R.w;
+  hipStream_t st = R.st;
+  const int64_t n = g->n, nnz = g->nnz;
+  Level L0;
+  L0.g.n = n;
+  L0.g.nnz = nnz;
+  const bool host = g->mem == LCC_MEM_HOST;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    if (bytes) hip_check(hipMemcpyAsync(dst, src, bytes, host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st), "input copy");
+  };
+  // offsets
+  if (g->offsets_bits == 64 && !host) {
+    L0.g.off = (const int64_t*)g->offsets;
+  } else if (g->offsets_bits == 64) {
+    cp(w.in_off, g->offsets, (size_t)(n + 1) * 8);
+    L0.g.off = w.in_off;
+  } else {
+    int32_t* tmp = (int32_t*)w.k0;  // staging for 32-bit offsets
+    cp(tmp, g->offsets, (size_t)(n + 1) * 4);
+    offsets32_to_64(tmp, w.in_off, n + 1, st);
+    L0.g.off = w.in_off;
+  }
+  if (host) { cp(w.in_idx, g->indices, (size_t)nnz * 4); L0.g.idx = w.in_idx; }
+  else L0.g.idx = g->indices;
+  if (!g->edge_w) {
+    k_ones<<<grid1(nnz), BLOCK, 0, st>>>(w.in_w, nnz);
+    L0.g.w = w.in_w;
+  } else if (host) {
+    cp(w.in_w, g->edge_w, (size_t)nnz * 4);
+    L0.g.w = w.in_w;
+  } else {
+    L0.g.w = g->edge_w;
+  }
+  const int64_t* vwg = nullptr;
+  if (g->vw_mode == LCC_VW_GIVEN) {
+    if (host) { cp(w.in_vwg, g->vertex_w, (size_t)n * 8); vwg = w.in_vwg; }
+    else vwg = g->vertex_w;
+  }
+  L0.g.vw = w.vw0;
+  L0.C = take<int32_t>(ctx, n);
+  zero_bytes(w.ctrl, sizeof(Ctrl), st);
+  // offsets
+  launch_validate_offsets(L0.g.off, n, nnz, w.ctrl, st);
+  R.read_ctrl("validate offsets");
+  if (ctx->h_ctrl->err_bits & ERRB_INVALID) fail(LCC_ERR_INVALID, "CSR offsets are not a valid row partition");
+  R.lv.push_back(L0);
+  Level& L = R.lv[0];
+  // buckets need only the offsets; vertex weights are derived by the row pass below
+  {
+    // prepare() reads vertex sums, which are not derived yet: buckets first, sums after the row pass
+    k_reset_level_counters<<<1, 1, 0, st>>>(w.ctrl);
+    launch_buckets(L.g.off, n, w.list0, w.ctrl, st);
+    R.read_ctrl("buckets");
+    Buckets& b = L.b;
+    b.list = w.list0;
+    for (int k = 0; k < NBUCKET; ++k) { b.count[k] = ctx->h_ctrl->bucket_count[k]; b.off[k] = ctx->h_ctrl->bucket_off[k]; }
+    b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
+    b.hub_chunks = ctx->h_ctrl->count3;
+    b.hub_chunk_off = w.hub_off0;
+    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    if (b.count[NBUCKET - 1])
+      launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
+  }
+  launch_validate_rows(L.g, L.b, (int)g->vw_mode, vwg, w.vw0, w.ctrl, st);
+  launch_vertex_sums(w.vw0, n, w.ctrl, st);
+  if (init_labels) k_labels_in_range<<<grid1(n), BLOCK, 0, st>>>(init_labels, n, w.ctrl);
+  R.read_ctrl("validate rows");
+  const Ctrl& c = *ctx->h_ctrl;
+  uint32_t e = c.err_bits;
+  if (!R.o.validate) e &= ERRB_INVALID | ERRB_VW_TOO_BIG;  // structural faults that would break the kernels
+  if (e & ERRB_INVALID) fail(LCC_ERR_INVALID, "neighbour index out of range (or initial label outside [0, n))");
+  if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
+  if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
+  if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
+  if (R.o.validate && (c.count0 != 0 || c.count1 != 0)) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
+  if (c.sum_we >= ((uint64_t)1 << 31)) fail(LCC_ERR_OVERFLOW, "total edge weight >= 2^31");
+  if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
+  L.sum_w2 = (int64_t)c.sum_w2;
+  R.W = c.sum_w;
+  const unsigned __int128 W = c.sum_w, WE = c.sum_we;
+  if (lam.den == 0) fail(LCC_ERR_LAMBDA, "lambda denominator is zero");
+  unsigned __int128 P = lam.num, Q = (unsigned __int128)lam.den * (lam.over_total_weight ? W : 1);
+  if (Q == 0 || P > Q) fail(LCC_ERR_LAMBDA, "lambda outside [0, 1] or undefined");
+  if (Q >> 64) fail(LCC_ERR_OVERFLOW, "lambda denominator >= 2^64");
+  uint64_t p = (uint64_t)P, q = (uint64_t)Q;
+  if (p == 0) q = 1;
+  else { uint64_t d = gcd64(p, q); p /= d; q /= d; }
+  if (p > 0 && W >= ((unsigned __int128)1 << 30)) fail(LCC_ERR_OVERFLOW, "q W_E + p W^2 >= 2^60");
+  if ((unsigned __int128)q * WE + (unsigned __int128)p * W * W >= ((unsigned __int128)1 << 60))
+    fail(LCC_ERR_OVERFLOW, "q W_E + p W^2 >= 2^60");
+  R.p = (int64_t)p;
+  R.q = (int64_t)q;
+  R.sc.p = R.p;
+  R.sc.q = R.q;
+  // tie window: |delta_u - delta_v| <= floor((eps_num q - 1) / (2 eps_den)), at least 0
+  __int128 num = (__int128)R.o.eps_num * q - 1;
+  __int128 den = 2 * (__int128)R.o.eps_den;
+  __int128 t = num >= 0 ? num / den : -1;
+  R.sc.tie = t < 0 ? 0 : (int64_t)t;
+}
+
+void fill_result(lcc_result* res, int64_t nc, __int128 N, int64_t p, int64_t q, int64_t sum_w2, uint64_t W,
+                 bool modularity, int levels, uint32_t flags) {
+  res->num_clusters = nc;
+  res->obj_num_hi = (int64_t)(N >> 64);
+  res->obj_num_lo = (uint64_t)N;
+  res->obj_den = (uint64_t)q;
+  res->objective = (double)N / (double)q;
+  if (modularity && W > 0) {
+    __int128 num = N - (__int128)p * sum_w2;
+    res->modularity = (double)num / ((double)q * (double)W);
+  } else {
+    res->modularity = NAN;
+  }
+  res->levels = levels;
+  res->flags = flags;
+}
+
+void check_graph_args(const lcc_graph* g) {
+  if (!g) fail(LCC_ERR_INVALID, "graph is NULL");
+  if (g->n < 0 || g->n > 2147483647LL) fail(LCC_ERR_INVALID, "n outside [0, 2^31)");
+  if (g->nnz < 0 || g->nnz > 2147483647LL * 2) fail(LCC_ERR_INVALID, "nnz outside [0, 2^32)");
+  if (g->offsets_bits != 32 && g->offsets_bits != 64) fail(LCC_ERR_INVALID, "offsets_bits must be 32 or 64");
+  if (g->offsets_bits == 32 && g->nnz > 2147483647LL) fail(LCC_ERR_INVALID, "32-bit offsets with nnz >= 2^31");
+  if (!g->offsets) fail(LCC_ERR_INVALID, "offsets is NULL");
+  if (g->nnz > 0 && !g->indices) fail(LCC_ERR_INVALID, "indices is NULL");
+  if (g->vw_mode != LCC_VW_GIVEN && g->vw_mode != LCC_VW_WEIGHTED_DEGREE && g->vw_mode != LCC_VW_UNIT)
+    fail(LCC_ERR_INVALID, "unknown vertex-weight mode");
+  if (g->vw_mode == LCC_VW_GIVEN && !g->vertex_w && g->n > 0) fail(LCC_ERR_INVALID, "vertex_w is NULL");
+  if (g->mem != LCC_MEM_HOST && g->mem != LCC_MEM_DEVICE) fail(LCC_ERR_INVALID, "unknown memory kind");
+}
+
+lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_variant variant,
+                        const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res,
+                        const int32_t* init_labels) {
+  if (!ctx) fail(LCC_ERR_INVALID, "context is NULL");
+  check_graph_args(g);
+  if (!res) fail(LCC_ERR_INVALID, "result is NULL");
+  if (g->n > 0 && !labels_out) fail(LCC_ERR_INVALID, "labels_out is NULL");
+  if (variant < LCC_LOUVAIN || variant > LCC_PLEIDEN_PLUS) fail(LCC_ERR_INVALID, "unknown variant");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  Run R(ctx, st);
+  if (opts) R.o = *opts; else default_opts(&R.o);
+  check_opts(R.o);
+  ctx->ensure_ws(g->n, g->nnz);
+  ctx->pool_reset();
+  struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
+  const int64_t n = g->n;
+  if (n == 0) {
+    fill_result(res, 0, 0, 0, 1, 0, 0, false, 0, 0);
+    if (R.o.trace) R.o.trace->count = 0;
+    return LCC_OK;
+  }
+  R.lv.reserve((size_t)R.o.max_levels + 2);
+  setup(R, g, lam, init_labels);
+  int top = 0;
+  if (variant == LCC_LOUVAIN || variant == LCC_PLOUVAIN) top = R.louvain(variant == LCC_PLOUVAIN);
+  else top = R.leiden(variant == LCC_PLEIDEN_PLUS, init_labels);
+  // final compaction on level 0 and the exact objective (Eq. 1) of the result
+  Level& L0 = R.lv[0];
+  int64_t nc = R.count_labels(L0.C, n);
+  int32_t* lab = (g->mem == LCC_MEM_DEVICE) ? labels_out : R.w.in_labels;
+  launch_map_labels(L0.C, R.w.rank, n, lab, st);
+  launch_cluster_weights(lab, L0.g.vw, n, R.w.W, nullptr, st);
+  launch_objective(L0.g, L0.b, lab, R.w.W, R.w.ctrl, st);
+  R.read_ctrl("objective");
+  __int128 N = (__int128)R.q * ctx->h_ctrl->obj_I - (__int128)R.p * (ctx->h_ctrl->obj_SW2 - L0.sum_w2);
+  if (g->mem == LCC_MEM_HOST) {
+    hip_check(hipMemcpyAsync(labels_out, lab, (size_t)n * 4, hipMemcpyDeviceToHost, st), "labels");
+    R.sync("labels");
+  }
+  const bool mod = g->vw_mode == LCC_VW_WEIGHTED_DEGREE && lam.over_total_weight;
+  fill_result(res, nc, N, R.p, R.q, L0.sum_w2, R.W, mod, top + 1, R.flags);
+  if (R.o.trace) {
+    R.emit_pass_records();
+    std::vector<int64_t> out;
+    for (size_t r = 0; r + 8 <= R.trace.size(); r += 8) {
+      if (R.trace[r] != -1) {
+        out.insert(out.end(), R.trace.begin() + r, R.trace.begin() + r + 8);
+        continue;
+      }
+      const int lvl = (int)R.trace[r + 1], ph = (int)R.trace[r + 2], s = (int)R.trace[r + 4];
+      const LMSlot& S = ctx->h_slots[s];
+      for (int i = 1; i <= R.o.pass_limit; ++i) {
+        int64_t Ni = R.q * S.I[i] - R.p * (S.SW2[i] - R.lv[lvl].sum_w2);
+        int64_t rr[8] = {1, lvl, ph, i, S.nL[i], S.nM[i], Ni, 0};
+        out.insert(out.end(), rr, rr + 8);
+      }
+    }
+    lcc_trace* tr = R.o.trace;
+    int64_t cnt = (int64_t)out.size() / 8;
+    tr->count = cnt;
+    if (tr->records) memcpy(tr->records, out.data(), (size_t)std::min(cnt, tr->capacity) * 64);
+  }
+  return LCC_OK;
+}
+
+template <typename F>
+lcc_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return LCC_ERR_OOM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return LCC_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+// =========================================================================================================
+// C-ABI
+// =========================================================================================================
+extern "C" {
+
+lcc_status lcc_create(int device, lcc_alloc_fn alloc, lcc_free_fn free_fn, void* user, lcc_ctx** out) {
+  return guarded([&]() -> lcc_status {
+    if (!out) fail(LCC_ERR_INVALID, "out is NULL");
+    if ((alloc == nullptr) != (free_fn == nullptr)) fail(LCC_ERR_INVALID, "alloc and free must both be set");
+    int ndev = 0;
+    hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) fail(LCC_ERR_INVALID, "no such device");
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    lcc_ctx* c = new lcc_ctx();
+    c->device = device;
+    c->alloc = alloc;
+    c->freef = free_fn;
+    c->user = user;
+    if (hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_slots, sizeof(LMSlot) * NSLOT) != hipSuccess) {
+      delete c;
+      fail(LCC_ERR_DEVICE, "pinned host allocation failed");
+    }
+    *out = c;
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_destroy(lcc_ctx* ctx) {
+  return guarded([&]() -> lcc_status {
+    if (!ctx) return LCC_OK;
+    {
+      std::lock_guard<std::mutex> lock(ctx->mu);
+      (void)hipSetDevice(ctx->device);
+      (void)hipDeviceSynchronize();
+      ctx->dfree(ctx->ws_base);
+      for (auto& c : ctx->pool.chunks) ctx->dfree(c.p);
+      ctx->pool.chunks.clear();
+      if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
+      if (ctx->h_slots) (void)hipHostFree(ctx->h_slots);
+    }
+    delete ctx;
+    return LCC_OK;
+  });
+}
+
+void lcc_default_options(lcc_options* opts) {
+  if (opts) default_opts(opts);
+}
+
+lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size_t* bytes) {
+  return guarded([&]() -> lcc_status {
+    if (!bytes || n < 0 || nnz < 0) fail(LCC_ERR_INVALID, "bad arguments");
+    if (variant < LCC_LOUVAIN || variant > LCC_PLEIDEN_PLUS) fail(LCC_ERR_INVALID, "unknown variant");
+    WS tmp{};
+    size_t ws = carve(tmp, nullptr, n, nnz);
+    // coarse levels: bounded by twice the input (geometric coarsening); the pool grows beyond on demand
+    *bytes = ws + 2 * level_bytes(n, nnz);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_cluster(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                       const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res) {
+  return guarded([&]() { return cluster_impl(ctx, g, lambda, variant, opts, stream, labels_out, res, nullptr); });
+}
+
+lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lambdas,
+                             const lcc_variant* variants, int64_t count, const lcc_options* opts, void* stream,
+                             int32_t* const* labels_out, lcc_result* res) {
+  return guarded([&]() -> lcc_status {
+    if (count < 0 || (count > 0 && (!gs || !lambdas || !variants || !labels_out || !res)))
+      fail(LCC_ERR_INVALID, "bad batch arguments");
+    for (int64_t i = 0; i < count; ++i) {
+      lcc_status s = cluster_impl(ctx, &gs[i], lambdas[i], variants[i], opts, stream, labels_out[i], &res[i], nullptr);
+      if (s != LCC_OK) return s;
+    }
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const int32_t* labels, void* stream,
+                         lcc_result* res) {
+  return guarded([&]() -> lcc_status {
+    if (!ctx || !res) fail(LCC_ERR_INVALID, "bad arguments");
+    check_graph_args(g);
+    if (g->n > 0 && !labels) fail(LCC_ERR_INVALID, "labels is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    Run R(ctx, st);
+    default_opts(&R.o);
+    ctx->ensure_ws(g->n, g->nnz);
+    ctx->pool_reset();
+    struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
+    if (g->n == 0) {
+      fill_result(res, 0, 0, 0, 1, 0, 0, false, 0, 0);
+      return LCC_OK;
+    }
+    const int32_t* lab = labels;
+    if (g->mem == LCC_MEM_HOST) {
+      hip_check(hipMemcpyAsync(R.w.in_labels, labels, (size_t)g->n * 4, hipMemcpyHostToDevice, st), "labels");
+      lab = R.w.in_labels;
+    }
+    R.lv.reserve(2);
+    setup(R, g, lam, lab);
+    Level& L0 = R.lv[0];
+    int64_t nc = R.count_labels(lab, g->n);
+    launch_cluster_weights(lab, L0.g.vw, g->n, R.w.W, nullptr, st);
+    launch_objective(L0.g, L0.b, lab, R.w.W, R.w.ctrl, st);
+    R.read_ctrl("objective");
+    __int128 N = (__int128)R.q * ctx->h_ctrl->obj_I - (__int128)R.p * (ctx->h_ctrl->obj_SW2 - L0.sum_w2);
+    const bool mod = g->vw_mode == LCC_VW_WEIGHTED_DEGREE && lam.over_total_weight;
+    fill_result(res, nc, N, R.p, R.q, L0.sum_w2, R.W, mod, 1, 0);
+    return LCC_OK;
+  });
+}
+
+const char* lcc_status_string(lcc_status st) {
+  switch (st) {
+    case LCC_OK: return "ok";
+    case LCC_ERR_INVALID: return "invalid argument or CSR structure";
+    case LCC_ERR_NOT_SYMMETRIC: return "graph not symmetric";
+    case LCC_ERR_SELF_LOOP: return "self-loop";
+    case LCC_ERR_UNSORTED: return "row not strictly ascending";
+    case LCC_ERR_WEIGHT: return "non-positive edge weight or negative vertex weight";
+    case LCC_ERR_LAMBDA: return "lambda outside [0, 1] or undefined";
+    case LCC_ERR_OVERFLOW: return "exactness bound exceeded";
+    case LCC_ERR_OOM: return "out of device memory";
+    case LCC_ERR_DEVICE: return "HIP runtime error";
+    case LCC_ERR_BUSY: return "admission refused";
+    case LCC_ERR_NOT_FOUND: return "unknown ticket";
+  }
+  return "unknown status";
+}
+
+const char* lcc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// Entry used by the server (server.hip): clustering with an initial clustering for pLeiden.
+lcc_status lcc_cluster_init_internal(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                                     const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res,
+                                     const int32_t* init) {
+  return guarded([&]() { return cluster_impl(ctx, g, lambda, variant, opts, stream, labels_out, res, init); });
+}
+
+int lcc_ctx_device_internal(const lcc_ctx* ctx) { return ctx->device; }
+void lcc_ctx_allocator_internal(const lcc_ctx* ctx, lcc_alloc_fn* a, lcc_free_fn* f, void** user) {
+  *a = ctx->alloc;
+  *f = ctx->freef;
+  *user = ctx->user;
+}

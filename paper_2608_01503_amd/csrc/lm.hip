@@ -1,0 +1,1214 @@
+// Local move (Alg. 2), afterburner filter (Alg. 3), update, objective, degree buckets and CSR validation.
+//
+// Integer form (lambda = p / q in lowest terms, every w' scaled by q):
+//   a(v,c) = sum of w(u,v) over neighbours u with C[u] = c        W_c = sum of w(u) over cluster c
+//   S(v,c) = q a(v,c) - p w(v) W_c            (c != C[v])         S_cur = q a(v,C[v]) - p w(v) (W_C[v] - w(v))
+//   N(C)   = q I(C) - p (sum_c W_c^2 - sum_v w(v)^2)              (lambdaCC = N / q, Eq. 1)
+// The host guarantees q W_E + p W^2 < 2^60, so every score, delta and objective fits in int64; the
+// temperature test multiplies by the rational phi and is done in 128 bits.
+//
+// Work decomposition per degree bucket (see common.h): groups of G lanes (G = 4..32, one neighbour per lane,
+// neighbour clusters aggregated by register shuffles), one wavefront per vertex with an LDS open-addressing
+// hash (degree <= 1024), one workgroup per vertex with an LDS hash (degree <= 4096), and hub vertices split
+// into 4096-edge chunks processed by independent workgroups with a global-memory hash in the edge arena.
+#include "common.h"
+
+namespace lcc {
+
+namespace {
+
+constexpr int HUB_CHUNK = 4096;
+constexpr int HUB_BLOCK = 256;
+constexpr int BIG_BLOCK = 256;
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------------------------------------
+// reductions over a group of G lanes (G <= 64: shuffles; G == BLOCK-sized: shuffles + LDS)
+// ---------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool better(int64_t s2, int32_t c2, int64_t s, int32_t c) {
+  return s2 > s || (s2 == s && c2 < c);
+}
+
+template <int G>
+__device__ __forceinline__ void argmax_reduce(int64_t& s, int32_t& c) {
+  if constexpr (G <= WAVE) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+      int64_t s2 = __shfl_xor(s, o, G);
+      int32_t c2 = __shfl_xor(c, o, G);
+      if (better(s2, c2, s, c)) { s = s2; c = c2; }
+    }
+  } else {
+    __shared__ int64_t ss[G / WAVE];
+    __shared__ int32_t cc[G / WAVE];
+    argmax_reduce<WAVE>(s, c);
+    int wv = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) { ss[wv] = s; cc[wv] = c; }
+    __syncthreads();
+    s = ss[0]; c = cc[0];
+#pragma unroll
+    for (int k = 1; k < G / WAVE; ++k)
+      if (better(ss[k], cc[k], s, c)) { s = ss[k]; c = cc[k]; }
+    __syncthreads();
+  }
+}
+
+template <int G>
+__device__ __forceinline__ int64_t sum_reduce(int64_t x) {
+  if constexpr (G <= WAVE) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+    return x;
+  } else {
+    __shared__ int64_t ss[G / WAVE];
+    x = sum_reduce<WAVE>(x);
+    int wv = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) ss[wv] = x;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < G / WAVE; ++k) t += ss[k];
+    __syncthreads();
+    return t;
+  }
+}
+
+// Destination and candidacy of one vertex from its own score and its best neighbouring cluster
+// (Alg. 2: argmax, the empty-cluster rule, the temperature rule w'(v,D) >= (1 - phi) w'(v,C[v])).
+// strict != 0 replaces the temperature rule by "the move strictly improves" (node optimality, Sec. V-A).
+struct Verdict {
+  int32_t d;
+  int64_t delta;
+  bool cand;
+};
+__device__ __forceinline__ Verdict decide(int64_t scur, int64_t sbest, int32_t cbest, uint32_t pa, uint32_t pb,
+                                          int strict) {
+  int32_t d;
+  int64_t sd;
+  if (scur < 0 && (cbest == INT32_MAX || sbest < 0)) {
+    d = D_EMPTY;
+    sd = 0;
+  } else if (cbest == INT32_MAX) {
+    return {D_NONE, 0, false};
+  } else {
+    d = cbest;
+    sd = sbest;
+  }
+  int64_t delta = sd - scur;
+  bool cand = strict ? (delta > 0) : ((__int128)pb * sd >= (__int128)(pb - pa) * scur);
+  return {cand ? d : D_NONE, cand ? delta : 0, cand};
+}
+
+// Per-block counters flushed with one global atomic each.
+struct BlockCounters {
+  unsigned long long ncand;
+  unsigned long long own;
+};
+
+__device__ __forceinline__ void counters_init(BlockCounters* bc) {
+  if (threadIdx.x == 0) { bc->ncand = 0; bc->own = 0; }
+  __syncthreads();
+}
+__device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* ncand, int64_t* own) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (bc->ncand && ncand) atomicAdd((unsigned long long*)ncand, bc->ncand);
+    if (bc->own && own) atomicAdd((unsigned long long*)own, bc->own);
+  }
+}
+
+__device__ __forceinline__ void finish_vertex(int32_t v, int32_t cv, int64_t wv, int64_t own, int64_t sbest,
+                                              int32_t cbest, const Score& sc, const int64_t* W, uint32_t pa,
+                                              uint32_t pb, int strict, VState* vs, BlockCounters* bc) {
+  int64_t scur = sc.q * own - sc.p * wv * (W[cv] - wv);
+  Verdict vd = decide(scur, sbest, cbest, pa, pb, strict);
+  VState o;
+  o.c = cv;
+  o.d = vd.d;
+  o.delta = vd.delta;
+  vs[v] = o;
+  if (vd.cand) atomicAdd(&bc->ncand, 1ull);
+  if (own) atomicAdd(&bc->own, (unsigned long long)own);
+}
+
+__device__ __forceinline__ uint32_t hslot(int32_t c, int bits) {
+  return ((uint32_t)c * 2654435761u) >> (32 - bits);
+}
+
+__device__ __forceinline__ int ceil_log2(int64_t x) {
+  int b = 0;
+  while (((int64_t)1 << b) < x) ++b;
+  return b;
+}
+
+__device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
+  int64_t lo = 0, hi = n7;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (chunk_off[mid] <= blk) lo = mid; else hi = mid;
+  }
+  return (int)lo;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Pass bookkeeping (single thread)
+// ---------------------------------------------------------------------------------------------------------
+
+// Start of pass i: decide whether it repeats pass i-1 exactly (pass i-1 moved nothing and the temperature
+// is unchanged), and reset the pass counters.
+__global__ void k_pass_begin(LMSlot* s, int i, int same_phi) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  s->copy = 0;
+  s->n_empty = 0;
+  if (i >= 2 && same_phi && s->nM[i - 1] == 0) {
+    s->skip[i] = 1;
+    s->nL[i] = s->nL[i - 1];
+    s->nM[i] = 0;
+    s->I[i - 1] = s->I[i - 2];
+    s->SW2[i] = s->SW2[i - 1];
+  } else {
+    s->skip[i] = 0;
+    s->nL[i] = 0;
+    s->nM[i] = 0;
+    s->I[i - 1] = 0;
+    s->SW2[i] = 0;
+  }
+}
+
+// Best-so-far check of state k (Alg. 2: C_out <- C when lambdaCC(C) > lambdaCC(C_out)).  Skipped when state
+// k equals state k-1, which was checked already.
+__global__ void k_best(LMSlot* s, int k, int skipk, int64_t p, int64_t q, int64_t sum_w2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  s->copy = 0;
+  if (skipk >= 0 && s->skip[skipk]) return;
+  int64_t N = q * s->I[k] - p * (s->SW2[k] - sum_w2);
+  if (k == 0) {
+    s->N0 = N;
+    s->Nbest = N;
+  } else if (N > s->Nbest) {
+    s->Nbest = N;
+    s->copy = 1;
+  }
+}
+
+__global__ void k_copy_if(const LMSlot* s, const int32_t* C, int32_t* Cout, int64_t n) {
+  if (!s->copy) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    Cout[i] = C[i];
+}
+
+__global__ void k_final_state(LMSlot* s, int last) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (s->skip[last]) s->I[last] = s->I[last - 1];
+  else s->I[last] = 0;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Singleton pass (first coarsening pass, Sec. IV-A: clusters are the vertices, no enumeration)
+// ---------------------------------------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64_t cnt, DevGraph g, Score sc,
+                                                      uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot,
+                                                      int pass) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  const int gl = threadIdx.x % G;
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  if (gid < cnt) {
+    const int32_t v = list[gid];
+    const int64_t b = g.off[v], e = g.off[v + 1];
+    const int64_t wv = g.vw[v];
+    int64_t bs = INT64_MIN;
+    int32_t bcl = INT32_MAX;
+    for (int64_t j = b + gl; j < e; j += G) {
+      int32_t u = g.idx[j];
+      int64_t s = sc.q * (int64_t)g.w[j] - sc.p * wv * g.vw[u];
+      if (better(s, u, bs, bcl)) { bs = s; bcl = u; }
+    }
+    argmax_reduce<G>(bs, bcl);
+    if (gl == 0) finish_vertex(v, v, wv, 0, bs, bcl, sc, g.vw, pa, pb, 0, vs, &bc);
+  }
+  counters_flush(&bc, &slot->nL[pass], nullptr);
+}
+
+template <int G>
+__global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t cnt, DevGraph g, Score sc,
+                                                  uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot, int pass) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  const int32_t v = list[blockIdx.x];
+  const int64_t b = g.off[v], e = g.off[v + 1];
+  const int64_t wv = g.vw[v];
+  int64_t bs = INT64_MIN;
+  int32_t bcl = INT32_MAX;
+  for (int64_t j = b + threadIdx.x; j < e; j += G) {
+    int32_t u = g.idx[j];
+    int64_t s = sc.q * (int64_t)g.w[j] - sc.p * wv * g.vw[u];
+    if (better(s, u, bs, bcl)) { bs = s; bcl = u; }
+  }
+  argmax_reduce<G>(bs, bcl);
+  if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, bs, bcl, sc, g.vw, pa, pb, 0, vs, &bc);
+  counters_flush(&bc, &slot->nL[pass], nullptr);
+}
+
+// Hub chunk of the singleton pass: partial argmax per chunk.
+__global__ __launch_bounds__(HUB_BLOCK) void k_single_hub(const int32_t* hubs, const int32_t* chunk_off,
+                                                          int64_t n7, DevGraph g, Score sc, int64_t* ps,
+                                                          int32_t* pc) {
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
+  const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
+  const int64_t wv = g.vw[v];
+  int64_t bs = INT64_MIN;
+  int32_t bcl = INT32_MAX;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) {
+    int32_t u = g.idx[j];
+    int64_t s = sc.q * (int64_t)g.w[j] - sc.p * wv * g.vw[u];
+    if (better(s, u, bs, bcl)) { bs = s; bcl = u; }
+  }
+  argmax_reduce<HUB_BLOCK>(bs, bcl);
+  if (threadIdx.x == 0) { ps[blockIdx.x] = bs; pc[blockIdx.x] = bcl; }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// General pass: enumerate neighbour clusters and take the argmax (Alg. 2 with DS = Enumerate(G, C))
+// ---------------------------------------------------------------------------------------------------------
+
+// degree <= G: lane l holds neighbour l; clusters aggregated by an all-pairs shuffle sweep of the group.
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t cnt, DevGraph g,
+                                                    const int32_t* C, const int64_t* W, Score sc, uint32_t pa,
+                                                    uint32_t pb, int strict, VState* vs, LMSlot* slot, int pass,
+                                                    int64_t* own_sum) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot && slot->skip[pass]) return;
+  const int gl = threadIdx.x % G;
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  if (gid < cnt) {
+    const int32_t v = list[gid];
+    const int64_t b = g.off[v];
+    const int d = (int)(g.off[v + 1] - b);
+    const int32_t cv = C[v];
+    const int64_t wv = g.vw[v];
+    const bool has = gl < d;
+    const int32_t c = has ? C[g.idx[b + gl]] : -1;
+    const int64_t wt = has ? (int64_t)g.w[b + gl] : 0;
+    int64_t acc = 0;
+    bool leader = has;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      int32_t ck = __shfl(c, k, G);
+      int64_t wk = __shfl(wt, k, G);
+      if (has && ck == c) {
+        acc += wk;
+        if (k < gl) leader = false;
+      }
+    }
+    int64_t own = (leader && c == cv) ? acc : 0;
+    int64_t bs = INT64_MIN;
+    int32_t bcl = INT32_MAX;
+    if (leader && c != cv) {
+      bs = sc.q * acc - sc.p * wv * W[c];
+      bcl = c;
+    }
+    argmax_reduce<G>(bs, bcl);
+    own = sum_reduce<G>(own);
+    if (gl == 0) finish_vertex(v, cv, wv, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc);
+  }
+  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+}
+
+// One wavefront per vertex, LDS open-addressing hash of capacity pow2ceil(2 d) <= SLOTS.
+template <int SLOTS>
+__global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_t cnt, DevGraph g,
+                                                     const int32_t* C, const int64_t* W, Score sc, uint32_t pa,
+                                                     uint32_t pb, int strict, VState* vs, LMSlot* slot,
+                                                     int pass, int64_t* own_sum) {
+  __shared__ int32_t hk[BLOCK / WAVE][SLOTS];
+  __shared__ uint32_t hv[BLOCK / WAVE][SLOTS];
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot && slot->skip[pass]) return;
+  const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
+  const bool active = gid < cnt;
+  int32_t v = 0, cv = 0;
+  int64_t b = 0, e = 0, wvt = 0;
+  int bits = 1;
+  if (active) {
+    v = list[gid];
+    b = g.off[v];
+    e = g.off[v + 1];
+    cv = C[v];
+    wvt = g.vw[v];
+    bits = ceil_log2(2 * (e - b));
+    if (bits < 1) bits = 1;
+    for (int s = lane; s < (1 << bits); s += WAVE) { hk[wv][s] = -1; hv[wv][s] = 0; }
+  }
+  __syncthreads();
+  if (active) {
+    const uint32_t mask = (1u << bits) - 1;
+    for (int64_t j = b + lane; j < e; j += WAVE) {
+      int32_t c = C[g.idx[j]];
+      uint32_t wt = (uint32_t)g.w[j];
+      uint32_t h = hslot(c, bits);
+      for (uint32_t probe = 0; probe <= mask; ++probe) {  // the table has room for every distinct key
+        int32_t prev = atomicCAS(&hk[wv][h], -1, c);
+        if (prev == -1 || prev == c) { atomicAdd(&hv[wv][h], wt); break; }
+        h = (h + 1) & mask;
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+    int64_t own = 0, bs = INT64_MIN;
+    int32_t bcl = INT32_MAX;
+    for (int s = lane; s < (1 << bits); s += WAVE) {
+      int32_t c = hk[wv][s];
+      if (c < 0) continue;
+      int64_t a = (int64_t)hv[wv][s];
+      if (c == cv) { own = a; continue; }
+      int64_t sc_ = sc.q * a - sc.p * wvt * W[c];
+      if (better(sc_, c, bs, bcl)) { bs = sc_; bcl = c; }
+    }
+    argmax_reduce<WAVE>(bs, bcl);
+    own = sum_reduce<WAVE>(own);
+    if (lane == 0) finish_vertex(v, cv, wvt, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc);
+  }
+  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+}
+
+// One workgroup per vertex, LDS hash of capacity pow2ceil(2 d) <= LDS_SLOTS_B6.
+__global__ __launch_bounds__(BIG_BLOCK) void k_enum_blk(const int32_t* list, DevGraph g, const int32_t* C,
+                                                        const int64_t* W, Score sc, uint32_t pa, uint32_t pb,
+                                                        int strict, VState* vs, LMSlot* slot, int pass,
+                                                        int64_t* own_sum) {
+  __shared__ int32_t hk[LDS_SLOTS_B6];
+  __shared__ uint32_t hv[LDS_SLOTS_B6];
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot && slot->skip[pass]) return;
+  const int32_t v = list[blockIdx.x];
+  const int64_t b = g.off[v], e = g.off[v + 1];
+  const int32_t cv = C[v];
+  const int64_t wvt = g.vw[v];
+  int bits = ceil_log2(2 * (e - b));
+  if (bits < 1) bits = 1;
+  const uint32_t mask = (1u << bits) - 1;
+  for (int s = threadIdx.x; s < (1 << bits); s += BIG_BLOCK) { hk[s] = -1; hv[s] = 0; }
+  __syncthreads();
+  for (int64_t j = b + threadIdx.x; j < e; j += BIG_BLOCK) {
+    int32_t c = C[g.idx[j]];
+    uint32_t wt = (uint32_t)g.w[j];
+    uint32_t h = hslot(c, bits);
+    for (uint32_t probe = 0; probe <= mask; ++probe) {
+      int32_t prev = atomicCAS(&hk[h], -1, c);
+      if (prev == -1 || prev == c) { atomicAdd(&hv[h], wt); break; }
+      h = (h + 1) & mask;
+    }
+  }
+  __syncthreads();
+  int64_t own = 0, bs = INT64_MIN;
+  int32_t bcl = INT32_MAX;
+  for (int s = threadIdx.x; s < (1 << bits); s += BIG_BLOCK) {
+    int32_t c = hk[s];
+    if (c < 0) continue;
+    int64_t a = (int64_t)hv[s];
+    if (c == cv) { own = a; continue; }
+    int64_t sc_ = sc.q * a - sc.p * wvt * W[c];
+    if (better(sc_, c, bs, bcl)) { bs = sc_; bcl = c; }
+  }
+  argmax_reduce<BIG_BLOCK>(bs, bcl);
+  own = sum_reduce<BIG_BLOCK>(own);
+  if (threadIdx.x == 0) finish_vertex(v, cv, wvt, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc);
+  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+}
+
+// Hubs: global-memory hash of 2 d slots (key, value) at slot offset 2 off[v] of the edge arena.  Chunk k
+// of a hub owns the 2 * HUB_CHUNK slots that start at 2 (off[v] + k HUB_CHUNK) for clearing and scanning;
+// insertions probe the whole table.
+__device__ __forceinline__ uint32_t hub_slot(int32_t c, int64_t cap) {
+  return (uint32_t)(((uint64_t)fmix32((uint32_t)c) * (uint64_t)cap) >> 32);
+}
+
+__global__ __launch_bounds__(HUB_BLOCK) void k_hub_clear(const int32_t* hubs, const int32_t* chunk_off,
+                                                         int64_t n7, const int64_t* off, uint32_t* arena,
+                                                         const LMSlot* slot, int pass) {
+  if (slot && pass >= 0 && slot->skip[pass]) return;
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int64_t s0 = 2 * (off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK);
+  const int64_t s1 = min(2 * off[v + 1], s0 + 2 * HUB_CHUNK);
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += HUB_BLOCK) {
+    arena[2 * s] = 0xFFFFFFFFu;
+    arena[2 * s + 1] = 0;
+  }
+}
+
+__global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, const int32_t* chunk_off,
+                                                          int64_t n7, DevGraph g, const int32_t* C,
+                                                          uint32_t* arena, const LMSlot* slot, int pass) {
+  if (slot && slot->skip[pass]) return;
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int64_t base = g.off[v];
+  const int64_t cap = 2 * (g.off[v + 1] - base);
+  const int64_t j0 = base + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
+  const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
+  uint32_t* tab = arena + 4 * base;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) {
+    int32_t c = C[g.idx[j]];
+    uint32_t wt = (uint32_t)g.w[j];
+    int64_t h = hub_slot(c, cap);
+    for (int64_t probe = 0; probe < cap; ++probe) {
+      uint32_t prev = atomicCAS(&tab[2 * h], 0xFFFFFFFFu, (uint32_t)c);
+      if (prev == 0xFFFFFFFFu || prev == (uint32_t)c) { atomicAdd(&tab[2 * h + 1], wt); break; }
+      if (++h == cap) h = 0;
+    }
+  }
+}
+
+// Scan this chunk's share of the table: partial best and own weight; clears the slots for the next pass.
+__global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, const int32_t* chunk_off,
+                                                        int64_t n7, DevGraph g, const int32_t* C,
+                                                        const int64_t* W, Score sc, uint32_t* arena,
+                                                        int64_t* ps, int32_t* pc, int64_t* pown,
+                                                        const LMSlot* slot, int pass) {
+  if (slot && slot->skip[pass]) return;
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int32_t cv = C[v];
+  const int64_t wvt = g.vw[v];
+  const int64_t s0 = 2 * (g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK);
+  const int64_t s1 = min(2 * g.off[v + 1], s0 + 2 * HUB_CHUNK);
+  int64_t own = 0, bs = INT64_MIN;
+  int32_t bcl = INT32_MAX;
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += HUB_BLOCK) {
+    uint32_t key = arena[2 * s];
+    if (key == 0xFFFFFFFFu) continue;
+    int32_t c = (int32_t)key;
+    int64_t a = (int64_t)arena[2 * s + 1];
+    arena[2 * s] = 0xFFFFFFFFu;
+    arena[2 * s + 1] = 0;
+    if (c == cv) { own = a; continue; }
+    int64_t sc_ = sc.q * a - sc.p * wvt * W[c];
+    if (better(sc_, c, bs, bcl)) { bs = sc_; bcl = c; }
+  }
+  argmax_reduce<HUB_BLOCK>(bs, bcl);
+  own = sum_reduce<HUB_BLOCK>(own);
+  if (threadIdx.x == 0) { ps[blockIdx.x] = bs; pc[blockIdx.x] = bcl; pown[blockIdx.x] = own; }
+}
+
+// Combine the chunks of each hub (pown may be null: singleton pass).
+__global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64_t n7, const int64_t* vw,
+                            const int32_t* C, const int64_t* W, Score sc, uint32_t pa, uint32_t pb, int strict,
+                            const int64_t* ps, const int32_t* pc, const int64_t* pown, VState* vs,
+                            LMSlot* slot, int pass, int64_t* own_sum) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot && slot->skip[pass]) return;
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n7) {
+    int32_t v = hubs[k];
+    int64_t bs = INT64_MIN, own = 0;
+    int32_t bcl = INT32_MAX;
+    for (int32_t ch = chunk_off[k]; ch < chunk_off[k + 1]; ++ch) {
+      if (better(ps[ch], pc[ch], bs, bcl)) { bs = ps[ch]; bcl = pc[ch]; }
+      if (pown) own += pown[ch];
+    }
+    int32_t cv = C ? C[v] : v;
+    finish_vertex(v, cv, vw[v], own, bs, bcl, sc, C ? W : vw, pa, pb, strict, vs, &bc);
+  }
+  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Afterburner filter (Alg. 3).  For candidate v, every adjacent candidate u ordered before v adjusts delta_v
+// by +-q w'(u,v); v is kept when the adjusted delta is >= 0.  Order: larger delta first; deltas within the
+// tie window are ordered by the splitmix64 hash of the vertex id.
+// ---------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool before(int32_t u, int64_t du, int32_t v, int64_t dv, int64_t tie) {
+  int64_t diff = du - dv;
+  int64_t ad = diff < 0 ? -diff : diff;
+  if (ad <= tie) return fmix64((uint64_t)(uint32_t)u) < fmix64((uint64_t)(uint32_t)v);
+  return diff > 0;
+}
+
+__device__ __forceinline__ int64_t ab_adjust(int32_t cv, int32_t dv, int32_t cu, int32_t du, int64_t wq) {
+  int64_t a = 0;
+  if (cv == cu) a += wq;
+  else if (dv == cu) a -= wq;
+  if (du != D_EMPTY) {
+    if (cv == du) a -= wq;
+    else if (dv == du) a += wq;
+  }
+  return a;
+}
+
+__device__ __forceinline__ int64_t ab_edge(const DevGraph& g, const VState* vs, const Score& sc, int64_t j,
+                                           int32_t v, const VState& me, int64_t wv) {
+  int32_t u = g.idx[j];
+  VState o = vs[u];
+  if (o.d == D_NONE) return 0;
+  if (!before(u, o.delta, v, me.delta, sc.tie)) return 0;
+  int64_t wq = sc.q * (int64_t)g.w[j] - sc.p * g.vw[u] * wv;
+  return ab_adjust(me.c, me.d, o.c, o.d, wq);
+}
+
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
+                                                  Score sc, uint8_t* keep, LMSlot* slot, int pass) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot->skip[pass]) return;
+  const int gl = threadIdx.x % G;
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  if (gid < cnt) {
+    const int32_t v = list[gid];
+    const VState me = vs[v];
+    if (me.d == D_NONE) {
+      if (gl == 0) keep[v] = 0;
+    } else {
+      const int64_t wv = g.vw[v];
+      int64_t acc = 0;
+      for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) acc += ab_edge(g, vs, sc, j, v, me, wv);
+      acc = sum_reduce<G>(acc);
+      if (gl == 0) {
+        bool k = me.delta + acc >= 0;
+        keep[v] = k;
+        if (k) atomicAdd(&bc.ncand, 1ull);
+      }
+    }
+  }
+  counters_flush(&bc, &slot->nM[pass], nullptr);
+}
+
+__global__ __launch_bounds__(BIG_BLOCK) void k_ab_blk(const int32_t* list, DevGraph g, const VState* vs, Score sc,
+                                                      uint8_t* keep, LMSlot* slot, int pass) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot->skip[pass]) return;
+  const int32_t v = list[blockIdx.x];
+  const VState me = vs[v];
+  if (me.d == D_NONE) {
+    if (threadIdx.x == 0) keep[v] = 0;
+    return;
+  }
+  const int64_t wv = g.vw[v];
+  int64_t acc = 0;
+  for (int64_t j = g.off[v] + threadIdx.x; j < g.off[v + 1]; j += BIG_BLOCK) acc += ab_edge(g, vs, sc, j, v, me, wv);
+  acc = sum_reduce<BIG_BLOCK>(acc);
+  if (threadIdx.x == 0) {
+    bool k = me.delta + acc >= 0;
+    keep[v] = k;
+    if (k) atomicAdd(&bc.ncand, 1ull);
+  }
+  counters_flush(&bc, &slot->nM[pass], nullptr);
+}
+
+__global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
+                                                      DevGraph g, const VState* vs, Score sc, int64_t* hacc,
+                                                      const LMSlot* slot, int pass) {
+  if (slot->skip[pass]) return;
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const VState me = vs[v];
+  if (me.d == D_NONE) return;
+  const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
+  const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
+  const int64_t wv = g.vw[v];
+  int64_t acc = 0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) acc += ab_edge(g, vs, sc, j, v, me, wv);
+  acc = sum_reduce<HUB_BLOCK>(acc);
+  if (threadIdx.x == 0 && acc) atomicAdd((unsigned long long*)&hacc[k], (unsigned long long)acc);
+}
+
+__global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs, int64_t* hacc, uint8_t* keep,
+                               LMSlot* slot, int pass) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot->skip[pass]) return;
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n7) {
+    int32_t v = hubs[k];
+    VState me = vs[v];
+    bool kp = me.d != D_NONE && me.delta + hacc[k] >= 0;
+    keep[v] = kp;
+    hacc[k] = 0;
+    if (kp) atomicAdd(&bc.ncand, 1ull);
+  }
+  counters_flush(&bc, &slot->nM[pass], nullptr);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Update (Alg. 2 line "C <- Update(L, C, D)"): simultaneous moves with integer atomics on the cluster
+// weights and sizes.  Movers to a new singleton take the ids left unused by all other moves, smallest first,
+// in ascending vertex order.
+// ---------------------------------------------------------------------------------------------------------
+__global__ void k_apply(int64_t n, const uint8_t* keep, const VState* vs, const int64_t* vw, int32_t* C,
+                        int64_t* W, int32_t* sz, uint8_t* empty, LMSlot* slot, int pass) {
+  if (slot && slot->skip[pass]) return;
+  __shared__ unsigned long long ne;
+  if (threadIdx.x == 0) ne = 0;
+  __syncthreads();
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    uint8_t e = 0;
+    if (keep[v]) {
+      VState s = vs[v];
+      int64_t wv = vw[v];
+      atomicAdd((unsigned long long*)&W[s.c], (unsigned long long)(-wv));
+      atomicSub(&sz[s.c], 1);
+      if (s.d == D_EMPTY) {
+        e = 1;
+        atomicAdd(&ne, 1ull);
+      } else {
+        C[v] = s.d;
+        atomicAdd((unsigned long long*)&W[s.d], (unsigned long long)wv);
+        atomicAdd(&sz[s.d], 1);
+      }
+    }
+    empty[v] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && ne) atomicAdd((unsigned long long*)&slot->n_empty, ne);
+}
+
+__global__ void k_free_flags(int64_t n, const int32_t* sz, uint8_t* fl, const LMSlot* slot) {
+  if (slot->n_empty == 0) return;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+    fl[c] = sz[c] == 0;
+}
+
+__global__ void k_free_list(int64_t n, const uint8_t* fl, const int32_t* rank, int32_t* freelist,
+                            const LMSlot* slot) {
+  if (slot->n_empty == 0) return;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+    if (fl[c]) freelist[rank[c]] = (int32_t)c;
+}
+
+__global__ void k_assign_empty(int64_t n, const uint8_t* empty, const int32_t* rank, const int32_t* freelist,
+                               const int64_t* vw, int32_t* C, int64_t* W, int32_t* sz, const LMSlot* slot) {
+  if (slot->n_empty == 0) return;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    if (!empty[v]) continue;
+    int32_t c = freelist[rank[v]];
+    C[v] = c;
+    W[c] = vw[v];
+    sz[c] = 1;
+  }
+}
+
+// sum over cluster ids of W_c^2
+__global__ void k_sw2(const int64_t* W, int64_t n, int64_t* out, const LMSlot* slot, int pass) {
+  if (slot && pass >= 0 && slot->skip[pass]) return;
+  int64_t s = 0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t x = W[c];
+    s += x * x;
+  }
+  s = sum_reduce<BLOCK>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Objective: ordered internal edge weight I(C) = sum over edges (u,v) with C[u] = C[v] of w(u,v)
+// ---------------------------------------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_internal_grp(const int32_t* list, int64_t cnt, DevGraph g,
+                                                        const int32_t* C, int64_t* out, const int32_t* skip) {
+  if (skip && *skip) return;
+  const int gl = threadIdx.x % G;
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  int64_t s = 0;
+  if (gid < cnt) {
+    const int32_t v = list[gid];
+    const int32_t cv = C[v];
+    for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G)
+      if (C[g.idx[j]] == cv) s += g.w[j];
+  }
+  s = sum_reduce<BLOCK>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
+}
+
+__global__ __launch_bounds__(BIG_BLOCK) void k_internal_blk(const int32_t* list, DevGraph g, const int32_t* C,
+                                                            int64_t* out, const int32_t* skip) {
+  if (skip && *skip) return;
+  const int32_t v = list[blockIdx.x];
+  const int32_t cv = C[v];
+  int64_t s = 0;
+  for (int64_t j = g.off[v] + threadIdx.x; j < g.off[v + 1]; j += BIG_BLOCK)
+    if (C[g.idx[j]] == cv) s += g.w[j];
+  s = sum_reduce<BIG_BLOCK>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
+}
+
+__global__ __launch_bounds__(HUB_BLOCK) void k_internal_hub(const int32_t* hubs, const int32_t* chunk_off,
+                                                            int64_t n7, DevGraph g, const int32_t* C, int64_t* out,
+                                                            const int32_t* skip) {
+  if (skip && *skip) return;
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int32_t cv = C[v];
+  const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
+  const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
+  int64_t s = 0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK)
+    if (C[g.idx[j]] == cv) s += g.w[j];
+  s = sum_reduce<HUB_BLOCK>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
+}
+
+__global__ void k_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, int32_t* sz) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t c = C[v];
+    atomicAdd((unsigned long long*)&W[c], (unsigned long long)vw[v]);
+    if (sz) atomicAdd(&sz[c], 1);
+  }
+}
+
+__global__ void k_copy_vw(const int64_t* vw, int64_t* W, int32_t* sz, int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    W[v] = vw[v];
+    sz[v] = 1;
+  }
+}
+
+__global__ void k_zero_i64(int64_t* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Degree buckets
+// ---------------------------------------------------------------------------------------------------------
+__global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl) {
+  __shared__ unsigned long long cnt[NBUCKET];
+  __shared__ unsigned long long chunks;
+  if (threadIdx.x < NBUCKET) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) chunks = 0;
+  __syncthreads();
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int64_t d = off[v + 1] - off[v];
+    int b = bucket_of(d);
+    atomicAdd(&cnt[b], 1ull);
+    if (b == NBUCKET - 1) atomicAdd(&chunks, (unsigned long long)cdiv(d, HUB_CHUNK));
+  }
+  __syncthreads();
+  if (threadIdx.x < NBUCKET && cnt[threadIdx.x])
+    atomicAdd((unsigned long long*)&ctrl->bucket_count[threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x == 0 && chunks) atomicAdd((unsigned long long*)&ctrl->count3, chunks);
+}
+
+__global__ void k_bucket_offsets(Ctrl* ctrl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t s = 0;
+  for (int b = 0; b < NBUCKET; ++b) {
+    ctrl->bucket_off[b] = s;
+    ctrl->bucket_cursor[b] = s;
+    s += ctrl->bucket_count[b];
+  }
+  ctrl->bucket_off[NBUCKET] = s;
+}
+
+__global__ void k_bucket_scatter(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+  // every lane of a wavefront runs the same number of iterations (n rounded up to the block stride)
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+    int64_t v = base + threadIdx.x;
+    bool valid = v < n;
+    int b = valid ? bucket_of(off[v + 1] - off[v]) : -1;
+    for (int bb = 0; bb < NBUCKET; ++bb) {
+      uint64_t m = __ballot(b == bb);
+      if (!m) continue;
+      int leader = __ffsll((unsigned long long)m) - 1;
+      int64_t pos = 0;
+      if (lane == leader) pos = (int64_t)atomicAdd((unsigned long long*)&ctrl->bucket_cursor[bb],
+                                                   (unsigned long long)__popcll(m));
+      pos = __shfl(pos, leader, WAVE);
+      if (b == bb) list[pos + __popcll(m & lt)] = (int32_t)v;
+    }
+  }
+}
+
+__global__ void k_hub_chunk_counts(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n7; k += (int64_t)gridDim.x * blockDim.x) {
+    int32_t v = hubs[k];
+    cnt[k] = (int32_t)cdiv(off[v + 1] - off[v], HUB_CHUNK);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Validation of the CSR (setup, Sec. II): offsets first, then one pass over the rows checking index range,
+// self-loops, strict ascending order and positive weights.  Symmetry is checked by a multiset fingerprint:
+// with rows strictly ascending, the graph is symmetric iff the multiset of stored (u, v, w) equals that of
+// (v, u, w); both sums of two independent 64-bit hashes over the stored entries are compared (an asymmetric
+// input passes only on a 2^-128-scale hash collision).
+// ---------------------------------------------------------------------------------------------------------
+__global__ void k_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* ctrl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    if (off[0] != 0 || off[n] != nnz) atomicOr(&ctrl->err_bits, ERRB_INVALID);
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    if (off[v + 1] < off[v]) atomicOr(&ctrl->err_bits, ERRB_INVALID);
+}
+
+__device__ __forceinline__ uint64_t fp_h1(uint32_t a, uint32_t b, uint32_t w) {
+  uint64_t key = ((uint64_t)a << 32) | b;
+  return fmix64(key ^ fmix64((uint64_t)w ^ 0x243F6A8885A308D3ULL));
+}
+__device__ __forceinline__ uint64_t fp_h2(uint32_t a, uint32_t b, uint32_t w) {
+  uint64_t key = ((uint64_t)a << 32) | b;
+  return fmix64(key * 0x9E3779B97F4A7C15ULL + (uint64_t)w + 0x13198A2E03707344ULL);
+}
+
+struct EdgeCheck {
+  uint32_t err = 0;
+  uint64_t f1 = 0, f2 = 0;
+  int64_t ws = 0;
+};
+
+__device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t j, int64_t rb, EdgeCheck& ec) {
+  int32_t u = g.idx[j];
+  int32_t wt = g.w[j];
+  ec.ws += wt;
+  if (u < 0 || u >= g.n) { ec.err |= ERRB_INVALID; return; }
+  if (u == v) ec.err |= ERRB_SELF_LOOP;
+  if (j > rb && g.idx[j - 1] >= u) ec.err |= ERRB_UNSORTED;
+  if (wt <= 0) ec.err |= ERRB_WEIGHT;
+  ec.f1 += fp_h1((uint32_t)v, (uint32_t)u, (uint32_t)wt) - fp_h1((uint32_t)u, (uint32_t)v, (uint32_t)wt);
+  ec.f2 += fp_h2((uint32_t)v, (uint32_t)u, (uint32_t)wt) - fp_h2((uint32_t)u, (uint32_t)v, (uint32_t)wt);
+}
+
+__device__ __forceinline__ int64_t vertex_weight(int vw_mode, int64_t ws, const int64_t* vw_given, int32_t v,
+                                                 uint32_t& err) {
+  if (vw_mode == 1) return ws;
+  if (vw_mode == 2) return 1;
+  int64_t x = vw_given[v];
+  if (x < 0) err |= ERRB_WEIGHT;
+  if (x >= ((int64_t)1 << 31)) err |= ERRB_VW_TOO_BIG;
+  return x;
+}
+
+__device__ __forceinline__ void flush_check(EdgeCheck ec, int64_t wsum, Ctrl* ctrl) {
+  // block-wide: every thread calls this
+  uint64_t f1 = (uint64_t)sum_reduce<BLOCK>((int64_t)ec.f1);
+  uint64_t f2 = (uint64_t)sum_reduce<BLOCK>((int64_t)ec.f2);
+  wsum = sum_reduce<BLOCK>(wsum);
+  if (ec.err) atomicOr(&ctrl->err_bits, ec.err);
+  if (threadIdx.x == 0) {
+    if (f1) atomicAdd((unsigned long long*)&ctrl->count0, (unsigned long long)f1);
+    if (f2) atomicAdd((unsigned long long*)&ctrl->count1, (unsigned long long)f2);
+    if (wsum) atomicAdd((unsigned long long*)&ctrl->sum_we, (unsigned long long)wsum);
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int64_t cnt, DevGraph g, int vw_mode,
+                                                        const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl) {
+  const int gl = threadIdx.x % G;
+  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  EdgeCheck ec;
+  int32_t v = -1;
+  if (gid < cnt) {
+    v = list[gid];
+    const int64_t rb = g.off[v], re = g.off[v + 1];
+    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, ec);
+  }
+  int64_t ws = sum_reduce<G>(ec.ws);
+  int64_t wsum = 0;
+  if (gid < cnt && gl == 0) {
+    vw_out[v] = vertex_weight(vw_mode, ws, vw_given, v, ec.err);
+    wsum = ws;
+  }
+  flush_check(ec, wsum, ctrl);
+}
+
+__global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list, DevGraph g, int vw_mode,
+                                                            const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl) {
+  const int32_t v = list[blockIdx.x];
+  const int64_t rb = g.off[v], re = g.off[v + 1];
+  EdgeCheck ec;
+  for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, ec);
+  int64_t ws = sum_reduce<BIG_BLOCK>(ec.ws);
+  if (threadIdx.x == 0) vw_out[v] = vertex_weight(vw_mode, ws, vw_given, v, ec.err);
+  flush_check(ec, threadIdx.x == 0 ? ws : 0, ctrl);
+}
+
+// hubs: chunk sums of the weighted degree land in hsum[k] (zeroed beforehand)
+__global__ __launch_bounds__(HUB_BLOCK) void k_validate_hub(const int32_t* hubs, const int32_t* chunk_off,
+                                                            int64_t n7, DevGraph g, int64_t* hsum, Ctrl* ctrl) {
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int64_t rb = g.off[v];
+  const int64_t j0 = rb + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
+  const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
+  EdgeCheck ec;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) check_edge(g, v, j, rb, ec);
+  int64_t ws = sum_reduce<HUB_BLOCK>(ec.ws);
+  if (threadIdx.x == 0 && ws) atomicAdd((unsigned long long*)&hsum[k], (unsigned long long)ws);
+  flush_check(ec, threadIdx.x == 0 ? ws : 0, ctrl);
+}
+
+__global__ void k_validate_hub_final(const int32_t* hubs, int64_t n7, int vw_mode, const int64_t* vw_given,
+                                     int64_t* hsum, int64_t* vw_out, Ctrl* ctrl) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n7) return;
+  int32_t v = hubs[k];
+  uint32_t err = 0;
+  vw_out[v] = vertex_weight(vw_mode, hsum[k], vw_given, v, err);
+  hsum[k] = 0;
+  if (err) atomicOr(&ctrl->err_bits, err);
+}
+
+__global__ void k_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl) {
+  int64_t s = 0, s2 = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int64_t x = vw[v];
+    s += x;
+    s2 += x * x;
+  }
+  s = sum_reduce<BLOCK>(s);
+  s2 = sum_reduce<BLOCK>(s2);
+  if (threadIdx.x == 0) {
+    if (s) atomicAdd((unsigned long long*)&ctrl->sum_w, (unsigned long long)s);
+    if (s2) atomicAdd((unsigned long long*)&ctrl->sum_w2, (unsigned long long)s2);
+  }
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = cdiv(n, BLOCK);
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (unsigned)g;
+}
+
+inline unsigned grp_blocks(int64_t cnt, int G) { return (unsigned)cdiv(cnt, BLOCK / G); }
+
+// Hub chunk scratch lives at the end of the per-chunk partial arrays.
+struct HubScratch {
+  int64_t* ps;
+  int32_t* pc;
+  int64_t* pown;
+  int64_t* hacc;
+};
+
+}  // namespace
+
+// =========================================================================================================
+// Host launchers
+// =========================================================================================================
+
+void launch_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* ctrl, hipStream_t st) {
+  k_validate_offsets<<<grid_for(n), BLOCK, 0, st>>>(off, n, nnz, ctrl);
+}
+
+void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, const int64_t* vw_given,
+                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st) {
+  const int32_t* L = b.list;
+  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vw_mode, vw_given, vw_out, ctrl);
+  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vw_mode, vw_given, vw_out, ctrl);
+  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vw_mode, vw_given, vw_out, ctrl);
+  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vw_mode, vw_given, vw_out, ctrl);
+  int64_t nw = b.count[4] + b.count[5];
+  if (nw) k_validate_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vw_mode, vw_given, vw_out, ctrl);
+  if (b.count[6]) k_validate_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, vw_mode, vw_given, vw_out, ctrl);
+  if (b.count[7]) {
+    const int32_t* hubs = L + b.off[7];
+    fill_i64(b.hub_acc, 0, b.count[7], st);
+    k_validate_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, b.hub_acc, ctrl);
+    k_validate_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vw_mode, vw_given, b.hub_acc, vw_out, ctrl);
+  }
+}
+
+void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st) {
+  k_bucket_count<<<grid_for(n), BLOCK, 0, st>>>(off, n, ctrl);
+  k_bucket_offsets<<<1, 1, 0, st>>>(ctrl);
+  k_bucket_scatter<<<grid_for(n), BLOCK, 0, st>>>(off, n, list, ctrl);
+}
+
+void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt, int32_t* chunk_off,
+                       void* temp, hipStream_t st) {
+  if (n7 == 0) return;
+  k_hub_chunk_counts<<<grid_for(n7), BLOCK, 0, st>>>(hubs, n7, off, cnt);
+  scan_i32_i32(cnt, chunk_off, n7, temp, st);
+}
+
+void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st) {
+  k_vertex_sums<<<grid_for(n), BLOCK, 0, st>>>(vw, n, ctrl);
+}
+
+void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, int32_t* sz,
+                            hipStream_t st) {
+  fill_i64(W, 0, n, st);
+  if (sz) fill_i32(sz, 0, n, st);
+  k_cluster_weights<<<grid_for(n), BLOCK, 0, st>>>(C, vw, n, W, sz);
+}
+
+static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
+                            const int32_t* skip, hipStream_t st) {
+  const int32_t* L = b.list;
+  if (b.count[0]) k_internal_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, out, skip);
+  if (b.count[1]) k_internal_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, out, skip);
+  if (b.count[2]) k_internal_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, out, skip);
+  if (b.count[3]) k_internal_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, out, skip);
+  int64_t nw = b.count[4] + b.count[5];
+  if (nw) k_internal_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, out, skip);
+  if (b.count[6]) k_internal_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, C, out, skip);
+  if (b.count[7]) k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, out, skip);
+}
+
+void launch_objective(const DevGraph& g, const Buckets& b, const int32_t* C, const int64_t* W, Ctrl* ctrl,
+                      hipStream_t st) {
+  k_zero_i64<<<1, 1, 0, st>>>(&ctrl->obj_I);
+  k_zero_i64<<<1, 1, 0, st>>>(&ctrl->obj_SW2);
+  launch_internal(g, b, C, &ctrl->obj_I, nullptr, st);
+  k_sw2<<<grid_for(g.n), BLOCK, 0, st>>>(W, g.n, &ctrl->obj_SW2, nullptr, -1);
+}
+
+static const int32_t* L_hubs(const Buckets& b);
+static HubScratch hub_scratch(const Buckets& b);
+
+// One pass of destinations + candidacy.  singleton: first coarsening pass (C = identity).
+static void launch_destinations(const DevGraph& g, const Buckets& b, const Score& sc, uint32_t pa, uint32_t pb,
+                                int strict, bool singleton, LMBuffers& bufs, LMSlot* slot, int pass,
+                                int64_t* own_sum, const HubScratch& hs, hipStream_t st) {
+  const int32_t* L = b.list;
+  const int32_t* C = bufs.C;
+  const int64_t* W = bufs.W;
+  VState* vs = bufs.vs;
+  const int32_t* hubs = L + b.off[7];
+  const int64_t n7 = b.count[7];
+  if (singleton) {
+    if (b.count[0]) k_single_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[1]) k_single_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[2]) k_single_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[3]) k_single_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, sc, pa, pb, vs, slot, pass);
+    int64_t nw = b.count[4] + b.count[5];
+    if (nw) k_single_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, sc, pa, pb, vs, slot, pass);
+    if (b.count[6]) k_single_blk<BIG_BLOCK><<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass);
+    if (n7) {
+      k_single_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, sc, hs.ps, hs.pc);
+      k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, nullptr, nullptr, sc, pa, pb, 0,
+                                                 hs.ps, hs.pc, nullptr, vs, slot, pass, nullptr);
+    }
+    return;
+  }
+  if (b.count[0]) k_enum_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  if (b.count[1]) k_enum_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  if (b.count[2]) k_enum_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  if (b.count[3]) k_enum_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  if (b.count[4]) k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  if (b.count[5]) k_enum_wave<LDS_SLOTS_B5><<<grp_blocks(b.count[5], WAVE), BLOCK, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  if (b.count[6]) k_enum_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  if (n7) {
+    unsigned nc = (unsigned)b.hub_chunks;
+    k_hub_insert<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, bufs.arena, slot, pass);
+    k_hub_scan<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, W, sc, bufs.arena, hs.ps, hs.pc, hs.pown, slot, pass);
+    k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, C, W, sc, pa, pb, strict, hs.ps,
+                                               hs.pc, hs.pown, vs, slot, pass, own_sum);
+  }
+}
+
+static const int32_t* L_hubs(const Buckets& b) { return b.list + b.off[7]; }
+
+static HubScratch hub_scratch(const Buckets& b) {
+  HubScratch hs;
+  hs.ps = b.hub_ps;
+  hs.pc = b.hub_pc;
+  hs.pown = b.hub_pown;
+  hs.hacc = b.hub_acc;
+  return hs;
+}
+
+static void launch_afterburner(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
+                               LMSlot* slot, int pass, const HubScratch& hs, hipStream_t st) {
+  const int32_t* L = b.list;
+  const VState* vs = bufs.vs;
+  uint8_t* keep = bufs.keep;
+  if (b.count[0]) k_ab_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vs, sc, keep, slot, pass);
+  if (b.count[1]) k_ab_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vs, sc, keep, slot, pass);
+  if (b.count[2]) k_ab_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vs, sc, keep, slot, pass);
+  if (b.count[3]) k_ab_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass);
+  int64_t nw = b.count[4] + b.count[5];
+  if (nw) k_ab_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vs, sc, keep, slot, pass);
+  if (b.count[6]) k_ab_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, vs, sc, keep, slot, pass);
+  if (b.count[7]) {
+    const int32_t* hubs = L + b.off[7];
+    k_ab_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, vs, sc, hs.hacc, slot, pass);
+    k_ab_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vs, hs.hacc, keep, slot, pass);
+  }
+}
+
+static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, int pass, hipStream_t st) {
+  const int64_t n = g.n;
+  k_apply<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.sz, bufs.empty, slot, pass);
+  // free ids (size 0 after every other move) and ranks of the movers to a new singleton; all no-ops unless
+  // some vertex moved to a new singleton in this pass
+  k_free_flags<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.sz, bufs.keep, slot);
+  scan_u8_i32(bufs.keep, bufs.scan_a, n, bufs.scan_temp, &slot->n_empty, st);
+  k_free_list<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, bufs.freelist, slot);
+  scan_u8_i32(bufs.empty, bufs.scan_b, n, bufs.scan_temp, &slot->n_empty, st);
+  k_assign_empty<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_b, bufs.freelist, g.vw, bufs.C, bufs.W,
+                                               bufs.sz, slot);
+}
+
+void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool singleton, LMBuffers& bufs,
+                LMSlot* slot, Ctrl* ctrl, hipStream_t st) {
+  (void)ctrl;
+  const int64_t n = g.n;
+  const HubScratch hs = hub_scratch(b);
+  const Score& sc = prm.sc;
+  zero_bytes(slot, sizeof(LMSlot), st);
+  // starting state: cluster weights, sizes, C_out = C, sum of squared cluster weights (state 0)
+  if (singleton) {
+    iota_i32(bufs.C, n, st);
+    k_copy_vw<<<grid_for(n), BLOCK, 0, st>>>(g.vw, bufs.W, bufs.sz, n);
+  } else {
+    launch_cluster_weights(bufs.C, g.vw, n, bufs.W, bufs.sz, st);
+  }
+  copy_i32(bufs.Cout, bufs.C, n, st);
+  k_sw2<<<grid_for(n), BLOCK, 0, st>>>(bufs.W, n, &slot->SW2[0], nullptr, -1);
+  if (b.count[7])
+    k_hub_clear<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L_hubs(b), b.hub_chunk_off, b.count[7], g.off,
+                                                             bufs.arena, nullptr, -1);
+  for (int i = 1; i <= prm.pass_limit; ++i) {
+    int same_phi = i >= 2 && prm.phi_num[i] == prm.phi_num[i - 1] && prm.phi_den[i] == prm.phi_den[i - 1];
+    k_pass_begin<<<1, 1, 0, st>>>(slot, i, same_phi);
+    bool single_now = singleton && i == 1;
+    launch_destinations(g, b, sc, prm.phi_num[i], prm.phi_den[i], 0, single_now, bufs, slot, i,
+                        &slot->I[i - 1], hs, st);
+    // best-so-far check of the state this pass started from (state i-1)
+    k_best<<<1, 1, 0, st>>>(slot, i - 1, i, sc.p, sc.q, prm.sum_w2);
+    k_copy_if<<<grid_for(n), BLOCK, 0, st>>>(slot, bufs.C, bufs.Cout, n);
+    launch_afterburner(g, b, sc, bufs, slot, i, hs, st);
+    apply_and_empty(g, bufs, slot, i, st);
+    k_sw2<<<grid_for(n), BLOCK, 0, st>>>(bufs.W, n, &slot->SW2[i], slot, i);
+  }
+  const int last = prm.pass_limit;
+  if (last >= 1) {
+    k_final_state<<<1, 1, 0, st>>>(slot, last);
+    launch_internal(g, b, bufs.C, &slot->I[last], &slot->skip[last], st);
+    k_best<<<1, 1, 0, st>>>(slot, last, last, sc.p, sc.q, prm.sum_w2);
+    k_copy_if<<<grid_for(n), BLOCK, 0, st>>>(slot, bufs.C, bufs.Cout, n);
+  } else {
+    k_best<<<1, 1, 0, st>>>(slot, 0, -1, sc.p, sc.q, prm.sum_w2);
+  }
+}
+
+void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {
+  apply_and_empty(g, bufs, slot, 0, st);
+}
+
+void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
+                                LMSlot* slot, hipStream_t st) {
+  const HubScratch hs = hub_scratch(b);
+  if (b.count[7])
+    k_hub_clear<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L_hubs(b), b.hub_chunk_off, b.count[7], g.off,
+                                                             bufs.arena, nullptr, -1);
+  launch_destinations(g, b, sc, 0, 1, 1, false, bufs, slot, 0, nullptr, hs, st);
+}
+
+}  // namespace lcc

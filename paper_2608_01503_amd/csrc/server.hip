@@ -1,0 +1,237 @@
+// Continuous-batching clustering server (lcc_server_* of include/lcc.h).
+//
+// The server owns S execution slots; each slot is a worker thread with its own context (workspace and level
+// pool on the device) and its own HIP stream, so the sweeps of concurrently admitted jobs overlap on the GPU.
+// A submitted job is copied to host memory and queued.  A free slot admits the oldest queued job whose
+// device footprint (lcc_workspace_bytes) fits the unreserved part of the HBM budget; a job that does not fit
+// yet is passed over by smaller ones at most a few times before it holds the next free slot, so a large
+// request cannot starve.  A finished job releases its reservation and its slot immediately and the next job
+// joins without waiting for the others.  Results are bit-identical to a plain lcc_cluster call.
+#include <algorithm>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/lcc.h"
+
+lcc_status lcc_cluster_init_internal(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                                     const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res,
+                                     const int32_t* init);
+int lcc_ctx_device_internal(const lcc_ctx* ctx);
+void lcc_ctx_allocator_internal(const lcc_ctx* ctx, lcc_alloc_fn* a, lcc_free_fn* f, void** user);
+
+namespace {
+
+constexpr int SLOTS = 8;
+constexpr int MAX_PASSED_OVER = 4;
+
+struct Job {
+  uint64_t ticket = 0;
+  int64_t n = 0, nnz = 0;
+  std::vector<int64_t> off;
+  std::vector<int32_t> idx, w;
+  std::vector<int64_t> vw;
+  bool has_w = false;
+  lcc_vw_mode vw_mode = LCC_VW_UNIT;
+  lcc_lambda lam{};
+  lcc_variant variant = LCC_PLOUVAIN;
+  lcc_options opts{};
+  bool has_opts = false;
+  size_t footprint = 0;
+  int passed_over = 0;
+  bool done = false;
+  lcc_status st = LCC_OK;
+  std::vector<int32_t> labels;
+  lcc_result res{};
+};
+
+}  // namespace
+
+struct lcc_server {
+  lcc_ctx* parent = nullptr;
+  size_t budget = 0, reserved = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::shared_ptr<Job>> queue;
+  std::map<uint64_t, std::shared_ptr<Job>> jobs;
+  std::vector<std::thread> workers;
+  std::vector<lcc_ctx*> ctxs;
+  std::vector<hipStream_t> streams;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+
+  // Pick the job a free slot runs next (caller holds mu).
+  std::shared_ptr<Job> pick() {
+    for (size_t i = 0; i < queue.size(); ++i) {
+      auto& j = queue[i];
+      if (reserved + j->footprint <= budget) {
+        for (size_t k = 0; k < i; ++k) queue[k]->passed_over++;
+        auto r = j;
+        queue.erase(queue.begin() + (long)i);
+        reserved += r->footprint;
+        return r;
+      }
+      if (j->passed_over >= MAX_PASSED_OVER) break;  // the head waits; nobody overtakes it any more
+    }
+    return nullptr;
+  }
+
+  void run_worker(int k) {
+    lcc_ctx* ctx = ctxs[k];
+    hipStream_t st = streams[k];
+    for (;;) {
+      std::shared_ptr<Job> j;
+      {
+        std::unique_lock<std::mutex> lock(mu);
+        cv.wait(lock, [&] { return stop || (j = pick()) != nullptr; });
+        if (!j) return;
+      }
+      lcc_graph g{};
+      g.n = j->n;
+      g.nnz = j->nnz;
+      g.offsets = j->off.data();
+      g.offsets_bits = 64;
+      g.indices = j->idx.data();
+      g.edge_w = j->has_w ? j->w.data() : nullptr;
+      g.vertex_w = j->vw_mode == LCC_VW_GIVEN ? j->vw.data() : nullptr;
+      g.vw_mode = j->vw_mode;
+      g.mem = LCC_MEM_HOST;
+      j->labels.assign((size_t)std::max<int64_t>(j->n, 1), 0);
+      lcc_status s = lcc_cluster_init_internal(ctx, &g, j->lam, j->variant, j->has_opts ? &j->opts : nullptr, st,
+                                               j->labels.data(), &j->res, nullptr);
+      {
+        std::lock_guard<std::mutex> lock(mu);
+        j->st = s;
+        j->done = true;
+        reserved -= j->footprint;
+        // the host copy of the graph is no longer needed
+        std::vector<int64_t>().swap(j->off);
+        std::vector<int32_t>().swap(j->idx);
+        std::vector<int32_t>().swap(j->w);
+        std::vector<int64_t>().swap(j->vw);
+      }
+      cv.notify_all();
+    }
+  }
+};
+
+extern "C" {
+
+lcc_status lcc_server_create(lcc_ctx* ctx, size_t hbm_budget, lcc_server** out) {
+  if (!ctx || !out || hbm_budget == 0) return LCC_ERR_INVALID;
+  auto* s = new lcc_server();
+  s->parent = ctx;
+  s->budget = hbm_budget;
+  int dev = lcc_ctx_device_internal(ctx);
+  lcc_alloc_fn a;
+  lcc_free_fn f;
+  void* user;
+  lcc_ctx_allocator_internal(ctx, &a, &f, &user);
+  if (hipSetDevice(dev) != hipSuccess) { delete s; return LCC_ERR_DEVICE; }
+  for (int k = 0; k < SLOTS; ++k) {
+    lcc_ctx* c = nullptr;
+    hipStream_t st = nullptr;
+    if (lcc_create(dev, a, f, user, &c) != LCC_OK || hipStreamCreate(&st) != hipSuccess) {
+      for (auto* x : s->ctxs) lcc_destroy(x);
+      for (auto x : s->streams) (void)hipStreamDestroy(x);
+      if (c) lcc_destroy(c);
+      delete s;
+      return LCC_ERR_DEVICE;
+    }
+    s->ctxs.push_back(c);
+    s->streams.push_back(st);
+  }
+  for (int k = 0; k < SLOTS; ++k) s->workers.emplace_back([s, k] { (void)hipSetDevice(lcc_ctx_device_internal(s->ctxs[k])); s->run_worker(k); });
+  *out = s;
+  return LCC_OK;
+}
+
+lcc_status lcc_submit(lcc_server* s, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                      const lcc_options* opts, uint64_t* ticket) {
+  if (!s || !g || !ticket) return LCC_ERR_INVALID;
+  if (g->n < 0 || g->nnz < 0 || !g->offsets || (g->nnz > 0 && !g->indices)) return LCC_ERR_INVALID;
+  if (g->offsets_bits != 32 && g->offsets_bits != 64) return LCC_ERR_INVALID;
+  if (g->vw_mode == LCC_VW_GIVEN && g->n > 0 && !g->vertex_w) return LCC_ERR_INVALID;
+  size_t fp = 0;
+  lcc_status st = lcc_workspace_bytes(g->n, g->nnz, variant, &fp);
+  if (st != LCC_OK) return st;
+  if (fp > s->budget) return LCC_ERR_BUSY;
+  auto j = std::make_shared<Job>();
+  j->n = g->n;
+  j->nnz = g->nnz;
+  j->vw_mode = g->vw_mode;
+  j->lam = lambda;
+  j->variant = variant;
+  if (opts) { j->opts = *opts; j->opts.trace = nullptr; j->has_opts = true; }
+  j->footprint = fp;
+  const hipMemcpyKind kind = g->mem == LCC_MEM_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  j->off.resize((size_t)g->n + 1);
+  if (g->offsets_bits == 64) {
+    if (hipMemcpy(j->off.data(), g->offsets, (size_t)(g->n + 1) * 8, kind) != hipSuccess) return LCC_ERR_DEVICE;
+  } else {
+    std::vector<int32_t> o32((size_t)g->n + 1);
+    if (hipMemcpy(o32.data(), g->offsets, (size_t)(g->n + 1) * 4, kind) != hipSuccess) return LCC_ERR_DEVICE;
+    for (size_t i = 0; i < o32.size(); ++i) j->off[i] = o32[i];
+  }
+  j->idx.resize((size_t)std::max<int64_t>(g->nnz, 1));
+  if (g->nnz && hipMemcpy(j->idx.data(), g->indices, (size_t)g->nnz * 4, kind) != hipSuccess) return LCC_ERR_DEVICE;
+  if (g->edge_w) {
+    j->has_w = true;
+    j->w.resize((size_t)std::max<int64_t>(g->nnz, 1));
+    if (g->nnz && hipMemcpy(j->w.data(), g->edge_w, (size_t)g->nnz * 4, kind) != hipSuccess) return LCC_ERR_DEVICE;
+  }
+  if (g->vw_mode == LCC_VW_GIVEN) {
+    j->vw.resize((size_t)std::max<int64_t>(g->n, 1));
+    if (g->n && hipMemcpy(j->vw.data(), g->vertex_w, (size_t)g->n * 8, kind) != hipSuccess) return LCC_ERR_DEVICE;
+  }
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    j->ticket = s->next_ticket++;
+    s->jobs[j->ticket] = j;
+    s->queue.push_back(j);
+    *ticket = j->ticket;
+  }
+  s->cv.notify_all();
+  return LCC_OK;
+}
+
+lcc_status lcc_poll(lcc_server* s, uint64_t ticket, int* done, int32_t* labels_out, lcc_result* res) {
+  if (!s || !done) return LCC_ERR_INVALID;
+  std::shared_ptr<Job> j;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return LCC_ERR_NOT_FOUND;
+    j = it->second;
+    if (!j->done) { *done = 0; return LCC_OK; }
+    s->jobs.erase(it);
+  }
+  *done = 1;
+  if (j->st != LCC_OK) return j->st;
+  if (labels_out && j->n > 0) memcpy(labels_out, j->labels.data(), (size_t)j->n * 4);
+  if (res) *res = j->res;
+  return LCC_OK;
+}
+
+lcc_status lcc_server_destroy(lcc_server* s) {
+  if (!s) return LCC_OK;
+  {
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_all();
+  for (auto& t : s->workers) t.join();
+  for (auto* c : s->ctxs) lcc_destroy(c);
+  for (auto st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
+  return LCC_OK;
+}
+
+}  // extern "C"

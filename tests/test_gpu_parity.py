@@ -1,0 +1,167 @@
+"""GPU parity: the HIP library (through the C-ABI) against the CPU oracle, bit for bit.
+
+Labels, the exact objective numerator, cluster and level counts, flags and the per-pass / per-level trace
+(candidates, kept moves, objective after every pass) must all be identical.  Inputs are seeded and
+synthetic; sizes span several tiles of every kernel and every degree bucket (sub-wave groups, wavefront,
+workgroup, hub chunks)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle as O
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [O.LOUVAIN, O.PLOUVAIN, O.PLEIDEN, O.PLEIDEN_PLUS]
+MOD = ((1, 1, True), O.VW_WEIGHTED_DEGREE)
+CPM20 = ((1, 20, False), O.VW_UNIT)
+CPM3 = ((1, 3, False), O.VW_UNIT)
+LP = ((0, 1, False), O.VW_UNIT)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_sbm_2000_all_variants(variant):
+    g = gg.config1_sbm()
+    U.assert_parity(g, variant, *MOD, offsets32=True)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("obj", [MOD, CPM20, CPM3, LP], ids=["mod", "cpm20", "cpm3", "lp"])
+def test_random_graphs(variant, obj):
+    for k, (n, p, wmax) in enumerate([(300, 0.02, 1), (1500, 0.004, 7), (5000, 0.001, 100)]):
+        g = gg.random_gnp(n, p, 100 + k, w_max=wmax)
+        U.assert_parity(g, variant, *obj)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_hubs_every_bucket(variant):
+    g = U.hub_graph()
+    d = np.diff(g.off)
+    assert d.max() > 4096 and ((d > 1024) & (d <= 4096)).any() and ((d > 128) & (d <= 1024)).any()
+    U.assert_parity(g, variant, *MOD)
+    U.assert_parity(g, variant, *CPM20)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_rmat_scale14(variant):
+    g = gg.rmat(14, 16, seed=7)
+    U.assert_parity(g, variant, *MOD)
+
+
+@pytest.mark.parametrize("variant", [O.PLEIDEN, O.PLOUVAIN])
+def test_lattice_cpm(variant):
+    g = gg.lattice(96, 80, 0.1, 100, 3)
+    U.assert_parity(g, variant, *CPM20)
+
+
+def test_given_vertex_weights_and_options():
+    g = gg.random_gnp(800, 0.01, 5, w_max=9)
+    vw = np.random.default_rng(1).integers(0, 20, size=g.n)
+    U.assert_parity(g, O.PLOUVAIN, (1, 400, False), O.VW_GIVEN, vw=vw)
+    U.assert_parity(g, O.PLEIDEN, (1, 400, False), O.VW_GIVEN, vw=vw)
+    # other temperature schedules, tie windows, pass limits and seeds
+    for kw in [dict(pass_limit=12, phases=((3, 4, 8), (1, 4, 12))), dict(phases=((0, 1, 6),)),
+               dict(eps=(0, 1)), dict(eps=(1, 2)), dict(pass_limit=1), dict(seed=12345)]:
+        U.assert_parity(g, O.PLOUVAIN, *MOD, opts_kw=kw)
+        U.assert_parity(g, O.PLEIDEN, *CPM20, opts_kw=kw)
+
+
+def test_host_memory_and_32bit_offsets():
+    g = gg.random_gnp(2500, 0.003, 17, w_max=4)
+    U.assert_parity(g, O.PLOUVAIN, *MOD, host=True)
+    U.assert_parity(g, O.PLEIDEN, *CPM20, offsets32=True)
+
+
+def test_edge_cases():
+    # isolated vertices only (CPM: everything stays a singleton)
+    g = gg.Graph(n=7, off=np.zeros(8, np.int64), idx=np.zeros(0, np.int32), w=np.zeros(0, np.int32))
+    for v in VARIANTS:
+        U.assert_parity(g, v, *CPM20)
+    # one edge, and a path
+    U.assert_parity(gg.from_pairs(2, [(0, 1)]), O.PLOUVAIN, *MOD)
+    U.assert_parity(gg.from_pairs(6, [(i, i + 1) for i in range(5)]), O.PLEIDEN, *MOD)
+    # two cliques joined by one edge
+    pairs = [(i, j) for i in range(6) for j in range(i + 1, 6)] + [(6 + i, 6 + j) for i in range(6) for j in range(i + 1, 6)]
+    g2 = gg.from_pairs(12, pairs + [(5, 6)])
+    for v in VARIANTS:
+        ref, res = U.assert_parity(g2, v, *MOD)
+        assert res.num_clusters == 2
+    # star with more leaves than a hub chunk
+    g3 = gg.from_pairs(9001, [(0, i) for i in range(1, 9001)])
+    for v in VARIANTS:
+        U.assert_parity(g3, v, *MOD)
+        U.assert_parity(g3, v, *CPM3)
+
+
+def test_empty_graph():
+    import paper_2608_01503_amd as L
+    g = gg.Graph(n=0, off=np.zeros(1, np.int64), idx=np.zeros(0, np.int32), w=np.zeros(0, np.int32))
+    lab, res = U.run_gpu(g, O.PLOUVAIN, *CPM20)
+    assert len(lab) == 0 and res.num_clusters == 0
+
+
+def _status_gpu(g, lam, vw_mode, vw=None):
+    import paper_2608_01503_amd as L
+    try:
+        U.run_gpu(g, O.PLOUVAIN, lam, vw_mode, vw)
+        return 0
+    except L.LccError as e:
+        return e.status
+
+
+def test_error_statuses_match_oracle():
+    def G(n, off, idx, w):
+        return gg.Graph(n=n, off=np.array(off, np.int64), idx=np.array(idx, np.int32), w=np.array(w, np.int32))
+    cases = [
+        (G(2, [0, 1, 2], [0, 0], [1, 1]), MOD),                   # self-loop
+        (G(3, [0, 2, 3, 4], [2, 1, 0, 0], [1, 1, 1, 1]), MOD),    # unsorted
+        (G(3, [0, 1, 2, 3], [1, 2, 0], [1, 1, 1]), MOD),          # not symmetric
+        (G(2, [0, 1, 2], [1, 0], [2, 3]), MOD),                   # asymmetric weight
+        (G(2, [0, 1, 2], [1, 0], [0, 0]), MOD),                   # weight 0
+        (G(2, [0, 1, 2], [1, 5], [1, 1]), MOD),                   # index out of range
+        (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [1, 1, 2, 2]), ((3, 2, False), O.VW_UNIT)),   # lambda > 1
+        (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [1, 1, 2, 2]), ((1, 0, False), O.VW_UNIT)),   # zero denominator
+        (G(2, [0, 1, 2], [1, 0], [2 ** 30, 2 ** 30]), MOD),       # total edge weight >= 2^31
+        (G(3, [0, 0, 0, 0], [], []), MOD),                        # modularity with no edges: W = 0
+    ]
+    for g, (lam, mode) in cases:
+        ref = O.cluster(g, O.PLOUVAIN, lam=lam, vw_mode=mode)
+        assert ref.status != 0
+        assert _status_gpu(g, lam, mode) == ref.status, (g, lam)
+
+
+def test_deterministic_repeat():
+    g = gg.rmat(13, 16, seed=11)
+    a, ra = U.run_gpu(g, O.PLEIDEN, *MOD)
+    b, rb = U.run_gpu(g, O.PLEIDEN, *MOD)
+    assert np.array_equal(a, b) and ra.N == rb.N
+
+
+def test_objective_entry_point():
+    import paper_2608_01503_amd as L
+    g = gg.random_gnp(3000, 0.002, 23, w_max=3)
+    rng = np.random.default_rng(2)
+    C = rng.integers(0, 50, size=g.n).astype(np.int32)
+    st, vw, p, q = O.setup(g)
+    want = O.objective(g, vw, p, q, C)
+    import torch
+    res = U.ctx().objective(U.device_graph(g, O.VW_WEIGHTED_DEGREE), torch.from_numpy(C).cuda(), (1, 1, True))
+    assert res.N == want and res.obj_den == q
+
+
+def test_batch_equals_single():
+    import torch
+    import paper_2608_01503_amd as L
+    gs = [gg.random_gnp(200 + 150 * k, 0.02, 300 + k, w_max=5) for k in range(6)]
+    lams = [(1, 1, True), (1, 20, False)] * 3
+    modes = [O.VW_WEIGHTED_DEGREE, O.VW_UNIT] * 3
+    variants = [O.PLOUVAIN, O.PLEIDEN, O.LOUVAIN, O.PLEIDEN_PLUS, O.PLOUVAIN, O.PLEIDEN]
+    graphs = [U.device_graph(g, m) for g, m in zip(gs, modes)]
+    labs, ress = U.ctx().cluster_batch(graphs, lams, variants)
+    torch.cuda.synchronize()
+    for g, lam, m, v, lab, res in zip(gs, lams, modes, variants, labs, ress):
+        ref = O.cluster(g, v, lam=lam, vw_mode=m)
+        assert np.array_equal(lab.cpu().numpy(), ref.labels) and res.N == ref.N

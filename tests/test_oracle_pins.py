@@ -80,6 +80,9 @@ def test_setup_rejects_invalid_graphs():
     assert O.setup(ok, O.VW_UNIT, (1, 0, False))[0] == -6                          # zero denominator
     big = _g(2, [0, 1, 2], [1, 0], [2 ** 30, 2 ** 30])
     assert O.setup(big)[0] == -7                                                   # total weight >= 2^31
+    vbig = np.array([2 ** 31, 1, 1], np.int64)
+    assert O.setup(ok, O.VW_GIVEN, (1, 20, False), vbig)[0] == -7                  # vertex weight >= 2^31
+    assert O.setup(ok, O.VW_GIVEN, (1, 20, False), -vbig)[0] == -5                 # negative vertex weight
 
 
 def test_setup_lambda_reduced():
