@@ -1,0 +1,121 @@
+#!/usr/bin/env python3
+"""Benchmark of the full clustering pipeline on one MI355X.
+
+Default workload: pLouvain (Louvain+) with modularity on the R-MAT graph of scale 22, edge factor 16,
+(a, b, c, d) = (0.57, 0.19, 0.19, 0.05), symmetrised, self-loops dropped, duplicates merged by summing
+integer weights (seed 2).  One step = one lcc_cluster call from a device-resident CSR to device-resident
+labels plus the exact objective: setup and validation, every local-move pass of coarsening and
+uncoarsening, contraction and projection.  value = directed CSR entries (2m) per second, the paper's
+processing rate (Sec. VII).
+
+Prints one JSON line.  The CPU baseline is the oracle (single-threaded, exact) timed on a bounded sample of
+the same workload (the same generator at a smaller scale).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "full-pipeline edges/s + HBM GB/s fraction; batched vs plain p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    import graphgen as gg
+    import paper_2608_01503_amd as L
+    if name == "rmat22":
+        return gg.config2_rmat(), L.LCC_PLOUVAIN, (1, 1, True), L.LCC_VW_WEIGHTED_DEGREE, \
+            "R-MAT scale 22, edge factor 16, (0.57,0.19,0.19,0.05), pLouvain+ (Louvain+), modularity"
+    if name == "sbm2000":
+        return gg.config1_sbm(), L.LCC_PLOUVAIN, (1, 1, True), L.LCC_VW_WEIGHTED_DEGREE, \
+            "SBM 20 x 100, p_in 0.1, p_out 0.002, pLouvain+ (Louvain+), modularity"
+    if name == "lattice4096":
+        return gg.config3a_lattice(), L.LCC_PLEIDEN, (1, 20, False), L.LCC_VW_UNIT, \
+            "4096 x 4096 lattice, 10% edges deleted, weights U[1,100], pLeiden, CPM lambda=1/20"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(scale: int):
+    """The oracle, as it stands, on R-MAT of a smaller scale (same generator and parameters)."""
+    import graphgen as gg
+    import oracle as O
+    g = gg.rmat(scale, 16, 0.57, 0.19, 0.19, 2)
+    t = time.perf_counter()
+    r = O.cluster(g, O.PLOUVAIN, lam=(1, 1, True), vw_mode=O.VW_WEIGHTED_DEGREE)
+    dt = time.perf_counter() - t
+    assert r.status == 0
+    return {"value": g.nnz / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"R-MAT scale {scale} (n={g.n}, nnz={g.nnz}), same generator and parameters, "
+                      f"pLouvain+ modularity, one single-threaded run of {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--cpu-scale", type=int, default=19)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2608_01503_amd as L
+
+    g, variant, lam, vw_mode, desc = workload(args.workload)
+    dev = torch.device("cuda:0")
+    off = torch.from_numpy(g.off).to(dev)
+    idx = torch.from_numpy(g.idx).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    graph = L.make_graph(off, idx, w, None, vw_mode)
+    labels = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ctx = L.Context(0)
+    opts = L.lcc_default_options()
+    stream = torch.cuda.current_stream()
+
+    res = None
+    for _ in range(args.warmup):
+        _, res = ctx.cluster(graph, lam, variant, opts, labels_out=labels, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, res = ctx.cluster(graph, lam, variant, opts, labels_out=labels, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / max(args.steps, 1)
+    value = g.nnz / sec
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "clusters": res.num_clusters if res else None,
+                   "modularity": res.modularity if res else None, "levels": res.levels if res else None},
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.cpu_scale),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

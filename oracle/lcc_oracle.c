@@ -80,7 +80,8 @@ static void put128(i128 x, int64_t* hl) {
 /* ---------------------------------------------------------------------------------------------------
  * Setup (Sec. II): validate the symmetric CSR, derive vertex weights, fix lambda = p / q.
  * Check order: arguments, structure, self-loops, sortedness, weights, symmetry, weight totals (total edge
- * weight < 2^31, given vertex weights < 2^31), lambda, exactness bound.
+ * weight < 2^32, so every weighted degree and coarse edge weight is < 2^31; given vertex weights < 2^31),
+ * lambda, exactness bound.
  * ------------------------------------------------------------------------------------------------- */
 static int64_t find_in_row(const ograph* g, int64_t row, int32_t key) {
   int64_t lo = g->off[row], hi = g->off[row + 1];
@@ -129,7 +130,7 @@ int orc_setup(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* 
     }
   i128 WE = 0, W = 0;
   for (int64_t j = 0; j < nnz; ++j) WE += EW(&g, j);
-  if (WE >= ((i128)1 << 31)) return ORC_ERR_OVERFLOW;
+  if (WE >= ((i128)1 << 32)) return ORC_ERR_OVERFLOW; /* every weighted degree < 2^31 */
   if (vw_mode == ORC_VW_GIVEN)
     for (int64_t v = 0; v < n; ++v)
       if (vw_in[v] >= ((int64_t)1 << 31)) return ORC_ERR_OVERFLOW;

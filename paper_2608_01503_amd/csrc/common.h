@@ -123,6 +123,34 @@ struct Score {
   int64_t tie;
 };
 
+
+// Block-level aggregation of (key -> int64 sum) in an LDS open-addressing table: many threads adding to the
+// same cluster id (a popular destination, a giant cluster) meet in LDS, and the tile is flushed to global
+// memory with one atomic per distinct key.  The caller guarantees fewer than SLOTS distinct keys per tile
+// and brackets add() with __syncthreads() after clear() and before flush().
+template <int SLOTS>
+struct LdsAgg {
+  int32_t* keys;
+  unsigned long long* vals;
+  __device__ __forceinline__ void clear() {
+    for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) { keys[s] = -1; vals[s] = 0; }
+  }
+  __device__ __forceinline__ void add(int32_t k, int64_t v) {
+    uint32_t h = ((uint32_t)k * 2654435761u) & (SLOTS - 1);
+    for (int probe = 0; probe < SLOTS; ++probe) {
+      int32_t prev = atomicCAS(&keys[h], -1, k);
+      if (prev == -1 || prev == k) { atomicAdd(&vals[h], (unsigned long long)v); return; }
+      h = (h + 1) & (SLOTS - 1);
+    }
+  }
+  __device__ __forceinline__ void flush(int64_t* out) {
+    for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
+      int32_t k = keys[s];
+      if (k >= 0 && vals[s]) atomicAdd((unsigned long long*)&out[k], vals[s]);
+    }
+  }
+};
+
 // Packed per-vertex local-move state read by the afterburner: cluster, destination (D_NONE when v is not a
 // candidate), delta.  16 bytes, one load per neighbour.
 struct alignas(16) VState {
@@ -144,6 +172,7 @@ void scan_i32_i32(const int32_t* in, int32_t* out, int64_t n, void* temp, hipStr
 void scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st);
 void scan_i64_i64(const int64_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st);
 void scan_u32_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t st);
+void scan_u32_i64(const uint32_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st);
 // LSD radix sort of (key, val) pairs over the 8-bit digits starting at the given bit shifts (ascending);
 // stable.  Ping-pongs between (k0, v0) and (k1, v1); returns 0 if the result is in (k0, v0), 1 otherwise.
 size_t radix_temp_bytes(int64_t m);
@@ -172,7 +201,6 @@ struct LMBuffers {
   int32_t* C;      // current clustering (labels in [0, n))
   int32_t* Cout;   // best-so-far clustering
   int64_t* W;      // cluster weights, indexed by cluster id
-  int32_t* sz;     // cluster sizes
   VState* vs;      // packed (C, D, delta)
   uint8_t* keep;   // afterburner verdict
   uint8_t* empty;  // kept movers to a new singleton
@@ -198,8 +226,7 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
 // LocalMoveAlt.  Fills bufs.vs and bufs.keep (keep = non-node-optimal).
 void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
                                 LMSlot* slot, hipStream_t st);
-void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, int32_t* sz,
-                            hipStream_t st);
+void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, hipStream_t st);
 // Exact objective pieces of clustering C: ctrl->obj_I and ctrl->obj_SW2 (W must hold C's cluster weights).
 void launch_objective(const DevGraph& g, const Buckets& b, const int32_t* C, const int64_t* W,
                       Ctrl* ctrl, hipStream_t st);
@@ -216,8 +243,11 @@ void launch_cross_count(const DevGraph& g, const Buckets& b, const int32_t* map,
 void launch_cross_emit(const DevGraph& g, const Buckets& b, const int32_t* map, int64_t* cursor,
                        uint64_t* keys, uint32_t* vals, hipStream_t st);
 void launch_heads(const uint64_t* keys, int64_t m, uint8_t* head, hipStream_t st);
+// coarse CSR from sorted (x << 32 | y) keys: uid = exclusive scan of run heads; pref = exclusive scan of the
+// values (m + 1); hstart/ux scratch of nnz_c + 1 entries.
 void launch_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8_t* head, const int32_t* uid,
-                         int64_t m, int32_t* cidx, int32_t* cw, int32_t* cdeg, hipStream_t st);
+                         int64_t m, int64_t nnzc, int64_t nc, int64_t* pref, int32_t* hstart, int32_t* ux,
+                         int32_t* cidx, int32_t* cw, int64_t* coff, void* temp, hipStream_t st);
 void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st);
 void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,
                        hipStream_t st);

@@ -42,9 +42,24 @@ __global__ void k_map(const int32_t* labels, const int32_t* rank, int64_t n, int
     map[v] = rank[labels[v]];
 }
 
-__global__ void k_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t* cvw) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd((unsigned long long*)&cvw[map[v]], (unsigned long long)vw[v]);
+__global__ __launch_bounds__(BLOCK) void k_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n,
+                                                     int64_t* cvw) {
+  constexpr int SLOTS = 4096, T = 2048;
+  __shared__ int32_t ak[SLOTS];
+  __shared__ unsigned long long av[SLOTS];
+  LdsAgg<SLOTS> agg{ak, av};
+  for (int64_t t0 = (int64_t)blockIdx.x * T; t0 < n; t0 += (int64_t)gridDim.x * T) {
+    agg.clear();
+    __syncthreads();
+    for (int k = threadIdx.x; k < T; k += BLOCK) {
+      int64_t v = t0 + k;
+      if (v >= n) break;
+      agg.add(map[v], vw[v]);
+    }
+    __syncthreads();
+    agg.flush(cvw);
+    __syncthreads();
+  }
 }
 
 // cross-cluster entries per fine vertex; G lanes per vertex (G = 64 also covers whole-block rows by
@@ -171,16 +186,35 @@ __global__ void k_heads(const uint64_t* keys, int64_t m, uint8_t* head) {
     head[i] = (i == 0 || keys[i] != keys[i - 1]);
 }
 
-__global__ void k_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8_t* head, const int32_t* uid,
-                               int64_t m, int32_t* cidx, int32_t* cw, int32_t* cdeg) {
+// run heads of the sorted keys become coarse entries: neighbour id, run start, row id
+__global__ void k_heads_write(const uint64_t* keys, int64_t m, const uint8_t* head, const int32_t* uid,
+                              int64_t nnzc, int32_t* cidx, int32_t* hstart, int32_t* ux) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!head[i]) continue;
     uint64_t k = keys[i];
-    int32_t u = uid[i] + head[i] - 1;
-    if (head[i]) {
-      cidx[u] = (int32_t)(uint32_t)k;
-      atomicAdd(&cdeg[(int32_t)(k >> 32)], 1);
+    int32_t u = uid[i];
+    cidx[u] = (int32_t)(uint32_t)k;
+    hstart[u] = (int32_t)i;
+    ux[u] = (int32_t)(k >> 32);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) hstart[nnzc] = (int32_t)m;
+}
+
+// run weight = difference of the value prefix sums at consecutive run starts
+__global__ void k_run_weights(const int64_t* pref, const int32_t* hstart, int64_t nnzc, int32_t* cw) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < nnzc; u += (int64_t)gridDim.x * blockDim.x)
+    cw[u] = (int32_t)(pref[hstart[u + 1]] - pref[hstart[u]]);
+}
+
+// row offsets: first entry whose row id is >= x (rows are sorted)
+__global__ void k_row_offsets(const int32_t* ux, int64_t nnzc, int64_t nc, int64_t* coff) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= nc; x += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nnzc;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (ux[mid] < x) lo = mid + 1; else hi = mid;
     }
-    atomicAdd(&cw[u], (int32_t)vals[i]);
+    coff[x] = lo;
   }
 }
 
@@ -208,7 +242,8 @@ void launch_map_labels(const int32_t* labels, const int32_t* rank, int64_t n, in
 }
 
 void launch_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t* cvw, hipStream_t st) {
-  k_coarse_vw<<<grid_for(n), BLOCK, 0, st>>>(map, vw, n, cvw);
+  unsigned g = (unsigned)(cdiv(n, 2048) < 1 ? 1 : (cdiv(n, 2048) > 4096 ? 4096 : cdiv(n, 2048)));
+  k_coarse_vw<<<g, BLOCK, 0, st>>>(map, vw, n, cvw);
 }
 
 void launch_cross_count(const DevGraph& g, const Buckets& b, const int32_t* map, int32_t* cnt, hipStream_t st) {
@@ -245,8 +280,12 @@ void launch_heads(const uint64_t* keys, int64_t m, uint8_t* head, hipStream_t st
 }
 
 void launch_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8_t* head, const int32_t* uid,
-                         int64_t m, int32_t* cidx, int32_t* cw, int32_t* cdeg, hipStream_t st) {
-  k_coarse_write<<<grid_for(m), BLOCK, 0, st>>>(keys, vals, head, uid, m, cidx, cw, cdeg);
+                         int64_t m, int64_t nnzc, int64_t nc, int64_t* pref, int32_t* hstart, int32_t* ux,
+                         int32_t* cidx, int32_t* cw, int64_t* coff, void* temp, hipStream_t st) {
+  scan_u32_i64(vals, pref, m, temp, st);
+  k_heads_write<<<grid_for(m), BLOCK, 0, st>>>(keys, m, head, uid, nnzc, cidx, hstart, ux);
+  k_run_weights<<<grid_for(nnzc), BLOCK, 0, st>>>(pref, hstart, nnzc, cw);
+  k_row_offsets<<<grid_for(nc + 1), BLOCK, 0, st>>>(ux, nnzc, nc, coff);
 }
 
 void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st) {

@@ -62,7 +62,7 @@ struct WS {
   LMSlot* slots;
   int64_t* in_off; int32_t* in_idx; int32_t* in_w; int64_t* in_vwg; int32_t* in_labels;
   int64_t* vw0;
-  int32_t *C, *Cout, *sz, *scan_a, *scan_b, *freelist;
+  int32_t *C, *Cout, *scan_a, *scan_b, *freelist;
   int64_t* W;
   VState* vs;
   uint8_t *keep, *empty, *used;
@@ -70,7 +70,7 @@ struct WS {
   int64_t* pos;
   int64_t* hub_ps; int32_t* hub_pc; int64_t* hub_pown; int64_t* hub_acc;
   uint64_t *k0, *k1; uint32_t *v0, *v1;
-  uint8_t* head; int32_t* uid;
+  uint8_t* head; int32_t* uid; int32_t* ux;
   int64_t *WB, *aB, *aX, *pw, *pc, *t64a, *t64b, *alt_gain;
   uint8_t *inU, *flip, *has_child, *member;
   int32_t *H, *par, *root, *tsz, *pos_of, *fail, *mpos, *alt_list;
@@ -90,7 +90,7 @@ size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
   w.in_vwg = c.take<int64_t>(n);
   w.in_labels = c.take<int32_t>(n);
   w.vw0 = c.take<int64_t>(n);
-  w.C = c.take<int32_t>(n); w.Cout = c.take<int32_t>(n); w.sz = c.take<int32_t>(n);
+  w.C = c.take<int32_t>(n); w.Cout = c.take<int32_t>(n);
   w.scan_a = c.take<int32_t>(n + 1); w.scan_b = c.take<int32_t>(n + 1); w.freelist = c.take<int32_t>(n);
   w.W = c.take<int64_t>(n);
   w.vs = c.take<VState>(n);
@@ -101,9 +101,9 @@ size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
   w.hub_ps = c.take<int64_t>(nch); w.hub_pc = c.take<int32_t>(nch); w.hub_pown = c.take<int64_t>(nch);
   w.hub_acc = c.take<int64_t>(n);
   // k0 and k1 are adjacent: together they also hold the hub hash tables (2 nnz slots of 8 bytes)
-  w.k0 = c.take<uint64_t>(M); w.k1 = c.take<uint64_t>(M);
-  w.v0 = c.take<uint32_t>(M); w.v1 = c.take<uint32_t>(M);
-  w.head = c.take<uint8_t>(M); w.uid = c.take<int32_t>(M + 1);
+  w.k0 = c.take<uint64_t>(M + 1); w.k1 = c.take<uint64_t>(M + 1);
+  w.v0 = c.take<uint32_t>(M + 1); w.v1 = c.take<uint32_t>(M + 1);
+  w.head = c.take<uint8_t>(M); w.uid = c.take<int32_t>(M + 1); w.ux = c.take<int32_t>(M + 1);
   w.WB = c.take<int64_t>(n); w.aB = c.take<int64_t>(n); w.aX = c.take<int64_t>(n);
   w.pw = c.take<int64_t>(n + 1); w.pc = c.take<int64_t>(n + 1);
   w.t64a = c.take<int64_t>(n); w.t64b = c.take<int64_t>(n); w.alt_gain = c.take<int64_t>(n);
@@ -279,7 +279,7 @@ struct Run {
 
   LMBuffers bufs() {
     LMBuffers B{};
-    B.C = w.C; B.Cout = w.Cout; B.W = w.W; B.sz = w.sz; B.vs = w.vs; B.keep = w.keep; B.empty = w.empty;
+    B.C = w.C; B.Cout = w.Cout; B.W = w.W; B.vs = w.vs; B.keep = w.keep; B.empty = w.empty;
     B.scan_a = w.scan_a; B.scan_b = w.scan_b; B.freelist = w.freelist; B.arena = (uint32_t*)w.k0;
     B.scan_temp = w.scan_temp;
     return B;
@@ -345,8 +345,6 @@ struct Run {
     int64_t nnzc = 0;
     int32_t* cidx;
     int32_t* cw;
-    int32_t* cdeg = take<int32_t>(ctx, nc);
-    fill_i32(cdeg, 0, nc, st);
     if (E > 0) {
       launch_cross_emit(L.g, L.b, L.map, w.pos, w.k0, w.v0, st);
       int ybits = 1;
@@ -357,6 +355,8 @@ struct Run {
       int which = radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, E, shifts, np, w.radix_temp, st);
       const uint64_t* ks = which ? w.k1 : w.k0;
       const uint32_t* vs = which ? w.v1 : w.v0;
+      int64_t* pref = (int64_t*)(which ? w.k0 : w.k1);  // the other key buffer is free
+      int32_t* hstart = (int32_t*)(which ? w.v0 : w.v1);
       launch_heads(ks, E, w.head, st);
       scan_u8_i32(w.head, w.uid, E, w.scan_temp, nullptr, st);
       int32_t nz = 0;
@@ -365,13 +365,12 @@ struct Run {
       nnzc = nz;
       cidx = take<int32_t>(ctx, nnzc);
       cw = take<int32_t>(ctx, nnzc);
-      fill_i32(cw, 0, nnzc, st);
-      launch_coarse_write(ks, vs, w.head, w.uid, E, cidx, cw, cdeg, st);
+      launch_coarse_write(ks, vs, w.head, w.uid, E, nnzc, nc, pref, hstart, w.ux, cidx, cw, coff, w.scan_temp, st);
     } else {
       cidx = take<int32_t>(ctx, 1);
       cw = take<int32_t>(ctx, 1);
+      fill_i64(coff, 0, nc + 1, st);
     }
-    scan_i32_i64(cdeg, coff, nc, w.scan_temp, st);
     N.g.n = nc;
     N.g.nnz = nnzc;
     N.g.off = coff;
@@ -443,12 +442,12 @@ struct Run {
         // C_l unchanged by the local move: the alternate local move (Sec. V-A) from C_l
         LMBuffers B = bufs();
         copy_i32(w.C, L.C, n, st);
-        launch_cluster_weights(w.C, L.g.vw, n, w.W, w.sz, st);
+        launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         if (nslot >= NSLOT) fail(LCC_ERR_INVALID, "too many local-move calls");
         int s2 = nslot++;
         lmalt(L.g, L.b, sc, B, w.slots + s2, w.ctrl, w.alt_list, w.alt_gain, st);
         copy_i32(L.C, w.C, n, st);
-        launch_cluster_weights(w.C, L.g.vw, n, w.W, nullptr, st);
+        launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         launch_objective(L.g, L.b, w.C, w.W, w.ctrl, st);
         read_ctrl("lmalt");
         N = q * ctx->h_ctrl->obj_I - p * (ctx->h_ctrl->obj_SW2 - L.sum_w2);
@@ -606,8 +605,8 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
   if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
   if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
-  if (R.o.validate && (c.count0 != 0 || c.count1 != 0)) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
-  if (c.sum_we >= ((uint64_t)1 << 31)) fail(LCC_ERR_OVERFLOW, "total edge weight >= 2^31");
+  if (R.o.validate && c.count0 != 0) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
+  if (c.sum_we >= ((uint64_t)1 << 32)) fail(LCC_ERR_OVERFLOW, "total edge weight >= 2^32");
   if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
   L.sum_w2 = (int64_t)c.sum_w2;
   R.W = c.sum_w;
@@ -697,7 +696,7 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
   int64_t nc = R.count_labels(L0.C, n);
   int32_t* lab = (g->mem == LCC_MEM_DEVICE) ? labels_out : R.w.in_labels;
   launch_map_labels(L0.C, R.w.rank, n, lab, st);
-  launch_cluster_weights(lab, L0.g.vw, n, R.w.W, nullptr, st);
+  launch_cluster_weights(lab, L0.g.vw, n, R.w.W, st);
   launch_objective(L0.g, L0.b, lab, R.w.W, R.w.ctrl, st);
   R.read_ctrl("objective");
   __int128 N = (__int128)R.q * ctx->h_ctrl->obj_I - (__int128)R.p * (ctx->h_ctrl->obj_SW2 - L0.sum_w2);
@@ -857,7 +856,7 @@ lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const
     setup(R, g, lam, lab);
     Level& L0 = R.lv[0];
     int64_t nc = R.count_labels(lab, g->n);
-    launch_cluster_weights(lab, L0.g.vw, g->n, R.w.W, nullptr, st);
+    launch_cluster_weights(lab, L0.g.vw, g->n, R.w.W, st);
     launch_objective(L0.g, L0.b, lab, R.w.W, R.w.ctrl, st);
     R.read_ctrl("objective");
     __int128 N = (__int128)R.q * ctx->h_ctrl->obj_I - (__int128)R.p * (ctx->h_ctrl->obj_SW2 - L0.sum_w2);

@@ -11,6 +11,8 @@
 // neighbour clusters aggregated by register shuffles), one wavefront per vertex with an LDS open-addressing
 // hash (degree <= 1024), one workgroup per vertex with an LDS hash (degree <= 4096), and hub vertices split
 // into 4096-edge chunks processed by independent workgroups with a global-memory hash in the edge arena.
+#include <algorithm>
+
 #include "common.h"
 
 namespace lcc {
@@ -448,20 +450,38 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_clear(const int32_t* hubs, co
   }
 }
 
+// Each chunk first aggregates its edges by cluster in LDS (a hub's neighbours often share few clusters), then
+// inserts one entry per distinct cluster into the hub's global table.
 __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, const int32_t* chunk_off,
                                                           int64_t n7, DevGraph g, const int32_t* C,
                                                           uint32_t* arena, const LMSlot* slot, int pass) {
   if (slot && slot->skip[pass]) return;
+  constexpr int S = 2 * HUB_CHUNK;
+  __shared__ int32_t lk[S];
+  __shared__ uint32_t lv[S];
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
   const int64_t base = g.off[v];
   const int64_t cap = 2 * (g.off[v + 1] - base);
   const int64_t j0 = base + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
-  uint32_t* tab = arena + 4 * base;
+  for (int s = threadIdx.x; s < S; s += HUB_BLOCK) { lk[s] = -1; lv[s] = 0; }
+  __syncthreads();
   for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) {
     int32_t c = C[g.idx[j]];
-    uint32_t wt = (uint32_t)g.w[j];
+    uint32_t h = hslot(c, 13);
+    for (int probe = 0; probe < S; ++probe) {
+      int32_t prev = atomicCAS(&lk[h], -1, c);
+      if (prev == -1 || prev == c) { atomicAdd(&lv[h], (uint32_t)g.w[j]); break; }
+      h = (h + 1) & (S - 1);
+    }
+  }
+  __syncthreads();
+  uint32_t* tab = arena + 4 * base;
+  for (int s = threadIdx.x; s < S; s += HUB_BLOCK) {
+    int32_t c = lk[s];
+    if (c < 0) continue;
+    uint32_t wt = lv[s];
     int64_t h = hub_slot(c, cap);
     for (int64_t probe = 0; probe < cap; ++probe) {
       uint32_t prev = atomicCAS(&tab[2 * h], 0xFFFFFFFFu, (uint32_t)c);
@@ -648,38 +668,57 @@ __global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs
 // weights and sizes.  Movers to a new singleton take the ids left unused by all other moves, smallest first,
 // in ascending vertex order.
 // ---------------------------------------------------------------------------------------------------------
-__global__ void k_apply(int64_t n, const uint8_t* keep, const VState* vs, const int64_t* vw, int32_t* C,
-                        int64_t* W, int32_t* sz, uint8_t* empty, LMSlot* slot, int pass) {
+constexpr int APPLY_TILE = 1024;   // vertices per workgroup tile (4 per thread)
+constexpr int AGG_SLOTS = 4096;    // > 2 * APPLY_TILE distinct cluster ids per tile
+
+__global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep, const VState* vs,
+                                                 const int64_t* vw, int32_t* C, int64_t* W, uint8_t* empty,
+                                                 LMSlot* slot, int pass) {
   if (slot && slot->skip[pass]) return;
+  __shared__ int32_t ak[AGG_SLOTS];
+  __shared__ unsigned long long av[AGG_SLOTS];
   __shared__ unsigned long long ne;
+  LdsAgg<AGG_SLOTS> agg{ak, av};
   if (threadIdx.x == 0) ne = 0;
-  __syncthreads();
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    uint8_t e = 0;
-    if (keep[v]) {
-      VState s = vs[v];
-      int64_t wv = vw[v];
-      atomicAdd((unsigned long long*)&W[s.c], (unsigned long long)(-wv));
-      atomicSub(&sz[s.c], 1);
-      if (s.d == D_EMPTY) {
-        e = 1;
-        atomicAdd(&ne, 1ull);
-      } else {
-        C[v] = s.d;
-        atomicAdd((unsigned long long*)&W[s.d], (unsigned long long)wv);
-        atomicAdd(&sz[s.d], 1);
+  for (int64_t t0 = (int64_t)blockIdx.x * APPLY_TILE; t0 < n; t0 += (int64_t)gridDim.x * APPLY_TILE) {
+    agg.clear();
+    __syncthreads();
+    for (int k = threadIdx.x; k < APPLY_TILE; k += BLOCK) {
+      int64_t v = t0 + k;
+      if (v >= n) break;
+      uint8_t e = 0;
+      if (keep[v]) {
+        VState s = vs[v];
+        int64_t wv = vw[v];
+        agg.add(s.c, -wv);
+        if (s.d == D_EMPTY) {
+          e = 1;
+          atomicAdd(&ne, 1ull);
+        } else {
+          C[v] = s.d;
+          agg.add(s.d, wv);
+        }
       }
+      empty[v] = e;
     }
-    empty[v] = e;
+    __syncthreads();
+    agg.flush(W);
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0 && ne) atomicAdd((unsigned long long*)&slot->n_empty, ne);
 }
 
-__global__ void k_free_flags(int64_t n, const int32_t* sz, uint8_t* fl, const LMSlot* slot) {
+// free cluster ids = ids no vertex holds once every move except those to a new singleton is applied
+__global__ void k_free_init(int64_t n, uint8_t* fl, const LMSlot* slot) {
   if (slot->n_empty == 0) return;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
-    fl[c] = sz[c] == 0;
+    fl[c] = 1;
+}
+
+__global__ void k_free_mark(int64_t n, const int32_t* C, const uint8_t* empty, uint8_t* fl, const LMSlot* slot) {
+  if (slot->n_empty == 0) return;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    if (!empty[v]) fl[C[v]] = 0;
 }
 
 __global__ void k_free_list(int64_t n, const uint8_t* fl, const int32_t* rank, int32_t* freelist,
@@ -690,14 +729,13 @@ __global__ void k_free_list(int64_t n, const uint8_t* fl, const int32_t* rank, i
 }
 
 __global__ void k_assign_empty(int64_t n, const uint8_t* empty, const int32_t* rank, const int32_t* freelist,
-                               const int64_t* vw, int32_t* C, int64_t* W, int32_t* sz, const LMSlot* slot) {
+                               const int64_t* vw, int32_t* C, int64_t* W, const LMSlot* slot) {
   if (slot->n_empty == 0) return;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     if (!empty[v]) continue;
     int32_t c = freelist[rank[v]];
     C[v] = c;
-    W[c] = vw[v];
-    sz[c] = 1;
+    W[c] = vw[v];  // a free id has weight 0
   }
 }
 
@@ -761,19 +799,29 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_internal_hub(const int32_t* hubs,
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
 }
 
-__global__ void k_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, int32_t* sz) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    int32_t c = C[v];
-    atomicAdd((unsigned long long*)&W[c], (unsigned long long)vw[v]);
-    if (sz) atomicAdd(&sz[c], 1);
+__global__ __launch_bounds__(BLOCK) void k_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n,
+                                                           int64_t* W) {
+  __shared__ int32_t ak[AGG_SLOTS];
+  __shared__ unsigned long long av[AGG_SLOTS];
+  LdsAgg<AGG_SLOTS> agg{ak, av};
+  constexpr int T = 2048;
+  for (int64_t t0 = (int64_t)blockIdx.x * T; t0 < n; t0 += (int64_t)gridDim.x * T) {
+    agg.clear();
+    __syncthreads();
+    for (int k = threadIdx.x; k < T; k += BLOCK) {
+      int64_t v = t0 + k;
+      if (v >= n) break;
+      agg.add(C[v], vw[v]);
+    }
+    __syncthreads();
+    agg.flush(W);
+    __syncthreads();
   }
 }
 
-__global__ void k_copy_vw(const int64_t* vw, int64_t* W, int32_t* sz, int64_t n) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+__global__ void k_copy_vw(const int64_t* vw, int64_t* W, int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     W[v] = vw[v];
-    sz[v] = 1;
-  }
 }
 
 __global__ void k_zero_i64(int64_t* p) {
@@ -812,25 +860,33 @@ __global__ void k_bucket_offsets(Ctrl* ctrl) {
   ctrl->bucket_off[NBUCKET] = s;
 }
 
-__global__ void k_bucket_scatter(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl) {
-  const int lane = threadIdx.x & (WAVE - 1);
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-  // every lane of a wavefront runs the same number of iterations (n rounded up to the block stride)
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-    int64_t v = base + threadIdx.x;
-    bool valid = v < n;
-    int b = valid ? bucket_of(off[v + 1] - off[v]) : -1;
-    for (int bb = 0; bb < NBUCKET; ++bb) {
-      uint64_t m = __ballot(b == bb);
-      if (!m) continue;
-      int leader = __ffsll((unsigned long long)m) - 1;
-      int64_t pos = 0;
-      if (lane == leader) pos = (int64_t)atomicAdd((unsigned long long*)&ctrl->bucket_cursor[bb],
-                                                   (unsigned long long)__popcll(m));
-      pos = __shfl(pos, leader, WAVE);
-      if (b == bb) list[pos + __popcll(m & lt)] = (int32_t)v;
+// Bucket lists: per workgroup tile, LDS counts per bucket, one global atomic per bucket, positions inside
+// the tile from LDS atomics (the order inside a bucket does not affect any result).
+__global__ __launch_bounds__(BLOCK) void k_bucket_scatter(const int64_t* off, int64_t n, int32_t* list,
+                                                          Ctrl* ctrl) {
+  __shared__ uint32_t cnt[NBUCKET];
+  __shared__ int64_t base[NBUCKET];
+  constexpr int T = 4 * BLOCK;
+  for (int64_t t0 = (int64_t)blockIdx.x * T; t0 < n; t0 += (int64_t)gridDim.x * T) {
+    if (threadIdx.x < NBUCKET) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int b[4];
+    uint32_t r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int64_t v = t0 + k * BLOCK + threadIdx.x;
+      b[k] = v < n ? bucket_of(off[v + 1] - off[v]) : -1;
+      if (b[k] >= 0) r[k] = atomicAdd(&cnt[b[k]], 1u);
     }
+    __syncthreads();
+    if (threadIdx.x < NBUCKET && cnt[threadIdx.x])
+      base[threadIdx.x] = (int64_t)atomicAdd((unsigned long long*)&ctrl->bucket_cursor[threadIdx.x],
+                                             (unsigned long long)cnt[threadIdx.x]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (b[k] >= 0) list[base[b[k]] + r[k]] = (int32_t)(t0 + k * BLOCK + threadIdx.x);
+    __syncthreads();
   }
 }
 
@@ -845,8 +901,8 @@ __global__ void k_hub_chunk_counts(const int32_t* hubs, int64_t n7, const int64_
 // Validation of the CSR (setup, Sec. II): offsets first, then one pass over the rows checking index range,
 // self-loops, strict ascending order and positive weights.  Symmetry is checked by a multiset fingerprint:
 // with rows strictly ascending, the graph is symmetric iff the multiset of stored (u, v, w) equals that of
-// (v, u, w); both sums of two independent 64-bit hashes over the stored entries are compared (an asymmetric
-// input passes only on a 2^-128-scale hash collision).
+// (v, u, w); the sums (mod 2^64) of a 64-bit hash of (u, v, w) and of (v, u, w) over the stored entries are
+// compared (an asymmetric input passes only on a hash collision).
 // ---------------------------------------------------------------------------------------------------------
 __global__ void k_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* ctrl) {
   if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -855,18 +911,14 @@ __global__ void k_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, C
     if (off[v + 1] < off[v]) atomicOr(&ctrl->err_bits, ERRB_INVALID);
 }
 
-__device__ __forceinline__ uint64_t fp_h1(uint32_t a, uint32_t b, uint32_t w) {
+__device__ __forceinline__ uint64_t fp_h(uint32_t a, uint32_t b, uint32_t w) {
   uint64_t key = ((uint64_t)a << 32) | b;
-  return fmix64(key ^ fmix64((uint64_t)w ^ 0x243F6A8885A308D3ULL));
-}
-__device__ __forceinline__ uint64_t fp_h2(uint32_t a, uint32_t b, uint32_t w) {
-  uint64_t key = ((uint64_t)a << 32) | b;
-  return fmix64(key * 0x9E3779B97F4A7C15ULL + (uint64_t)w + 0x13198A2E03707344ULL);
+  return fmix64(key ^ ((uint64_t)w * 0x9E3779B97F4A7C15ULL));
 }
 
 struct EdgeCheck {
   uint32_t err = 0;
-  uint64_t f1 = 0, f2 = 0;
+  uint64_t f1 = 0;
   int64_t ws = 0;
 };
 
@@ -878,8 +930,7 @@ __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t
   if (u == v) ec.err |= ERRB_SELF_LOOP;
   if (j > rb && g.idx[j - 1] >= u) ec.err |= ERRB_UNSORTED;
   if (wt <= 0) ec.err |= ERRB_WEIGHT;
-  ec.f1 += fp_h1((uint32_t)v, (uint32_t)u, (uint32_t)wt) - fp_h1((uint32_t)u, (uint32_t)v, (uint32_t)wt);
-  ec.f2 += fp_h2((uint32_t)v, (uint32_t)u, (uint32_t)wt) - fp_h2((uint32_t)u, (uint32_t)v, (uint32_t)wt);
+  ec.f1 += fp_h((uint32_t)v, (uint32_t)u, (uint32_t)wt) - fp_h((uint32_t)u, (uint32_t)v, (uint32_t)wt);
 }
 
 __device__ __forceinline__ int64_t vertex_weight(int vw_mode, int64_t ws, const int64_t* vw_given, int32_t v,
@@ -895,12 +946,10 @@ __device__ __forceinline__ int64_t vertex_weight(int vw_mode, int64_t ws, const 
 __device__ __forceinline__ void flush_check(EdgeCheck ec, int64_t wsum, Ctrl* ctrl) {
   // block-wide: every thread calls this
   uint64_t f1 = (uint64_t)sum_reduce<BLOCK>((int64_t)ec.f1);
-  uint64_t f2 = (uint64_t)sum_reduce<BLOCK>((int64_t)ec.f2);
   wsum = sum_reduce<BLOCK>(wsum);
   if (ec.err) atomicOr(&ctrl->err_bits, ec.err);
   if (threadIdx.x == 0) {
     if (f1) atomicAdd((unsigned long long*)&ctrl->count0, (unsigned long long)f1);
-    if (f2) atomicAdd((unsigned long long*)&ctrl->count1, (unsigned long long)f2);
     if (wsum) atomicAdd((unsigned long long*)&ctrl->sum_we, (unsigned long long)wsum);
   }
 }
@@ -1026,7 +1075,7 @@ void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, cons
 void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st) {
   k_bucket_count<<<grid_for(n), BLOCK, 0, st>>>(off, n, ctrl);
   k_bucket_offsets<<<1, 1, 0, st>>>(ctrl);
-  k_bucket_scatter<<<grid_for(n), BLOCK, 0, st>>>(off, n, list, ctrl);
+  k_bucket_scatter<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4 * BLOCK), 8192)), BLOCK, 0, st>>>(off, n, list, ctrl);
 }
 
 void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt, int32_t* chunk_off,
@@ -1040,11 +1089,9 @@ void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st
   k_vertex_sums<<<grid_for(n), BLOCK, 0, st>>>(vw, n, ctrl);
 }
 
-void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, int32_t* sz,
-                            hipStream_t st) {
+void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, hipStream_t st) {
   fill_i64(W, 0, n, st);
-  if (sz) fill_i32(sz, 0, n, st);
-  k_cluster_weights<<<grid_for(n), BLOCK, 0, st>>>(C, vw, n, W, sz);
+  k_cluster_weights<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 2048), 4096)), BLOCK, 0, st>>>(C, vw, n, W);
 }
 
 static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
@@ -1144,15 +1191,17 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const Score&
 
 static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, int pass, hipStream_t st) {
   const int64_t n = g.n;
-  k_apply<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.sz, bufs.empty, slot, pass);
-  // free ids (size 0 after every other move) and ranks of the movers to a new singleton; all no-ops unless
-  // some vertex moved to a new singleton in this pass
-  k_free_flags<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.sz, bufs.keep, slot);
+  unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 4096));
+  k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass);
+  // free ids and ranks of the movers to a new singleton; all no-ops unless some vertex moved to a new
+  // singleton in this pass
+  k_free_init<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, slot);
+  k_free_mark<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.C, bufs.empty, bufs.keep, slot);
   scan_u8_i32(bufs.keep, bufs.scan_a, n, bufs.scan_temp, &slot->n_empty, st);
   k_free_list<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, bufs.freelist, slot);
   scan_u8_i32(bufs.empty, bufs.scan_b, n, bufs.scan_temp, &slot->n_empty, st);
   k_assign_empty<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_b, bufs.freelist, g.vw, bufs.C, bufs.W,
-                                               bufs.sz, slot);
+                                               slot);
 }
 
 void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool singleton, LMBuffers& bufs,
@@ -1165,9 +1214,9 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
   // starting state: cluster weights, sizes, C_out = C, sum of squared cluster weights (state 0)
   if (singleton) {
     iota_i32(bufs.C, n, st);
-    k_copy_vw<<<grid_for(n), BLOCK, 0, st>>>(g.vw, bufs.W, bufs.sz, n);
+    k_copy_vw<<<grid_for(n), BLOCK, 0, st>>>(g.vw, bufs.W, n);
   } else {
-    launch_cluster_weights(bufs.C, g.vw, n, bufs.W, bufs.sz, st);
+    launch_cluster_weights(bufs.C, g.vw, n, bufs.W, st);
   }
   copy_i32(bufs.Cout, bufs.C, n, st);
   k_sw2<<<grid_for(n), BLOCK, 0, st>>>(bufs.W, n, &slot->SW2[0], nullptr, -1);

@@ -218,6 +218,9 @@ void scan_i32_i64(const int32_t* in, int64_t* out, int64_t n, void* temp, hipStr
 void scan_i64_i64(const int64_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st) {
   scan_impl<int64_t, int64_t>(in, out, n, temp, nullptr, st);
 }
+void scan_u32_i64(const uint32_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st) {
+  scan_impl<uint32_t, int64_t>(in, out, n, temp, nullptr, st);
+}
 void scan_u32_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp, hipStream_t st) {
   scan_impl<uint32_t, uint32_t>(in, out, n, temp, nullptr, st);
 }

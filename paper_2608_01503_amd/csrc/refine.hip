@@ -383,7 +383,7 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
   const uint64_t s_t = seed_stream(seed, t);
   const uint32_t fseed = (uint32_t)(s_t >> 32);
   // constraint-cluster weights and U
-  launch_cluster_weights(B, g.vw, n, rb.WB, nullptr, st);
+  launch_cluster_weights(B, g.vw, n, rb.WB, st);
   k_set_i64<<<1, 1, 0, st>>>(&ctrl->refine_U, 0);
   if (b.count[0]) k_aB_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
   if (b.count[1]) k_aB_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);

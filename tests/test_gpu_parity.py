@@ -124,7 +124,7 @@ def test_error_statuses_match_oracle():
         (G(2, [0, 1, 2], [1, 5], [1, 1]), MOD),                   # index out of range
         (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [1, 1, 2, 2]), ((3, 2, False), O.VW_UNIT)),   # lambda > 1
         (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [1, 1, 2, 2]), ((1, 0, False), O.VW_UNIT)),   # zero denominator
-        (G(2, [0, 1, 2], [1, 0], [2 ** 30, 2 ** 30]), MOD),       # total edge weight >= 2^31
+        (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [2 ** 31 - 1] * 4), MOD),       # total edge weight >= 2^32
         (G(3, [0, 0, 0, 0], [], []), MOD),                        # modularity with no edges: W = 0
     ]
     for g, (lam, mode) in cases:

@@ -78,8 +78,8 @@ def test_setup_rejects_invalid_graphs():
     assert O.setup(_g(2, [0, 1, 2], [1, 5], [1, 1]))[0] == -1                     # index out of range
     assert O.setup(ok, O.VW_UNIT, (3, 2, False))[0] == -6                          # lambda > 1
     assert O.setup(ok, O.VW_UNIT, (1, 0, False))[0] == -6                          # zero denominator
-    big = _g(2, [0, 1, 2], [1, 0], [2 ** 30, 2 ** 30])
-    assert O.setup(big)[0] == -7                                                   # total weight >= 2^31
+    big = _g(3, [0, 1, 3, 4], [1, 0, 2, 1], [2 ** 31 - 1] * 4)
+    assert O.setup(big)[0] == -7                                                   # total weight >= 2^32
     vbig = np.array([2 ** 31, 1, 1], np.int64)
     assert O.setup(ok, O.VW_GIVEN, (1, 20, False), vbig)[0] == -7                  # vertex weight >= 2^31
     assert O.setup(ok, O.VW_GIVEN, (1, 20, False), -vbig)[0] == -5                 # negative vertex weight
