@@ -61,8 +61,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22")
-    ap.add_argument("--cpu-scale", type=int, default=19)
+    ap.add_argument("--cpu-scale", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--family", default="auto", help="kernel family timed live for the roofline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (counter calibration for HBM traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU path is not built",
@@ -71,6 +74,17 @@ def main():
 
     import torch
     import paper_2608_01503_amd as L
+    from paper_2608_01503_amd import lcc as LL
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 3}), flush=True)
+        return
 
     g, variant, lam, vw_mode, desc = workload(args.workload)
     dev = torch.device("cuda:0")
@@ -86,14 +100,34 @@ def main():
     res = None
     for _ in range(args.warmup):
         _, res = ctx.cluster(graph, lam, variant, opts, labels_out=labels, stream=stream)
+    # roofline kernel: the single-kernel local-move family with the most time in one profiled (untimed) call
+    single_kernel = [f for f in LL.PROFILE_FAMILIES if f in LL.FAMILY_KERNELS and "+" not in LL.FAMILY_KERNELS[f]]
+    if args.family == "auto":
+        ctx.profile_enable(single_kernel)
+        ctx.cluster(graph, lam, variant, opts, labels_out=labels, stream=stream)
+        prof = ctx.profile_read(reset=True)
+        family = max(single_kernel, key=lambda f: prof[f][1])
+    else:
+        family = args.family
+    ctx.profile_enable([family])
+    ctx.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, res = ctx.cluster(graph, lam, variant, opts, labels_out=labels, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    launches, kms, kbytes = ctx.profile_read(reset=True)[family]
+    ctx.profile_enable([])
     sec = (t1 - t0) / max(args.steps, 1)
     value = g.nnz / sec
+    achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": LL.FAMILY_KERNELS.get(family, family), "family": family,
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None, "launches": launches,
+                "avg_launch_ms": kms / launches if launches else None,
+                "bytes_per_launch": kbytes / launches if launches else None,
+                "share_of_step": (kms / max(args.steps, 1)) / (sec * 1e3)}
 
     out = {
         "metric": METRIC,
@@ -110,7 +144,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "clusters": res.num_clusters if res else None,
                    "modularity": res.modularity if res else None, "levels": res.levels if res else None},
-        "roofline": None,
+        "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.cpu_scale),
     }
     print(json.dumps(out), flush=True)

@@ -178,6 +178,22 @@ lcc_status lcc_submit(lcc_server* s, const lcc_graph* g, lcc_lambda lambda, lcc_
 lcc_status lcc_poll(lcc_server* s, uint64_t ticket, int* done, int32_t* labels_out, lcc_result* res);
 lcc_status lcc_server_destroy(lcc_server* s);
 
+/* Kernel timing (diagnostics, for measuring kernels against the memory roofline).  While a family bit is
+ * set, the launches of that kernel family in lcc_cluster calls on the context are bracketed by HIP events on
+ * the call's stream; their durations and algorithmic bytes (what the method must move: per edge and per
+ * vertex of the launch, plus one cluster-weight read per enumerated (vertex, cluster) pair) are added to a
+ * per-family tally.  Families (bit = index): 0-7 enumeration + argmax of local-move passes for degree
+ * buckets 0-7, 8 the first (singleton) pass, 9 reserved.  lcc_profile_read copies up to `capacity` tallies
+ * (in family order) and sets *count to the number of families; reset != 0 clears them. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} lcc_kernel_stat;
+lcc_status lcc_profile_enable(lcc_ctx* ctx, uint64_t family_mask);
+lcc_status lcc_profile_read(lcc_ctx* ctx, lcc_kernel_stat* stats, int32_t capacity, int32_t* count, int32_t reset);
+
 const char* lcc_status_string(lcc_status st);
 const char* lcc_last_error(void);
 

@@ -80,6 +80,8 @@ struct Ctrl {
   int64_t lmalt_k, lmalt_best_k;
   int64_t refine_U, refine_m;
   int64_t lmalt_best;
+  int64_t bucket_edges[NBUCKET];  // sum of degrees per bucket (level being prepared)
+  int64_t pairs[NBUCKET];         // distinct (vertex, other cluster) pairs enumerated, per bucket (accumulated)
 };
 
 enum : uint32_t {
@@ -108,6 +110,7 @@ struct Buckets {
   int64_t off[NBUCKET + 1] = {};
   // hub (last bucket) vertices are processed in fixed-size edge chunks: chunk range of hub k is
   // [hub_chunk_off[k], hub_chunk_off[k+1]); per-chunk partial results and per-hub accumulators:
+  int64_t edges[NBUCKET] = {};
   const int32_t* hub_chunk_off = nullptr;
   int64_t hub_chunks = 0;
   int64_t* hub_ps = nullptr;
@@ -159,6 +162,18 @@ struct alignas(16) VState {
   int64_t delta;
 };
 
+// Optional kernel timing (diagnostics): launch sites bracket instrumented launches with prof_begin/prof_end;
+// both are no-ops unless the calling thread's context has profiling enabled for that family.  bytes = the
+// launch's algorithmic bytes known on the host; device-counted parts are added by the driver.
+enum ProfFamily : int {
+  PF_ENUM_B0 = 0,  // ..PF_ENUM_B0 + 7: enumeration + argmax of local-move passes, per degree bucket
+  PF_SINGLE = 8,   // first (singleton) local-move pass, all buckets
+  PF_AFTERBURNER = 9,
+  PF_COUNT = 10
+};
+void prof_begin(int family, hipStream_t st);
+void prof_end(int family, double bytes, hipStream_t st);
+
 // ---------------------------------------------------------------------------------------------------------
 // Host-side launchers (all asynchronous on `st`)
 // ---------------------------------------------------------------------------------------------------------
@@ -209,6 +224,7 @@ struct LMBuffers {
   int32_t* freelist;
   uint32_t* arena; // 2 * nnz (key, value) slots for the global-memory hash
   void* scan_temp;
+  int64_t* pairs;  // per-bucket counters of enumerated (vertex, cluster) pairs, or null
 };
 
 struct LMParams {

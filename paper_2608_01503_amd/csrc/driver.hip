@@ -145,6 +145,21 @@ struct lcc_ctx {
   Ctrl* h_ctrl = nullptr;       // pinned mirror
   LMSlot* h_slots = nullptr;    // pinned mirror
   std::mutex mu;
+  // kernel timing (diagnostics)
+  uint64_t prof_mask = 0;
+  struct ProfRec { int fam; hipEvent_t a, b; double bytes; };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfRec> prof_recs;
+  hipEvent_t prof_open[PF_COUNT] = {};
+  int64_t prof_launches[PF_COUNT] = {};
+  double prof_ms[PF_COUNT] = {};
+  double prof_bytes[PF_COUNT] = {};
+  hipEvent_t event() {
+    if (!ev_pool.empty()) { hipEvent_t e = ev_pool.back(); ev_pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
 
   void* dalloc(size_t bytes) {
     void* p = nullptr;
@@ -191,7 +206,50 @@ struct lcc_ctx {
   void pool_reset() { pool.cur = 0; pool.off = 0; }
 };
 
+thread_local lcc_ctx* g_prof_ctx = nullptr;  // context whose call runs on this thread, when profiling
+
+namespace lcc {
+void prof_begin(int family, hipStream_t st) {
+  lcc_ctx* c = g_prof_ctx;
+  if (!c || !((c->prof_mask >> family) & 1)) return;
+  hipEvent_t e = c->event();
+  if (!e) return;
+  (void)hipEventRecord(e, st);
+  c->prof_open[family] = e;
+}
+void prof_end(int family, double bytes, hipStream_t st) {
+  lcc_ctx* c = g_prof_ctx;
+  if (!c || !((c->prof_mask >> family) & 1) || !c->prof_open[family]) return;
+  hipEvent_t e = c->event();
+  if (!e) return;
+  (void)hipEventRecord(e, st);
+  c->prof_recs.push_back({family, c->prof_open[family], e, bytes});
+  c->prof_open[family] = nullptr;
+}
+}  // namespace lcc
+
 namespace {
+
+const char* const PROF_NAMES[PF_COUNT] = {"enum_b0", "enum_b1", "enum_b2", "enum_b3", "enum_b4", "enum_b5",
+                                          "enum_b6", "enum_b7", "single", "afterburner"};
+
+// After the call's stream has completed: fold the recorded launches into the context's tallies.
+void prof_resolve(lcc_ctx* c, const Ctrl* h) {
+  for (auto& r : c->prof_recs) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof_launches[r.fam] += 1;
+      c->prof_ms[r.fam] += ms;
+      c->prof_bytes[r.fam] += r.bytes;
+    }
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof_recs.clear();
+  // device-counted part of the enumeration bytes: one 8-byte cluster-weight read per distinct pair
+  for (int k = 0; k < NBUCKET; ++k)
+    if ((c->prof_mask >> (PF_ENUM_B0 + k)) & 1) c->prof_bytes[PF_ENUM_B0 + k] += 8.0 * (double)h->pairs[k];
+}
 
 template <typename T>
 T* take(lcc_ctx* ctx, int64_t count) {
@@ -208,7 +266,7 @@ struct Level {
 
 __global__ void k_reset_level_counters(Ctrl* c) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int b = 0; b < NBUCKET; ++b) { c->bucket_count[b] = 0; c->bucket_cursor[b] = 0; }
+  for (int b = 0; b < NBUCKET; ++b) { c->bucket_count[b] = 0; c->bucket_cursor[b] = 0; c->bucket_edges[b] = 0; }
   c->count3 = 0;
   c->sum_w = 0;
   c->sum_w2 = 0;
@@ -268,7 +326,11 @@ struct Run {
     read_ctrl("buckets");
     Buckets& b = L.b;
     b.list = list;
-    for (int k = 0; k < NBUCKET; ++k) { b.count[k] = ctx->h_ctrl->bucket_count[k]; b.off[k] = ctx->h_ctrl->bucket_off[k]; }
+    for (int k = 0; k < NBUCKET; ++k) {
+      b.count[k] = ctx->h_ctrl->bucket_count[k];
+      b.off[k] = ctx->h_ctrl->bucket_off[k];
+      b.edges[k] = ctx->h_ctrl->bucket_edges[k];
+    }
     b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = hub_off;
@@ -282,6 +344,7 @@ struct Run {
     B.C = w.C; B.Cout = w.Cout; B.W = w.W; B.vs = w.vs; B.keep = w.keep; B.empty = w.empty;
     B.scan_a = w.scan_a; B.scan_b = w.scan_b; B.freelist = w.freelist; B.arena = (uint32_t*)w.k0;
     B.scan_temp = w.scan_temp;
+    B.pairs = &w.ctrl->pairs[0];
     return B;
   }
 
@@ -586,7 +649,11 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     R.read_ctrl("buckets");
     Buckets& b = L.b;
     b.list = w.list0;
-    for (int k = 0; k < NBUCKET; ++k) { b.count[k] = ctx->h_ctrl->bucket_count[k]; b.off[k] = ctx->h_ctrl->bucket_off[k]; }
+    for (int k = 0; k < NBUCKET; ++k) {
+      b.count[k] = ctx->h_ctrl->bucket_count[k];
+      b.off[k] = ctx->h_ctrl->bucket_off[k];
+      b.edges[k] = ctx->h_ctrl->bucket_edges[k];
+    }
     b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = w.hub_off0;
@@ -677,6 +744,16 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
   Run R(ctx, st);
   if (opts) R.o = *opts; else default_opts(&R.o);
   check_opts(R.o);
+  struct ProfGuard {
+    lcc_ctx* c;
+    explicit ProfGuard(lcc_ctx* x) : c(x) { g_prof_ctx = x->prof_mask ? x : nullptr; }
+    ~ProfGuard() {
+      g_prof_ctx = nullptr;
+      for (auto& r : c->prof_recs) { c->ev_pool.push_back(r.a); c->ev_pool.push_back(r.b); }
+      c->prof_recs.clear();
+      for (auto& e : c->prof_open) if (e) { c->ev_pool.push_back(e); e = nullptr; }
+    }
+  } prof_guard(ctx);
   ctx->ensure_ws(g->n, g->nnz);
   ctx->pool_reset();
   struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
@@ -699,6 +776,7 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
   launch_cluster_weights(lab, L0.g.vw, n, R.w.W, st);
   launch_objective(L0.g, L0.b, lab, R.w.W, R.w.ctrl, st);
   R.read_ctrl("objective");
+  if (ctx->prof_mask) prof_resolve(ctx, ctx->h_ctrl);
   __int128 N = (__int128)R.q * ctx->h_ctrl->obj_I - (__int128)R.p * (ctx->h_ctrl->obj_SW2 - L0.sum_w2);
   if (g->mem == LCC_MEM_HOST) {
     hip_check(hipMemcpyAsync(labels_out, lab, (size_t)n * 4, hipMemcpyDeviceToHost, st), "labels");
@@ -788,6 +866,7 @@ lcc_status lcc_destroy(lcc_ctx* ctx) {
       ctx->pool.chunks.clear();
       if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
       if (ctx->h_slots) (void)hipHostFree(ctx->h_slots);
+      for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     }
     delete ctx;
     return LCC_OK;
@@ -862,6 +941,36 @@ lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const
     __int128 N = (__int128)R.q * ctx->h_ctrl->obj_I - (__int128)R.p * (ctx->h_ctrl->obj_SW2 - L0.sum_w2);
     const bool mod = g->vw_mode == LCC_VW_WEIGHTED_DEGREE && lam.over_total_weight;
     fill_result(res, nc, N, R.p, R.q, L0.sum_w2, R.W, mod, 1, 0);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_profile_enable(lcc_ctx* ctx, uint64_t family_mask) {
+  return guarded([&]() -> lcc_status {
+    if (!ctx) fail(LCC_ERR_INVALID, "context is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->prof_mask = family_mask & ((1ull << PF_COUNT) - 1);
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_profile_read(lcc_ctx* ctx, lcc_kernel_stat* stats, int32_t capacity, int32_t* count, int32_t reset) {
+  return guarded([&]() -> lcc_status {
+    if (!ctx || !count || (capacity > 0 && !stats)) fail(LCC_ERR_INVALID, "bad arguments");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int32_t k = 0;
+    for (int f = 0; f < PF_COUNT; ++f) {
+      if (k < capacity) {
+        memset(&stats[k], 0, sizeof(stats[k]));
+        snprintf(stats[k].name, sizeof(stats[k].name), "%s", PROF_NAMES[f]);
+        stats[k].launches = ctx->prof_launches[f];
+        stats[k].total_ms = ctx->prof_ms[f];
+        stats[k].bytes = ctx->prof_bytes[f];
+      }
+      ++k;
+      if (reset) { ctx->prof_launches[f] = 0; ctx->prof_ms[f] = 0; ctx->prof_bytes[f] = 0; }
+    }
+    *count = k;
     return LCC_OK;
   });
 }

@@ -106,17 +106,20 @@ __device__ __forceinline__ Verdict decide(int64_t scur, int64_t sbest, int32_t c
 struct BlockCounters {
   unsigned long long ncand;
   unsigned long long own;
+  unsigned long long pairs;
 };
 
 __device__ __forceinline__ void counters_init(BlockCounters* bc) {
-  if (threadIdx.x == 0) { bc->ncand = 0; bc->own = 0; }
+  if (threadIdx.x == 0) { bc->ncand = 0; bc->own = 0; bc->pairs = 0; }
   __syncthreads();
 }
-__device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* ncand, int64_t* own) {
+__device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* ncand, int64_t* own,
+                                               int64_t* pairs = nullptr) {
   __syncthreads();
   if (threadIdx.x == 0) {
     if (bc->ncand && ncand) atomicAdd((unsigned long long*)ncand, bc->ncand);
     if (bc->own && own) atomicAdd((unsigned long long*)own, bc->own);
+    if (bc->pairs && pairs) atomicAdd((unsigned long long*)pairs, bc->pairs);
   }
 }
 
@@ -151,6 +154,182 @@ __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_
     if (chunk_off[mid] <= blk) lo = mid; else hi = mid;
   }
   return (int)lo;
+}
+
+
+// ---------------------------------------------------------------------------------------------------------
+// Row helpers.  Every lane keeps U edges (or table slots) in flight: the index loads, then the dependent
+// gathers, are issued back to back before any of them is consumed, so one lane's gathers overlap instead of
+// forming a serial chain.
+// ---------------------------------------------------------------------------------------------------------
+constexpr int U = 4;
+
+__device__ __forceinline__ void lds_insert(int32_t* hk, uint32_t* hv, int bits, int32_t c, uint32_t wt) {
+  const uint32_t mask = (1u << bits) - 1;
+  uint32_t h = hslot(c, bits);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {  // the table has room for every distinct key
+    int32_t prev = atomicCAS(&hk[h], -1, c);
+    if (prev == -1 || prev == c) { atomicAdd(&hv[h], wt); return; }
+    h = (h + 1) & mask;
+  }
+}
+
+// a(v, c) for the edges b + t, b + t + S, ... < e into the LDS table; edges into v's own cluster cv are
+// summed in registers (returned) instead.  Many lanes of a wavefront often carry the same cluster id (clusters
+// grow over the passes), and same-address LDS atomics serialise: before inserting, each batch combines the
+// lanes holding the two most frequent-looking keys (the first remaining lane's key, twice) with a ballot and
+// a wavefront sum, and one lane inserts the total.  The loop is uniform over the wavefront (lanes past the
+// end carry no key) so the ballots and shuffles see every lane.
+__device__ __forceinline__ int64_t insert_row(const DevGraph& g, const int32_t* C, int64_t b, int64_t e, int t,
+                                              int S, int32_t cv, int32_t* hk, uint32_t* hv, int bits) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t tw = t - lane;  // first lane of this wavefront
+  int64_t own = 0;
+  for (int64_t j0 = b + t, jw = b + tw; jw < e; j0 += (int64_t)S * U, jw += (int64_t)S * U) {
+    int32_t cs[U];
+    uint32_t ws[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      int64_t j = j0 + (int64_t)k * S;
+      cs[k] = -1;
+      ws[k] = 0;
+      if (j < e) { cs[k] = g.idx[j]; ws[k] = (uint32_t)g.w[j]; }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (cs[k] >= 0) cs[k] = C[cs[k]];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      int32_t key = cs[k];
+      uint32_t val = ws[k];
+      if (key == cv) { own += val; key = -1; }
+#pragma unroll
+      for (int round = 0; round < 2; ++round) {
+        uint64_t act = __ballot(key >= 0);
+        if (!act) break;
+        int lead = __ffsll((unsigned long long)act) - 1;
+        int32_t lk = __shfl(key, lead, WAVE);
+        uint64_t m = __ballot(key == lk);
+        if (__popcll(m) < 2) break;  // no sharing left worth combining
+        uint32_t part = key == lk ? val : 0u;
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, WAVE);
+        if (lane == lead) lds_insert(hk, hv, bits, lk, part);
+        if (key == lk) key = -1;
+      }
+      if (key >= 0) lds_insert(hk, hv, bits, key, val);
+    }
+  }
+  return own;
+}
+
+struct Best {
+  int64_t s;
+  int32_t c;
+  int64_t own;
+  int64_t np;
+};
+
+__device__ __forceinline__ Best best_init() { return Best{INT64_MIN, INT32_MAX, 0, 0}; }
+
+// slots t, t + S, ... < cap: best other cluster, weight to the own cluster, number of other clusters
+__device__ __forceinline__ void scan_table(const int32_t* hk, const uint32_t* hv, int cap, int t, int S, int32_t cv,
+                                           int64_t wv, const int64_t* W, const Score& sc, Best& r) {
+  for (int s0 = t; s0 < cap; s0 += S * U) {
+    int32_t ks[U];
+    int64_t as[U], Ws[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      int sl = s0 + k * S;
+      ks[k] = sl < cap ? hk[sl] : -1;
+      as[k] = ks[k] >= 0 ? (int64_t)hv[sl] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) Ws[k] = (ks[k] >= 0 && ks[k] != cv) ? W[ks[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (ks[k] < 0) continue;
+      if (ks[k] == cv) { r.own += as[k]; continue; }
+      ++r.np;
+      int64_t val = sc.q * as[k] - sc.p * wv * Ws[k];
+      if (better(val, ks[k], r.s, r.c)) { r.s = val; r.c = ks[k]; }
+    }
+  }
+}
+
+// reduction of Best over G lanes (G <= 64) or a block of G threads; the result is valid in lane / thread 0
+template <int G>
+__device__ __forceinline__ void best_reduce(Best& r) {
+  constexpr int WD = G < WAVE ? G : WAVE;
+#pragma unroll
+  for (int o = WD / 2; o > 0; o >>= 1) {
+    int64_t s2 = __shfl_xor(r.s, o, WD);
+    int32_t c2 = __shfl_xor(r.c, o, WD);
+    r.own += __shfl_xor(r.own, o, WD);
+    r.np += __shfl_xor(r.np, o, WD);
+    if (better(s2, c2, r.s, r.c)) { r.s = s2; r.c = c2; }
+  }
+  if constexpr (G > WAVE) {
+    __shared__ Best sb[G / WAVE];
+    if ((threadIdx.x & (WAVE - 1)) == 0) sb[threadIdx.x / WAVE] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int k = 1; k < G / WAVE; ++k) {
+        r.own += sb[k].own;
+        r.np += sb[k].np;
+        if (better(sb[k].s, sb[k].c, r.s, r.c)) { r.s = sb[k].s; r.c = sb[k].c; }
+      }
+    }
+  }
+}
+
+// singleton pass: best neighbour u by S = q w(u,v) - p w(v) w(u)
+__device__ __forceinline__ void single_row(const DevGraph& g, const Score& sc, int64_t b, int64_t e, int t, int S,
+                                           int64_t wv, Best& r) {
+  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+    int32_t us[U];
+    int64_t ws[U], vu[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      int64_t j = j0 + (int64_t)k * S;
+      us[k] = -1;
+      ws[k] = 0;
+      if (j < e) { us[k] = g.idx[j]; ws[k] = g.w[j]; }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) vu[k] = us[k] >= 0 ? g.vw[us[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (us[k] < 0) continue;
+      int64_t val = sc.q * ws[k] - sc.p * wv * vu[k];
+      if (better(val, us[k], r.s, r.c)) { r.s = val; r.c = us[k]; }
+    }
+  }
+}
+
+// internal weight of v: sum of w(u,v) over neighbours in v's cluster
+__device__ __forceinline__ int64_t internal_row(const DevGraph& g, const int32_t* C, int64_t b, int64_t e, int t,
+                                                int S, int32_t cv) {
+  int64_t acc = 0;
+  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+    int32_t cs[U];
+    int64_t ws[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      int64_t j = j0 + (int64_t)k * S;
+      cs[k] = -1;
+      ws[k] = 0;
+      if (j < e) { cs[k] = g.idx[j]; ws[k] = g.w[j]; }
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (cs[k] >= 0) cs[k] = C[cs[k]];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (cs[k] == cv) acc += ws[k];
+  }
+  return acc;
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -216,20 +395,14 @@ __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64
   __shared__ BlockCounters bc;
   counters_init(&bc);
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
-  if (gid < cnt) {
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
-    const int64_t b = g.off[v], e = g.off[v + 1];
     const int64_t wv = g.vw[v];
-    int64_t bs = INT64_MIN;
-    int32_t bcl = INT32_MAX;
-    for (int64_t j = b + gl; j < e; j += G) {
-      int32_t u = g.idx[j];
-      int64_t s = sc.q * (int64_t)g.w[j] - sc.p * wv * g.vw[u];
-      if (better(s, u, bs, bcl)) { bs = s; bcl = u; }
-    }
-    argmax_reduce<G>(bs, bcl);
-    if (gl == 0) finish_vertex(v, v, wv, 0, bs, bcl, sc, g.vw, pa, pb, 0, vs, &bc);
+    Best r = best_init();
+    single_row(g, sc, g.off[v], g.off[v + 1], gl, G, wv, r);
+    best_reduce<G>(r);
+    if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc);
   }
   counters_flush(&bc, &slot->nL[pass], nullptr);
 }
@@ -239,18 +412,15 @@ __global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t c
                                                   uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot, int pass) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
-  const int32_t v = list[blockIdx.x];
-  const int64_t b = g.off[v], e = g.off[v + 1];
-  const int64_t wv = g.vw[v];
-  int64_t bs = INT64_MIN;
-  int32_t bcl = INT32_MAX;
-  for (int64_t j = b + threadIdx.x; j < e; j += G) {
-    int32_t u = g.idx[j];
-    int64_t s = sc.q * (int64_t)g.w[j] - sc.p * wv * g.vw[u];
-    if (better(s, u, bs, bcl)) { bs = s; bcl = u; }
+  for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
+    const int32_t v = list[vi];
+    const int64_t wv = g.vw[v];
+    Best r = best_init();
+    single_row(g, sc, g.off[v], g.off[v + 1], threadIdx.x, G, wv, r);
+    best_reduce<G>(r);
+    if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc);
+    __syncthreads();
   }
-  argmax_reduce<G>(bs, bcl);
-  if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, bs, bcl, sc, g.vw, pa, pb, 0, vs, &bc);
   counters_flush(&bc, &slot->nL[pass], nullptr);
 }
 
@@ -283,13 +453,13 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t cnt, DevGraph g,
                                                     const int32_t* C, const int64_t* W, Score sc, uint32_t pa,
                                                     uint32_t pb, int strict, VState* vs, LMSlot* slot, int pass,
-                                                    int64_t* own_sum) {
+                                                    int64_t* own_sum, int64_t* pairs) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot && slot->skip[pass]) return;
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
-  if (gid < cnt) {
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
     const int64_t b = g.off[v];
     const int d = (int)(g.off[v + 1] - b);
@@ -315,12 +485,13 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
     if (leader && c != cv) {
       bs = sc.q * acc - sc.p * wv * W[c];
       bcl = c;
+      atomicAdd(&bc.pairs, 1ull);
     }
     argmax_reduce<G>(bs, bcl);
     own = sum_reduce<G>(own);
     if (gl == 0) finish_vertex(v, cv, wv, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc);
   }
-  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
 }
 
 // One wavefront per vertex, LDS open-addressing hash of capacity pow2ceil(2 d) <= SLOTS.
@@ -328,105 +499,81 @@ template <int SLOTS>
 __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_t cnt, DevGraph g,
                                                      const int32_t* C, const int64_t* W, Score sc, uint32_t pa,
                                                      uint32_t pb, int strict, VState* vs, LMSlot* slot,
-                                                     int pass, int64_t* own_sum) {
+                                                     int pass, int64_t* own_sum, int64_t* pairs) {
   __shared__ int32_t hk[BLOCK / WAVE][SLOTS];
   __shared__ uint32_t hv[BLOCK / WAVE][SLOTS];
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot && slot->skip[pass]) return;
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv;
-  const bool active = gid < cnt;
-  int32_t v = 0, cv = 0;
-  int64_t b = 0, e = 0, wvt = 0;
-  int bits = 1;
-  if (active) {
-    v = list[gid];
-    b = g.off[v];
-    e = g.off[v + 1];
-    cv = C[v];
-    wvt = g.vw[v];
-    bits = ceil_log2(2 * (e - b));
-    if (bits < 1) bits = 1;
-    for (int s = lane; s < (1 << bits); s += WAVE) { hk[wv][s] = -1; hv[wv][s] = 0; }
-  }
-  __syncthreads();
-  if (active) {
-    const uint32_t mask = (1u << bits) - 1;
-    for (int64_t j = b + lane; j < e; j += WAVE) {
-      int32_t c = C[g.idx[j]];
-      uint32_t wt = (uint32_t)g.w[j];
-      uint32_t h = hslot(c, bits);
-      for (uint32_t probe = 0; probe <= mask; ++probe) {  // the table has room for every distinct key
-        int32_t prev = atomicCAS(&hk[wv][h], -1, c);
-        if (prev == -1 || prev == c) { atomicAdd(&hv[wv][h], wt); break; }
-        h = (h + 1) & mask;
+  for (int64_t base = (int64_t)blockIdx.x * (BLOCK / WAVE); base < cnt; base += (int64_t)gridDim.x * (BLOCK / WAVE)) {
+    const int64_t gid = base + wv;
+    const bool active = gid < cnt;
+    int32_t v = 0, cv = 0;
+    int64_t b = 0, e = 0, wvt = 0;
+    int bits = 1;
+    if (active) {
+      v = list[gid];
+      b = g.off[v];
+      e = g.off[v + 1];
+      cv = C[v];
+      wvt = g.vw[v];
+      bits = ceil_log2(2 * (e - b));
+      if (bits < 1) bits = 1;
+      for (int sl = lane; sl < (1 << bits); sl += WAVE) { hk[wv][sl] = -1; hv[wv][sl] = 0; }
+    }
+    __syncthreads();
+    int64_t own_reg = 0;
+    if (active) own_reg = insert_row(g, C, b, e, lane, WAVE, cv, hk[wv], hv[wv], bits);
+    __syncthreads();
+    if (active) {
+      Best r = best_init();
+      scan_table(hk[wv], hv[wv], 1 << bits, lane, WAVE, cv, wvt, W, sc, r);
+      r.own += own_reg;
+      best_reduce<WAVE>(r);
+      if (lane == 0) {
+        finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc);
+        if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
-  if (active) {
-    int64_t own = 0, bs = INT64_MIN;
-    int32_t bcl = INT32_MAX;
-    for (int s = lane; s < (1 << bits); s += WAVE) {
-      int32_t c = hk[wv][s];
-      if (c < 0) continue;
-      int64_t a = (int64_t)hv[wv][s];
-      if (c == cv) { own = a; continue; }
-      int64_t sc_ = sc.q * a - sc.p * wvt * W[c];
-      if (better(sc_, c, bs, bcl)) { bs = sc_; bcl = c; }
-    }
-    argmax_reduce<WAVE>(bs, bcl);
-    own = sum_reduce<WAVE>(own);
-    if (lane == 0) finish_vertex(v, cv, wvt, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc);
-  }
-  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
 }
 
-// One workgroup per vertex, LDS hash of capacity pow2ceil(2 d) <= LDS_SLOTS_B6.
-__global__ __launch_bounds__(BIG_BLOCK) void k_enum_blk(const int32_t* list, DevGraph g, const int32_t* C,
-                                                        const int64_t* W, Score sc, uint32_t pa, uint32_t pb,
-                                                        int strict, VState* vs, LMSlot* slot, int pass,
-                                                        int64_t* own_sum) {
-  __shared__ int32_t hk[LDS_SLOTS_B6];
-  __shared__ uint32_t hv[LDS_SLOTS_B6];
+// One workgroup of BS threads per vertex sharing an LDS hash of capacity pow2ceil(2 d) <= SLOTS.
+template <int BS, int SLOTS>
+__global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
+                                                 const int64_t* W, Score sc, uint32_t pa, uint32_t pb,
+                                                 int strict, VState* vs, LMSlot* slot, int pass,
+                                                 int64_t* own_sum, int64_t* pairs) {
+  __shared__ int32_t hk[SLOTS];
+  __shared__ uint32_t hv[SLOTS];
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot && slot->skip[pass]) return;
-  const int32_t v = list[blockIdx.x];
-  const int64_t b = g.off[v], e = g.off[v + 1];
-  const int32_t cv = C[v];
-  const int64_t wvt = g.vw[v];
-  int bits = ceil_log2(2 * (e - b));
-  if (bits < 1) bits = 1;
-  const uint32_t mask = (1u << bits) - 1;
-  for (int s = threadIdx.x; s < (1 << bits); s += BIG_BLOCK) { hk[s] = -1; hv[s] = 0; }
-  __syncthreads();
-  for (int64_t j = b + threadIdx.x; j < e; j += BIG_BLOCK) {
-    int32_t c = C[g.idx[j]];
-    uint32_t wt = (uint32_t)g.w[j];
-    uint32_t h = hslot(c, bits);
-    for (uint32_t probe = 0; probe <= mask; ++probe) {
-      int32_t prev = atomicCAS(&hk[h], -1, c);
-      if (prev == -1 || prev == c) { atomicAdd(&hv[h], wt); break; }
-      h = (h + 1) & mask;
+  for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
+    const int32_t v = list[vi];
+    const int64_t b = g.off[v], e = g.off[v + 1];
+    const int32_t cv = C[v];
+    const int64_t wvt = g.vw[v];
+    int bits = ceil_log2(2 * (e - b));
+    if (bits < 1) bits = 1;
+    for (int sl = threadIdx.x; sl < (1 << bits); sl += BS) { hk[sl] = -1; hv[sl] = 0; }
+    __syncthreads();
+    const int64_t own_reg = insert_row(g, C, b, e, threadIdx.x, BS, cv, hk, hv, bits);
+    __syncthreads();
+    Best r = best_init();
+    scan_table(hk, hv, 1 << bits, threadIdx.x, BS, cv, wvt, W, sc, r);
+    r.own += own_reg;
+    best_reduce<BS>(r);
+    if (threadIdx.x == 0) {
+      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc);
+      if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
     }
+    __syncthreads();
   }
-  __syncthreads();
-  int64_t own = 0, bs = INT64_MIN;
-  int32_t bcl = INT32_MAX;
-  for (int s = threadIdx.x; s < (1 << bits); s += BIG_BLOCK) {
-    int32_t c = hk[s];
-    if (c < 0) continue;
-    int64_t a = (int64_t)hv[s];
-    if (c == cv) { own = a; continue; }
-    int64_t sc_ = sc.q * a - sc.p * wvt * W[c];
-    if (better(sc_, c, bs, bcl)) { bs = sc_; bcl = c; }
-  }
-  argmax_reduce<BIG_BLOCK>(bs, bcl);
-  own = sum_reduce<BIG_BLOCK>(own);
-  if (threadIdx.x == 0) finish_vertex(v, cv, wvt, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc);
-  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
 }
 
 // Hubs: global-memory hash of 2 d slots (key, value) at slot offset 2 off[v] of the edge arena.  Chunk k
@@ -467,15 +614,9 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, c
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   for (int s = threadIdx.x; s < S; s += HUB_BLOCK) { lk[s] = -1; lv[s] = 0; }
   __syncthreads();
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) {
-    int32_t c = C[g.idx[j]];
-    uint32_t h = hslot(c, 13);
-    for (int probe = 0; probe < S; ++probe) {
-      int32_t prev = atomicCAS(&lk[h], -1, c);
-      if (prev == -1 || prev == c) { atomicAdd(&lv[h], (uint32_t)g.w[j]); break; }
-      h = (h + 1) & (S - 1);
-    }
-  }
+  // own-cluster edges also go through the table here (the scan reads the hub's own weight from it)
+  const int64_t own = insert_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, -3, lk, lv, 13);
+  (void)own;
   __syncthreads();
   uint32_t* tab = arena + 4 * base;
   for (int s = threadIdx.x; s < S; s += HUB_BLOCK) {
@@ -496,7 +637,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
                                                         int64_t n7, DevGraph g, const int32_t* C,
                                                         const int64_t* W, Score sc, uint32_t* arena,
                                                         int64_t* ps, int32_t* pc, int64_t* pown,
-                                                        const LMSlot* slot, int pass) {
+                                                        const LMSlot* slot, int pass, int64_t* pairs) {
   if (slot && slot->skip[pass]) return;
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
@@ -504,7 +645,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
   const int64_t wvt = g.vw[v];
   const int64_t s0 = 2 * (g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK);
   const int64_t s1 = min(2 * g.off[v + 1], s0 + 2 * HUB_CHUNK);
-  int64_t own = 0, bs = INT64_MIN;
+  int64_t own = 0, bs = INT64_MIN, np_ = 0;
   int32_t bcl = INT32_MAX;
   for (int64_t s = s0 + threadIdx.x; s < s1; s += HUB_BLOCK) {
     uint32_t key = arena[2 * s];
@@ -514,12 +655,17 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
     arena[2 * s] = 0xFFFFFFFFu;
     arena[2 * s + 1] = 0;
     if (c == cv) { own = a; continue; }
+    ++np_;
     int64_t sc_ = sc.q * a - sc.p * wvt * W[c];
     if (better(sc_, c, bs, bcl)) { bs = sc_; bcl = c; }
   }
   argmax_reduce<HUB_BLOCK>(bs, bcl);
   own = sum_reduce<HUB_BLOCK>(own);
-  if (threadIdx.x == 0) { ps[blockIdx.x] = bs; pc[blockIdx.x] = bcl; pown[blockIdx.x] = own; }
+  np_ = sum_reduce<HUB_BLOCK>(np_);
+  if (threadIdx.x == 0) {
+    ps[blockIdx.x] = bs; pc[blockIdx.x] = bcl; pown[blockIdx.x] = own;
+    if (pairs && np_) atomicAdd((unsigned long long*)pairs, (unsigned long long)np_);
+  }
 }
 
 // Combine the chunks of each hub (pown may be null: singleton pass).
@@ -568,14 +714,52 @@ __device__ __forceinline__ int64_t ab_adjust(int32_t cv, int32_t dv, int32_t cu,
   return a;
 }
 
-__device__ __forceinline__ int64_t ab_edge(const DevGraph& g, const VState* vs, const Score& sc, int64_t j,
-                                           int32_t v, const VState& me, int64_t wv) {
-  int32_t u = g.idx[j];
-  VState o = vs[u];
-  if (o.d == D_NONE) return 0;
-  if (!before(u, o.delta, v, me.delta, sc.tie)) return 0;
-  int64_t wq = sc.q * (int64_t)g.w[j] - sc.p * g.vw[u] * wv;
-  return ab_adjust(me.c, me.d, o.c, o.d, wq);
+__device__ __forceinline__ int ab_pattern(int32_t cv, int32_t dv, int32_t cu, int32_t du) {
+  int a = 0;
+  if (cv == cu) a += 1;
+  else if (dv == cu) a -= 1;
+  if (du != D_EMPTY) {
+    if (cv == du) a -= 1;
+    else if (dv == du) a += 1;
+  }
+  return a;
+}
+
+// sum of the adjustments of candidate v over the edges b + t, b + t + S, ... < e
+__device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, const Score& sc, int64_t b,
+                                          int64_t e, int t, int S, int32_t v, const VState& me, int64_t wv) {
+  int64_t acc = 0;
+  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+    int32_t us[U];
+    int64_t ws[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      int64_t j = j0 + (int64_t)k * S;
+      us[k] = -1;
+      ws[k] = 0;
+      if (j < e) { us[k] = g.idx[j]; ws[k] = g.w[j]; }
+    }
+    VState os[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      os[k] = VState{0, D_NONE, 0};
+      if (us[k] >= 0) os[k] = vs[us[k]];
+    }
+    int pat[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      pat[k] = 0;
+      if (os[k].d != D_NONE && before(us[k], os[k].delta, v, me.delta, sc.tie))
+        pat[k] = ab_pattern(me.c, me.d, os[k].c, os[k].d);
+    }
+    int64_t vu[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) vu[k] = pat[k] ? g.vw[us[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (pat[k]) acc += (int64_t)pat[k] * (sc.q * ws[k] - sc.p * vu[k] * wv);
+  }
+  return acc;
 }
 
 template <int G>
@@ -585,16 +769,14 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
   counters_init(&bc);
   if (slot->skip[pass]) return;
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
-  if (gid < cnt) {
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
     const VState me = vs[v];
     if (me.d == D_NONE) {
       if (gl == 0) keep[v] = 0;
     } else {
-      const int64_t wv = g.vw[v];
-      int64_t acc = 0;
-      for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) acc += ab_edge(g, vs, sc, j, v, me, wv);
+      int64_t acc = ab_row(g, vs, sc, g.off[v], g.off[v + 1], gl, G, v, me, g.vw[v]);
       acc = sum_reduce<G>(acc);
       if (gl == 0) {
         bool k = me.delta + acc >= 0;
@@ -606,25 +788,26 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
   counters_flush(&bc, &slot->nM[pass], nullptr);
 }
 
-__global__ __launch_bounds__(BIG_BLOCK) void k_ab_blk(const int32_t* list, DevGraph g, const VState* vs, Score sc,
-                                                      uint8_t* keep, LMSlot* slot, int pass) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
+                                               Score sc, uint8_t* keep, LMSlot* slot, int pass) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot->skip[pass]) return;
-  const int32_t v = list[blockIdx.x];
-  const VState me = vs[v];
-  if (me.d == D_NONE) {
-    if (threadIdx.x == 0) keep[v] = 0;
-    return;
-  }
-  const int64_t wv = g.vw[v];
-  int64_t acc = 0;
-  for (int64_t j = g.off[v] + threadIdx.x; j < g.off[v + 1]; j += BIG_BLOCK) acc += ab_edge(g, vs, sc, j, v, me, wv);
-  acc = sum_reduce<BIG_BLOCK>(acc);
-  if (threadIdx.x == 0) {
-    bool k = me.delta + acc >= 0;
-    keep[v] = k;
-    if (k) atomicAdd(&bc.ncand, 1ull);
+  for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
+    const int32_t v = list[vi];
+    const VState me = vs[v];
+    if (me.d == D_NONE) {  // uniform over the block
+      if (threadIdx.x == 0) keep[v] = 0;
+      continue;
+    }
+    int64_t acc = ab_row(g, vs, sc, g.off[v], g.off[v + 1], threadIdx.x, BS, v, me, g.vw[v]);
+    acc = sum_reduce<BS>(acc);
+    if (threadIdx.x == 0) {
+      bool k = me.delta + acc >= 0;
+      keep[v] = k;
+      if (k) atomicAdd(&bc.ncand, 1ull);
+    }
   }
   counters_flush(&bc, &slot->nM[pass], nullptr);
 }
@@ -640,8 +823,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const
   const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   const int64_t wv = g.vw[v];
-  int64_t acc = 0;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) acc += ab_edge(g, vs, sc, j, v, me, wv);
+  int64_t acc = ab_row(g, vs, sc, j0, j1, threadIdx.x, HUB_BLOCK, v, me, wv);
   acc = sum_reduce<HUB_BLOCK>(acc);
   if (threadIdx.x == 0 && acc) atomicAdd((unsigned long long*)&hacc[k], (unsigned long long)acc);
 }
@@ -759,27 +941,26 @@ __global__ __launch_bounds__(BLOCK) void k_internal_grp(const int32_t* list, int
                                                         const int32_t* C, int64_t* out, const int32_t* skip) {
   if (skip && *skip) return;
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
   int64_t s = 0;
-  if (gid < cnt) {
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
-    const int32_t cv = C[v];
-    for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G)
-      if (C[g.idx[j]] == cv) s += g.w[j];
+    s += internal_row(g, C, g.off[v], g.off[v + 1], gl, G, C[v]);
   }
   s = sum_reduce<BLOCK>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
 }
 
-__global__ __launch_bounds__(BIG_BLOCK) void k_internal_blk(const int32_t* list, DevGraph g, const int32_t* C,
-                                                            int64_t* out, const int32_t* skip) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_internal_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
+                                                     int64_t* out, const int32_t* skip) {
   if (skip && *skip) return;
-  const int32_t v = list[blockIdx.x];
-  const int32_t cv = C[v];
   int64_t s = 0;
-  for (int64_t j = g.off[v] + threadIdx.x; j < g.off[v + 1]; j += BIG_BLOCK)
-    if (C[g.idx[j]] == cv) s += g.w[j];
-  s = sum_reduce<BIG_BLOCK>(s);
+  for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
+    const int32_t v = list[vi];
+    s += internal_row(g, C, g.off[v], g.off[v + 1], threadIdx.x, BS, C[v]);
+  }
+  s = sum_reduce<BS>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
 }
 
@@ -792,9 +973,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_internal_hub(const int32_t* hubs,
   const int32_t cv = C[v];
   const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
-  int64_t s = 0;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK)
-    if (C[g.idx[j]] == cv) s += g.w[j];
+  int64_t s = internal_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, cv);
   s = sum_reduce<HUB_BLOCK>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
 }
@@ -832,20 +1011,23 @@ __global__ void k_zero_i64(int64_t* p) {
 // Degree buckets
 // ---------------------------------------------------------------------------------------------------------
 __global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl) {
-  __shared__ unsigned long long cnt[NBUCKET];
+  __shared__ unsigned long long cnt[NBUCKET], edg[NBUCKET];
   __shared__ unsigned long long chunks;
-  if (threadIdx.x < NBUCKET) cnt[threadIdx.x] = 0;
+  if (threadIdx.x < NBUCKET) { cnt[threadIdx.x] = 0; edg[threadIdx.x] = 0; }
   if (threadIdx.x == 0) chunks = 0;
   __syncthreads();
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     int64_t d = off[v + 1] - off[v];
     int b = bucket_of(d);
     atomicAdd(&cnt[b], 1ull);
+    if (d) atomicAdd(&edg[b], (unsigned long long)d);
     if (b == NBUCKET - 1) atomicAdd(&chunks, (unsigned long long)cdiv(d, HUB_CHUNK));
   }
   __syncthreads();
   if (threadIdx.x < NBUCKET && cnt[threadIdx.x])
     atomicAdd((unsigned long long*)&ctrl->bucket_count[threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x < NBUCKET && edg[threadIdx.x])
+    atomicAdd((unsigned long long*)&ctrl->bucket_edges[threadIdx.x], edg[threadIdx.x]);
   if (threadIdx.x == 0 && chunks) atomicAdd((unsigned long long*)&ctrl->count3, chunks);
 }
 
@@ -958,19 +1140,19 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int64_t cnt, DevGraph g, int vw_mode,
                                                         const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl) {
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
   EdgeCheck ec;
-  int32_t v = -1;
-  if (gid < cnt) {
-    v = list[gid];
-    const int64_t rb = g.off[v], re = g.off[v + 1];
-    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, ec);
-  }
-  int64_t ws = sum_reduce<G>(ec.ws);
   int64_t wsum = 0;
-  if (gid < cnt && gl == 0) {
-    vw_out[v] = vertex_weight(vw_mode, ws, vw_given, v, ec.err);
-    wsum = ws;
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
+    const int32_t v = list[gid];
+    const int64_t rb = g.off[v], re = g.off[v + 1];
+    const int64_t ws0 = ec.ws;
+    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, ec);
+    int64_t ws = sum_reduce<G>(ec.ws - ws0);
+    if (gl == 0) {
+      vw_out[v] = vertex_weight(vw_mode, ws, vw_given, v, ec.err);
+      wsum += ws;
+    }
   }
   flush_check(ec, wsum, ctrl);
 }
@@ -1034,7 +1216,15 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)g;
 }
 
-inline unsigned grp_blocks(int64_t cnt, int G) { return (unsigned)cdiv(cnt, BLOCK / G); }
+// Persistent launches: workgroups loop over their share of the vertices.  Launching one short workgroup per
+// vertex (or per few vertices) is bound by the workgroup dispatch rate, not by memory.
+constexpr int64_t MAX_BLOCKS = 2048;
+inline unsigned grp_blocks(int64_t cnt, int G) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(cnt, BLOCK / G), MAX_BLOCKS));
+}
+inline unsigned vtx_blocks(int64_t cnt, int64_t cap = MAX_BLOCKS) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cnt, cap));
+}
 
 // Hub chunk scratch lives at the end of the per-chunk partial arrays.
 struct HubScratch {
@@ -1103,7 +1293,7 @@ static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* 
   if (b.count[3]) k_internal_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, out, skip);
   int64_t nw = b.count[4] + b.count[5];
   if (nw) k_internal_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, out, skip);
-  if (b.count[6]) k_internal_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, C, out, skip);
+  if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, out, skip);
   if (b.count[7]) k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, out, skip);
 }
 
@@ -1129,33 +1319,49 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   const int32_t* hubs = L + b.off[7];
   const int64_t n7 = b.count[7];
   if (singleton) {
+    double sb = 0;
+    for (int k = 0; k < NBUCKET; ++k) sb += 16.0 * (double)b.edges[k] + 48.0 * (double)b.count[k];
+    prof_begin(PF_SINGLE, st);
     if (b.count[0]) k_single_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, sc, pa, pb, vs, slot, pass);
     if (b.count[1]) k_single_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, sc, pa, pb, vs, slot, pass);
     if (b.count[2]) k_single_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, sc, pa, pb, vs, slot, pass);
     if (b.count[3]) k_single_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, sc, pa, pb, vs, slot, pass);
     int64_t nw = b.count[4] + b.count[5];
     if (nw) k_single_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, sc, pa, pb, vs, slot, pass);
-    if (b.count[6]) k_single_blk<BIG_BLOCK><<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[6]) k_single_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass);
     if (n7) {
       k_single_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, sc, hs.ps, hs.pc);
       k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, nullptr, nullptr, sc, pa, pb, 0,
                                                  hs.ps, hs.pc, nullptr, vs, slot, pass, nullptr);
     }
+    prof_end(PF_SINGLE, sb, st);
     return;
   }
-  if (b.count[0]) k_enum_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
-  if (b.count[1]) k_enum_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
-  if (b.count[2]) k_enum_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
-  if (b.count[3]) k_enum_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
-  if (b.count[4]) k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
-  if (b.count[5]) k_enum_wave<LDS_SLOTS_B5><<<grp_blocks(b.count[5], WAVE), BLOCK, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
-  if (b.count[6]) k_enum_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum);
+  int64_t* P = strict ? nullptr : bufs.pairs;  // distinct-pair counters (diagnostics), per bucket
+  auto eb = [&](int k) { return 12.0 * (double)b.edges[k] + 56.0 * (double)b.count[k]; };
+#define LCC_ENUM(k, launch)                      \
+  if (b.count[k]) {                              \
+    prof_begin(PF_ENUM_B0 + k, st);              \
+    launch;                                      \
+    prof_end(PF_ENUM_B0 + k, eb(k), st);         \
+  }
+  LCC_ENUM(0, (k_enum_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 0 : nullptr)))
+  LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 1 : nullptr)))
+  LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 2 : nullptr)))
+  LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 3 : nullptr)))
+  LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 4 : nullptr)))
+  LCC_ENUM(5, (k_enum_blk<256, LDS_SLOTS_B5><<<vtx_blocks(b.count[5]), 256, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 5 : nullptr)))
+  LCC_ENUM(6, (k_enum_blk<1024, LDS_SLOTS_B6><<<vtx_blocks(b.count[6], 512), 1024, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 6 : nullptr)))
+#undef LCC_ENUM
   if (n7) {
     unsigned nc = (unsigned)b.hub_chunks;
+    prof_begin(PF_ENUM_B0 + 7, st);
     k_hub_insert<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, bufs.arena, slot, pass);
-    k_hub_scan<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, W, sc, bufs.arena, hs.ps, hs.pc, hs.pown, slot, pass);
+    k_hub_scan<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, W, sc, bufs.arena, hs.ps, hs.pc, hs.pown, slot, pass,
+                                         P ? P + 7 : nullptr);
     k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, C, W, sc, pa, pb, strict, hs.ps,
                                                hs.pc, hs.pown, vs, slot, pass, own_sum);
+    prof_end(PF_ENUM_B0 + 7, eb(7), st);
   }
 }
 
@@ -1181,7 +1387,7 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const Score&
   if (b.count[3]) k_ab_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass);
   int64_t nw = b.count[4] + b.count[5];
   if (nw) k_ab_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vs, sc, keep, slot, pass);
-  if (b.count[6]) k_ab_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, vs, sc, keep, slot, pass);
+  if (b.count[6]) k_ab_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vs, sc, keep, slot, pass);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
     k_ab_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, vs, sc, hs.hacc, slot, pass);

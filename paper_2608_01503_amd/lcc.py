@@ -26,7 +26,15 @@ LCC_FLAG_LEVEL_CAP, LCC_FLAG_REFINE_NO_PROGRESS = 1, 2
 
 EXPORTED = ["lcc_create", "lcc_destroy", "lcc_default_options", "lcc_workspace_bytes", "lcc_cluster",
             "lcc_cluster_batch", "lcc_objective", "lcc_server_create", "lcc_submit", "lcc_poll",
-            "lcc_server_destroy", "lcc_status_string", "lcc_last_error"]
+            "lcc_server_destroy", "lcc_profile_enable", "lcc_profile_read", "lcc_status_string", "lcc_last_error"]
+
+# kernel families of lcc_profile_enable (bit = index) and the kernel each one times
+PROFILE_FAMILIES = ["enum_b0", "enum_b1", "enum_b2", "enum_b3", "enum_b4", "enum_b5", "enum_b6", "enum_b7",
+                    "single", "afterburner"]
+FAMILY_KERNELS = {"enum_b0": "k_enum_grp<4>", "enum_b1": "k_enum_grp<8>", "enum_b2": "k_enum_grp<16>",
+                  "enum_b3": "k_enum_grp<32>", "enum_b4": "k_enum_wave<256>", "enum_b5": "k_enum_blk<256, 2048>",
+                  "enum_b6": "k_enum_blk<1024, 8192>", "enum_b7": "k_hub_insert+k_hub_scan+k_hub_final",
+                  "single": "k_single_*"}
 
 
 class lcc_graph(ctypes.Structure):
@@ -48,6 +56,11 @@ class lcc_options(ctypes.Structure):
                 ("phi_den", ctypes.c_uint32 * 8), ("phi_until", ctypes.c_uint32 * 8), ("eps_num", ctypes.c_uint32),
                 ("eps_den", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("max_levels", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("trace", ctypes.POINTER(lcc_trace))]
+
+
+class lcc_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class lcc_result(ctypes.Structure):
@@ -96,6 +109,10 @@ def load():
     lib.lcc_poll.argtypes = [v, u64, P(ctypes.c_int), v, P(lcc_result)]
     lib.lcc_server_destroy.restype = st
     lib.lcc_server_destroy.argtypes = [v]
+    lib.lcc_profile_enable.restype = st
+    lib.lcc_profile_enable.argtypes = [v, u64]
+    lib.lcc_profile_read.restype = st
+    lib.lcc_profile_read.argtypes = [v, P(lcc_kernel_stat), ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32]
     lib.lcc_status_string.restype = ctypes.c_char_p
     lib.lcc_status_string.argtypes = [ctypes.c_int]
     lib.lcc_last_error.restype = ctypes.c_char_p
@@ -283,6 +300,22 @@ class Context:
         st = _stream_handle(stream, graphs[0] if graphs else None)
         _check(lib.lcc_cluster_batch(self.handle, G, L, V, k, ctypes.byref(o), st, P, R))
         return [lab[:g.n] for lab, g in zip(labels_out, graphs)], [_result(R[i]) for i in range(k)]
+
+    def profile_enable(self, families):
+        """Time the named kernel families (see PROFILE_FAMILIES) in subsequent calls; [] disables."""
+        mask = 0
+        for f in families:
+            mask |= 1 << PROFILE_FAMILIES.index(f)
+        _check(load().lcc_profile_enable(self.handle, mask))
+
+    def profile_read(self, reset: bool = False) -> dict:
+        """{family: (launches, total_ms, algorithmic_bytes)}"""
+        cap = len(PROFILE_FAMILIES)
+        arr = (lcc_kernel_stat * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(load().lcc_profile_read(self.handle, arr, cap, ctypes.byref(cnt), int(reset)))
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms), float(arr[i].bytes))
+                for i in range(min(cnt.value, cap))}
 
     def objective(self, graph: lcc_graph, labels, lam=(1, 1, True), stream=None) -> Result:
         res = lcc_result()

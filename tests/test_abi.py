@@ -29,6 +29,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(lcc.lcc_lambda) == 24
     assert ctypes.sizeof(lcc.lcc_result) == 56
     assert ctypes.sizeof(lcc.lcc_options) == 4 + 4 + 3 * 32 + 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(lcc.lcc_kernel_stat) == 32 + 8 + 8 + 8
 
 
 def test_host_only_entry_points():
