@@ -14,6 +14,7 @@ the same workload (the same generator at a smaller scale).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +42,30 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def counter_traffic(family: str, workload_name: str):
+    """HBM bytes per launch of the family's kernel, from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    committed under profiles/ (each counter scaled by what it reads for a plain 1 GiB device copy).  None when
+    there is no summary for this family and workload, or when the kernel's sources changed since the counters
+    were taken (the summary records a SHA-256 of them)."""
+    path = os.path.join(ROOT, "profiles", f"counters_{family}_{workload_name}.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#", "|")):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for f in rec["sources"].split():
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def cpu_baseline(scale: int):
     """The oracle, as it stands, on R-MAT of a smaller scale (same generator and parameters)."""
     import graphgen as gg
@@ -61,7 +86,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22")
-    ap.add_argument("--cpu-scale", type=int, default=20)
+    ap.add_argument("--cpu-scale", type=int, default=21)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--family", default="auto", help="kernel family timed live for the roofline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -122,11 +147,13 @@ def main():
     sec = (t1 - t0) / max(args.steps, 1)
     value = g.nnz / sec
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
+    traffic = counter_traffic(family, args.workload)
     roofline = {"bound": "hbm", "kernel": LL.FAMILY_KERNELS.get(family, family), "family": family,
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "launches": launches,
+                "traffic": traffic, "traffic_unit": "HBM bytes per launch", "launches": launches,
                 "avg_launch_ms": kms / launches if launches else None,
                 "bytes_per_launch": kbytes / launches if launches else None,
+                "traffic_over_algorithmic": traffic / (kbytes / launches) if traffic and launches else None,
                 "share_of_step": (kms / max(args.steps, 1)) / (sec * 1e3)}
 
     out = {
