@@ -9,6 +9,10 @@ Workload recipes (sizes follow the paper's graph families, Table 1):
   * ``sbm``     planted partition, unit weights (community structure)
   * ``rmat``    R-MAT with quadrant probabilities (a, b, c, d), multiplicity weights (skewed degrees)
   * ``lattice`` 2-D 4-neighbour grid with a fixed fraction of edges deleted, weights uniform in [1, w_max]
+  * ``knn``     k = 15 nearest-neighbour graphs of 50-D Gaussian-mixture points (geometric families), weights
+                exp(-d^2 / sigma^2) quantised to 1..1000; ``knn_batch_spec`` gives the sizes of the batched
+                workload and ``knn_graph_torch`` builds the same graphs with torch tensors on a GPU (a data tool,
+                used where brute force on the host would take hours)
 """
 from __future__ import annotations
 
@@ -55,6 +59,12 @@ def _load():
                                     ctypes.c_uint64, P64, PP64, PP32, PP32]
         lib.gen_from_pairs.restype = ctypes.c_int64
         lib.gen_from_pairs.argtypes = [ctypes.c_int64, ctypes.c_int64, P32, P32, P32, PP64, PP32, PP32]
+        lib.gen_knn_points.restype = None
+        lib.gen_knn_points.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                       ctypes.c_uint64, ctypes.POINTER(ctypes.c_int8)]
+        lib.gen_knn.restype = None
+        lib.gen_knn.argtypes = [ctypes.POINTER(ctypes.c_int8), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                P32, P64]
         lib.gen_free.restype = None
         lib.gen_free.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -170,3 +180,115 @@ def config3a_lattice() -> Graph:
 def config3b_rmat() -> Graph:
     """R-MAT scale 26, edge factor 16, same generator as the scale-22 graph, seed 4."""
     return rmat(26, 16, 0.57, 0.19, 0.19, 4)
+
+
+# k-nearest-neighbour graphs (batched workload) ----------------------------------------------------
+
+KNN_DIM = 50
+KNN_K = 15
+_GOLDEN = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def _fmix64_int(z: int) -> int:
+    z &= _M64
+    z ^= z >> 30
+    z = (z * 0xBF58476D1CE4E5B9) & _M64
+    z ^= z >> 27
+    z = (z * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def _draw(seed: int, stream: int, ctr: int) -> int:
+    key = _fmix64_int(seed ^ _fmix64_int(stream + _GOLDEN))
+    return _fmix64_int(key + (ctr + 1) * _GOLDEN)
+
+
+def knn_batch_spec(count: int = 4096, seed: int = 5, n_min: int = 500, n_max: int = 50000):
+    """(n_g, K_g) of graph g: n_g = round(exp(U[ln n_min, ln n_max])), K_g uniform in 5..40 components.
+    Draws come from the generator stream 2^32 + g of `seed` (the points use streams 2g and 2g + 1)."""
+    import math
+    out = []
+    for g in range(count):
+        u = ((_draw(seed, (1 << 32) + g, 0) >> 11) + 1) / float(1 << 53)
+        n = int(round(math.exp(math.log(n_min) + u * (math.log(n_max) - math.log(n_min)))))
+        K = 5 + _draw(seed, (1 << 32) + g, 1) % 36
+        out.append((n, int(K)))
+    return out
+
+
+def knn_points(n: int, K: int, seed: int, graph: int, dim: int = KNN_DIM) -> np.ndarray:
+    """int8[n, dim] Gaussian-mixture points on the 1/8 grid (see gen.c for the integer recipe)."""
+    lib = _load()
+    out = np.zeros((n, dim), dtype=np.int8)
+    lib.gen_knn_points(n, dim, K, seed, graph, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return out
+
+
+def knn_weights(d2: np.ndarray, sigma2: float) -> np.ndarray:
+    """clamp(floor(1000 exp(-d^2 / sigma^2) + 1/2), 1, 1000)."""
+    w = np.floor(1000.0 * np.exp(-d2.astype(np.float64) / sigma2) + 0.5)
+    return np.clip(w, 1, 1000).astype(np.int32)
+
+
+def knn_graph(n: int, K: int, seed: int, graph: int, k: int = KNN_K, dim: int = KNN_DIM) -> Graph:
+    """Exact k-NN graph on the host (brute force, for graphs up to a few tens of thousands of vertices):
+    sigma^2 = mean squared distance over the directed kNN edges, symmetrised by union with one weight per
+    pair (distances are symmetric)."""
+    lib = _load()
+    pts = knn_points(n, K, seed, graph, dim)
+    nbr = np.zeros(n * k, dtype=np.int32)
+    d2 = np.zeros(n * k, dtype=np.int64)
+    lib.gen_knn(pts.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n, dim, k,
+                nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), d2.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    sigma2 = float(d2.sum()) / float(len(d2))
+    u = np.repeat(np.arange(n, dtype=np.int64), k)
+    v = nbr.astype(np.int64)
+    a, b = np.minimum(u, v), np.maximum(u, v)
+    key, first = np.unique(a * n + b, return_index=True)
+    w = knn_weights(d2[first], sigma2)
+    pairs = np.stack([key // n, key % n], axis=1)
+    return from_pairs(n, pairs, w, name=f"knn{n}")
+
+
+def knn_graph_torch(n: int, K: int, seed: int, graph: int, device, k: int = KNN_K, dim: int = KNN_DIM,
+                    rows_per_chunk: int = 2048):
+    """The same graph as ``knn_graph``, built with torch on `device`.  Returns (off int64, idx int32, w int32)
+    device tensors.  Exact: coordinates are small integers, distances are formed in float64 (exact below
+    2^53) and neighbours are ranked by the integer key d^2 * 2^16 + index."""
+    import torch
+    pts = torch.from_numpy(knn_points(n, K, seed, graph, dim)).to(device)
+    x = pts.to(torch.float64)
+    sq = (x * x).sum(1)
+    nbrs, d2s = [], []
+    idx = torch.arange(n, device=device, dtype=torch.int64)
+    for r0 in range(0, n, rows_per_chunk):
+        r1 = min(n, r0 + rows_per_chunk)
+        D = sq[r0:r1, None] + sq[None, :] - 2.0 * (x[r0:r1] @ x.T)
+        key = D.round().to(torch.int64) * 65536 + idx[None, :]
+        key[torch.arange(r1 - r0, device=device), idx[r0:r1]] = torch.iinfo(torch.int64).max
+        top = torch.topk(key, k, dim=1, largest=False, sorted=True).values
+        nbrs.append(top & 0xFFFF)
+        d2s.append(top >> 16)
+        del D, key
+    nbr = torch.cat(nbrs).reshape(-1)
+    d2 = torch.cat(d2s).reshape(-1)
+    sigma2 = float(d2.sum().item()) / float(d2.numel())
+    u = idx.repeat_interleave(k)
+    a, b = torch.minimum(u, nbr), torch.maximum(u, nbr)
+    # both directions of every pair, one weight per pair
+    src = torch.cat([a, b])
+    dst = torch.cat([b, a])
+    dd = torch.cat([d2, d2])
+    key = src * n + dst
+    order = torch.argsort(key, stable=True)
+    key, dd = key[order], dd[order]
+    keep = torch.ones_like(key, dtype=torch.bool)
+    keep[1:] = key[1:] != key[:-1]
+    key, dd = key[keep], dd[keep]
+    w = torch.floor(1000.0 * torch.exp(-dd.to(torch.float64) / sigma2) + 0.5).clamp(1, 1000).to(torch.int32)
+    rows = key // n
+    cols = (key % n).to(torch.int32)
+    off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    off[1:] = torch.cumsum(torch.bincount(rows, minlength=n), 0)
+    return off, cols.contiguous(), w.contiguous()

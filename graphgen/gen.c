@@ -259,3 +259,74 @@ int64_t gen_from_pairs(int64_t n, int64_t m, const int32_t* pu, const int32_t* p
                        int64_t** off, int32_t** idx, int32_t** w) {
   return build_csr(n, m, pu, pv, pw, off, idx, w);
 }
+
+/* ---------------------------------------------------------------------------------------------------
+ * k-nearest-neighbour graphs of Gaussian-mixture points (the batched workload).
+ *
+ * Points live on an integer grid of 1/8 unit so that every distance is an exact integer:
+ *   normal draw  = Irwin-Hall sum of twelve 16-bit uniforms minus 6 * 65536   (unit 1/65536, sd ~ 1)
+ *   mean[c][d]   = 3 * normal(key_means, c * dim + d)                          (sd 3)
+ *   component(i) = high 32 bits of draw(key_pts, i * (3 dim + 1)) scaled to [0, K)
+ *   x[i][d]      = clamp(floor((mean + normal) / 8192 + 1/2), -127, 127)      (unit 1/8)
+ * with key_means = key(seed, 2 graph) and key_pts = key(seed, 2 graph + 1).  Only integer operations, so
+ * any implementation of this recipe gives the same points.
+ * ------------------------------------------------------------------------------------------------- */
+static inline int64_t irwin_hall12(uint64_t key, uint64_t ctr0) {
+  int64_t s = 0;
+  for (int t = 0; t < 3; ++t) {
+    uint64_t x = rdraw(key, ctr0 + (uint64_t)t);
+    s += (int64_t)(x & 0xFFFF) + (int64_t)((x >> 16) & 0xFFFF) + (int64_t)((x >> 32) & 0xFFFF) + (int64_t)(x >> 48);
+  }
+  return s - 6 * 65536;
+}
+
+void gen_knn_points(int64_t n, int32_t dim, int32_t K, uint64_t seed, uint64_t graph, int8_t* out) {
+  const uint64_t km = rkey(seed, 2 * graph), kp = rkey(seed, 2 * graph + 1);
+  int64_t* mean = (int64_t*)malloc((size_t)K * dim * sizeof(int64_t));
+  for (int64_t c = 0; c < K; ++c)
+    for (int64_t d = 0; d < dim; ++d) mean[c * dim + d] = 3 * irwin_hall12(km, 3 * (uint64_t)(c * dim + d));
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t base = (uint64_t)i * (uint64_t)(3 * dim + 1);
+    const uint64_t cx = rdraw(kp, base);
+    const int64_t c = (int64_t)(((cx >> 32) * (uint64_t)K) >> 32);
+    for (int64_t d = 0; d < dim; ++d) {
+      int64_t a = mean[c * dim + d] + irwin_hall12(kp, base + 1 + 3 * (uint64_t)d);
+      int64_t x = (a + 4096) >> 13;
+      if (x > 127) x = 127;
+      if (x < -127) x = -127;
+      out[i * dim + d] = (int8_t)x;
+    }
+  }
+  free(mean);
+}
+
+/* Exact k nearest neighbours of every point by brute force: squared distances are integers, ties go to the
+ * lower index.  nbr[i*k + t], d2[i*k + t] in ascending (distance, index) order.  Requires n > k. */
+void gen_knn(const int8_t* pts, int64_t n, int32_t dim, int32_t k, int32_t* nbr, int64_t* d2) {
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t* bd = d2 + i * k;
+    int32_t* bj = nbr + i * k;
+    int cnt = 0;
+    const int8_t* pi = pts + i * dim;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const int8_t* pj = pts + j * dim;
+      int64_t s = 0;
+      for (int d = 0; d < dim; ++d) {
+        int64_t t = (int64_t)pi[d] - pj[d];
+        s += t * t;
+      }
+      if (cnt == k && s >= bd[k - 1]) continue;  /* (s, j) is not below the current k-th: j > its index */
+      int pos = cnt < k ? cnt++ : k - 1;
+      while (pos > 0 && bd[pos - 1] > s) {
+        bd[pos] = bd[pos - 1];
+        bj[pos] = bj[pos - 1];
+        --pos;
+      }
+      bd[pos] = s;
+      bj[pos] = (int32_t)j;
+    }
+  }
+}

@@ -157,8 +157,15 @@ lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size
 lcc_status lcc_cluster(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
                        const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res);
 
-/* Cluster `count` independent graphs (each with its own lambda and variant) in one call.  Results are
- * identical to `count` separate lcc_cluster calls.  labels_out[i] and res[i] as for lcc_cluster. */
+/* Cluster `count` independent graphs (each with its own lambda, vertex-weight mode and variant) in one call.
+ * Results are identical to `count` separate lcc_cluster calls.  labels_out[i] and res[i] as for lcc_cluster.
+ * When every graph is device-resident and uses LCC_LOUVAIN or LCC_PLOUVAIN (and opts->trace is NULL), the
+ * graphs are processed together: their CSRs are concatenated into one union graph on the device and every
+ * kernel launch of a level covers all graphs still coarsening (Alg. 1 applied to the union, with each graph's
+ * own lambda, objective, best-so-far state and level count).  Otherwise the graphs run one after another.
+ * The workspace is sized for the union (sum of n, sum of nnz).  On a failure the status of the first problem
+ * found is returned and no result is written; in the fused form structural faults of any graph (CSR layout,
+ * symmetry, weights) are reported before lambda and bound problems, which are checked per graph in order. */
 lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lambdas,
                              const lcc_variant* variants, int64_t count, const lcc_options* opts, void* stream,
                              int32_t* const* labels_out, lcc_result* res);

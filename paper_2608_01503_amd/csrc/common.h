@@ -126,6 +126,38 @@ struct Score {
   int64_t tie;
 };
 
+// Several independent graphs can be clustered together as one union level: their vertex ranges are
+// concatenated (graph k owns ids [vbase[k], vbase[k+1]) at every level) and no edge joins two graphs.  Each
+// graph keeps its own lambda and tie window, and every id-dependent choice (the afterburner's hash order) uses
+// the graph-local id, so each graph's result equals the result of clustering it alone.
+// ScoreSrc gives the kernels the scoring parameters of a vertex: `s` for every vertex of a single graph, or
+// tab[gid[v]] in a union.  ownv (union only) receives each vertex's weight to its own cluster.
+struct ScoreSrc {
+  Score s{};
+  const Score* tab = nullptr;
+  const int32_t* gid = nullptr;
+  const int32_t* vbase = nullptr;
+  int64_t* ownv = nullptr;
+  __device__ __forceinline__ Score at(int32_t v) const { return tab ? tab[gid[v]] : s; }
+  __device__ __forceinline__ int32_t base(int32_t v) const { return tab ? vbase[gid[v]] : 0; }
+};
+
+// Per-graph state of a union local move (device arrays; G graphs).
+struct SegLM {
+  int32_t G = 0;
+  const Score* score = nullptr;     // [G]
+  const int32_t* gid = nullptr;     // per vertex of the level
+  const int32_t* vbase = nullptr;   // [G + 1]
+  const int64_t* sumw2 = nullptr;   // [G] sum of w(v)^2 over the graph's vertices at this level
+  int64_t* I = nullptr;             // [(MAX_PASSES + 1) * G] internal weight of state k of graph g
+  int64_t* SW2 = nullptr;           // [(MAX_PASSES + 1) * G]
+  int64_t* Nbest = nullptr;         // [G]
+  int64_t* N0 = nullptr;            // [G]
+  int32_t* copy = nullptr;          // [G] C_out <- C for this graph after the current best-so-far check
+  int64_t* ownv = nullptr;          // per vertex scratch
+  uint8_t* fl = nullptr;            // per vertex scratch (free-id flags)
+};
+
 
 // Block-level aggregation of (key -> int64 sum) in an LDS open-addressing table: many threads adding to the
 // same cluster id (a popular destination, a giant cluster) meet in LDS, and the tile is flushed to global
@@ -203,9 +235,19 @@ void offsets32_to_64(const int32_t* in, int64_t* out, int64_t n1, hipStream_t st
 
 // lm.hip: setup, buckets, local move, objective
 void launch_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* ctrl, hipStream_t st);
+// Union levels: vw_mode per graph (gmode[gid[v]]) when gmode is not null; rowsum (if not null) receives
+// every vertex's weighted degree.
 void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, const int64_t* vw_given,
-                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st);
-void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st);
+                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st, const int32_t* gid = nullptr,
+                          const int8_t* gmode = nullptr, int64_t* rowsum = nullptr);
+// Degree buckets of the vertices of a level; with gid/gact only the vertices whose graph has gact set.
+void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st,
+                    const int32_t* gid = nullptr, const uint8_t* gact = nullptr);
+// out[k] = sum of x[i] (or x[i]^2) over i in [vbase[k], vbase[k+1]), k < G
+void launch_seg_sum(const int64_t* x, int square, const int32_t* vbase, int64_t G, int64_t* out, hipStream_t st);
+// per-vertex internal weight (sum of w(u,v) over neighbours in v's cluster) into out[v]
+void launch_internal_per_vertex(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
+                                hipStream_t st);
 // chunk offsets of the hubs (n7 entries of the last bucket): chunk_off[n7+1] via cnt[n7] scratch
 void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt, int32_t* chunk_off,
                        void* temp, hipStream_t st);
@@ -229,6 +271,7 @@ struct LMBuffers {
 
 struct LMParams {
   Score sc;
+  SegLM seg;       // union of several graphs when seg.G > 0 (sc unused then)
   int pass_limit;
   uint32_t phi_num[MAX_PASSES + 1], phi_den[MAX_PASSES + 1];  // per pass (1-based)
   int64_t sum_w2;  // sum of w(v)^2 of the level
@@ -250,9 +293,15 @@ void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hi
 
 // contract.hip
 // used flags of labels -> rank (compact map) : rank[c] for c in [0, n), count at rank[n].
+// With gid/gact (a union of graphs) only the labels of the graphs with gact set count; map is -1 elsewhere.
 void launch_label_rank(const int32_t* labels, int64_t n, uint8_t* used, int32_t* rank, void* temp,
-                       hipStream_t st);
-void launch_map_labels(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map, hipStream_t st);
+                       hipStream_t st, const int32_t* gid = nullptr, const uint8_t* gact = nullptr);
+void launch_map_labels(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map, hipStream_t st,
+                       const int32_t* gid = nullptr, const uint8_t* gact = nullptr);
+// union: graph of every coarse vertex (cgid[map[v]] = gid[v]); every graph's first id after a compaction by
+// rank (vbase_c[k] = rank[vbase[k]], k <= G)
+void launch_coarse_gid(const int32_t* map, const int32_t* gid, int64_t n, int32_t* cgid, hipStream_t st);
+void launch_rebase(const int32_t* rank, const int32_t* vbase, int64_t G, int32_t* vbase_c, hipStream_t st);
 void launch_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t* cvw, hipStream_t st);
 void launch_cross_count(const DevGraph& g, const Buckets& b, const int32_t* map, int32_t* cnt,
                         hipStream_t st);
@@ -264,7 +313,11 @@ void launch_heads(const uint64_t* keys, int64_t m, uint8_t* head, hipStream_t st
 void launch_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8_t* head, const int32_t* uid,
                          int64_t m, int64_t nnzc, int64_t nc, int64_t* pref, int32_t* hstart, int32_t* ux,
                          int32_t* cidx, int32_t* cw, int64_t* coff, void* temp, hipStream_t st);
-void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st);
+// fine_C[v] = coarse_C[map[v]] where map[v] >= 0; in a union (gid set) rebased from graph gid[v]'s coarse id
+// range (vbase_c) to its fine id range (vbase_f)
+void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st,
+                    const int32_t* gid = nullptr, const int32_t* vbase_f = nullptr,
+                    const int32_t* vbase_c = nullptr);
 void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,
                        hipStream_t st);
 

@@ -32,14 +32,29 @@ __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_
   return (int)lo;
 }
 
-__global__ void k_mark_used(const int32_t* labels, int64_t n, uint8_t* used) {
+// In a union of graphs, gact (per graph, indexed through gid) restricts the labels to the graphs that go on
+// to the next level; the other graphs' vertices map to -1 and produce no coarse vertex or entry.
+__global__ void k_mark_used(const int32_t* labels, int64_t n, uint8_t* used, const int32_t* gid,
+                            const uint8_t* gact) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    used[labels[v]] = 1;
+    if (!gact || gact[gid[v]]) used[labels[v]] = 1;
 }
 
-__global__ void k_map(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map) {
+__global__ void k_map(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map, const int32_t* gid,
+                      const uint8_t* gact) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    map[v] = rank[labels[v]];
+    map[v] = (!gact || gact[gid[v]]) ? rank[labels[v]] : -1;
+}
+
+// graph of each coarse vertex, and each graph's first coarse id (vbase_c[k] = rank[vbase[k]], k <= G)
+__global__ void k_coarse_gid(const int32_t* map, const int32_t* gid, int64_t n, int32_t* cgid) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    if (map[v] >= 0) cgid[map[v]] = gid[v];
+}
+
+__global__ void k_rebase(const int32_t* rank, const int32_t* vbase, int64_t G, int32_t* vbase_c) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= G; k += (int64_t)gridDim.x * blockDim.x)
+    vbase_c[k] = rank[vbase[k]];
 }
 
 __global__ __launch_bounds__(BLOCK) void k_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n,
@@ -54,7 +69,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_vw(const int32_t* map, const i
     for (int k = threadIdx.x; k < T; k += BLOCK) {
       int64_t v = t0 + k;
       if (v >= n) break;
-      agg.add(map[v], vw[v]);
+      if (map[v] >= 0) agg.add(map[v], vw[v]);
     }
     __syncthreads();
     agg.flush(cvw);
@@ -218,27 +233,44 @@ __global__ void k_row_offsets(const int32_t* ux, int64_t nnzc, int64_t nc, int64
   }
 }
 
-__global__ void k_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    fine_C[v] = coarse_C[map[v]];
+// vertices with map -1 (graphs of a union that stopped at this level) keep their clustering.  In a union a
+// coarse label of graph k lies in k's coarse id range: it is moved to the same offset in k's fine id range.
+__global__ void k_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C,
+                          const int32_t* gid, const int32_t* vbase_f, const int32_t* vbase_c) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = map[v];
+    if (x < 0) continue;
+    int32_t c = coarse_C[x];
+    if (gid) c += vbase_f[gid[v]] - vbase_c[gid[v]];
+    fine_C[v] = c;
+  }
 }
 
 __global__ void k_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    Cc[map[v]] = rankB[B[v]];
+    if (map[v] >= 0) Cc[map[v]] = rankB[B[v]];
 }
 
 }  // namespace
 
 void launch_label_rank(const int32_t* labels, int64_t n, uint8_t* used, int32_t* rank, void* temp,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t* gid, const uint8_t* gact) {
   fill_u8(used, 0, n, st);
-  k_mark_used<<<grid_for(n), BLOCK, 0, st>>>(labels, n, used);
+  k_mark_used<<<grid_for(n), BLOCK, 0, st>>>(labels, n, used, gid, gact);
   scan_u8_i32(used, rank, n, temp, nullptr, st);
 }
 
-void launch_map_labels(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map, hipStream_t st) {
-  k_map<<<grid_for(n), BLOCK, 0, st>>>(labels, rank, n, map);
+void launch_map_labels(const int32_t* labels, const int32_t* rank, int64_t n, int32_t* map, hipStream_t st,
+                       const int32_t* gid, const uint8_t* gact) {
+  k_map<<<grid_for(n), BLOCK, 0, st>>>(labels, rank, n, map, gid, gact);
+}
+
+void launch_coarse_gid(const int32_t* map, const int32_t* gid, int64_t n, int32_t* cgid, hipStream_t st) {
+  k_coarse_gid<<<grid_for(n), BLOCK, 0, st>>>(map, gid, n, cgid);
+}
+
+void launch_rebase(const int32_t* rank, const int32_t* vbase, int64_t G, int32_t* vbase_c, hipStream_t st) {
+  k_rebase<<<grid_for(G + 1), BLOCK, 0, st>>>(rank, vbase, G, vbase_c);
 }
 
 void launch_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t* cvw, hipStream_t st) {
@@ -288,8 +320,9 @@ void launch_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8
   k_row_offsets<<<grid_for(nc + 1), BLOCK, 0, st>>>(ux, nnzc, nc, coff);
 }
 
-void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st) {
-  k_project<<<grid_for(n), BLOCK, 0, st>>>(coarse_C, map, n, fine_C);
+void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st,
+                    const int32_t* gid, const int32_t* vbase_f, const int32_t* vbase_c) {
+  k_project<<<grid_for(n), BLOCK, 0, st>>>(coarse_C, map, n, fine_C, gid, vbase_f, vbase_c);
 }
 
 void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,

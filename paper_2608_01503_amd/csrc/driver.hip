@@ -74,6 +74,7 @@ struct WS {
   int64_t *WB, *aB, *aX, *pw, *pc, *t64a, *t64b, *alt_gain;
   uint8_t *inU, *flip, *has_child, *member;
   int32_t *H, *par, *root, *tsz, *pos_of, *fail, *mpos, *alt_list;
+  int32_t* gid0;  // union of graphs: graph of every level-0 vertex
   void* scan_temp;
   void* radix_temp;
 };
@@ -112,6 +113,7 @@ size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
   w.H = c.take<int32_t>(n); w.par = c.take<int32_t>(n); w.root = c.take<int32_t>(n); w.tsz = c.take<int32_t>(n);
   w.pos_of = c.take<int32_t>(n); w.fail = c.take<int32_t>(n); w.mpos = c.take<int32_t>(n + 1);
   w.alt_list = c.take<int32_t>(n);
+  w.gid0 = c.take<int32_t>(n);
   w.scan_temp = c.take<char>((int64_t)scan_temp_bytes(M + 1));
   w.radix_temp = c.take<char>((int64_t)radix_temp_bytes(M));
   return c.off;
@@ -262,6 +264,11 @@ struct Level {
   int32_t* map = nullptr;  // fine vertex -> coarse vertex of the next level
   int32_t* C = nullptr;    // clustering of this level
   int64_t sum_w2 = 0;
+  // union of graphs: graph of every vertex, first vertex of every graph (device and host), per-graph sum w^2
+  int32_t* gid = nullptr;
+  int32_t* vbase = nullptr;
+  std::vector<int32_t> hvb;
+  int64_t* sumw2g = nullptr;
 };
 
 __global__ void k_reset_level_counters(Ctrl* c) {
@@ -300,6 +307,13 @@ struct Run {
   uint32_t flags = 0;
   uint64_t W = 0;
   uint64_t refine_calls = 0;
+  // union of G graphs (G > 0): per-graph scoring parameters and local-move statistics on the device
+  int64_t G = 0;
+  Score* d_score = nullptr;
+  int64_t *gI = nullptr, *gSW2 = nullptr, *gNbest = nullptr, *gN0 = nullptr;
+  int32_t* gcopy = nullptr;
+  uint8_t* gact = nullptr;
+  int32_t* gtmp = nullptr;
 
   Run(lcc_ctx* c, hipStream_t s) : ctx(c), st(s), w(c->w) {}
 
@@ -317,14 +331,19 @@ struct Run {
     trace.insert(trace.end(), r, r + 8);
   }
 
-  // degree buckets of a level + hub chunk offsets + vertex weight sums
-  void prepare(Level& L, int32_t* list, int32_t* hub_off) {
+  // degree buckets of a level + hub chunk offsets + vertex weight sums.  In a union, `act` restricts the
+  // buckets to the graphs with act set and `into` receives them instead of L.b.
+  void prepare(Level& L, int32_t* list, int32_t* hub_off, const uint8_t* act = nullptr, Buckets* into = nullptr) {
     const int64_t n = L.g.n;
     k_reset_level_counters<<<1, 1, 0, st>>>(w.ctrl);
-    launch_buckets(L.g.off, n, list, w.ctrl, st);
-    launch_vertex_sums(L.g.vw, n, w.ctrl, st);
+    launch_buckets(L.g.off, n, list, w.ctrl, st, G ? L.gid : nullptr, act);
+    if (!into) launch_vertex_sums(L.g.vw, n, w.ctrl, st);
+    if (G && !into) {
+      L.sumw2g = take<int64_t>(ctx, G);
+      launch_seg_sum(L.g.vw, 1, L.vbase, G, L.sumw2g, st);
+    }
     read_ctrl("buckets");
-    Buckets& b = L.b;
+    Buckets& b = into ? *into : L.b;
     b.list = list;
     for (int k = 0; k < NBUCKET; ++k) {
       b.count[k] = ctx->h_ctrl->bucket_count[k];
@@ -335,7 +354,7 @@ struct Run {
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = hub_off;
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
-    L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
+    if (!into) L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
     if (b.count[NBUCKET - 1]) launch_hub_chunks(list + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, hub_off, w.scan_temp, st);
   }
 
@@ -359,18 +378,33 @@ struct Run {
       P.phi_den[i] = o.phi_den[k];
     }
     P.sum_w2 = L.sum_w2;
+    if (G) {
+      SegLM& q = P.seg;
+      q.G = (int32_t)G;
+      q.score = d_score;
+      q.gid = L.gid;
+      q.vbase = L.vbase;
+      q.sumw2 = L.sumw2g;
+      q.I = gI;
+      q.SW2 = gSW2;
+      q.Nbest = gNbest;
+      q.N0 = gN0;
+      q.copy = gcopy;
+      q.ownv = w.t64a;
+      q.fl = w.flip;
+    }
     return P;
   }
 
   // LocalMovePasses on level l from L.C (or singletons); result in L.C.  Returns the slot used.
-  int local_move_level(int l, bool singleton, int phase) {
+  int local_move_level(int l, bool singleton, int phase, const Buckets* only = nullptr) {
     Level& L = lv[l];
     if (nslot >= NSLOT) fail(LCC_ERR_INVALID, "too many local-move calls");
     int s = nslot++;
     rec(-1, l, phase, 0, s, 0, 0, 0);  // marker: the pass records of slot s go here
     LMBuffers B = bufs();
     if (!singleton) copy_i32(w.C, L.C, L.g.n, st);
-    local_move(L.g, L.b, lm_params(L), singleton, B, w.slots + s, w.ctrl, st);
+    local_move(L.g, only ? *only : L.b, lm_params(L), singleton, B, w.slots + s, w.ctrl, st);
     copy_i32(L.C, w.Cout, L.g.n, st);
     return s;
   }
@@ -389,13 +423,39 @@ struct Run {
     return nc;
   }
 
-  // Contract level l by `labels` (rank already in w.rank, nc clusters) into a new level l+1.
-  void contract(int l, const int32_t* labels, int64_t nc) {
+  // Union: number of distinct labels of every graph of level L (labels of graph k lie in its own id range).
+  std::vector<int64_t> count_labels_seg(const int32_t* labels, const Level& L) {
+    launch_label_rank(labels, L.g.n, w.used, w.rank, w.scan_temp, st);
+    launch_rebase(w.rank, L.vbase, G, gtmp, st);
+    std::vector<int32_t> h((size_t)G + 1);
+    hip_check(hipMemcpyAsync(h.data(), gtmp, (size_t)(G + 1) * 4, hipMemcpyDeviceToHost, st), "counts");
+    sync("counts");
+    std::vector<int64_t> nc((size_t)G);
+    for (int64_t k = 0; k < G; ++k) nc[k] = h[k + 1] - h[k];
+    return nc;
+  }
+
+  // Contract level l by `labels` (rank already in w.rank, nc clusters) into a new level l+1.  In a union only
+  // the graphs with gact set go on (the rank is recomputed over their labels; nc is derived here).
+  void contract(int l, const int32_t* labels, int64_t nc, const uint8_t* gact = nullptr) {
     Level& L = lv[l];
     const int64_t n = L.g.n;
-    L.map = take<int32_t>(ctx, n);
-    launch_map_labels(labels, w.rank, n, L.map, st);
     Level N;
+    if (G) {
+      launch_label_rank(labels, n, w.used, w.rank, w.scan_temp, st, L.gid, gact);
+      N.vbase = take<int32_t>(ctx, G + 1);
+      launch_rebase(w.rank, L.vbase, G, N.vbase, st);
+      N.hvb.resize((size_t)G + 1);
+      hip_check(hipMemcpyAsync(N.hvb.data(), N.vbase, (size_t)(G + 1) * 4, hipMemcpyDeviceToHost, st), "vbase");
+      sync("vbase");
+      nc = N.hvb[G];
+    }
+    L.map = take<int32_t>(ctx, n);
+    launch_map_labels(labels, w.rank, n, L.map, st, G ? L.gid : nullptr, gact);
+    if (G) {
+      N.gid = take<int32_t>(ctx, nc);
+      launch_coarse_gid(L.map, L.gid, n, N.gid, st);
+    }
     int64_t* coff = take<int64_t>(ctx, nc + 1);
     int64_t* cvw = take<int64_t>(ctx, nc);
     fill_i64(cvw, 0, nc, st);
@@ -474,6 +534,59 @@ struct Run {
       }
     }
     return top;
+  }
+
+  // ---------------------------------------------------------------------------------------------------
+  // Alg. 1 on a union of graphs: every graph follows its own level sequence.  A graph whose local move leaves
+  // as many clusters as vertices (or that reaches the level cap) stops coarsening at that level (top[k]) and
+  // is left out of every coarser level; on the way back, level l's uncoarsening local move covers only the
+  // graphs with top[k] > l and plus[k].
+  // ---------------------------------------------------------------------------------------------------
+  int louvain_seg(const std::vector<uint8_t>& plus, std::vector<int>& top, std::vector<uint32_t>& gflags) {
+    std::vector<uint8_t> cont((size_t)G);
+    for (int64_t k = 0; k < G; ++k) cont[k] = lv[0].hvb[k + 1] > lv[0].hvb[k];
+    int l = 0;
+    for (;;) {
+      local_move_level(l, true, 0);
+      Level& L = lv[l];
+      std::vector<int64_t> nc = count_labels_seg(L.C, L);
+      bool any = false;
+      for (int64_t k = 0; k < G; ++k) {
+        if (!cont[k]) continue;
+        const int64_t nk = L.hvb[k + 1] - L.hvb[k];
+        if (nc[k] == nk) {
+          top[k] = l;
+          cont[k] = 0;
+        } else if (l + 1 >= o.max_levels) {
+          top[k] = l;
+          gflags[k] |= LCC_FLAG_LEVEL_CAP;
+          cont[k] = 0;
+        } else {
+          any = true;
+        }
+      }
+      if (!any) break;
+      hip_check(hipMemcpyAsync(gact, cont.data(), (size_t)G, hipMemcpyHostToDevice, st), "active graphs");
+      contract(l, L.C, 0, gact);
+      ++l;
+    }
+    const int T = l;
+    std::vector<uint8_t> act((size_t)G);
+    for (int k = T - 1; k >= 0; --k) {
+      Level& L = lv[k];
+      launch_project(lv[k + 1].C, L.map, L.g.n, L.C, st, L.gid, L.vbase, lv[k + 1].vbase);
+      bool any = false;
+      for (int64_t g = 0; g < G; ++g) {
+        act[g] = top[g] > k && plus[g];
+        any = any || act[g];
+      }
+      if (!any) continue;
+      hip_check(hipMemcpyAsync(gact, act.data(), (size_t)G, hipMemcpyHostToDevice, st), "active graphs");
+      Buckets only;
+      prepare(L, take<int32_t>(ctx, L.g.n), take<int32_t>(ctx, L.g.n + 1), gact, &only);
+      local_move_level(k, false, 1, &only);
+    }
+    return T;
   }
 
   // ---------------------------------------------------------------------------------------------------
@@ -699,6 +812,31 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   R.sc.tie = t < 0 ? 0 : (int64_t)t;
 }
 
+// Scoring parameters of one graph (lambda = p / q in lowest terms, tie window), or a failure status.
+lcc_status graph_score(lcc_lambda lam, unsigned __int128 W, unsigned __int128 WE, const lcc_options& o, Score* out,
+                       const char** why) {
+  if (WE >= ((unsigned __int128)1 << 32)) { *why = "total edge weight >= 2^32"; return LCC_ERR_OVERFLOW; }
+  if (lam.den == 0) { *why = "lambda denominator is zero"; return LCC_ERR_LAMBDA; }
+  unsigned __int128 P = lam.num, Q = (unsigned __int128)lam.den * (lam.over_total_weight ? W : 1);
+  if (Q == 0 || P > Q) { *why = "lambda outside [0, 1] or undefined"; return LCC_ERR_LAMBDA; }
+  if (Q >> 64) { *why = "lambda denominator >= 2^64"; return LCC_ERR_OVERFLOW; }
+  uint64_t p = (uint64_t)P, q = (uint64_t)Q;
+  if (p == 0) q = 1;
+  else { uint64_t d = gcd64(p, q); p /= d; q /= d; }
+  if ((p > 0 && W >= ((unsigned __int128)1 << 30)) ||
+      (unsigned __int128)q * WE + (unsigned __int128)p * W * W >= ((unsigned __int128)1 << 60)) {
+    *why = "q W_E + p W^2 >= 2^60";
+    return LCC_ERR_OVERFLOW;
+  }
+  out->p = (int64_t)p;
+  out->q = (int64_t)q;
+  __int128 num = (__int128)o.eps_num * q - 1;
+  __int128 den = 2 * (__int128)o.eps_den;
+  __int128 t = num >= 0 ? num / den : -1;
+  out->tie = t < 0 ? 0 : (int64_t)t;
+  return LCC_OK;
+}
+
 void fill_result(lcc_result* res, int64_t nc, __int128 N, int64_t p, int64_t q, int64_t sum_w2, uint64_t W,
                  bool modularity, int levels, uint32_t flags) {
   res->num_clusters = nc;
@@ -758,8 +896,12 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
   ctx->pool_reset();
   struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
   const int64_t n = g->n;
-  if (n == 0) {
-    fill_result(res, 0, 0, 0, 1, 0, 0, false, 0, 0);
+  if (n == 0) {  // lambda is still checked (modularity is undefined without weight); one level, no cluster
+    Score s0{};
+    const char* why = "";
+    lcc_status ls = graph_score(lam, 0, 0, R.o, &s0, &why);
+    if (ls != LCC_OK) fail(ls, why);
+    fill_result(res, 0, 0, s0.p, s0.q, 0, 0, false, 1, 0);
     if (R.o.trace) R.o.trace->count = 0;
     return LCC_OK;
   }
@@ -804,6 +946,241 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
     int64_t cnt = (int64_t)out.size() / 8;
     tr->count = cnt;
     if (tr->records) memcpy(tr->records, out.data(), (size_t)std::min(cnt, tr->capacity) * 64);
+  }
+  return LCC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Batched form: several device-resident graphs clustered in one pass over their union (Louvain / Louvain+).
+// Graph k's vertices occupy ids [vb[k], vb[k+1]) and its entries [eb[k], eb[k+1]) of the union CSR.
+// ---------------------------------------------------------------------------------------------------------
+struct GDesc {
+  const void* off;
+  const int32_t* idx;
+  const int32_t* w;
+  const int64_t* vw;
+  int64_t n, nnz, vb, eb;
+  int32_t bits, mode;
+};
+
+// largest k < G with key(k) <= x (graphs with no vertices / entries are skipped naturally)
+__device__ __forceinline__ int64_t find_graph(const GDesc* d, int64_t G, int64_t x, bool edges) {
+  int64_t lo = 0, hi = G;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((edges ? d[mid].eb : d[mid].vb) <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t off_at(const GDesc& g, int64_t i) {
+  return g.bits == 64 ? ((const int64_t*)g.off)[i] : (int64_t)((const int32_t*)g.off)[i];
+}
+
+__global__ void k_union_vertices(const GDesc* d, int64_t G, int64_t N, int64_t E, int64_t* off, int32_t* gid,
+                                 int64_t* vwg, Ctrl* ctrl) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t0 == 0) off[N] = E;
+  for (int64_t v = t0; v < N; v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = find_graph(d, G, v, false);
+    const GDesc& g = d[k];
+    const int64_t vl = v - g.vb;
+    const int64_t a = off_at(g, vl), b = off_at(g, vl + 1);
+    if (b < a || (vl == 0 && a != 0) || (vl == g.n - 1 && b != g.nnz)) atomicOr(&ctrl->err_bits, ERRB_INVALID);
+    off[v] = g.eb + a;
+    gid[v] = (int32_t)k;
+    if (g.mode == LCC_VW_GIVEN) vwg[v] = g.vw[vl];
+  }
+}
+
+__global__ void k_union_edges(const GDesc* d, int64_t G, int64_t E, int32_t* idx, int32_t* w) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = find_graph(d, G, j, true);
+    const GDesc& g = d[k];
+    const int64_t jl = j - g.eb;
+    const int32_t u = g.idx[jl];
+    idx[j] = (u >= 0 && u < g.n) ? (int32_t)(g.vb + u) : -1;  // -1 fails the row validation
+    w[j] = g.w ? g.w[jl] : 1;
+  }
+}
+
+// labels_out[k][v - vb[k]] = compact label of v within graph k
+__global__ void k_write_labels_seg(const int32_t* C, const int32_t* rank, const int32_t* gid, const int32_t* vbase,
+                                   int32_t* const* outs, int64_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k = gid[v];
+    const int32_t b = vbase[k];
+    outs[k][v - b] = rank[C[v]] - rank[b];
+  }
+}
+
+bool fusable(const lcc_graph* gs, const lcc_variant* variants, int64_t count, const lcc_options* opts) {
+  if (count < 2 || (opts && opts->trace)) return false;
+  int64_t n = 0, e = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    if (gs[i].mem != LCC_MEM_DEVICE) return false;
+    if (variants[i] != LCC_LOUVAIN && variants[i] != LCC_PLOUVAIN) return false;
+    n += gs[i].n;
+    e += gs[i].nnz;
+  }
+  return n < 2147483647LL && e < ((int64_t)1 << 40);
+}
+
+lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lams, const lcc_variant* variants,
+                               int64_t G, const lcc_options* opts, void* stream, int32_t* const* labels_out,
+                               lcc_result* res) {
+  for (int64_t i = 0; i < G; ++i) {
+    check_graph_args(&gs[i]);
+    if (gs[i].n == 0 && gs[i].nnz != 0) fail(LCC_ERR_INVALID, "a graph without vertices has entries");
+    if (gs[i].n > 0 && !labels_out[i]) fail(LCC_ERR_INVALID, "labels_out is NULL");
+    if (variants[i] < LCC_LOUVAIN || variants[i] > LCC_PLEIDEN_PLUS) fail(LCC_ERR_INVALID, "unknown variant");
+  }
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  Run R(ctx, st);
+  if (opts) R.o = *opts; else default_opts(&R.o);
+  check_opts(R.o);
+  R.o.trace = nullptr;
+  std::vector<int64_t> vb((size_t)G + 1, 0), eb((size_t)G + 1, 0);
+  for (int64_t i = 0; i < G; ++i) { vb[i + 1] = vb[i] + gs[i].n; eb[i + 1] = eb[i] + gs[i].nnz; }
+  const int64_t n = vb[G], nnz = eb[G];
+  if (n == 0) {
+    std::vector<Score> s0((size_t)G);
+    for (int64_t i = 0; i < G; ++i) {
+      const char* why = "";
+      lcc_status ls = graph_score(lams[i], 0, 0, R.o, &s0[i], &why);
+      if (ls != LCC_OK) fail(ls, std::string("graph ") + std::to_string(i) + ": " + why);
+    }
+    for (int64_t i = 0; i < G; ++i) fill_result(&res[i], 0, 0, s0[i].p, s0[i].q, 0, 0, false, 1, 0);
+    return LCC_OK;
+  }
+  ctx->ensure_ws(n, nnz);
+  ctx->pool_reset();
+  struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
+  WS& w = R.w;
+  R.G = G;
+  R.lv.reserve((size_t)R.o.max_levels + 2);
+  // per-graph device arrays
+  R.d_score = take<Score>(ctx, G);
+  R.gI = take<int64_t>(ctx, (MAX_PASSES + 1) * G);
+  R.gSW2 = take<int64_t>(ctx, (MAX_PASSES + 1) * G);
+  R.gNbest = take<int64_t>(ctx, G);
+  R.gN0 = take<int64_t>(ctx, G);
+  R.gcopy = take<int32_t>(ctx, G);
+  R.gact = take<uint8_t>(ctx, G);
+  R.gtmp = take<int32_t>(ctx, G + 1);
+  int8_t* gmode = take<int8_t>(ctx, G);
+  GDesc* d_desc = take<GDesc>(ctx, G);
+  int64_t* gW = take<int64_t>(ctx, 3 * G);  // W, W_E, sum w^2 per graph
+  std::vector<GDesc> desc((size_t)G);
+  std::vector<int8_t> hmode((size_t)G);
+  bool any_given = false;
+  for (int64_t i = 0; i < G; ++i) {
+    const lcc_graph& g = gs[i];
+    desc[i] = GDesc{g.offsets, g.indices, g.edge_w, g.vertex_w, g.n, g.nnz, vb[i], eb[i], g.offsets_bits,
+                    (int32_t)g.vw_mode};
+    hmode[i] = (int8_t)g.vw_mode;
+    any_given = any_given || g.vw_mode == LCC_VW_GIVEN;
+  }
+  hip_check(hipMemcpyAsync(d_desc, desc.data(), sizeof(GDesc) * G, hipMemcpyHostToDevice, st), "descriptors");
+  hip_check(hipMemcpyAsync(gmode, hmode.data(), (size_t)G, hipMemcpyHostToDevice, st), "modes");
+  // level 0: the union CSR in the workspace
+  Level L0;
+  L0.g.n = n;
+  L0.g.nnz = nnz;
+  L0.g.off = w.in_off;
+  L0.g.idx = w.in_idx;
+  L0.g.w = w.in_w;
+  L0.g.vw = w.vw0;
+  L0.gid = w.gid0;
+  L0.vbase = take<int32_t>(ctx, G + 1);
+  L0.hvb.resize((size_t)G + 1);
+  for (int64_t i = 0; i <= G; ++i) L0.hvb[i] = (int32_t)vb[i];
+  hip_check(hipMemcpyAsync(L0.vbase, L0.hvb.data(), (size_t)(G + 1) * 4, hipMemcpyHostToDevice, st), "vbase");
+  L0.C = take<int32_t>(ctx, n);
+  zero_bytes(w.ctrl, sizeof(Ctrl), st);
+  k_union_vertices<<<grid1(n), BLOCK, 0, st>>>(d_desc, G, n, nnz, w.in_off, w.gid0, w.in_vwg, w.ctrl);
+  if (nnz) k_union_edges<<<grid1(nnz), BLOCK, 0, st>>>(d_desc, G, nnz, w.in_idx, w.in_w);
+  R.read_ctrl("union");
+  if (ctx->h_ctrl->err_bits & ERRB_INVALID) fail(LCC_ERR_INVALID, "CSR offsets of a graph are not a valid row partition");
+  R.lv.push_back(L0);
+  Level& L = R.lv[0];
+  {
+    k_reset_level_counters<<<1, 1, 0, st>>>(w.ctrl);
+    launch_buckets(L.g.off, n, w.list0, w.ctrl, st);
+    R.read_ctrl("buckets");
+    Buckets& b = L.b;
+    b.list = w.list0;
+    for (int k = 0; k < NBUCKET; ++k) {
+      b.count[k] = ctx->h_ctrl->bucket_count[k];
+      b.off[k] = ctx->h_ctrl->bucket_off[k];
+      b.edges[k] = ctx->h_ctrl->bucket_edges[k];
+    }
+    b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
+    b.hub_chunks = ctx->h_ctrl->count3;
+    b.hub_chunk_off = w.hub_off0;
+    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    if (b.count[NBUCKET - 1])
+      launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
+  }
+  launch_validate_rows(L.g, L.b, LCC_VW_UNIT, any_given ? w.in_vwg : nullptr, w.vw0, w.ctrl, st, w.gid0, gmode,
+                       w.t64b);
+  launch_seg_sum(w.vw0, 0, L.vbase, G, gW, st);
+  launch_seg_sum(w.t64b, 0, L.vbase, G, gW + G, st);
+  L.sumw2g = gW + 2 * G;
+  launch_seg_sum(w.vw0, 1, L.vbase, G, L.sumw2g, st);
+  std::vector<int64_t> hW((size_t)(3 * G));
+  hip_check(hipMemcpyAsync(hW.data(), gW, sizeof(int64_t) * 3 * G, hipMemcpyDeviceToHost, st), "graph sums");
+  R.read_ctrl("validate rows");
+  const Ctrl& c = *ctx->h_ctrl;
+  uint32_t e = c.err_bits;
+  if (!R.o.validate) e &= ERRB_INVALID | ERRB_VW_TOO_BIG;
+  if (e & ERRB_INVALID) fail(LCC_ERR_INVALID, "neighbour index out of range in a graph of the batch");
+  if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
+  if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
+  if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
+  if (R.o.validate && c.count0 != 0) fail(LCC_ERR_NOT_SYMMETRIC, "a graph of the batch is not symmetric");
+  if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
+  std::vector<Score> sc((size_t)G);
+  for (int64_t i = 0; i < G; ++i) {
+    const char* why = "";
+    lcc_status s = graph_score(lams[i], (uint64_t)hW[i], (uint64_t)hW[G + i], R.o, &sc[i], &why);
+    if (s != LCC_OK) fail(s, std::string("graph ") + std::to_string(i) + ": " + why);
+  }
+  hip_check(hipMemcpyAsync(R.d_score, sc.data(), sizeof(Score) * G, hipMemcpyHostToDevice, st), "scores");
+  // the method
+  std::vector<uint8_t> plus((size_t)G);
+  for (int64_t i = 0; i < G; ++i) plus[i] = variants[i] == LCC_PLOUVAIN;
+  std::vector<int> top((size_t)G, 0);
+  std::vector<uint32_t> gflags((size_t)G, 0);
+  R.louvain_seg(plus, top, gflags);
+  // per-graph compact labels and exact objective (Eq. 1) on level 0
+  Level& F = R.lv[0];
+  launch_label_rank(F.C, n, w.used, w.rank, w.scan_temp, st);
+  int32_t** d_outs = take<int32_t*>(ctx, G);
+  hip_check(hipMemcpyAsync(d_outs, labels_out, sizeof(int32_t*) * G, hipMemcpyHostToDevice, st), "outputs");
+  k_write_labels_seg<<<grid1(n), BLOCK, 0, st>>>(F.C, w.rank, F.gid, F.vbase, d_outs, n);
+  launch_rebase(w.rank, F.vbase, G, R.gtmp, st);
+  launch_cluster_weights(F.C, F.g.vw, n, w.W, st);
+  launch_internal_per_vertex(F.g, F.b, F.C, w.t64a, st);
+  int64_t* gobj = take<int64_t>(ctx, 2 * G);
+  launch_seg_sum(w.t64a, 0, F.vbase, G, gobj, st);
+  launch_seg_sum(w.W, 1, F.vbase, G, gobj + G, st);
+  std::vector<int64_t> ho((size_t)(2 * G));
+  std::vector<int32_t> hr((size_t)G + 1);
+  hip_check(hipMemcpyAsync(ho.data(), gobj, sizeof(int64_t) * 2 * G, hipMemcpyDeviceToHost, st), "objective");
+  hip_check(hipMemcpyAsync(hr.data(), R.gtmp, sizeof(int32_t) * (G + 1), hipMemcpyDeviceToHost, st), "counts");
+  R.sync("batch result");
+  for (int64_t i = 0; i < G; ++i) {
+    if (gs[i].n == 0) {
+      fill_result(&res[i], 0, 0, sc[i].p, sc[i].q, 0, 0, false, 1, 0);
+      continue;
+    }
+    const __int128 N = (__int128)sc[i].q * ho[i] - (__int128)sc[i].p * (ho[G + i] - hW[2 * G + i]);
+    const bool mod = gs[i].vw_mode == LCC_VW_WEIGHTED_DEGREE && lams[i].over_total_weight;
+    fill_result(&res[i], hr[i + 1] - hr[i], N, sc[i].p, sc[i].q, hW[2 * G + i], (uint64_t)hW[i], mod, top[i] + 1,
+                gflags[i]);
   }
   return LCC_OK;
 }
@@ -900,6 +1277,9 @@ lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda
   return guarded([&]() -> lcc_status {
     if (count < 0 || (count > 0 && (!gs || !lambdas || !variants || !labels_out || !res)))
       fail(LCC_ERR_INVALID, "bad batch arguments");
+    if (!ctx) fail(LCC_ERR_INVALID, "context is NULL");
+    if (fusable(gs, variants, count, opts))
+      return cluster_batch_fused(ctx, gs, lambdas, variants, count, opts, stream, labels_out, res);
     for (int64_t i = 0; i < count; ++i) {
       lcc_status s = cluster_impl(ctx, &gs[i], lambdas[i], variants[i], opts, stream, labels_out[i], &res[i], nullptr);
       if (s != LCC_OK) return s;

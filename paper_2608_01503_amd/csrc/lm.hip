@@ -125,7 +125,8 @@ __device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* ncand
 
 __device__ __forceinline__ void finish_vertex(int32_t v, int32_t cv, int64_t wv, int64_t own, int64_t sbest,
                                               int32_t cbest, const Score& sc, const int64_t* W, uint32_t pa,
-                                              uint32_t pb, int strict, VState* vs, BlockCounters* bc) {
+                                              uint32_t pb, int strict, VState* vs, BlockCounters* bc,
+                                              int64_t* ownv) {
   int64_t scur = sc.q * own - sc.p * wv * (W[cv] - wv);
   Verdict vd = decide(scur, sbest, cbest, pa, pb, strict);
   VState o;
@@ -135,6 +136,7 @@ __device__ __forceinline__ void finish_vertex(int32_t v, int32_t cv, int64_t wv,
   vs[v] = o;
   if (vd.cand) atomicAdd(&bc->ncand, 1ull);
   if (own) atomicAdd(&bc->own, (unsigned long long)own);
+  if (ownv) ownv[v] = own;
 }
 
 __device__ __forceinline__ uint32_t hslot(int32_t c, int bits) {
@@ -389,7 +391,7 @@ __global__ void k_final_state(LMSlot* s, int last) {
 // Singleton pass (first coarsening pass, Sec. IV-A: clusters are the vertices, no enumeration)
 // ---------------------------------------------------------------------------------------------------------
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64_t cnt, DevGraph g, Score sc,
+__global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64_t cnt, DevGraph g, ScoreSrc ss,
                                                       uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot,
                                                       int pass) {
   __shared__ BlockCounters bc;
@@ -399,26 +401,28 @@ __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64
        gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
     const int64_t wv = g.vw[v];
+    const Score sc = ss.at(v);
     Best r = best_init();
     single_row(g, sc, g.off[v], g.off[v + 1], gl, G, wv, r);
     best_reduce<G>(r);
-    if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc);
+    if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
   }
   counters_flush(&bc, &slot->nL[pass], nullptr);
 }
 
 template <int G>
-__global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t cnt, DevGraph g, Score sc,
+__global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t cnt, DevGraph g, ScoreSrc ss,
                                                   uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot, int pass) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
     const int64_t wv = g.vw[v];
+    const Score sc = ss.at(v);
     Best r = best_init();
     single_row(g, sc, g.off[v], g.off[v + 1], threadIdx.x, G, wv, r);
     best_reduce<G>(r);
-    if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc);
+    if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
     __syncthreads();
   }
   counters_flush(&bc, &slot->nL[pass], nullptr);
@@ -426,10 +430,11 @@ __global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t c
 
 // Hub chunk of the singleton pass: partial argmax per chunk.
 __global__ __launch_bounds__(HUB_BLOCK) void k_single_hub(const int32_t* hubs, const int32_t* chunk_off,
-                                                          int64_t n7, DevGraph g, Score sc, int64_t* ps,
+                                                          int64_t n7, DevGraph g, ScoreSrc ss, int64_t* ps,
                                                           int32_t* pc) {
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
+  const Score sc = ss.at(v);
   const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   const int64_t wv = g.vw[v];
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_single_hub(const int32_t* hubs, c
 // degree <= G: lane l holds neighbour l; clusters aggregated by an all-pairs shuffle sweep of the group.
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t cnt, DevGraph g,
-                                                    const int32_t* C, const int64_t* W, Score sc, uint32_t pa,
+                                                    const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
                                                     uint32_t pb, int strict, VState* vs, LMSlot* slot, int pass,
                                                     int64_t* own_sum, int64_t* pairs) {
   __shared__ BlockCounters bc;
@@ -465,6 +470,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
     const int d = (int)(g.off[v + 1] - b);
     const int32_t cv = C[v];
     const int64_t wv = g.vw[v];
+    const Score sc = ss.at(v);
     const bool has = gl < d;
     const int32_t c = has ? C[g.idx[b + gl]] : -1;
     const int64_t wt = has ? (int64_t)g.w[b + gl] : 0;
@@ -489,7 +495,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
     }
     argmax_reduce<G>(bs, bcl);
     own = sum_reduce<G>(own);
-    if (gl == 0) finish_vertex(v, cv, wv, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc);
+    if (gl == 0) finish_vertex(v, cv, wv, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
   }
   counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
 }
@@ -497,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
 // One wavefront per vertex, LDS open-addressing hash of capacity pow2ceil(2 d) <= SLOTS.
 template <int SLOTS>
 __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_t cnt, DevGraph g,
-                                                     const int32_t* C, const int64_t* W, Score sc, uint32_t pa,
+                                                     const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
                                                      uint32_t pb, int strict, VState* vs, LMSlot* slot,
                                                      int pass, int64_t* own_sum, int64_t* pairs) {
   __shared__ int32_t hk[BLOCK / WAVE][SLOTS];
@@ -527,12 +533,13 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
     if (active) own_reg = insert_row(g, C, b, e, lane, WAVE, cv, hk[wv], hv[wv], bits);
     __syncthreads();
     if (active) {
+      const Score sc = ss.at(v);
       Best r = best_init();
       scan_table(hk[wv], hv[wv], 1 << bits, lane, WAVE, cv, wvt, W, sc, r);
       r.own += own_reg;
       best_reduce<WAVE>(r);
       if (lane == 0) {
-        finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc);
+        finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
         if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
       }
     }
@@ -544,7 +551,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
 // One workgroup of BS threads per vertex sharing an LDS hash of capacity pow2ceil(2 d) <= SLOTS.
 template <int BS, int SLOTS>
 __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
-                                                 const int64_t* W, Score sc, uint32_t pa, uint32_t pb,
+                                                 const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb,
                                                  int strict, VState* vs, LMSlot* slot, int pass,
                                                  int64_t* own_sum, int64_t* pairs) {
   __shared__ int32_t hk[SLOTS];
@@ -563,12 +570,13 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
     __syncthreads();
     const int64_t own_reg = insert_row(g, C, b, e, threadIdx.x, BS, cv, hk, hv, bits);
     __syncthreads();
+    const Score sc = ss.at(v);
     Best r = best_init();
     scan_table(hk, hv, 1 << bits, threadIdx.x, BS, cv, wvt, W, sc, r);
     r.own += own_reg;
     best_reduce<BS>(r);
     if (threadIdx.x == 0) {
-      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc);
+      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
       if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
     }
     __syncthreads();
@@ -635,12 +643,13 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, c
 // Scan this chunk's share of the table: partial best and own weight; clears the slots for the next pass.
 __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, const int32_t* chunk_off,
                                                         int64_t n7, DevGraph g, const int32_t* C,
-                                                        const int64_t* W, Score sc, uint32_t* arena,
+                                                        const int64_t* W, ScoreSrc ss, uint32_t* arena,
                                                         int64_t* ps, int32_t* pc, int64_t* pown,
                                                         const LMSlot* slot, int pass, int64_t* pairs) {
   if (slot && slot->skip[pass]) return;
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
+  const Score sc = ss.at(v);
   const int32_t cv = C[v];
   const int64_t wvt = g.vw[v];
   const int64_t s0 = 2 * (g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK);
@@ -670,7 +679,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
 
 // Combine the chunks of each hub (pown may be null: singleton pass).
 __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64_t n7, const int64_t* vw,
-                            const int32_t* C, const int64_t* W, Score sc, uint32_t pa, uint32_t pb, int strict,
+                            const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb, int strict,
                             const int64_t* ps, const int32_t* pc, const int64_t* pown, VState* vs,
                             LMSlot* slot, int pass, int64_t* own_sum) {
   __shared__ BlockCounters bc;
@@ -686,7 +695,7 @@ __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64
       if (pown) own += pown[ch];
     }
     int32_t cv = C ? C[v] : v;
-    finish_vertex(v, cv, vw[v], own, bs, bcl, sc, C ? W : vw, pa, pb, strict, vs, &bc);
+    finish_vertex(v, cv, vw[v], own, bs, bcl, ss.at(v), C ? W : vw, pa, pb, strict, vs, &bc, ss.ownv);
   }
   counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
 }
@@ -696,6 +705,7 @@ __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64
 // by +-q w'(u,v); v is kept when the adjusted delta is >= 0.  Order: larger delta first; deltas within the
 // tie window are ordered by the splitmix64 hash of the vertex id.
 // ---------------------------------------------------------------------------------------------------------
+// u and v are graph-local ids (the level id minus the graph's first id in a union of graphs).
 __device__ __forceinline__ bool before(int32_t u, int64_t du, int32_t v, int64_t dv, int64_t tie) {
   int64_t diff = du - dv;
   int64_t ad = diff < 0 ? -diff : diff;
@@ -726,8 +736,9 @@ __device__ __forceinline__ int ab_pattern(int32_t cv, int32_t dv, int32_t cu, in
 }
 
 // sum of the adjustments of candidate v over the edges b + t, b + t + S, ... < e
-__device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, const Score& sc, int64_t b,
-                                          int64_t e, int t, int S, int32_t v, const VState& me, int64_t wv) {
+__device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, const Score& sc, int32_t base,
+                                          int64_t b, int64_t e, int t, int S, int32_t v, const VState& me,
+                                          int64_t wv) {
   int64_t acc = 0;
   for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
     int32_t us[U];
@@ -749,7 +760,7 @@ __device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, c
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       pat[k] = 0;
-      if (os[k].d != D_NONE && before(us[k], os[k].delta, v, me.delta, sc.tie))
+      if (os[k].d != D_NONE && before(us[k] - base, os[k].delta, v - base, me.delta, sc.tie))
         pat[k] = ab_pattern(me.c, me.d, os[k].c, os[k].d);
     }
     int64_t vu[U];
@@ -764,7 +775,7 @@ __device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, c
 
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
-                                                  Score sc, uint8_t* keep, LMSlot* slot, int pass) {
+                                                  ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot->skip[pass]) return;
@@ -776,7 +787,7 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
     if (me.d == D_NONE) {
       if (gl == 0) keep[v] = 0;
     } else {
-      int64_t acc = ab_row(g, vs, sc, g.off[v], g.off[v + 1], gl, G, v, me, g.vw[v]);
+      int64_t acc = ab_row(g, vs, ss.at(v), ss.base(v), g.off[v], g.off[v + 1], gl, G, v, me, g.vw[v]);
       acc = sum_reduce<G>(acc);
       if (gl == 0) {
         bool k = me.delta + acc >= 0;
@@ -790,7 +801,7 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
-                                               Score sc, uint8_t* keep, LMSlot* slot, int pass) {
+                                               ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot->skip[pass]) return;
@@ -801,7 +812,7 @@ __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt,
       if (threadIdx.x == 0) keep[v] = 0;
       continue;
     }
-    int64_t acc = ab_row(g, vs, sc, g.off[v], g.off[v + 1], threadIdx.x, BS, v, me, g.vw[v]);
+    int64_t acc = ab_row(g, vs, ss.at(v), ss.base(v), g.off[v], g.off[v + 1], threadIdx.x, BS, v, me, g.vw[v]);
     acc = sum_reduce<BS>(acc);
     if (threadIdx.x == 0) {
       bool k = me.delta + acc >= 0;
@@ -813,7 +824,7 @@ __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt,
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
-                                                      DevGraph g, const VState* vs, Score sc, int64_t* hacc,
+                                                      DevGraph g, const VState* vs, ScoreSrc ss, int64_t* hacc,
                                                       const LMSlot* slot, int pass) {
   if (slot->skip[pass]) return;
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
@@ -823,7 +834,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const
   const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   const int64_t wv = g.vw[v];
-  int64_t acc = ab_row(g, vs, sc, j0, j1, threadIdx.x, HUB_BLOCK, v, me, wv);
+  int64_t acc = ab_row(g, vs, ss.at(v), ss.base(v), j0, j1, threadIdx.x, HUB_BLOCK, v, me, wv);
   acc = sum_reduce<HUB_BLOCK>(acc);
   if (threadIdx.x == 0 && acc) atomicAdd((unsigned long long*)&hacc[k], (unsigned long long)acc);
 }
@@ -936,37 +947,53 @@ __global__ void k_sw2(const int64_t* W, int64_t n, int64_t* out, const LMSlot* s
 // ---------------------------------------------------------------------------------------------------------
 // Objective: ordered internal edge weight I(C) = sum over edges (u,v) with C[u] = C[v] of w(u,v)
 // ---------------------------------------------------------------------------------------------------------
+// out: one total over all rows (atomic), or per_v[v] per row when per_v is not null
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_internal_grp(const int32_t* list, int64_t cnt, DevGraph g,
-                                                        const int32_t* C, int64_t* out, const int32_t* skip) {
+                                                        const int32_t* C, int64_t* out, const int32_t* skip,
+                                                        int64_t* per_v) {
   if (skip && *skip) return;
   const int gl = threadIdx.x % G;
   int64_t s = 0;
   for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
        gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
-    s += internal_row(g, C, g.off[v], g.off[v + 1], gl, G, C[v]);
+    int64_t x = internal_row(g, C, g.off[v], g.off[v + 1], gl, G, C[v]);
+    if (per_v) {
+      x = sum_reduce<G>(x);
+      if (gl == 0) per_v[v] = x;
+    } else {
+      s += x;
+    }
   }
+  if (per_v) return;
   s = sum_reduce<BLOCK>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
 }
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_internal_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
-                                                     int64_t* out, const int32_t* skip) {
+                                                     int64_t* out, const int32_t* skip, int64_t* per_v) {
   if (skip && *skip) return;
   int64_t s = 0;
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
-    s += internal_row(g, C, g.off[v], g.off[v + 1], threadIdx.x, BS, C[v]);
+    int64_t x = internal_row(g, C, g.off[v], g.off[v + 1], threadIdx.x, BS, C[v]);
+    if (per_v) {
+      x = sum_reduce<BS>(x);
+      if (threadIdx.x == 0) per_v[v] = x;
+    } else {
+      s += x;
+    }
   }
+  if (per_v) return;
   s = sum_reduce<BS>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_internal_hub(const int32_t* hubs, const int32_t* chunk_off,
                                                             int64_t n7, DevGraph g, const int32_t* C, int64_t* out,
-                                                            const int32_t* skip) {
+                                                            const int32_t* skip, int64_t* per_v) {
   if (skip && *skip) return;
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
@@ -975,7 +1002,77 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_internal_hub(const int32_t* hubs,
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   int64_t s = internal_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, cv);
   s = sum_reduce<HUB_BLOCK>(s);
-  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)(per_v ? &per_v[v] : out), (unsigned long long)s);
+}
+
+// per_v[hubs[k]] = 0 before the hub chunks add into it
+__global__ void k_zero_listed(const int32_t* list, int64_t cnt, int64_t* per_v, const int32_t* skip) {
+  if (skip && *skip) return;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += (int64_t)gridDim.x * blockDim.x)
+    per_v[list[k]] = 0;
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Union of graphs: per-graph sums and the per-graph best-so-far decision
+// ---------------------------------------------------------------------------------------------------------
+
+// out[k] = sum of x[i] (square: x[i]^2) over i in [vbase[k], vbase[k+1]); one workgroup per graph.  When pass
+// `pass` repeats the previous one (slot->skip), the previous state's sums are copied from prev instead.
+__global__ __launch_bounds__(BLOCK) void k_seg_sum(const int64_t* x, int square, const int32_t* vbase, int64_t G,
+                                                   int64_t* out, const int64_t* prev, const LMSlot* slot,
+                                                   int pass) {
+  const bool skip = slot && pass >= 0 && slot->skip[pass];
+  for (int64_t k = blockIdx.x; k < G; k += gridDim.x) {
+    if (skip) {
+      if (threadIdx.x == 0) out[k] = prev[k];
+      continue;
+    }
+    int64_t s = 0;
+    for (int64_t i = (int64_t)vbase[k] + threadIdx.x; i < vbase[k + 1]; i += BLOCK) {
+      int64_t v = x[i];
+      s += square ? v * v : v;
+    }
+    s = sum_reduce<BLOCK>(s);
+    if (threadIdx.x == 0) out[k] = s;
+  }
+}
+
+// Best-so-far check of state k for every graph (Alg. 2: C_out <- C when the graph's objective improves).
+__global__ void k_best_seg(SegLM sg, const LMSlot* slot, int k, int skipk) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < sg.G; g += (int64_t)gridDim.x * blockDim.x) {
+    sg.copy[g] = 0;
+    if (skipk >= 0 && slot->skip[skipk]) continue;
+    const Score sc = sg.score[g];
+    const int64_t N = sc.q * sg.I[(int64_t)k * sg.G + g] - sc.p * (sg.SW2[(int64_t)k * sg.G + g] - sg.sumw2[g]);
+    if (k == 0) {
+      sg.N0[g] = N;
+      sg.Nbest[g] = N;
+    } else if (N > sg.Nbest[g]) {
+      sg.Nbest[g] = N;
+      sg.copy[g] = 1;
+    }
+  }
+}
+
+__global__ void k_copy_if_seg(const int32_t* copy, const int32_t* gid, const int32_t* C, int32_t* Cout, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (copy[gid[i]]) Cout[i] = C[i];
+}
+
+// Movers to a new singleton in a union: the i-th mover of graph k (ascending id) takes the i-th free id of
+// graph k; both lists are ascending over the whole union and each graph's share is a contiguous run.
+__global__ void k_assign_empty_seg(int64_t n, const uint8_t* empty, const int32_t* rank_free,
+                                   const int32_t* rank_mv, const int32_t* freelist, const int32_t* gid,
+                                   const int32_t* vbase, const int64_t* vw, int32_t* C, int64_t* W,
+                                   const LMSlot* slot) {
+  if (slot->n_empty == 0) return;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    if (!empty[v]) continue;
+    const int32_t b = vbase[gid[v]];
+    const int32_t c = freelist[rank_free[b] + (rank_mv[v] - rank_mv[b])];
+    C[v] = c;
+    W[c] = vw[v];
+  }
 }
 
 __global__ __launch_bounds__(BLOCK) void k_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n,
@@ -1010,13 +1107,14 @@ __global__ void k_zero_i64(int64_t* p) {
 // ---------------------------------------------------------------------------------------------------------
 // Degree buckets
 // ---------------------------------------------------------------------------------------------------------
-__global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl) {
+__global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl, const int32_t* gid, const uint8_t* gact) {
   __shared__ unsigned long long cnt[NBUCKET], edg[NBUCKET];
   __shared__ unsigned long long chunks;
   if (threadIdx.x < NBUCKET) { cnt[threadIdx.x] = 0; edg[threadIdx.x] = 0; }
   if (threadIdx.x == 0) chunks = 0;
   __syncthreads();
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    if (gact && !gact[gid[v]]) continue;
     int64_t d = off[v + 1] - off[v];
     int b = bucket_of(d);
     atomicAdd(&cnt[b], 1ull);
@@ -1045,7 +1143,7 @@ __global__ void k_bucket_offsets(Ctrl* ctrl) {
 // Bucket lists: per workgroup tile, LDS counts per bucket, one global atomic per bucket, positions inside
 // the tile from LDS atomics (the order inside a bucket does not affect any result).
 __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(const int64_t* off, int64_t n, int32_t* list,
-                                                          Ctrl* ctrl) {
+                                                          Ctrl* ctrl, const int32_t* gid, const uint8_t* gact) {
   __shared__ uint32_t cnt[NBUCKET];
   __shared__ int64_t base[NBUCKET];
   constexpr int T = 4 * BLOCK;
@@ -1057,7 +1155,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(const int64_t* off, in
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       int64_t v = t0 + k * BLOCK + threadIdx.x;
-      b[k] = v < n ? bucket_of(off[v + 1] - off[v]) : -1;
+      b[k] = (v < n && (!gact || gact[gid[v]])) ? bucket_of(off[v + 1] - off[v]) : -1;
       if (b[k] >= 0) r[k] = atomicAdd(&cnt[b[k]], 1u);
     }
     __syncthreads();
@@ -1115,6 +1213,15 @@ __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t
   ec.f1 += fp_h((uint32_t)v, (uint32_t)u, (uint32_t)wt) - fp_h((uint32_t)u, (uint32_t)v, (uint32_t)wt);
 }
 
+// vertex-weight mode of a vertex (per graph in a union), and the optional per-vertex weighted-degree output
+struct VwSrc {
+  int mode;
+  const int32_t* gid;
+  const int8_t* gmode;
+  int64_t* rowsum;
+  __device__ __forceinline__ int at(int32_t v) const { return gmode ? (int)gmode[gid[v]] : mode; }
+};
+
 __device__ __forceinline__ int64_t vertex_weight(int vw_mode, int64_t ws, const int64_t* vw_given, int32_t v,
                                                  uint32_t& err) {
   if (vw_mode == 1) return ws;
@@ -1137,7 +1244,7 @@ __device__ __forceinline__ void flush_check(EdgeCheck ec, int64_t wsum, Ctrl* ct
 }
 
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int64_t cnt, DevGraph g, int vw_mode,
+__global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int64_t cnt, DevGraph g, VwSrc vm,
                                                         const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl) {
   const int gl = threadIdx.x % G;
   EdgeCheck ec;
@@ -1150,22 +1257,31 @@ __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int
     for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, ec);
     int64_t ws = sum_reduce<G>(ec.ws - ws0);
     if (gl == 0) {
-      vw_out[v] = vertex_weight(vw_mode, ws, vw_given, v, ec.err);
+      vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
+      if (vm.rowsum) vm.rowsum[v] = ws;
       wsum += ws;
     }
   }
   flush_check(ec, wsum, ctrl);
 }
 
-__global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list, DevGraph g, int vw_mode,
+__global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list, int64_t cnt, DevGraph g, VwSrc vm,
                                                             const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl) {
-  const int32_t v = list[blockIdx.x];
-  const int64_t rb = g.off[v], re = g.off[v + 1];
   EdgeCheck ec;
-  for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, ec);
-  int64_t ws = sum_reduce<BIG_BLOCK>(ec.ws);
-  if (threadIdx.x == 0) vw_out[v] = vertex_weight(vw_mode, ws, vw_given, v, ec.err);
-  flush_check(ec, threadIdx.x == 0 ? ws : 0, ctrl);
+  int64_t wsum = 0;
+  for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
+    const int32_t v = list[vi];
+    const int64_t rb = g.off[v], re = g.off[v + 1];
+    const int64_t ws0 = ec.ws;
+    for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, ec);
+    int64_t ws = sum_reduce<BIG_BLOCK>(ec.ws - ws0);
+    if (threadIdx.x == 0) {
+      vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
+      if (vm.rowsum) vm.rowsum[v] = ws;
+      wsum += ws;
+    }
+  }
+  flush_check(ec, wsum, ctrl);
 }
 
 // hubs: chunk sums of the weighted degree land in hsum[k] (zeroed beforehand)
@@ -1183,13 +1299,14 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_validate_hub(const int32_t* hubs,
   flush_check(ec, threadIdx.x == 0 ? ws : 0, ctrl);
 }
 
-__global__ void k_validate_hub_final(const int32_t* hubs, int64_t n7, int vw_mode, const int64_t* vw_given,
+__global__ void k_validate_hub_final(const int32_t* hubs, int64_t n7, VwSrc vm, const int64_t* vw_given,
                                      int64_t* hsum, int64_t* vw_out, Ctrl* ctrl) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n7) return;
   int32_t v = hubs[k];
   uint32_t err = 0;
-  vw_out[v] = vertex_weight(vw_mode, hsum[k], vw_given, v, err);
+  vw_out[v] = vertex_weight(vm.at(v), hsum[k], vw_given, v, err);
+  if (vm.rowsum) vm.rowsum[v] = hsum[k];
   hsum[k] = 0;
   if (err) atomicOr(&ctrl->err_bits, err);
 }
@@ -1245,27 +1362,30 @@ void launch_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* c
 }
 
 void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, const int64_t* vw_given,
-                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st) {
+                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st, const int32_t* gid, const int8_t* gmode,
+                          int64_t* rowsum) {
   const int32_t* L = b.list;
-  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vw_mode, vw_given, vw_out, ctrl);
-  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vw_mode, vw_given, vw_out, ctrl);
-  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vw_mode, vw_given, vw_out, ctrl);
-  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vw_mode, vw_given, vw_out, ctrl);
+  const VwSrc vm{vw_mode, gid, gmode, rowsum};
+  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vm, vw_given, vw_out, ctrl);
+  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vm, vw_given, vw_out, ctrl);
+  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vm, vw_given, vw_out, ctrl);
+  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vm, vw_given, vw_out, ctrl);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_validate_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vw_mode, vw_given, vw_out, ctrl);
-  if (b.count[6]) k_validate_blk<<<(unsigned)b.count[6], BIG_BLOCK, 0, st>>>(L + b.off[6], g, vw_mode, vw_given, vw_out, ctrl);
+  if (nw) k_validate_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vm, vw_given, vw_out, ctrl);
+  if (b.count[6]) k_validate_blk<<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vm, vw_given, vw_out, ctrl);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
     fill_i64(b.hub_acc, 0, b.count[7], st);
     k_validate_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, b.hub_acc, ctrl);
-    k_validate_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vw_mode, vw_given, b.hub_acc, vw_out, ctrl);
+    k_validate_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vm, vw_given, b.hub_acc, vw_out, ctrl);
   }
 }
 
-void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st) {
-  k_bucket_count<<<grid_for(n), BLOCK, 0, st>>>(off, n, ctrl);
+void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st, const int32_t* gid,
+                    const uint8_t* gact) {
+  k_bucket_count<<<grid_for(n), BLOCK, 0, st>>>(off, n, ctrl, gid, gact);
   k_bucket_offsets<<<1, 1, 0, st>>>(ctrl);
-  k_bucket_scatter<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4 * BLOCK), 8192)), BLOCK, 0, st>>>(off, n, list, ctrl);
+  k_bucket_scatter<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4 * BLOCK), 8192)), BLOCK, 0, st>>>(off, n, list, ctrl, gid, gact);
 }
 
 void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt, int32_t* chunk_off,
@@ -1285,16 +1405,30 @@ void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int6
 }
 
 static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
-                            const int32_t* skip, hipStream_t st) {
+                            const int32_t* skip, hipStream_t st, int64_t* per_v = nullptr) {
   const int32_t* L = b.list;
-  if (b.count[0]) k_internal_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, out, skip);
-  if (b.count[1]) k_internal_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, out, skip);
-  if (b.count[2]) k_internal_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, out, skip);
-  if (b.count[3]) k_internal_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, out, skip);
+  if (b.count[0]) k_internal_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, out, skip, per_v);
+  if (b.count[1]) k_internal_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, out, skip, per_v);
+  if (b.count[2]) k_internal_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, out, skip, per_v);
+  if (b.count[3]) k_internal_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, out, skip, per_v);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_internal_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, out, skip);
-  if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, out, skip);
-  if (b.count[7]) k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, out, skip);
+  if (nw) k_internal_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, out, skip, per_v);
+  if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, out, skip, per_v);
+  if (b.count[7]) {
+    if (per_v) k_zero_listed<<<grid_for(b.count[7]), BLOCK, 0, st>>>(L + b.off[7], b.count[7], per_v, skip);
+    k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, out, skip, per_v);
+  }
+}
+
+void launch_internal_per_vertex(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
+                                hipStream_t st) {
+  launch_internal(g, b, C, nullptr, nullptr, st, out);
+}
+
+static unsigned seg_blocks(int64_t G) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(G, MAX_BLOCKS)); }
+
+void launch_seg_sum(const int64_t* x, int square, const int32_t* vbase, int64_t G, int64_t* out, hipStream_t st) {
+  if (G > 0) k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(x, square, vbase, G, out, nullptr, nullptr, -1);
 }
 
 void launch_objective(const DevGraph& g, const Buckets& b, const int32_t* C, const int64_t* W, Ctrl* ctrl,
@@ -1309,7 +1443,7 @@ static const int32_t* L_hubs(const Buckets& b);
 static HubScratch hub_scratch(const Buckets& b);
 
 // One pass of destinations + candidacy.  singleton: first coarsening pass (C = identity).
-static void launch_destinations(const DevGraph& g, const Buckets& b, const Score& sc, uint32_t pa, uint32_t pb,
+static void launch_destinations(const DevGraph& g, const Buckets& b, const ScoreSrc& sc, uint32_t pa, uint32_t pb,
                                 int strict, bool singleton, LMBuffers& bufs, LMSlot* slot, int pass,
                                 int64_t* own_sum, const HubScratch& hs, hipStream_t st) {
   const int32_t* L = b.list;
@@ -1376,7 +1510,7 @@ static HubScratch hub_scratch(const Buckets& b) {
   return hs;
 }
 
-static void launch_afterburner(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
+static void launch_afterburner(const DevGraph& g, const Buckets& b, const ScoreSrc& sc, LMBuffers& bufs,
                                LMSlot* slot, int pass, const HubScratch& hs, hipStream_t st) {
   const int32_t* L = b.list;
   const VState* vs = bufs.vs;
@@ -1395,19 +1529,49 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const Score&
   }
 }
 
-static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, int pass, hipStream_t st) {
+static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, const SegLM& sg, LMSlot* slot, int pass,
+                            hipStream_t st) {
   const int64_t n = g.n;
   unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 4096));
   k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass);
   // free ids and ranks of the movers to a new singleton; all no-ops unless some vertex moved to a new
-  // singleton in this pass
-  k_free_init<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, slot);
-  k_free_mark<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.C, bufs.empty, bufs.keep, slot);
-  scan_u8_i32(bufs.keep, bufs.scan_a, n, bufs.scan_temp, &slot->n_empty, st);
-  k_free_list<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, bufs.freelist, slot);
+  // singleton in this pass.  A single graph reuses keep as the free-id flags; a union keeps keep intact (only
+  // the listed vertices rewrite it) and uses its own flags.
+  uint8_t* fl = sg.G ? sg.fl : bufs.keep;
+  k_free_init<<<grid_for(n), BLOCK, 0, st>>>(n, fl, slot);
+  k_free_mark<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.C, bufs.empty, fl, slot);
+  scan_u8_i32(fl, bufs.scan_a, n, bufs.scan_temp, &slot->n_empty, st);
+  k_free_list<<<grid_for(n), BLOCK, 0, st>>>(n, fl, bufs.scan_a, bufs.freelist, slot);
   scan_u8_i32(bufs.empty, bufs.scan_b, n, bufs.scan_temp, &slot->n_empty, st);
-  k_assign_empty<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_b, bufs.freelist, g.vw, bufs.C, bufs.W,
-                                               slot);
+  if (sg.G)
+    k_assign_empty_seg<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_a, bufs.scan_b, bufs.freelist, sg.gid,
+                                                     sg.vbase, g.vw, bufs.C, bufs.W, slot);
+  else
+    k_assign_empty<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_b, bufs.freelist, g.vw, bufs.C, bufs.W,
+                                                 slot);
+}
+
+// Objective bookkeeping of state k after pass `pass` (union: per graph).
+static void state_sums_sw2(const SegLM& sg, const int64_t* W, int64_t n, LMSlot* slot, int k, int pass,
+                           hipStream_t st) {
+  if (sg.G) {
+    const int64_t G = sg.G;
+    k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(W, 1, sg.vbase, G, sg.SW2 + (int64_t)k * G,
+                                              k ? sg.SW2 + (int64_t)(k - 1) * G : nullptr, pass >= 0 ? slot : nullptr, pass);
+  } else {
+    k_sw2<<<grid_for(n), BLOCK, 0, st>>>(W, n, &slot->SW2[k], pass >= 0 ? slot : nullptr, pass);
+  }
+}
+
+static void best_so_far(const SegLM& sg, LMSlot* slot, const LMParams& prm, LMBuffers& bufs, int64_t n, int k,
+                        int skipk, hipStream_t st) {
+  if (sg.G) {
+    k_best_seg<<<grid_for(sg.G), BLOCK, 0, st>>>(sg, slot, k, skipk);
+    if (k > 0) k_copy_if_seg<<<grid_for(n), BLOCK, 0, st>>>(sg.copy, sg.gid, bufs.C, bufs.Cout, n);
+  } else {
+    k_best<<<1, 1, 0, st>>>(slot, k, skipk, prm.sc.p, prm.sc.q, prm.sum_w2);
+    if (k > 0) k_copy_if<<<grid_for(n), BLOCK, 0, st>>>(slot, bufs.C, bufs.Cout, n);
+  }
 }
 
 void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool singleton, LMBuffers& bufs,
@@ -1415,7 +1579,11 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
   (void)ctrl;
   const int64_t n = g.n;
   const HubScratch hs = hub_scratch(b);
-  const Score& sc = prm.sc;
+  const SegLM& sg = prm.seg;
+  const int64_t G = sg.G;
+  ScoreSrc sc;
+  sc.s = prm.sc;
+  if (G) { sc.tab = sg.score; sc.gid = sg.gid; sc.vbase = sg.vbase; sc.ownv = sg.ownv; }
   zero_bytes(slot, sizeof(LMSlot), st);
   // starting state: cluster weights, sizes, C_out = C, sum of squared cluster weights (state 0)
   if (singleton) {
@@ -1425,7 +1593,11 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
     launch_cluster_weights(bufs.C, g.vw, n, bufs.W, st);
   }
   copy_i32(bufs.Cout, bufs.C, n, st);
-  k_sw2<<<grid_for(n), BLOCK, 0, st>>>(bufs.W, n, &slot->SW2[0], nullptr, -1);
+  if (G) {  // vertices outside the bucket lists never move and add nothing to their graph's sums
+    fill_u8(bufs.keep, 0, n, st);
+    fill_i64(sg.ownv, 0, n, st);
+  }
+  state_sums_sw2(sg, bufs.W, n, slot, 0, -1, st);
   if (b.count[7])
     k_hub_clear<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L_hubs(b), b.hub_chunk_off, b.count[7], g.off,
                                                              bufs.arena, nullptr, -1);
@@ -1435,26 +1607,33 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
     bool single_now = singleton && i == 1;
     launch_destinations(g, b, sc, prm.phi_num[i], prm.phi_den[i], 0, single_now, bufs, slot, i,
                         &slot->I[i - 1], hs, st);
+    if (G)  // internal weight of state i-1 per graph, from the own-cluster weights the pass just summed
+      k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(sg.ownv, 0, sg.vbase, G, sg.I + (int64_t)(i - 1) * G,
+                                                i >= 2 ? sg.I + (int64_t)(i - 2) * G : nullptr, slot, i);
     // best-so-far check of the state this pass started from (state i-1)
-    k_best<<<1, 1, 0, st>>>(slot, i - 1, i, sc.p, sc.q, prm.sum_w2);
-    k_copy_if<<<grid_for(n), BLOCK, 0, st>>>(slot, bufs.C, bufs.Cout, n);
+    best_so_far(sg, slot, prm, bufs, n, i - 1, i, st);
     launch_afterburner(g, b, sc, bufs, slot, i, hs, st);
-    apply_and_empty(g, bufs, slot, i, st);
-    k_sw2<<<grid_for(n), BLOCK, 0, st>>>(bufs.W, n, &slot->SW2[i], slot, i);
+    apply_and_empty(g, bufs, sg, slot, i, st);
+    state_sums_sw2(sg, bufs.W, n, slot, i, i, st);
   }
   const int last = prm.pass_limit;
   if (last >= 1) {
     k_final_state<<<1, 1, 0, st>>>(slot, last);
-    launch_internal(g, b, bufs.C, &slot->I[last], &slot->skip[last], st);
-    k_best<<<1, 1, 0, st>>>(slot, last, last, sc.p, sc.q, prm.sum_w2);
-    k_copy_if<<<grid_for(n), BLOCK, 0, st>>>(slot, bufs.C, bufs.Cout, n);
+    if (G) {
+      launch_internal(g, b, bufs.C, nullptr, &slot->skip[last], st, sg.ownv);
+      k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(sg.ownv, 0, sg.vbase, G, sg.I + (int64_t)last * G,
+                                                sg.I + (int64_t)(last - 1) * G, slot, last);
+    } else {
+      launch_internal(g, b, bufs.C, &slot->I[last], &slot->skip[last], st);
+    }
+    best_so_far(sg, slot, prm, bufs, n, last, last, st);
   } else {
-    k_best<<<1, 1, 0, st>>>(slot, 0, -1, sc.p, sc.q, prm.sum_w2);
+    best_so_far(sg, slot, prm, bufs, n, 0, -1, st);
   }
 }
 
 void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {
-  apply_and_empty(g, bufs, slot, 0, st);
+  apply_and_empty(g, bufs, SegLM{}, slot, 0, st);
 }
 
 void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
@@ -1463,7 +1642,9 @@ void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score
   if (b.count[7])
     k_hub_clear<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L_hubs(b), b.hub_chunk_off, b.count[7], g.off,
                                                              bufs.arena, nullptr, -1);
-  launch_destinations(g, b, sc, 0, 1, 1, false, bufs, slot, 0, nullptr, hs, st);
+  ScoreSrc ss;
+  ss.s = sc;
+  launch_destinations(g, b, ss, 0, 1, 1, false, bufs, slot, 0, nullptr, hs, st);
 }
 
 }  // namespace lcc
