@@ -140,6 +140,133 @@ def bench_knn_batch(args):
     ctx.close()
 
 
+def bench_serve(args):
+    """Served form: a Poisson request stream (SBM, R-MAT scales 12-20, kNN; modularity or CPM 1/10, 1/20,
+    1/50; pLouvain+ or pLeiden) against the continuous-batching server and against a FIFO server that runs one
+    request at a time with plain lcc_cluster calls, at 0.5, 0.8 and 0.95 of the FIFO server's saturated
+    throughput.  Latency = completion - arrival; both servers take host-resident graphs."""
+    import threading
+    import numpy as np
+    import torch
+    import graphgen as gg
+    import paper_2608_01503_amd as L
+    dev = torch.device("cuda:0")
+    pool = gg.serve_pool()
+    t0 = time.perf_counter()
+    fam = {"sbm": [], "rmat": [], "knn": []}
+    for spec in pool:
+        if spec[0] == "knn":
+            _, n, K, i = spec
+            off, idx, w = gg.knn_graph_torch(n, K, 6, i, dev)
+            g = gg.Graph(n=n, off=off.cpu().numpy(), idx=idx.cpu().numpy(), w=w.cpu().numpy(), name=f"knn{n}")
+        else:
+            g = gg.serve_graph(spec)
+        fam[spec[0]].append(g)
+    print(f"# request pool built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    total = args.serve_warm + args.serve_count
+    reqs = gg.serve_requests(total, {k: len(v) for k, v in fam.items()})
+    items = []
+    for f, e, o, v in reqs:
+        g = fam[f][e]
+        lam, mode = gg.SERVE_OBJECTIVES[o]
+        items.append((g, L.make_graph(g.off, g.idx, g.w, None, mode), lam, v))
+    ctx = L.Context(0, allocator="hip")
+    opts = L.lcc_default_options()
+    big = max(range(len(items)), key=lambda i: items[i][0].nnz)
+    ctx.cluster(items[big][1], items[big][2], items[big][3], opts)   # workspace at its largest
+    # FIFO service times, back to back: the saturated throughput
+    svc = []
+    for g, gr, lam, v in items[:min(len(items), 200)]:
+        a = time.perf_counter()
+        ctx.cluster(gr, lam, v, opts)
+        svc.append(time.perf_counter() - a)
+    qps_sat = 1.0 / float(np.mean(svc))
+    print(f"# FIFO saturated throughput {qps_sat:.1f} requests/s", file=sys.stderr, flush=True)
+    srv_ctx = L.Context(0, allocator="hip")
+    srv = L.Server(srv_ctx, 200 << 30)
+    # warm the server's slots on the largest request
+    for _ in range(8):
+        t = srv.submit(items[big][1], items[big][2], items[big][3])
+        while srv.poll(t, items[big][0].n) is None:
+            time.sleep(0.001)
+    rng = np.random.default_rng(6)
+    pct = lambda x, q: float(np.percentile(np.asarray(x), q))
+    runs = []
+    for load in (0.5, 0.8, 0.95):
+        qps = load * qps_sat
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=len(items)))
+        # FIFO: one request at a time, in arrival order
+        fifo_lat, fifo_N = [], []
+        start = time.perf_counter()
+        for (g, gr, lam, v), ta in zip(items, arr):
+            now = time.perf_counter() - start
+            if now < ta:
+                time.sleep(ta - now)
+            _, r = ctx.cluster(gr, lam, v, opts)
+            fifo_lat.append(time.perf_counter() - start - ta)
+            fifo_N.append(r.N)
+            if len(fifo_lat) % 50 == 0:
+                print(f"# load {load} fifo: {len(fifo_lat)} requests done", file=sys.stderr, flush=True)
+        fifo_span = time.perf_counter() - start
+        # continuous batching server: a thread submits at the arrival times, this thread polls
+        tickets = [None] * len(items)
+        done_at = [None] * len(items)
+        srv_N = [None] * len(items)
+        start = time.perf_counter()
+
+        def submitter():
+            for k, ((g, gr, lam, v), ta) in enumerate(zip(items, arr)):
+                now = time.perf_counter() - start
+                if now < ta:
+                    time.sleep(ta - now)
+                tickets[k] = srv.submit(gr, lam, v)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        left = set(range(len(items)))
+        while left:
+            for k in list(left):
+                if tickets[k] is None:
+                    continue
+                r = srv.poll(tickets[k], items[k][0].n)
+                if r is not None:
+                    done_at[k] = time.perf_counter() - start
+                    srv_N[k] = r[1].N
+                    left.discard(k)
+                    if len(left) % 50 == 0:
+                        print(f"# load {load} server: {len(left)} requests left", file=sys.stderr, flush=True)
+            time.sleep(0.0002)
+        th.join()
+        srv_span = time.perf_counter() - start
+        w0 = args.serve_warm
+        srv_lat = [done_at[k] - arr[k] for k in range(len(items))]
+        edges = sum(it[0].nnz for it in items[w0:])
+        runs.append({"load": load, "qps": qps,
+                     "fifo": {"p50_s": pct(fifo_lat[w0:], 50), "p99_s": pct(fifo_lat[w0:], 99),
+                              "edges_per_s": sum(it[0].nnz for it in items) / fifo_span},
+                     "server": {"p50_s": pct(srv_lat[w0:], 50), "p99_s": pct(srv_lat[w0:], 99),
+                                "edges_per_s": sum(it[0].nnz for it in items) / srv_span},
+                     "results_identical": fifo_N == srv_N, "measured_requests": len(items) - w0,
+                     "measured_edges": edges})
+        print(f"# load {load}: fifo p99 {runs[-1]['fifo']['p99_s']:.4f} s, server p99 {runs[-1]['server']['p99_s']:.4f} s",
+              file=sys.stderr, flush=True)
+    srv.close()
+    hi = runs[-1]
+    out = {
+        "metric": METRIC, "value": hi["server"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
+        "steps": len(items), "warmup": args.serve_warm, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "Poisson request stream: SBM (b blocks of 100, 2..7000), R-MAT scales 12-20, "
+                               "kNN (500..50,000 vertices); modularity or CPM 1/10, 1/20, 1/50; pLouvain+ or "
+                               "pLeiden; host-resident graphs", "pool_graphs": len(pool),
+                   "requests": len(items), "fifo_saturated_qps": qps_sat},
+        "runs": runs,
+    }
+    print(json.dumps(out), flush=True)
+    srv_ctx.close()
+    ctx.close()
+
+
 def cpu_baseline(scale: int):
     """The oracle, as it stands, on R-MAT of a smaller scale (same generator and parameters)."""
     import graphgen as gg
@@ -164,6 +291,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--family", default="auto", help="kernel family timed live for the roofline")
     ap.add_argument("--knn-count", type=int, default=4096, help="graphs of the kNN batch workload")
+    ap.add_argument("--serve-count", type=int, default=240, help="measured requests of the served workload")
+    ap.add_argument("--serve-warm", type=int, default=24, help="warm-up requests of the served workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (counter calibration for HBM traffic)")
     args = ap.parse_args()
@@ -188,6 +317,9 @@ def main():
 
     if args.workload == "knn":
         bench_knn_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
     g, variant, lam, vw_mode, desc = workload(args.workload)
     dev = torch.device("cuda:0")

@@ -292,3 +292,53 @@ def knn_graph_torch(n: int, K: int, seed: int, graph: int, device, k: int = KNN_
     off = torch.zeros(n + 1, dtype=torch.int64, device=device)
     off[1:] = torch.cumsum(torch.bincount(rows, minlength=n), 0)
     return off, cols.contiguous(), w.contiguous()
+
+
+# Request stream of the served workload ------------------------------------------------------------
+
+SERVE_OBJECTIVES = [((1, 1, True), 1), ((1, 10, False), 2), ((1, 20, False), 2), ((1, 50, False), 2)]
+"""(lambda, vertex-weight mode): modularity (weighted degree), CPM 1/10, 1/20, 1/50 (unit weights)."""
+
+
+def serve_pool(seed: int = 6, sbm_blocks=(2, 7000), rmat_scales=(12, 20), knn_n=(500, 50000), n_sbm: int = 16,
+               n_knn: int = 16):
+    """Graph specs the request stream draws from: SBM with b blocks of 100 (p_in 0.1, p_out 3.8 / (n - 100),
+    b log-spaced), R-MAT of every scale in the range (edge factor 16), kNN graphs of the batched workload's
+    generator (sizes log-uniform).  Returns a list of ("sbm", b) / ("rmat", scale) / ("knn", n, K, index)."""
+    import math
+    pool = []
+    lo, hi = sbm_blocks
+    for i in range(n_sbm):
+        b = int(round(math.exp(math.log(lo) + (math.log(hi) - math.log(lo)) * i / max(1, n_sbm - 1))))
+        pool.append(("sbm", b))
+    for s in range(rmat_scales[0], rmat_scales[1] + 1):
+        pool.append(("rmat", s))
+    for i, (n, K) in enumerate(knn_batch_spec(n_knn, seed, knn_n[0], knn_n[1])):
+        pool.append(("knn", n, K, i))
+    return pool
+
+
+def serve_graph(spec, seed: int = 6) -> Graph:
+    """Host graph of a pool entry (kNN graphs by host brute force: use small kNN sizes on the host)."""
+    if spec[0] == "sbm":
+        b = spec[1]
+        n = 100 * b
+        return sbm(b, 100, 0.1, 3.8 / (n - 100), seed)
+    if spec[0] == "rmat":
+        return rmat(spec[1], 16, 0.57, 0.19, 0.19, seed)
+    _, n, K, i = spec
+    return knn_graph(n, K, seed, i)
+
+
+def serve_requests(count: int, pool_size_by_family, seed: int = 6):
+    """Request k: family uniform over (sbm, rmat, knn), a pool entry of that family uniform, objective uniform
+    over SERVE_OBJECTIVES, variant pLouvain+ or pLeiden with probability 1/2 each.  Returns a list of
+    (family, entry, objective index, variant) with variant 1 = pLouvain+, 2 = pLeiden."""
+    out = []
+    fams = ["sbm", "rmat", "knn"]
+    for k in range(count):
+        d = [_draw(seed, (1 << 33) + k, t) for t in range(4)]
+        fam = fams[d[0] % 3]
+        out.append((fam, int(d[1] % pool_size_by_family[fam]), int(d[2] % len(SERVE_OBJECTIVES)),
+                    1 if d[3] % 2 == 0 else 2))
+    return out

@@ -159,8 +159,8 @@ lcc_status lcc_cluster(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_
 
 /* Cluster `count` independent graphs (each with its own lambda, vertex-weight mode and variant) in one call.
  * Results are identical to `count` separate lcc_cluster calls.  labels_out[i] and res[i] as for lcc_cluster.
- * When every graph is device-resident and uses LCC_LOUVAIN or LCC_PLOUVAIN (and opts->trace is NULL), the
- * graphs are processed together: their CSRs are concatenated into one union graph on the device and every
+ * When every graph uses LCC_LOUVAIN or LCC_PLOUVAIN (and opts->trace is NULL), the graphs are processed
+ * together (host graphs are first copied to the device): their CSRs are concatenated into one union graph and every
  * kernel launch of a level covers all graphs still coarsening (Alg. 1 applied to the union, with each graph's
  * own lambda, objective, best-so-far state and level count).  Otherwise the graphs run one after another.
  * The workspace is sized for the union (sum of n, sum of nnz).  On a failure the status of the first problem
@@ -175,10 +175,21 @@ lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda
 lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, const int32_t* labels,
                          void* stream, lcc_result* res);
 
-/* Continuous-batching server over one context: jobs are admitted while their footprint
- * (lcc_workspace_bytes) fits in hbm_budget, their level state stays on the device, and the sweeps of
- * concurrently admitted jobs are co-scheduled.  lcc_submit copies the graph before returning.
- * lcc_poll: *done = 1 and outputs written once the job finished (labels_out on the host). */
+/* Continuous-batching server over one context (its device and allocator).  The server runs 8 execution
+ * slots, each with its own context and HIP stream, so admitted jobs run concurrently on the GPU.  A free slot
+ * admits the oldest queued job whose footprint (lcc_workspace_bytes) fits the unreserved part of hbm_budget
+ * (a job passed over 4 times blocks further overtaking); if that job is a Louvain / Louvain+ request of at
+ * most 2^22 entries, the slot also takes the other queued such requests with the same options (up to 256
+ * requests, 2^25 entries) and runs them as one fused lcc_cluster_batch call.  Results are identical to plain
+ * lcc_cluster calls.
+ *   lcc_server_create  hbm_budget > 0 bytes; the server keeps ctx's device and allocator (ctx must outlive it)
+ *   lcc_submit         copies the graph (host or device memory) before returning and queues the job; returns
+ *                      LCC_ERR_BUSY when the job's footprint alone exceeds hbm_budget; *ticket identifies it
+ *   lcc_poll           *done = 0 while the job runs; once finished, *done = 1, labels_out (n int32, host
+ *                      memory, may be NULL) and *res are written, the job's status is returned and the ticket
+ *                      is released (LCC_ERR_NOT_FOUND afterwards)
+ *   lcc_server_destroy waits for running jobs; queued jobs are dropped.  Thread-safe: submit and poll may be
+ *                      called from any threads. */
 lcc_status lcc_server_create(lcc_ctx* ctx, size_t hbm_budget, lcc_server** out);
 lcc_status lcc_submit(lcc_server* s, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
                       const lcc_options* opts, uint64_t* ticket);

@@ -1018,7 +1018,6 @@ bool fusable(const lcc_graph* gs, const lcc_variant* variants, int64_t count, co
   if (count < 2 || (opts && opts->trace)) return false;
   int64_t n = 0, e = 0;
   for (int64_t i = 0; i < count; ++i) {
-    if (gs[i].mem != LCC_MEM_DEVICE) return false;
     if (variants[i] != LCC_LOUVAIN && variants[i] != LCC_PLOUVAIN) return false;
     n += gs[i].n;
     e += gs[i].nnz;
@@ -1076,10 +1075,23 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   std::vector<GDesc> desc((size_t)G);
   std::vector<int8_t> hmode((size_t)G);
   bool any_given = false;
+  std::vector<int32_t*> dev_out(labels_out, labels_out + G);  // host graphs: labels staged on the device
   for (int64_t i = 0; i < G; ++i) {
     const lcc_graph& g = gs[i];
     desc[i] = GDesc{g.offsets, g.indices, g.edge_w, g.vertex_w, g.n, g.nnz, vb[i], eb[i], g.offsets_bits,
                     (int32_t)g.vw_mode};
+    if (g.mem == LCC_MEM_HOST && g.n > 0) {  // stage the graph's arrays in device memory
+      auto up = [&](const void* src, size_t bytes) -> void* {
+        void* d = ctx->pool_take(bytes);
+        hip_check(hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, st), "input copy");
+        return d;
+      };
+      desc[i].off = up(g.offsets, (size_t)(g.n + 1) * (g.offsets_bits / 8));
+      if (g.nnz) desc[i].idx = (const int32_t*)up(g.indices, (size_t)g.nnz * 4);
+      if (g.nnz && g.edge_w) desc[i].w = (const int32_t*)up(g.edge_w, (size_t)g.nnz * 4);
+      if (g.vw_mode == LCC_VW_GIVEN) desc[i].vw = (const int64_t*)up(g.vertex_w, (size_t)g.n * 8);
+      dev_out[i] = take<int32_t>(ctx, g.n);
+    }
     hmode[i] = (int8_t)g.vw_mode;
     any_given = any_given || g.vw_mode == LCC_VW_GIVEN;
   }
@@ -1159,7 +1171,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   Level& F = R.lv[0];
   launch_label_rank(F.C, n, w.used, w.rank, w.scan_temp, st);
   int32_t** d_outs = take<int32_t*>(ctx, G);
-  hip_check(hipMemcpyAsync(d_outs, labels_out, sizeof(int32_t*) * G, hipMemcpyHostToDevice, st), "outputs");
+  hip_check(hipMemcpyAsync(d_outs, dev_out.data(), sizeof(int32_t*) * G, hipMemcpyHostToDevice, st), "outputs");
   k_write_labels_seg<<<grid1(n), BLOCK, 0, st>>>(F.C, w.rank, F.gid, F.vbase, d_outs, n);
   launch_rebase(w.rank, F.vbase, G, R.gtmp, st);
   launch_cluster_weights(F.C, F.g.vw, n, w.W, st);
@@ -1171,6 +1183,9 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   std::vector<int32_t> hr((size_t)G + 1);
   hip_check(hipMemcpyAsync(ho.data(), gobj, sizeof(int64_t) * 2 * G, hipMemcpyDeviceToHost, st), "objective");
   hip_check(hipMemcpyAsync(hr.data(), R.gtmp, sizeof(int32_t) * (G + 1), hipMemcpyDeviceToHost, st), "counts");
+  for (int64_t i = 0; i < G; ++i)
+    if (gs[i].mem == LCC_MEM_HOST && gs[i].n > 0)
+      hip_check(hipMemcpyAsync(labels_out[i], dev_out[i], (size_t)gs[i].n * 4, hipMemcpyDeviceToHost, st), "labels");
   R.sync("batch result");
   for (int64_t i = 0; i < G; ++i) {
     if (gs[i].n == 0) {

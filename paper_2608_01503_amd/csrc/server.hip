@@ -5,8 +5,11 @@
 // A submitted job is copied to host memory and queued.  A free slot admits the oldest queued job whose
 // device footprint (lcc_workspace_bytes) fits the unreserved part of the HBM budget; a job that does not fit
 // yet is passed over by smaller ones at most a few times before it holds the next free slot, so a large
-// request cannot starve.  A finished job releases its reservation and its slot immediately and the next job
-// joins without waiting for the others.  Results are bit-identical to a plain lcc_cluster call.
+// request cannot starve.  When the admitted job is a small Louvain / Louvain+ request, the slot also takes
+// the other queued small Louvain requests with the same options that fit the budget and runs them all as one
+// fused batch (lcc_cluster_batch: one union graph per kernel launch), so a burst of small requests costs
+// about one request's launches.  A finished slot releases its reservations at once and the next job joins
+// without waiting for the others.  Results are bit-identical to a plain lcc_cluster call.
 #include <algorithm>
 #include <condition_variable>
 #include <cstring>
@@ -31,6 +34,9 @@ namespace {
 
 constexpr int SLOTS = 8;
 constexpr int MAX_PASSED_OVER = 4;
+constexpr int64_t FUSE_NNZ = (int64_t)1 << 22;        // requests up to this many entries may be fused
+constexpr int64_t FUSE_TOTAL_NNZ = (int64_t)1 << 25;  // entries of one fused group
+constexpr size_t FUSE_MAX = 256;                      // requests of one fused group
 
 struct Job {
   uint64_t ticket = 0;
@@ -83,39 +89,105 @@ struct lcc_server {
     return nullptr;
   }
 
+  static bool fusable(const Job& j) {
+    return (j.variant == LCC_LOUVAIN || j.variant == LCC_PLOUVAIN) && j.nnz <= FUSE_NNZ;
+  }
+  static bool same_opts(const Job& a, const Job& b) {
+    return a.has_opts == b.has_opts && (!a.has_opts || memcmp(&a.opts, &b.opts, sizeof(lcc_options)) == 0);
+  }
+
+  // The admitted job plus the queued small Louvain jobs that can join it (caller holds mu).
+  std::vector<std::shared_ptr<Job>> pick_group() {
+    std::vector<std::shared_ptr<Job>> grp;
+    auto head = pick();
+    if (!head) return grp;
+    grp.push_back(head);
+    if (!fusable(*head)) return grp;
+    int64_t total = head->nnz;
+    for (size_t i = 0; i < queue.size() && grp.size() < FUSE_MAX;) {
+      auto& j = queue[i];
+      if (fusable(*j) && same_opts(*head, *j) && total + j->nnz <= FUSE_TOTAL_NNZ &&
+          reserved + j->footprint <= budget) {
+        reserved += j->footprint;
+        total += j->nnz;
+        grp.push_back(j);
+        queue.erase(queue.begin() + (long)i);
+      } else {
+        ++i;
+      }
+    }
+    return grp;
+  }
+
+  static lcc_graph host_graph(Job& j) {
+    lcc_graph g{};
+    g.n = j.n;
+    g.nnz = j.nnz;
+    g.offsets = j.off.data();
+    g.offsets_bits = 64;
+    g.indices = j.idx.data();
+    g.edge_w = j.has_w ? j.w.data() : nullptr;
+    g.vertex_w = j.vw_mode == LCC_VW_GIVEN ? j.vw.data() : nullptr;
+    g.vw_mode = j.vw_mode;
+    g.mem = LCC_MEM_HOST;
+    j.labels.assign((size_t)std::max<int64_t>(j.n, 1), 0);
+    return g;
+  }
+
+  void run_one(lcc_ctx* ctx, hipStream_t st, Job& j) {
+    lcc_graph g = host_graph(j);
+    j.st = lcc_cluster_init_internal(ctx, &g, j.lam, j.variant, j.has_opts ? &j.opts : nullptr, st,
+                                     j.labels.data(), &j.res, nullptr);
+  }
+
+  void run_group(lcc_ctx* ctx, hipStream_t st, std::vector<std::shared_ptr<Job>>& grp) {
+    if (grp.size() == 1) {
+      run_one(ctx, st, *grp[0]);
+      return;
+    }
+    const size_t m = grp.size();
+    std::vector<lcc_graph> gs(m);
+    std::vector<lcc_lambda> lams(m);
+    std::vector<lcc_variant> vars(m);
+    std::vector<int32_t*> outs(m);
+    std::vector<lcc_result> res(m);
+    for (size_t i = 0; i < m; ++i) {
+      gs[i] = host_graph(*grp[i]);
+      lams[i] = grp[i]->lam;
+      vars[i] = grp[i]->variant;
+      outs[i] = grp[i]->labels.data();
+    }
+    lcc_status s = lcc_cluster_batch(ctx, gs.data(), lams.data(), vars.data(), (int64_t)m,
+                                     grp[0]->has_opts ? &grp[0]->opts : nullptr, st, outs.data(), res.data());
+    if (s == LCC_OK) {
+      for (size_t i = 0; i < m; ++i) { grp[i]->st = LCC_OK; grp[i]->res = res[i]; }
+      return;
+    }
+    for (auto& j : grp) run_one(ctx, st, *j);  // some request is invalid: give each its own status
+  }
+
   void run_worker(int k) {
     lcc_ctx* ctx = ctxs[k];
     hipStream_t st = streams[k];
     for (;;) {
-      std::shared_ptr<Job> j;
+      std::vector<std::shared_ptr<Job>> grp;
       {
         std::unique_lock<std::mutex> lock(mu);
-        cv.wait(lock, [&] { return stop || (j = pick()) != nullptr; });
-        if (!j) return;
+        cv.wait(lock, [&] { return stop || !(grp = pick_group()).empty(); });
+        if (grp.empty()) return;
       }
-      lcc_graph g{};
-      g.n = j->n;
-      g.nnz = j->nnz;
-      g.offsets = j->off.data();
-      g.offsets_bits = 64;
-      g.indices = j->idx.data();
-      g.edge_w = j->has_w ? j->w.data() : nullptr;
-      g.vertex_w = j->vw_mode == LCC_VW_GIVEN ? j->vw.data() : nullptr;
-      g.vw_mode = j->vw_mode;
-      g.mem = LCC_MEM_HOST;
-      j->labels.assign((size_t)std::max<int64_t>(j->n, 1), 0);
-      lcc_status s = lcc_cluster_init_internal(ctx, &g, j->lam, j->variant, j->has_opts ? &j->opts : nullptr, st,
-                                               j->labels.data(), &j->res, nullptr);
+      run_group(ctx, st, grp);
       {
         std::lock_guard<std::mutex> lock(mu);
-        j->st = s;
-        j->done = true;
-        reserved -= j->footprint;
-        // the host copy of the graph is no longer needed
-        std::vector<int64_t>().swap(j->off);
-        std::vector<int32_t>().swap(j->idx);
-        std::vector<int32_t>().swap(j->w);
-        std::vector<int64_t>().swap(j->vw);
+        for (auto& j : grp) {
+          j->done = true;
+          reserved -= j->footprint;
+          // the host copy of the graph is no longer needed
+          std::vector<int64_t>().swap(j->off);
+          std::vector<int32_t>().swap(j->idx);
+          std::vector<int32_t>().swap(j->w);
+          std::vector<int64_t>().swap(j->vw);
+        }
       }
       cv.notify_all();
     }

@@ -82,6 +82,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    # torch first: its HIP runtime must be the one loaded into the process (liblcc.so links the same soname
+    # and then binds to it); loading liblcc.so first would pull in a second runtime under torch
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     v, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
