@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 namespace lcc {
 
 constexpr int WAVE = 64;
@@ -333,7 +335,8 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
             int32_t* R, RefineBuffers& rb, Ctrl* ctrl, hipStream_t st);
 
 // lmalt.hip: LocalMoveAlt (Sec. V-A)
-void lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs, LMSlot* slot, Ctrl* ctrl,
-           int32_t* list, int64_t* gain, hipStream_t st);
+// Returns false (nothing done) when the mover count is 2^30 or more.
+bool lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs, LMSlot* slot, Ctrl* ctrl,
+           int32_t* list, int64_t* gain, const std::function<void*(size_t)>& take, hipStream_t st);
 
 }  // namespace lcc

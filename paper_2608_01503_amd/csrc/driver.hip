@@ -621,7 +621,9 @@ struct Run {
         launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         if (nslot >= NSLOT) fail(LCC_ERR_INVALID, "too many local-move calls");
         int s2 = nslot++;
-        lmalt(L.g, L.b, sc, B, w.slots + s2, w.ctrl, w.alt_list, w.alt_gain, st);
+        if (!lmalt(L.g, L.b, sc, B, w.slots + s2, w.ctrl, w.alt_list, w.alt_gain,
+                   [this](size_t bytes) { return ctx->pool_take(bytes); }, st))
+          fail(LCC_ERR_INVALID, "alternate local move with 2^30 or more movers is not supported");
         copy_i32(L.C, w.C, n, st);
         launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         launch_objective(L.g, L.b, w.C, w.W, w.ctrl, st);

@@ -1,12 +1,19 @@
 // LocalMoveAlt (Sec. V-A): used when the synchronous local move leaves the objective unchanged.
 //
 // Every vertex that is not node optimal (its best destination strictly improves the objective) is a mover,
-// taken in ascending vertex id with its destination fixed up front.  The exact objective change of applying
-// the movers one after another is delta_i adjusted by EVERY earlier mover j -- the afterburner rule of Alg. 3
-// with w'(u,v) = w(u,v) - lambda w(u) w(v) over all pairs, adjacent or not.  The shortest prefix with the
-// largest total change is committed (it is non-empty: the first mover alone improves).  One workgroup per
-// mover sums over the earlier movers; the edge weight w(v_j, v_i) is found by binary search in v_i's sorted
-// row only when the cluster pattern of the pair makes it matter.
+// taken in ascending vertex id with its destination fixed up front.  Applied one after another, mover i
+// (v: A -> B) changes the objective by 2 g_i with
+//   g_i = delta_i + q * sum over earlier movers u adjacent to v of w(u,v) * s(u, v)
+//                 - p * w(v) * (F_B(i) - F_A(i)),
+//   F_c(i) = sum over earlier movers u of w(u) ([D_u = c] - [C_u = c])    (the weight that flowed into c),
+// s(u, v) = [D_u = B] - [C_u = B] - [D_u = A] + [C_u = A] (the afterburner pattern of Alg. 3; a move to a new
+// singleton never meets another mover's cluster).  The adjacent sum is one pass over the movers' rows; the
+// flows are prefix sums per cluster in mover order: one record per (mover, touched cluster) event and query,
+// radix-sorted by (cluster, mover index, query before event) and scanned.  The shortest prefix with the
+// largest total change is committed (it is non-empty: the first mover alone improves).
+#include <algorithm>
+#include <functional>
+
 #include "common.h"
 
 namespace lcc {
@@ -43,36 +50,80 @@ __device__ __forceinline__ int pattern(int32_t cv, int32_t dv, int32_t cu, int32
   return a;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_gain(const int32_t* list, int64_t k, DevGraph g, const VState* vs,
-                                                Score sc, int64_t* gain) {
-  const int64_t i = blockIdx.x;
-  const int32_t vi = list[i];
-  const VState me = vs[vi];
-  const int64_t wi = g.vw[vi];
-  const int64_t rb = g.off[vi], re = g.off[vi + 1];
-  int64_t acc = 0;
-  for (int64_t j = threadIdx.x; j < i; j += BLOCK) {
-    const int32_t vj = list[j];
-    const VState o = vs[vj];
-    int a = pattern(me.c, me.d, o.c, o.d);
-    if (a == 0) continue;
-    int64_t lo = rb, hi = re;
-    while (lo < hi) {
-      int64_t mid = lo + ((hi - lo) >> 1);
-      if (g.idx[mid] < vj) lo = mid + 1; else hi = mid;
+// q-free adjacent part: adj[i] = sum over earlier adjacent movers u of w(u, v_i) s(u, v_i); one wavefront
+// per mover (grid-stride), lanes over the row
+__global__ __launch_bounds__(BLOCK) void k_gain_adj(const int32_t* list, int64_t k, DevGraph g, const VState* vs,
+                                                    const uint8_t* mv, const int32_t* pos, int64_t* adj) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE; i < k;
+       i += (int64_t)gridDim.x * (BLOCK / WAVE)) {
+    const int32_t v = list[i];
+    const VState me = vs[v];
+    int64_t acc = 0;
+    for (int64_t j = g.off[v] + lane; j < g.off[v + 1]; j += WAVE) {
+      const int32_t u = g.idx[j];
+      if (!mv[u] || pos[u] >= i) continue;
+      const VState o = vs[u];
+      acc += (int64_t)pattern(me.c, me.d, o.c, o.d) * g.w[j];
     }
-    int64_t w = (lo < re && g.idx[lo] == vj) ? (int64_t)g.w[lo] : 0;
-    acc += (int64_t)a * (sc.q * w - sc.p * g.vw[vj] * wi);
-  }
-  __shared__ int64_t ws[BLOCK / WAVE];
 #pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
-  if ((threadIdx.x & (WAVE - 1)) == 0) ws[threadIdx.x / WAVE] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t t = 0;
-    for (int w = 0; w < BLOCK / WAVE; ++w) t += ws[w];
-    gain[i] = me.delta + t;
+    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+    if (lane == 0) adj[i] = acc;
+  }
+}
+
+// Records of mover j (4 j .. 4 j + 3): event "leaves C" (-w), event "enters D" (+w), query at D, query at C.
+// key = cluster << 33 | j << 1 | (event ? 1 : 0); unused records (D = new singleton) get the largest key.
+constexpr uint64_t NO_KEY = ~0ull;
+
+__global__ void k_alt_records(const int32_t* list, int64_t k, const VState* vs, const int64_t* vw, uint64_t* key,
+                              uint32_t* val, int64_t* evw) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < k; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = list[j];
+    const VState s = vs[v];
+    const int64_t w = vw[v];
+    const uint64_t jj = (uint64_t)j << 1;
+    const bool fresh = s.d == D_EMPTY;
+    key[4 * j + 0] = ((uint64_t)(uint32_t)s.c << 33) | jj | 1;
+    key[4 * j + 1] = fresh ? NO_KEY : (((uint64_t)(uint32_t)s.d << 33) | jj | 1);
+    key[4 * j + 2] = fresh ? NO_KEY : (((uint64_t)(uint32_t)s.d << 33) | jj);
+    key[4 * j + 3] = ((uint64_t)(uint32_t)s.c << 33) | jj;
+    for (int t = 0; t < 4; ++t) val[4 * j + t] = (uint32_t)(4 * j + t);
+    evw[4 * j + 0] = -w;
+    evw[4 * j + 1] = fresh ? 0 : w;
+    evw[4 * j + 2] = 0;
+    evw[4 * j + 3] = 0;
+  }
+}
+
+// sorted position p: x = the event weight (0 for queries), head = first record of a cluster
+__global__ void k_alt_gather(const uint64_t* key, const uint32_t* val, const int64_t* evw, int64_t m, int64_t* x,
+                             uint8_t* head) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+    x[p] = (key[p] & 1) ? evw[val[p]] : 0;
+    head[p] = p == 0 || (key[p] >> 33) != (key[p - 1] >> 33);
+  }
+}
+
+// S = exclusive prefix of x, H = exclusive prefix of heads: segment of p = H[p] + head[p] - 1
+__global__ void k_alt_base(const uint8_t* head, const int32_t* H, const int64_t* S, int64_t m, int64_t* base) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x)
+    if (head[p]) base[H[p]] = S[p];
+}
+
+__global__ void k_alt_query(const uint64_t* key, const uint32_t* val, const uint8_t* head, const int32_t* H,
+                            const int64_t* S, const int64_t* base, int64_t m, int64_t* F) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x)
+    if (key[p] != NO_KEY && !(key[p] & 1)) F[val[p]] = S[p] - base[H[p] + head[p] - 1];
+}
+
+__global__ void k_gain(const int32_t* list, int64_t k, const VState* vs, const int64_t* vw, Score sc,
+                       const int64_t* adj, const int64_t* F, int64_t* gain) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = list[i];
+    const VState me = vs[v];
+    const int64_t fB = me.d == D_EMPTY ? 0 : F[4 * i + 2];
+    gain[i] = me.delta + sc.q * adj[i] - sc.p * vw[v] * (fB - F[4 * i + 3]);
   }
 }
 
@@ -131,10 +182,12 @@ __global__ void k_set_counts(Ctrl* ctrl, int64_t k) {
 
 }  // namespace
 
-// Precondition: bufs.C is the clustering, bufs.W / bufs.sz its cluster weights and sizes.  On return bufs.C
-// holds the result; ctrl->lmalt_k and ctrl->lmalt_best_k the mover count and the committed prefix.
-void lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs, LMSlot* slot, Ctrl* ctrl,
-           int32_t* list, int64_t* gain, hipStream_t st) {
+// Precondition: bufs.C is the clustering, bufs.W its cluster weights.  On return bufs.C holds the result;
+// ctrl->lmalt_k and ctrl->lmalt_best_k the mover count and the committed prefix.  take() hands out device
+// scratch that stays valid until the call's stream has finished (sized by the mover count).  Returns false
+// (nothing changed) when there are 2^30 movers or more.
+bool lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs, LMSlot* slot, Ctrl* ctrl,
+           int32_t* list, int64_t* gain, const std::function<void*(size_t)>& take, hipStream_t st) {
   const int64_t n = g.n;
   zero_bytes(slot, sizeof(LMSlot), st);
   launch_destinations_strict(g, b, sc, bufs, slot, st);
@@ -145,12 +198,42 @@ void lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs
   hipStreamSynchronize(st);
   const int64_t k = k32;
   k_set_counts<<<1, 1, 0, st>>>(ctrl, k);
-  if (k == 0) return;
+  if (k == 0) return true;
+  if (4 * k > (int64_t)UINT32_MAX) return false;  // record ids are 32-bit
   k_mover_list<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, list);
-  k_gain<<<(unsigned)k, BLOCK, 0, st>>>(list, k, g, bufs.vs, sc, gain);
+  const int64_t m = 4 * k;
+  auto* key0 = (uint64_t*)take((size_t)m * 8);
+  auto* key1 = (uint64_t*)take((size_t)m * 8);
+  auto* val0 = (uint32_t*)take((size_t)m * 4);
+  auto* val1 = (uint32_t*)take((size_t)m * 4);
+  auto* evw = (int64_t*)take((size_t)m * 8);
+  auto* x = (int64_t*)take((size_t)m * 8);
+  auto* S = (int64_t*)take((size_t)(m + 1) * 8);
+  auto* head = (uint8_t*)take((size_t)m);
+  auto* H = (int32_t*)take((size_t)(m + 1) * 4);
+  auto* base = (int64_t*)take((size_t)m * 8);
+  auto* F = (int64_t*)take((size_t)m * 8);
+  auto* adj = (int64_t*)take((size_t)k * 8);
+  void* stemp = take(scan_temp_bytes(m + 1));
+  void* rtemp = take(radix_temp_bytes(m));
+  const unsigned gw = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(k, BLOCK / WAVE), 2048));
+  k_gain_adj<<<gw, BLOCK, 0, st>>>(list, k, g, bufs.vs, bufs.keep, bufs.scan_a, adj);
+  k_alt_records<<<grid_for(k), BLOCK, 0, st>>>(list, k, bufs.vs, g.vw, key0, val0, evw);
+  int shifts[8];
+  for (int t = 0; t < 8; ++t) shifts[t] = 8 * t;
+  const int which = radix_sort_pairs(key0, val0, key1, val1, m, shifts, 8, rtemp, st);
+  const uint64_t* ks = which ? key1 : key0;
+  const uint32_t* vs_ = which ? val1 : val0;
+  k_alt_gather<<<grid_for(m), BLOCK, 0, st>>>(ks, vs_, evw, m, x, head);
+  scan_i64_i64(x, S, m, stemp, st);
+  scan_u8_i32(head, H, m, stemp, nullptr, st);
+  k_alt_base<<<grid_for(m), BLOCK, 0, st>>>(head, H, S, m, base);
+  k_alt_query<<<grid_for(m), BLOCK, 0, st>>>(ks, vs_, head, H, S, base, m, F);
+  k_gain<<<grid_for(k), BLOCK, 0, st>>>(list, k, bufs.vs, g.vw, sc, adj, F, gain);
   k_best_prefix<<<1, BLOCK, 0, st>>>(gain, k, ctrl);
   k_commit_prefix<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, ctrl);
   launch_apply_and_empty(g, bufs, slot, st);
+  return true;
 }
 
 }  // namespace lcc

@@ -234,7 +234,10 @@ class Context:
                     return None
 
             def _f(p, user):
-                torch.cuda.caching_allocator_delete(p)
+                try:
+                    torch.cuda.caching_allocator_delete(p)
+                except Exception:  # interpreter shutdown: torch is already torn down, the process frees it
+                    pass
 
             self._alloc_cb = ALLOC_FN(_a)
             self._free_cb = FREE_FN(_f)

@@ -165,3 +165,12 @@ def test_batch_equals_single():
     for g, lam, m, v, lab, res in zip(gs, lams, modes, variants, labs, ress):
         ref = O.cluster(g, v, lam=lam, vw_mode=m)
         assert np.array_equal(lab.cpu().numpy(), ref.labels) and res.N == ref.N
+
+
+def test_pleiden_cpm_large_alternate_moves():
+    """R-MAT scale 16 with CPM 1/10: about 30 levels run the alternate local move, with up to ~7,500 movers
+    (the per-cluster prefix flows span several sort tiles)."""
+    g = gg.rmat(16, 16, seed=8)
+    ref, res = U.assert_parity(g, O.PLEIDEN, (1, 10, False), O.VW_UNIT)
+    k = [int(r[4]) for r in ref.trace if r[0] == 3]
+    assert len(k) > 10 and max(k) > 4096
