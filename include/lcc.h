@@ -157,6 +157,20 @@ lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size
 lcc_status lcc_cluster(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
                        const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res);
 
+/* lcc_cluster with the iteration inputs of the paper (Sec. II-B, Sec. IV-D), each optional (NULL = none),
+ * n int32 in the same memory space as the graph, borrowed for the call:
+ *   init_labels  labels in [0, n) (LCC_ERR_INVALID otherwise).  pLeiden / pLeiden+ start from this clustering
+ *                (Alg. 5's C_in: feeding a result back iterates pLeiden); Louvain / Louvain+ start the level-0
+ *                local move from it instead of singletons (the iteration the Leiden authors describe)
+ *   constraint   any int32 labels; Louvain / Louvain+ only and not together with init_labels
+ *                (LCC_ERR_INVALID otherwise).  The coarsening local moves only join clusters of neighbours
+ *                with the vertex's own constraint label, so every coarse vertex lies inside one constraint
+ *                cluster; the uncoarsening local moves are free.  Feeding a Louvain+ result back as the
+ *                constraint is the paper's new Louvain+ iteration. */
+lcc_status lcc_cluster_ex(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                          const lcc_options* opts, void* stream, const int32_t* init_labels,
+                          const int32_t* constraint, int32_t* labels_out, lcc_result* res);
+
 /* Cluster `count` independent graphs (each with its own lambda, vertex-weight mode and variant) in one call.
  * Results are identical to `count` separate lcc_cluster calls.  labels_out[i] and res[i] as for lcc_cluster.
  * When every graph uses LCC_LOUVAIN or LCC_PLOUVAIN (and opts->trace is NULL), the graphs are processed

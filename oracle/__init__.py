@@ -75,6 +75,9 @@ def _load():
         lib.orc_cluster.restype = ctypes.c_int
         lib.orc_cluster.argtypes = g + [ctypes.c_int, u64, u64, ctypes.c_int, ctypes.c_int, P(Opts), P(i32),
                                         P(i64), P(i64), i64, P(i64)]
+        lib.orc_cluster_ex.restype = ctypes.c_int
+        lib.orc_cluster_ex.argtypes = g + [ctypes.c_int, u64, u64, ctypes.c_int, ctypes.c_int, P(Opts), P(i32),
+                                           P(i32), P(i32), P(i64), P(i64), i64, P(i64)]
         lib.orc_setup.restype = ctypes.c_int
         lib.orc_setup.argtypes = g + [ctypes.c_int, u64, u64, ctypes.c_int, P(i64), P(u64)]
         lib.orc_objective.restype = None
@@ -127,8 +130,10 @@ class Result:
 
 
 def cluster(g, variant=PLOUVAIN, lam=(1, 1, True), vw_mode=VW_WEIGHTED_DEGREE, vw=None, opts=None,
-            trace_cap=1 << 16) -> Result:
-    """Full clustering.  ``lam`` = (num, den, over_total_weight): lambda = num/den or num/(den W)."""
+            trace_cap=1 << 16, init=None, constraint=None) -> Result:
+    """Full clustering.  ``lam`` = (num, den, over_total_weight): lambda = num/den or num/(den W).
+    ``init``: starting clustering (pLeiden: Alg. 5's C_in; Louvain: the level-0 local move's start).
+    ``constraint``: Louvain / Louvain+ coarsening confined to the constraint clusters (Sec. IV-D)."""
     lib = _load()
     keep, ga = _garrays(g, vw)
     labels = np.zeros(max(g.n, 1), dtype=np.int32)
@@ -136,9 +141,12 @@ def cluster(g, variant=PLOUVAIN, lam=(1, 1, True), vw_mode=VW_WEIGHTED_DEGREE, v
     tr = np.zeros(8 * trace_cap, dtype=np.int64)
     tcount = ctypes.c_int64(0)
     o = opts if opts is not None else make_opts()
-    st = lib.orc_cluster(*ga, vw_mode, lam[0], lam[1], int(bool(lam[2])), variant, ctypes.byref(o),
-                         _p(labels, ctypes.c_int32), _p(res, ctypes.c_int64), _p(tr, ctypes.c_int64),
-                         trace_cap, ctypes.byref(tcount))
+    ia = np.ascontiguousarray(init, dtype=np.int32) if init is not None else None
+    ca = np.ascontiguousarray(constraint, dtype=np.int32) if constraint is not None else None
+    st = lib.orc_cluster_ex(*ga, vw_mode, lam[0], lam[1], int(bool(lam[2])), variant, ctypes.byref(o),
+                            _p(ia, ctypes.c_int32), _p(ca, ctypes.c_int32),
+                            _p(labels, ctypes.c_int32), _p(res, ctypes.c_int64), _p(tr, ctypes.c_int64),
+                            trace_cap, ctypes.byref(tcount))
     del keep
     if st != 0:
         return Result(status=st)

@@ -39,6 +39,7 @@ typedef struct {
   const int32_t* idx;
   const int32_t* ew; /* NULL => all 1 */
   const int64_t* vw;
+  const int32_t* B;  /* constraint clustering of the coarsening local move (Sec. IV-D), NULL => none */
 } ograph;
 
 static inline int64_t EW(const ograph* g, int64_t j) { return g->ew ? g->ew[j] : 1; }
@@ -231,13 +232,15 @@ static void cluster_weights(const ograph* g, const int32_t* C, int64_t* Wc, int6
 }
 
 /* Destination of v (Alg. 2, the argmax and the empty-cluster rule).  Candidate destinations are the
- * clusters adjacent to v other than C[v]; ties go to the lowest cluster id.  If v's own contribution is
+ * clusters adjacent to v other than C[v] (under a constraint clustering B only through neighbours u with
+ * B[u] = B[v]: the new Louvain+ iteration of Sec. IV-D); ties go to the lowest cluster id.  If v's own contribution is
  * negative and no adjacent cluster scores >= 0, D = EMPTY with score 0.  Returns 0 when v has no
  * destination at all.  Writes *S_cur and *S_D. */
 static int destination(const ograph* g, i128 p, i128 q, const int32_t* C, scratch* s, int64_t v,
                        int32_t* D, i128* S_cur, i128* S_D) {
   int64_t nt = 0;
   for (int64_t j = g->off[v]; j < g->off[v + 1]; ++j) {
+    if (g->B && g->B[g->idx[j]] != g->B[v]) continue;
     int32_t c = C[g->idx[j]];
     if (s->acc[c] == 0) s->touched[nt++] = c;
     s->acc[c] += EW(g, j);
@@ -668,10 +671,11 @@ typedef struct {
   int32_t *idx, *ew;
   int32_t* map;      /* fine vertex -> coarse vertex of the next level */
   int32_t* C;        /* clustering of this level */
+  int32_t* Bown;     /* constraint of the coarse vertices (owned, NULL at level 0 or unconstrained) */
 } level_t;
 
 static void level_free(level_t* L, int owned) {
-  if (owned) { free(L->off); free(L->vw); free(L->idx); free(L->ew); }
+  if (owned) { free(L->off); free(L->vw); free(L->idx); free(L->ew); free(L->Bown); }
   free(L->map);
   free(L->C);
 }
@@ -703,18 +707,26 @@ static void make_next_level(level_t* lv, int64_t l, const int32_t* labels, int64
   orc_contract(n, L->g.off, L->g.idx, L->g.ew, L->g.vw, NULL, NULL, L->map, nc, N->off, N->idx, N->ew,
                N->vw, NULL, NULL);
   N->g.n = nc; N->g.off = N->off; N->g.idx = N->idx; N->g.ew = N->ew; N->g.vw = N->vw;
+  if (L->g.B) {  /* a coarse vertex lies inside one constraint cluster: it inherits that cluster */
+    N->Bown = (int32_t*)xcalloc((size_t)nc, sizeof(int32_t));
+    for (int64_t v = 0; v < n; ++v) N->Bown[L->map[v]] = L->g.B[v];
+    N->g.B = N->Bown;
+  }
   N->C = (int32_t*)xcalloc((size_t)nc, sizeof(int32_t));
   *nc_out = nc;
 }
 
-/* Alg. 1: Louvain (no uncoarsening) and Louvain+ (local move again after each projection). */
-static int run_louvain(level_t* lv, i128 p, i128 q, const orc_opts* o, int plus, tracer* tr, int64_t* top,
-                       uint32_t* flags) {
+/* Alg. 1: Louvain (no uncoarsening) and Louvain+ (local move again after each projection).
+ * init (optional): the level-0 local move starts from it instead of singletons (the iteration the Leiden
+ * authors describe).  A constraint clustering lv[0].g.B (optional) confines the coarsening local moves to
+ * clusters inside one constraint cluster; the uncoarsening local moves are free (the iteration of Sec. IV-D). */
+static int run_louvain(level_t* lv, i128 p, i128 q, const orc_opts* o, int plus, const int32_t* init,
+                       tracer* tr, int64_t* top, uint32_t* flags) {
   int64_t l = 0;
   for (;;) {
     level_t* L = &lv[l];
     int64_t n = L->g.n;
-    for (int64_t v = 0; v < n; ++v) L->C[v] = (int32_t)v;
+    for (int64_t v = 0; v < n; ++v) L->C[v] = (l == 0 && init) ? init[v] : (int32_t)v;
     i128 N = local_move(&L->g, p, q, o, L->C, tr, l, 0);
     int64_t nc = count_distinct(n, L->C);
     trace_rec(tr, TR_LEVEL, l, 0, 0, n, L->g.off[n], nc, (int64_t)N);
@@ -729,7 +741,9 @@ static int run_louvain(level_t* lv, i128 p, i128 q, const orc_opts* o, int plus,
     level_t* L = &lv[k];
     for (int64_t v = 0; v < L->g.n; ++v) L->C[v] = lv[k + 1].C[L->map[v]];
     if (plus) {
-      i128 N = local_move(&L->g, p, q, o, L->C, tr, k, 1);
+      ograph free_g = L->g;
+      free_g.B = NULL;
+      i128 N = local_move(&free_g, p, q, o, L->C, tr, k, 1);
       trace_rec(tr, TR_LEVEL, k, 1, 0, L->g.n, L->g.off[L->g.n], count_distinct(L->g.n, L->C), (int64_t)N);
     }
   }
@@ -811,6 +825,14 @@ int orc_cluster(int64_t n, const int64_t* off, const int32_t* idx, const int32_t
                 int vw_mode, uint64_t lam_num, uint64_t lam_den, int lam_over_total, int variant,
                 const orc_opts* opts, int32_t* labels_out, int64_t* result, int64_t* trace,
                 int64_t trace_cap, int64_t* trace_count) {
+  return orc_cluster_ex(n, off, idx, ew, vw_in, vw_mode, lam_num, lam_den, lam_over_total, variant, opts, NULL,
+                        NULL, labels_out, result, trace, trace_cap, trace_count);
+}
+
+int orc_cluster_ex(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* ew, const int64_t* vw_in,
+                   int vw_mode, uint64_t lam_num, uint64_t lam_den, int lam_over_total, int variant,
+                   const orc_opts* opts, const int32_t* init, const int32_t* constraint, int32_t* labels_out,
+                   int64_t* result, int64_t* trace, int64_t trace_cap, int64_t* trace_count) {
   orc_opts o;
   if (opts) o = *opts; else default_opts(&o);
   if (o.max_levels <= 0 || o.max_levels > 1024 || o.pass_limit < 0 || o.n_phi < 1 || o.n_phi > 8 ||
@@ -819,22 +841,26 @@ int orc_cluster(int64_t n, const int64_t* off, const int32_t* idx, const int32_t
   for (int k = 0; k < o.n_phi; ++k)
     if (o.phi_den[k] == 0 || o.phi_num[k] > o.phi_den[k]) return ORC_ERR_INVALID;
   if (variant < ORC_LOUVAIN || variant > ORC_PLEIDEN_PLUS) return ORC_ERR_INVALID;
+  if (constraint && (init || variant == ORC_PLEIDEN || variant == ORC_PLEIDEN_PLUS)) return ORC_ERR_INVALID;
   int64_t* vw = (int64_t*)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
   uint64_t pq[2];
   int st = orc_setup(n, off, idx, ew, vw_in, vw_mode, lam_num, lam_den, lam_over_total, vw, pq);
   if (st != ORC_OK) { free(vw); return st; }
+  if (init)
+    for (int64_t v = 0; v < n; ++v)
+      if (init[v] < 0 || init[v] >= n) { free(vw); return ORC_ERR_INVALID; }
   i128 p = pq[0], q = pq[1];
   tracer tr = {trace, trace_cap, 0};
   level_t* lv = (level_t*)xcalloc((size_t)o.max_levels + 1, sizeof(level_t));
-  lv[0].g.n = n; lv[0].g.off = off; lv[0].g.idx = idx; lv[0].g.ew = ew; lv[0].g.vw = vw;
+  lv[0].g.n = n; lv[0].g.off = off; lv[0].g.idx = idx; lv[0].g.ew = ew; lv[0].g.vw = vw; lv[0].g.B = constraint;
   lv[0].C = (int32_t*)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
   int64_t top = 0;
   uint32_t flags = 0;
   if (n > 0) {
     if (variant == ORC_LOUVAIN || variant == ORC_PLOUVAIN)
-      run_louvain(lv, p, q, &o, variant == ORC_PLOUVAIN, &tr, &top, &flags);
+      run_louvain(lv, p, q, &o, variant == ORC_PLOUVAIN, init, &tr, &top, &flags);
     else
-      run_leiden(lv, p, q, &o, variant == ORC_PLEIDEN_PLUS, NULL, &tr, &top, &flags);
+      run_leiden(lv, p, q, &o, variant == ORC_PLEIDEN_PLUS, init, &tr, &top, &flags);
   }
   int32_t* id_map = (int32_t*)xcalloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
   int64_t nc = n > 0 ? compact_labels(n, lv[0].C, id_map) : 0;

@@ -42,6 +42,17 @@ int orc_cluster(int64_t n, const int64_t* off, const int32_t* idx, const int32_t
                 const orc_opts* opts, int32_t* labels_out, int64_t* result, int64_t* trace,
                 int64_t trace_cap, int64_t* trace_count);
 
+/* As orc_cluster, with the iteration inputs (Sec. II-B, Sec. IV-D), each optional:
+ *   init        n labels in [0, n): pLeiden / pLeiden+ start from this clustering (Alg. 5's C_in); Louvain /
+ *               Louvain+ start the level-0 local move from it instead of singletons
+ *   constraint  n labels (any int32): Louvain / Louvain+ only, and not together with init; the coarsening
+ *               local moves may only join clusters whose members share the vertex's constraint label, the
+ *               uncoarsening local moves are free */
+int orc_cluster_ex(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* ew, const int64_t* vw_in,
+                   int vw_mode, uint64_t lam_num, uint64_t lam_den, int lam_over_total, int variant,
+                   const orc_opts* opts, const int32_t* init, const int32_t* constraint, int32_t* labels_out,
+                   int64_t* result, int64_t* trace, int64_t trace_cap, int64_t* trace_count);
+
 /* Setup only: validate, derive vertex weights into vw_out[n], lambda into pq[2] (reduced). */
 int orc_setup(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* ew, const int64_t* vw_in,
               int vw_mode, uint64_t lam_num, uint64_t lam_den, int lam_over_total, int64_t* vw_out,

@@ -133,15 +133,19 @@ struct Score {
 // graph keeps its own lambda and tie window, and every id-dependent choice (the afterburner's hash order) uses
 // the graph-local id, so each graph's result equals the result of clustering it alone.
 // ScoreSrc gives the kernels the scoring parameters of a vertex: `s` for every vertex of a single graph, or
-// tab[gid[v]] in a union.  ownv (union only) receives each vertex's weight to its own cluster.
+// tab[gid[v]] in a union.  ownv (union only) receives each vertex's weight to its own cluster.  cons (optional)
+// is a constraint clustering of the level's vertices: a vertex only considers the clusters of neighbours with
+// its own constraint label (the coarsening of the constrained Louvain+ iteration).
 struct ScoreSrc {
   Score s{};
   const Score* tab = nullptr;
   const int32_t* gid = nullptr;
   const int32_t* vbase = nullptr;
   int64_t* ownv = nullptr;
+  const int32_t* cons = nullptr;
   __device__ __forceinline__ Score at(int32_t v) const { return tab ? tab[gid[v]] : s; }
   __device__ __forceinline__ int32_t base(int32_t v) const { return tab ? vbase[gid[v]] : 0; }
+  __device__ __forceinline__ int32_t con(int32_t v) const { return cons ? cons[v] : 0; }
 };
 
 // Per-graph state of a union local move (device arrays; G graphs).
@@ -274,6 +278,7 @@ struct LMBuffers {
 struct LMParams {
   Score sc;
   SegLM seg;       // union of several graphs when seg.G > 0 (sc unused then)
+  const int32_t* cons = nullptr;  // constraint clustering of the level's vertices (or null)
   int pass_limit;
   uint32_t phi_num[MAX_PASSES + 1], phi_den[MAX_PASSES + 1];  // per pass (1-based)
   int64_t sum_w2;  // sum of w(v)^2 of the level

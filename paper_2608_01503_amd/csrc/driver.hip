@@ -269,6 +269,8 @@ struct Level {
   int32_t* vbase = nullptr;
   std::vector<int32_t> hvb;
   int64_t* sumw2g = nullptr;
+  // constraint clustering of the level's vertices (constrained Louvain+ coarsening), or null
+  int32_t* B = nullptr;
 };
 
 __global__ void k_reset_level_counters(Ctrl* c) {
@@ -367,9 +369,10 @@ struct Run {
     return B;
   }
 
-  LMParams lm_params(const Level& L) {
+  LMParams lm_params(const Level& L, bool constrained = false) {
     LMParams P{};
     P.sc = sc;
+    P.cons = constrained ? L.B : nullptr;
     P.pass_limit = o.pass_limit;
     for (int i = 1; i <= o.pass_limit; ++i) {
       int k = 0;
@@ -404,7 +407,7 @@ struct Run {
     rec(-1, l, phase, 0, s, 0, 0, 0);  // marker: the pass records of slot s go here
     LMBuffers B = bufs();
     if (!singleton) copy_i32(w.C, L.C, L.g.n, st);
-    local_move(L.g, only ? *only : L.b, lm_params(L), singleton, B, w.slots + s, w.ctrl, st);
+    local_move(L.g, only ? *only : L.b, lm_params(L, phase == 0), singleton, B, w.slots + s, w.ctrl, st);
     copy_i32(L.C, w.Cout, L.g.n, st);
     return s;
   }
@@ -455,6 +458,10 @@ struct Run {
     if (G) {
       N.gid = take<int32_t>(ctx, nc);
       launch_coarse_gid(L.map, L.gid, n, N.gid, st);
+    }
+    if (L.B) {  // a coarse vertex lies inside one constraint cluster: it inherits that cluster
+      N.B = take<int32_t>(ctx, nc);
+      launch_coarse_gid(L.map, L.B, n, N.B, st);
     }
     int64_t* coff = take<int64_t>(ctx, nc + 1);
     int64_t* cvw = take<int64_t>(ctx, nc);
@@ -509,10 +516,13 @@ struct Run {
   // ---------------------------------------------------------------------------------------------------
   // Alg. 1: Louvain / Louvain+
   // ---------------------------------------------------------------------------------------------------
-  int louvain(bool plus) {
+  // init (optional): the level-0 local move starts from it instead of singletons.  A constraint in lv[0].B
+  // confines the coarsening local moves; the uncoarsening ones are free (the iteration of Sec. IV-D).
+  int louvain(bool plus, const int32_t* init = nullptr) {
     int l = 0;
+    if (init) copy_i32(lv[0].C, init, lv[0].g.n, st);
     for (;;) {
-      int s = local_move_level(l, true, 0);
+      int s = local_move_level(l, !(l == 0 && init), 0);
       Level& L = lv[l];
       int64_t nc = count_labels(L.C, L.g.n);
       LMSlot S = read_slot(s);
@@ -872,12 +882,14 @@ void check_graph_args(const lcc_graph* g) {
 
 lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_variant variant,
                         const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res,
-                        const int32_t* init_labels) {
+                        const int32_t* init_labels, const int32_t* constraint = nullptr) {
   if (!ctx) fail(LCC_ERR_INVALID, "context is NULL");
   check_graph_args(g);
   if (!res) fail(LCC_ERR_INVALID, "result is NULL");
   if (g->n > 0 && !labels_out) fail(LCC_ERR_INVALID, "labels_out is NULL");
   if (variant < LCC_LOUVAIN || variant > LCC_PLEIDEN_PLUS) fail(LCC_ERR_INVALID, "unknown variant");
+  if (constraint && (init_labels || variant == LCC_PLEIDEN || variant == LCC_PLEIDEN_PLUS))
+    fail(LCC_ERR_INVALID, "a constraint clustering applies to Louvain variants without initial labels");
   std::lock_guard<std::mutex> lock(ctx->mu);
   hip_check(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
@@ -908,9 +920,20 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
     return LCC_OK;
   }
   R.lv.reserve((size_t)R.o.max_levels + 2);
+  if (g->mem == LCC_MEM_HOST) {  // the optional per-vertex inputs follow the graph to the device
+    auto up = [&](const int32_t* src) -> const int32_t* {
+      if (!src) return nullptr;
+      int32_t* d = take<int32_t>(ctx, n);
+      hip_check(hipMemcpyAsync(d, src, (size_t)n * 4, hipMemcpyHostToDevice, st), "input copy");
+      return d;
+    };
+    init_labels = up(init_labels);
+    constraint = up(constraint);
+  }
   setup(R, g, lam, init_labels);
+  R.lv[0].B = const_cast<int32_t*>(constraint);
   int top = 0;
-  if (variant == LCC_LOUVAIN || variant == LCC_PLOUVAIN) top = R.louvain(variant == LCC_PLOUVAIN);
+  if (variant == LCC_LOUVAIN || variant == LCC_PLOUVAIN) top = R.louvain(variant == LCC_PLOUVAIN, init_labels);
   else top = R.leiden(variant == LCC_PLEIDEN_PLUS, init_labels);
   // final compaction on level 0 and the exact objective (Eq. 1) of the result
   Level& L0 = R.lv[0];
@@ -1395,6 +1418,14 @@ const char* lcc_last_error(void) { return g_last_error.c_str(); }
 }  // extern "C"
 
 // Entry used by the server (server.hip): clustering with an initial clustering for pLeiden.
+lcc_status lcc_cluster_ex(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                          const lcc_options* opts, void* stream, const int32_t* init_labels,
+                          const int32_t* constraint, int32_t* labels_out, lcc_result* res) {
+  return guarded([&]() {
+    return cluster_impl(ctx, g, lambda, variant, opts, stream, labels_out, res, init_labels, constraint);
+  });
+}
+
 lcc_status lcc_cluster_init_internal(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
                                      const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res,
                                      const int32_t* init) {

@@ -183,7 +183,8 @@ __device__ __forceinline__ void lds_insert(int32_t* hk, uint32_t* hv, int bits, 
 // a wavefront sum, and one lane inserts the total.  The loop is uniform over the wavefront (lanes past the
 // end carry no key) so the ballots and shuffles see every lane.
 __device__ __forceinline__ int64_t insert_row(const DevGraph& g, const int32_t* C, int64_t b, int64_t e, int t,
-                                              int S, int32_t cv, int32_t* hk, uint32_t* hv, int bits) {
+                                              int S, int32_t cv, int32_t* hk, uint32_t* hv, int bits,
+                                              const int32_t* cons, int32_t bv) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int64_t tw = t - lane;  // first lane of this wavefront
   int64_t own = 0;
@@ -196,6 +197,11 @@ __device__ __forceinline__ int64_t insert_row(const DevGraph& g, const int32_t* 
       cs[k] = -1;
       ws[k] = 0;
       if (j < e) { cs[k] = g.idx[j]; ws[k] = (uint32_t)g.w[j]; }
+    }
+    if (cons) {
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (cs[k] >= 0 && cons[cs[k]] != bv) cs[k] = -1;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k)
@@ -288,7 +294,7 @@ __device__ __forceinline__ void best_reduce(Best& r) {
 
 // singleton pass: best neighbour u by S = q w(u,v) - p w(v) w(u)
 __device__ __forceinline__ void single_row(const DevGraph& g, const Score& sc, int64_t b, int64_t e, int t, int S,
-                                           int64_t wv, Best& r) {
+                                           int64_t wv, Best& r, const int32_t* cons, int32_t bv) {
   for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
     int32_t us[U];
     int64_t ws[U], vu[U];
@@ -298,6 +304,11 @@ __device__ __forceinline__ void single_row(const DevGraph& g, const Score& sc, i
       us[k] = -1;
       ws[k] = 0;
       if (j < e) { us[k] = g.idx[j]; ws[k] = g.w[j]; }
+    }
+    if (cons) {
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (us[k] >= 0 && cons[us[k]] != bv) us[k] = -1;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) vu[k] = us[k] >= 0 ? g.vw[us[k]] : 0;
@@ -403,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64
     const int64_t wv = g.vw[v];
     const Score sc = ss.at(v);
     Best r = best_init();
-    single_row(g, sc, g.off[v], g.off[v + 1], gl, G, wv, r);
+    single_row(g, sc, g.off[v], g.off[v + 1], gl, G, wv, r, ss.cons, ss.con(v));
     best_reduce<G>(r);
     if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
   }
@@ -420,7 +431,7 @@ __global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t c
     const int64_t wv = g.vw[v];
     const Score sc = ss.at(v);
     Best r = best_init();
-    single_row(g, sc, g.off[v], g.off[v + 1], threadIdx.x, G, wv, r);
+    single_row(g, sc, g.off[v], g.off[v + 1], threadIdx.x, G, wv, r, ss.cons, ss.con(v));
     best_reduce<G>(r);
     if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
     __syncthreads();
@@ -438,10 +449,12 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_single_hub(const int32_t* hubs, c
   const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   const int64_t wv = g.vw[v];
+  const int32_t bv = ss.con(v);
   int64_t bs = INT64_MIN;
   int32_t bcl = INT32_MAX;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) {
     int32_t u = g.idx[j];
+    if (ss.cons && ss.cons[u] != bv) continue;
     int64_t s = sc.q * (int64_t)g.w[j] - sc.p * wv * g.vw[u];
     if (better(s, u, bs, bcl)) { bs = s; bcl = u; }
   }
@@ -471,8 +484,9 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
     const int32_t cv = C[v];
     const int64_t wv = g.vw[v];
     const Score sc = ss.at(v);
-    const bool has = gl < d;
-    const int32_t c = has ? C[g.idx[b + gl]] : -1;
+    const int32_t u = gl < d ? g.idx[b + gl] : -1;
+    const bool has = u >= 0 && (!ss.cons || ss.cons[u] == ss.cons[v]);
+    const int32_t c = has ? C[u] : -1;
     const int64_t wt = has ? (int64_t)g.w[b + gl] : 0;
     int64_t acc = 0;
     bool leader = has;
@@ -530,7 +544,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
     }
     __syncthreads();
     int64_t own_reg = 0;
-    if (active) own_reg = insert_row(g, C, b, e, lane, WAVE, cv, hk[wv], hv[wv], bits);
+    if (active) own_reg = insert_row(g, C, b, e, lane, WAVE, cv, hk[wv], hv[wv], bits, ss.cons, ss.con(v));
     __syncthreads();
     if (active) {
       const Score sc = ss.at(v);
@@ -568,7 +582,7 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
     if (bits < 1) bits = 1;
     for (int sl = threadIdx.x; sl < (1 << bits); sl += BS) { hk[sl] = -1; hv[sl] = 0; }
     __syncthreads();
-    const int64_t own_reg = insert_row(g, C, b, e, threadIdx.x, BS, cv, hk, hv, bits);
+    const int64_t own_reg = insert_row(g, C, b, e, threadIdx.x, BS, cv, hk, hv, bits, ss.cons, ss.con(v));
     __syncthreads();
     const Score sc = ss.at(v);
     Best r = best_init();
@@ -609,7 +623,8 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_clear(const int32_t* hubs, co
 // inserts one entry per distinct cluster into the hub's global table.
 __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, const int32_t* chunk_off,
                                                           int64_t n7, DevGraph g, const int32_t* C,
-                                                          uint32_t* arena, const LMSlot* slot, int pass) {
+                                                          uint32_t* arena, const LMSlot* slot, int pass,
+                                                          const int32_t* cons) {
   if (slot && slot->skip[pass]) return;
   constexpr int S = 2 * HUB_CHUNK;
   __shared__ int32_t lk[S];
@@ -623,7 +638,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, c
   for (int s = threadIdx.x; s < S; s += HUB_BLOCK) { lk[s] = -1; lv[s] = 0; }
   __syncthreads();
   // own-cluster edges also go through the table here (the scan reads the hub's own weight from it)
-  const int64_t own = insert_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, -3, lk, lv, 13);
+  const int64_t own = insert_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, -3, lk, lv, 13, cons, cons ? cons[v] : 0);
   (void)own;
   __syncthreads();
   uint32_t* tab = arena + 4 * base;
@@ -1490,7 +1505,7 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   if (n7) {
     unsigned nc = (unsigned)b.hub_chunks;
     prof_begin(PF_ENUM_B0 + 7, st);
-    k_hub_insert<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, bufs.arena, slot, pass);
+    k_hub_insert<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, bufs.arena, slot, pass, sc.cons);
     k_hub_scan<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, W, sc, bufs.arena, hs.ps, hs.pc, hs.pown, slot, pass,
                                          P ? P + 7 : nullptr);
     k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, C, W, sc, pa, pb, strict, hs.ps,
@@ -1583,6 +1598,7 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
   const int64_t G = sg.G;
   ScoreSrc sc;
   sc.s = prm.sc;
+  sc.cons = prm.cons;
   if (G) { sc.tab = sg.score; sc.gid = sg.gid; sc.vbase = sg.vbase; sc.ownv = sg.ownv; }
   zero_bytes(slot, sizeof(LMSlot), st);
   // starting state: cluster weights, sizes, C_out = C, sum of squared cluster weights (state 0)

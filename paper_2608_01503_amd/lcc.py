@@ -25,7 +25,7 @@ LCC_MEM_HOST, LCC_MEM_DEVICE = 0, 1
 LCC_FLAG_LEVEL_CAP, LCC_FLAG_REFINE_NO_PROGRESS = 1, 2
 
 EXPORTED = ["lcc_create", "lcc_destroy", "lcc_default_options", "lcc_workspace_bytes", "lcc_cluster",
-            "lcc_cluster_batch", "lcc_objective", "lcc_server_create", "lcc_submit", "lcc_poll",
+            "lcc_cluster_ex", "lcc_cluster_batch", "lcc_objective", "lcc_server_create", "lcc_submit", "lcc_poll",
             "lcc_server_destroy", "lcc_profile_enable", "lcc_profile_read", "lcc_status_string", "lcc_last_error"]
 
 # kernel families of lcc_profile_enable (bit = index) and the kernel each one times
@@ -99,6 +99,9 @@ def load():
     lib.lcc_workspace_bytes.argtypes = [i64, i64, ctypes.c_int, P(ctypes.c_size_t)]
     lib.lcc_cluster.restype = st
     lib.lcc_cluster.argtypes = [v, P(lcc_graph), lcc_lambda, ctypes.c_int, P(lcc_options), v, v, P(lcc_result)]
+    lib.lcc_cluster_ex.restype = st
+    lib.lcc_cluster_ex.argtypes = [v, P(lcc_graph), lcc_lambda, ctypes.c_int, P(lcc_options), v, v, v, v,
+                                   P(lcc_result)]
     lib.lcc_cluster_batch.restype = st
     lib.lcc_cluster_batch.argtypes = [v, P(lcc_graph), P(lcc_lambda), P(ctypes.c_int), i64, P(lcc_options), v,
                                       P(v), P(lcc_result)]
@@ -257,9 +260,10 @@ class Context:
             pass
 
     def cluster(self, graph: lcc_graph, lam=(1, 1, True), variant=LCC_PLOUVAIN, opts: lcc_options | None = None,
-                labels_out=None, stream=None, trace_capacity: int = 0):
+                labels_out=None, stream=None, trace_capacity: int = 0, init=None, constraint=None):
         """Cluster one graph.  Returns (labels, Result).  labels_out defaults to a new int32 array in the
-        graph's memory space (torch tensor on the device, numpy on the host)."""
+        graph's memory space (torch tensor on the device, numpy on the host).  init / constraint: optional
+        int32 arrays in the graph's memory space (lcc_cluster_ex)."""
         lib = load()
         n = graph.n
         if labels_out is None:
@@ -277,8 +281,12 @@ class Context:
             o.trace = ctypes.pointer(tr)
         res = lcc_result()
         st = _stream_handle(stream, graph)
-        _check(lib.lcc_cluster(self.handle, ctypes.byref(graph), lam_of(lam), variant, ctypes.byref(o), st,
-                               _ptr(labels_out), ctypes.byref(res)))
+        if init is None and constraint is None:
+            _check(lib.lcc_cluster(self.handle, ctypes.byref(graph), lam_of(lam), variant, ctypes.byref(o), st,
+                                   _ptr(labels_out), ctypes.byref(res)))
+        else:
+            _check(lib.lcc_cluster_ex(self.handle, ctypes.byref(graph), lam_of(lam), variant, ctypes.byref(o), st,
+                                      _ptr(init), _ptr(constraint), _ptr(labels_out), ctypes.byref(res)))
         trace = None
         if tr is not None:
             cnt = min(tr.count, trace_capacity)

@@ -35,26 +35,34 @@ def host_graph(g, vw_mode, vw=None):
                         vw_mode)
 
 
-def run_gpu(g, variant, lam, vw_mode, vw=None, opts_kw=None, host=False, offsets32=False, trace=True):
+def run_gpu(g, variant, lam, vw_mode, vw=None, opts_kw=None, host=False, offsets32=False, trace=True, init=None,
+            constraint=None):
     import torch
     import paper_2608_01503_amd as L
     graph = host_graph(g, vw_mode, vw) if host else device_graph(g, vw_mode, vw, offsets32)
     opts = L.lcc_default_options(**(opts_kw or {}))
-    labels, res = ctx().cluster(graph, lam, variant, opts, trace_capacity=1 << 14 if trace else 0)
+
+    def arr(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        return a if host else torch.from_numpy(a).cuda()
+    labels, res = ctx().cluster(graph, lam, variant, opts, trace_capacity=1 << 14 if trace else 0,
+                                init=arr(init), constraint=arr(constraint))
     torch.cuda.synchronize()
     lab = labels if isinstance(labels, np.ndarray) else labels.cpu().numpy()
     return lab, res
 
 
-def run_oracle(g, variant, lam, vw_mode, vw=None, opts_kw=None):
+def run_oracle(g, variant, lam, vw_mode, vw=None, opts_kw=None, init=None, constraint=None):
     kw = dict(opts_kw or {})
     kw.pop("validate", None)
     o = O.make_opts(**kw) if kw else None
-    return O.cluster(g, variant, lam=lam, vw_mode=vw_mode, vw=vw, opts=o)
+    return O.cluster(g, variant, lam=lam, vw_mode=vw_mode, vw=vw, opts=o, init=init, constraint=constraint)
 
 
 def assert_parity(g, variant, lam, vw_mode, vw=None, opts_kw=None, **kw):
-    ref = run_oracle(g, variant, lam, vw_mode, vw, opts_kw)
+    ref = run_oracle(g, variant, lam, vw_mode, vw, opts_kw, init=kw.get("init"), constraint=kw.get("constraint"))
     lab, res = run_gpu(g, variant, lam, vw_mode, vw, opts_kw, **kw)
     assert ref.status == 0
     assert np.array_equal(lab, ref.labels), f"labels differ ({(lab != ref.labels).sum()} of {g.n})"

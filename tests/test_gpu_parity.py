@@ -174,3 +174,41 @@ def test_pleiden_cpm_large_alternate_moves():
     ref, res = U.assert_parity(g, O.PLEIDEN, (1, 10, False), O.VW_UNIT)
     k = [int(r[4]) for r in ref.trace if r[0] == 3]
     assert len(k) > 10 and max(k) > 4096
+
+
+@pytest.mark.parametrize("variant", [O.PLEIDEN, O.PLEIDEN_PLUS])
+def test_iterated_pleiden_from_initial_clustering(variant):
+    """pLeiden fed its own previous output (Alg. 5's C_in), three iterations, each against the oracle."""
+    for g, obj in [(gg.config1_sbm(), MOD), (gg.rmat(13, 16, seed=12), CPM20), (U.hub_graph(), MOD)]:
+        prev = U.run_oracle(g, variant, *obj).labels
+        for _ in range(3):
+            ref, res = U.assert_parity(g, variant, *obj, init=prev)
+            prev = ref.labels
+
+
+def test_louvain_initial_and_constraint_clusterings():
+    rng = np.random.default_rng(4)
+    for g, obj in [(gg.config1_sbm(), MOD), (gg.rmat(14, 16, seed=13), MOD), (gg.lattice(60, 50, 0.1, 100, 3), CPM20),
+                   (U.hub_graph(), CPM3)]:
+        first = U.run_oracle(g, O.PLOUVAIN, *obj)
+        # the Louvain+ iteration of Sec. IV-D: the previous result as the constraint
+        U.assert_parity(g, O.PLOUVAIN, *obj, constraint=first.labels)
+        U.assert_parity(g, O.LOUVAIN, *obj, constraint=rng.integers(0, 9, size=g.n))
+        # the older iteration: the previous result as the level-0 start
+        U.assert_parity(g, O.PLOUVAIN, *obj, init=first.labels)
+    g = gg.random_gnp(2500, 0.003, 17, w_max=4)
+    first = U.run_oracle(g, O.PLOUVAIN, *MOD)
+    U.assert_parity(g, O.PLOUVAIN, *MOD, host=True, constraint=first.labels)
+    U.assert_parity(g, O.PLEIDEN, *MOD, host=True, init=first.labels)
+
+
+def test_iteration_input_errors():
+    import paper_2608_01503_amd as L
+    g = gg.random_gnp(300, 0.02, 7, w_max=3)
+    z = np.zeros(g.n, dtype=np.int32)
+    for kw, variant in [(dict(constraint=z), O.PLEIDEN), (dict(constraint=z, init=z), O.PLOUVAIN),
+                        (dict(init=np.full(g.n, g.n, dtype=np.int32)), O.PLEIDEN)]:
+        assert U.run_oracle(g, variant, *MOD, **kw).status == -1
+        with pytest.raises(L.LccError) as e:
+            U.run_gpu(g, variant, *MOD, **kw)
+        assert e.value.status == -1

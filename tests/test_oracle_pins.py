@@ -588,3 +588,87 @@ def test_config1_quality_and_determinism():
     planted = np.arange(g.n) // 100
     Qp = defs.textbook_modularity(g, planted)
     assert r1.num_clusters == 20 and abs(Q - Qp) < 0.02
+
+
+# ------------------------------------------------------------------------------------------------
+# iteration inputs (Sec. II-B, Sec. IV-D): initial clustering and constraint clustering
+# ------------------------------------------------------------------------------------------------
+
+def _node_optimal(g, labels, vw, p, q):
+    """Every vertex is node optimal (Sec. II-B): no move to a neighbouring cluster or to a new singleton
+    (score 0) strictly improves the objective.  Exact integer scores from the definitions."""
+    labels = np.asarray(labels, dtype=np.int64)
+    Wc = {}
+    for v in range(g.n):
+        Wc[int(labels[v])] = Wc.get(int(labels[v]), 0) + int(vw[v])
+    for v in range(g.n):
+        cv = int(labels[v])
+        a = {}
+        for j in range(g.off[v], g.off[v + 1]):
+            c = int(labels[g.idx[j]])
+            a[c] = a.get(c, 0) + int(g.w[j])
+        wv = int(vw[v])
+        s_cur = q * a.get(cv, 0) - p * wv * (Wc[cv] - wv)
+        best = max([q * av - p * wv * Wc[c] for c, av in a.items() if c != cv] + [0])
+        if best > s_cur:
+            return False
+    return True
+
+
+def test_iterated_pleiden_stable_iteration_is_node_optimal():
+    """Feeding pLeiden its own output (Alg. 5 with C_in) until the output repeats: in a stable iteration every
+    vertex is node optimal (Sec. II-B), every cluster is connected and clusters are gamma-separated."""
+    graphs = [gg.config1_sbm(), gg.random_gnp(300, 0.03, 71, w_max=5), gg.lattice(12, 12, 0.1, 100, 3)]
+    for g in graphs:
+        for mode, lam in [(O.VW_WEIGHTED_DEGREE, (1, 1, True)), (O.VW_UNIT, (1, 20, False))]:
+            st, vw, p, q = O.setup(g, mode, lam)
+            r = O.cluster(g, O.PLEIDEN, lam=lam, vw_mode=mode)
+            stable = False
+            for _ in range(30):
+                r2 = O.cluster(g, O.PLEIDEN, lam=lam, vw_mode=mode, init=r.labels)
+                assert r2.status == 0 and r2.N >= r.N  # an iteration never loses objective
+                if defs.same_partition(r2.labels, r.labels):
+                    stable = True
+                    break
+                r = r2
+            assert stable, (g.name, lam)
+            assert _node_optimal(g, r.labels, vw, p, q)
+            for mem in defs.clusters_of(r.labels).values():
+                assert defs.connected_within(g, mem)
+
+
+def test_louvain_init_is_the_level0_start():
+    """Louvain from an initial clustering: the level-0 local move starts from it.  Starting from the
+    singletons is the plain run; starting from a node-optimal stable clustering changes nothing at level 0."""
+    g = gg.random_gnp(400, 0.02, 81, w_max=4)
+    r = O.cluster(g, O.LOUVAIN)
+    same = O.cluster(g, O.LOUVAIN, init=np.arange(g.n, dtype=np.int32))
+    assert np.array_equal(same.labels, r.labels) and same.N == r.N
+    bad = O.cluster(g, O.PLOUVAIN, init=np.full(g.n, g.n, dtype=np.int32))
+    assert bad.status == -1
+
+
+def test_constraint_special_cases():
+    """One constraint cluster = no constraint; singleton constraints forbid every merge (all singletons)."""
+    for g in [gg.config1_sbm(), gg.random_gnp(500, 0.01, 91, w_max=7)]:
+        for mode, lam in [(O.VW_WEIGHTED_DEGREE, (1, 1, True)), (O.VW_UNIT, (1, 20, False))]:
+            free = O.cluster(g, O.PLOUVAIN, lam=lam, vw_mode=mode)
+            one = O.cluster(g, O.PLOUVAIN, lam=lam, vw_mode=mode, constraint=np.full(g.n, 7, dtype=np.int32))
+            assert np.array_equal(one.labels, free.labels) and one.N == free.N
+            sing = O.cluster(g, O.PLOUVAIN, lam=lam, vw_mode=mode, constraint=np.arange(g.n, dtype=np.int32))
+            assert sing.num_clusters == g.n and sing.levels == 1
+    g = gg.config1_sbm()
+    assert O.cluster(g, O.PLEIDEN, constraint=np.zeros(g.n, np.int32)).status == -1
+    assert O.cluster(g, O.PLOUVAIN, init=np.arange(g.n, dtype=np.int32),
+                     constraint=np.zeros(g.n, np.int32)).status == -1
+
+
+def test_constrained_coarsening_stays_inside_constraint():
+    """Without uncoarsening (LOUVAIN) the result is the coarsening's: every cluster lies inside one constraint
+    cluster (Sec. IV-D: the constrained coarsening only joins clusters inside a constraint cluster)."""
+    rng = np.random.default_rng(5)
+    for g in [gg.config1_sbm(), gg.random_gnp(600, 0.01, 95, w_max=3), gg.lattice(15, 15, 0.1, 100, 3)]:
+        B = rng.integers(0, 6, size=g.n).astype(np.int32)
+        r = O.cluster(g, O.LOUVAIN, constraint=B)
+        for mem in defs.clusters_of(r.labels).values():
+            assert len({int(B[v]) for v in mem}) == 1
