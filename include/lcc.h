@@ -110,7 +110,17 @@ typedef struct {
   int32_t max_levels;
   int32_t validate;
   lcc_trace* trace;
+  int32_t symmetry;  /* LCC_SYM_*: the local move's symmetry breaking (default LCC_SYM_AFTERBURNER) */
+  int32_t reserved;  /* 0 */
 } lcc_options;
+
+/* Symmetry breaking of the local move (Sec. IV-A); the other two are the ablations of Table 2:
+ *   LCC_SYM_AFTERBURNER  the afterburner filter, Alg. 3
+ *   LCC_SYM_NONE         no symmetry breaking: every candidate moves
+ *   LCC_SYM_MLH          minimum label heuristic in odd passes (a candidate moves only to a cluster of lower id
+ *                        than its current one, or to a new singleton); every candidate moves in even passes
+ * The paper pairs both ablations with phi = 0 (phi_num = 0 in every phase). */
+enum { LCC_SYM_AFTERBURNER = 0, LCC_SYM_NONE = 1, LCC_SYM_MLH = 2 };
 
 enum { LCC_FLAG_LEVEL_CAP = 1, LCC_FLAG_REFINE_NO_PROGRESS = 2 };
 

@@ -44,11 +44,16 @@ class Opts(ctypes.Structure):
     _fields_ = [("pass_limit", ctypes.c_int32), ("n_phi", ctypes.c_int32),
                 ("phi_num", ctypes.c_uint32 * 8), ("phi_den", ctypes.c_uint32 * 8),
                 ("phi_until", ctypes.c_uint32 * 8), ("eps_num", ctypes.c_uint32),
-                ("eps_den", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("max_levels", ctypes.c_int32)]
+                ("eps_den", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("max_levels", ctypes.c_int32),
+                ("symmetry", ctypes.c_int32)]
 
 
-def make_opts(pass_limit=6, phases=((3, 4, 4), (1, 4, 6)), eps=(1, 10), seed=1, max_levels=64) -> Opts:
-    """Options: ``phases`` is a list of (phi_num, phi_den, last_pass)."""
+SYM_AFTERBURNER, SYM_NONE, SYM_MLH = 0, 1, 2
+
+
+def make_opts(pass_limit=6, phases=((3, 4, 4), (1, 4, 6)), eps=(1, 10), seed=1, max_levels=64,
+              symmetry=SYM_AFTERBURNER) -> Opts:
+    """Options: ``phases`` is a list of (phi_num, phi_den, last_pass); ``symmetry`` an ORC_SYM_* mode."""
     o = Opts()
     o.pass_limit = pass_limit
     o.n_phi = len(phases)
@@ -57,6 +62,7 @@ def make_opts(pass_limit=6, phases=((3, 4, 4), (1, 4, 6)), eps=(1, 10), seed=1, 
     o.eps_num, o.eps_den = eps
     o.seed = seed
     o.max_levels = max_levels
+    o.symmetry = symmetry
     return o
 
 
@@ -83,7 +89,8 @@ def _load():
         lib.orc_objective.restype = None
         lib.orc_objective.argtypes = g + [u64, u64, P(i32), P(i64)]
         lib.orc_lm_pass.restype = None
-        lib.orc_lm_pass.argtypes = g + [u64, u64, u32, u32, u32, u32, P(i32), P(i32), P(i64), P(u64), P(i64),
+        lib.orc_lm_pass.argtypes = g + [u64, u64, u32, u32, u32, u32, ctypes.c_int32, ctypes.c_int32, P(i32), P(i32),
+                                        P(i64), P(u64), P(i64),
                                         P(u64), P(ctypes.c_uint8), P(ctypes.c_uint8), P(i64)]
         lib.orc_local_move.restype = None
         lib.orc_local_move.argtypes = g + [u64, u64, P(Opts), P(i32), P(i64)]
@@ -178,7 +185,7 @@ def objective(g, vw, p, q, C) -> int:
     return _i128(out[0], out[1])
 
 
-def lm_pass(g, vw, p, q, C, phi=(3, 4), eps=(1, 10)):
+def lm_pass(g, vw, p, q, C, phi=(3, 4), eps=(1, 10), symmetry=0, pass_no=1):
     """One synchronous pass; returns dict with the new C and the per-vertex decisions."""
     lib = _load()
     keep, ga = _garrays(g, vw)
@@ -192,7 +199,7 @@ def lm_pass(g, vw, p, q, C, phi=(3, 4), eps=(1, 10)):
     cand = np.zeros(n, np.uint8)
     kp = np.zeros(n, np.uint8)
     cnt = np.zeros(2, np.int64)
-    lib.orc_lm_pass(*ga, p, q, phi[0], phi[1], eps[0], eps[1], _p(C, ctypes.c_int32), _p(D, ctypes.c_int32),
+    lib.orc_lm_pass(*ga, p, q, phi[0], phi[1], eps[0], eps[1], symmetry, pass_no, _p(C, ctypes.c_int32), _p(D, ctypes.c_int32),
                     _p(dh, ctypes.c_int64), _p(dl, ctypes.c_uint64), _p(ah, ctypes.c_int64), _p(al, ctypes.c_uint64), _p(cand, ctypes.c_uint8),
                     _p(kp, ctypes.c_uint8), _p(cnt, ctypes.c_int64))
     del keep

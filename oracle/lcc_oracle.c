@@ -287,9 +287,10 @@ static void apply_moves(const ograph* g, int32_t* C, const int32_t* D, const uin
 }
 
 /* One pass of Alg. 2 from the snapshot C, with temperature phi = phi_num / phi_den, followed by the
- * afterburner filter of Alg. 3 and the update.  Counts |L| and |M| into counts. */
+ * symmetry breaking (the afterburner filter of Alg. 3, or an ablation of Table 2) and the update.  `pass` is
+ * the 1-based pass number (the minimum label heuristic is active in odd passes).  Counts |L| and |M|. */
 static void lm_pass(const ograph* g, i128 p, i128 q, uint32_t phi_num, uint32_t phi_den, uint32_t eps_num,
-                    uint32_t eps_den, int32_t* C, scratch* s, int64_t* counts) {
+                    uint32_t eps_den, int symmetry, int pass, int32_t* C, scratch* s, int64_t* counts) {
   int64_t n = g->n;
   cluster_weights(g, C, s->Wc, s->size);
   int64_t nL = 0, nM = 0;
@@ -303,6 +304,19 @@ static void lm_pass(const ograph* g, i128 p, i128 q, uint32_t phi_num, uint32_t 
     s->delta[v] = sd - scur;
     /* candidate test: w'(v, D) >= (1 - phi) w'(v, C[v]) */
     if ((i128)phi_den * sd >= (i128)(phi_den - phi_num) * scur) { s->cand[v] = 1; ++nL; }
+  }
+  if (symmetry != ORC_SYM_AFTERBURNER) {
+    for (int64_t v = 0; v < n; ++v) {
+      if (!s->cand[v]) continue;
+      s->dadj[v] = s->delta[v];
+      int ok = 1;
+      if (symmetry == ORC_SYM_MLH && (pass & 1)) ok = s->D[v] == ORC_EMPTY || s->D[v] < C[v];
+      if (ok) { s->keep[v] = 1; ++nM; }
+    }
+    apply_moves(g, C, s->D, s->keep, s->size);
+    counts[0] = nL;
+    counts[1] = nM;
+    return;
   }
   /* Alg. 3: adjust delta_v by every adjacent candidate ordered before v */
   for (int64_t v = 0; v < n; ++v) {
@@ -329,12 +343,13 @@ static void lm_pass(const ograph* g, i128 p, i128 q, uint32_t phi_num, uint32_t 
 
 void orc_lm_pass(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* ew, const int64_t* vw,
                  uint64_t p, uint64_t q, uint32_t phi_num, uint32_t phi_den, uint32_t eps_num,
-                 uint32_t eps_den, int32_t* C, int32_t* D, int64_t* delta_hi, uint64_t* delta_lo,
-                 int64_t* dadj_hi, uint64_t* dadj_lo, uint8_t* cand, uint8_t* keep, int64_t* counts) {
+                 uint32_t eps_den, int32_t symmetry, int32_t pass, int32_t* C, int32_t* D, int64_t* delta_hi,
+                 uint64_t* delta_lo, int64_t* dadj_hi, uint64_t* dadj_lo, uint8_t* cand, uint8_t* keep,
+                 int64_t* counts) {
   ograph g = {n, off, idx, ew, vw};
   scratch s;
   scratch_init(&s, n);
-  lm_pass(&g, p, q, phi_num, phi_den, eps_num, eps_den, C, &s, counts);
+  lm_pass(&g, p, q, phi_num, phi_den, eps_num, eps_den, symmetry, pass, C, &s, counts);
   for (int64_t v = 0; v < n; ++v) {
     if (D) D[v] = s.D[v];
     if (delta_hi) delta_hi[v] = (int64_t)(s.delta[v] >> 64);
@@ -385,7 +400,7 @@ static i128 local_move(const ograph* g, i128 p, i128 q, const orc_opts* o, int32
     uint32_t pn, pd;
     phi_of_pass(o, i, &pn, &pd);
     int64_t counts[2];
-    lm_pass(g, p, q, pn, pd, o->eps_num, o->eps_den, C, &s, counts);
+    lm_pass(g, p, q, pn, pd, o->eps_num, o->eps_den, o->symmetry, i, C, &s, counts);
     i128 N = objective(g, p, q, C);
     trace_rec(tr, TR_LMPASS, level, phase, i, counts[0], counts[1], (int64_t)N, 0);
     if (N > Nbest) { Nbest = N; memcpy(Cout, C, (size_t)n * sizeof(int32_t)); }
@@ -836,7 +851,7 @@ int orc_cluster_ex(int64_t n, const int64_t* off, const int32_t* idx, const int3
   orc_opts o;
   if (opts) o = *opts; else default_opts(&o);
   if (o.max_levels <= 0 || o.max_levels > 1024 || o.pass_limit < 0 || o.n_phi < 1 || o.n_phi > 8 ||
-      o.eps_den == 0)
+      o.eps_den == 0 || o.symmetry < ORC_SYM_AFTERBURNER || o.symmetry > ORC_SYM_MLH)
     return ORC_ERR_INVALID;
   for (int k = 0; k < o.n_phi; ++k)
     if (o.phi_den[k] == 0 || o.phi_num[k] > o.phi_den[k]) return ORC_ERR_INVALID;

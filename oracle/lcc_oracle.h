@@ -31,7 +31,15 @@ typedef struct {
   uint32_t eps_num, eps_den;                          /* afterburner tie window, 1/10 */
   uint64_t seed;                                      /* refinement randomness */
   int32_t max_levels;                                 /* 64 */
+  int32_t symmetry;                                   /* ORC_SYM_*: afterburner (default) or an ablation */
 } orc_opts;
+
+/* Symmetry breaking of the local move (Sec. IV-A; the ablations of Table 2):
+ *   ORC_SYM_AFTERBURNER  Alg. 3
+ *   ORC_SYM_NONE         every candidate moves
+ *   ORC_SYM_MLH          minimum label heuristic in odd passes (a candidate moves only to a cluster of lower
+ *                        id than its own, or to a new singleton), every candidate moves in even passes */
+enum { ORC_SYM_AFTERBURNER = 0, ORC_SYM_NONE = 1, ORC_SYM_MLH = 2 };
 
 /* Full clustering: setup (validation, vertex weights, lambda = p/q), then the chosen variant.
  * labels_out[n]: compact labels 0..c-1.  result[0..5] = {num_clusters, N_hi, N_lo (objective numerator,
@@ -67,8 +75,9 @@ void orc_objective(int64_t n, const int64_t* off, const int32_t* idx, const int3
  * counts[0] = |L|, counts[1] = |M|.  Any output pointer may be NULL. */
 void orc_lm_pass(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* ew, const int64_t* vw,
                  uint64_t p, uint64_t q, uint32_t phi_num, uint32_t phi_den, uint32_t eps_num,
-                 uint32_t eps_den, int32_t* C, int32_t* D, int64_t* delta_hi, uint64_t* delta_lo,
-                 int64_t* dadj_hi, uint64_t* dadj_lo, uint8_t* cand, uint8_t* keep, int64_t* counts);
+                 uint32_t eps_den, int32_t symmetry, int32_t pass, int32_t* C, int32_t* D, int64_t* delta_hi,
+                 uint64_t* delta_lo, int64_t* dadj_hi, uint64_t* dadj_lo, uint8_t* cand, uint8_t* keep,
+                 int64_t* counts);
 
 /* LocalMovePasses from C (in place: C becomes C_out).  Returns the objective of C_out in N_hi_lo. */
 void orc_local_move(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* ew, const int64_t* vw,

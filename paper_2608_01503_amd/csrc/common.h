@@ -257,7 +257,7 @@ void launch_internal_per_vertex(const DevGraph& g, const Buckets& b, const int32
 // chunk offsets of the hubs (n7 entries of the last bucket): chunk_off[n7+1] via cnt[n7] scratch
 void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt, int32_t* chunk_off,
                        void* temp, hipStream_t st);
-constexpr int64_t HUB_CHUNK_EDGES = 4096;
+constexpr int64_t HUB_CHUNK_EDGES = 2048;
 void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st);
 
 struct LMBuffers {
@@ -279,6 +279,7 @@ struct LMParams {
   Score sc;
   SegLM seg;       // union of several graphs when seg.G > 0 (sc unused then)
   const int32_t* cons = nullptr;  // constraint clustering of the level's vertices (or null)
+  int symmetry = 0;                // 0 afterburner (Alg. 3), 1 none, 2 minimum label heuristic in odd passes
   int pass_limit;
   uint32_t phi_num[MAX_PASSES + 1], phi_den[MAX_PASSES + 1];  // per pass (1-based)
   int64_t sum_w2;  // sum of w(v)^2 of the level

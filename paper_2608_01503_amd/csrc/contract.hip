@@ -21,7 +21,11 @@ inline unsigned grid_for(int64_t n) {
   if (g > 65536) g = 65536;
   return (unsigned)g;
 }
-inline unsigned grp_blocks(int64_t cnt, int G) { return (unsigned)cdiv(cnt, BLOCK / G); }
+// persistent launches (at most 2048 workgroups looping over their share of the vertices)
+inline unsigned grp_blocks(int64_t cnt, int G) {
+  int64_t b = cdiv(cnt, BLOCK / G);
+  return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
 
 __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
   int64_t lo = 0, hi = n7;
@@ -83,15 +87,16 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_cross_count_grp(const int32_t* list, int64_t cnt, DevGraph g,
                                                            const int32_t* map, int32_t* out) {
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
-  if (gid >= cnt) return;
-  const int32_t v = list[gid];
-  const int32_t x = map[v];
-  int c = 0;
-  for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) c += map[g.idx[j]] != x;
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
+    const int32_t v = list[gid];
+    const int32_t x = map[v];
+    int c = 0;
+    for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) c += map[g.idx[j]] != x;
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, G);
-  if (gl == 0) out[v] = c;
+    for (int o = G / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, G);
+    if (gl == 0) out[v] = c;
+  }
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_cross_count_chunk(const int32_t* hubs, const int32_t* chunk_off,
@@ -116,7 +121,9 @@ __global__ __launch_bounds__(BLOCK) void k_cross_emit_grp(const int32_t* list, i
                                                           const int32_t* map, int64_t* cursor, uint64_t* keys,
                                                           uint32_t* vals) {
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  // the loop bound is the same for every lane of the workgroup: the ballots below see whole wavefronts
+  for (int64_t gb0 = (int64_t)blockIdx.x * (BLOCK / G); gb0 < cnt; gb0 += (int64_t)gridDim.x * (BLOCK / G)) {
+  const int64_t gid = gb0 + threadIdx.x / G;
   // groups past the end still execute the ballots (uniform control flow inside the wavefront)
   const bool active = gid < cnt;
   const int32_t v = active ? list[gid] : 0;
@@ -147,6 +154,7 @@ __global__ __launch_bounds__(BLOCK) void k_cross_emit_grp(const int32_t* list, i
       keys[p] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
       vals[p] = (uint32_t)g.w[j];
     }
+  }
   }
 }
 

@@ -381,6 +381,7 @@ struct Run {
       P.phi_den[i] = o.phi_den[k];
     }
     P.sum_w2 = L.sum_w2;
+    P.symmetry = o.symmetry;
     if (G) {
       SegLM& q = P.seg;
       q.G = (int32_t)G;
@@ -708,6 +709,7 @@ void check_opts(const lcc_options& o) {
     if (o.phi_den[k] == 0 || o.phi_num[k] > o.phi_den[k]) fail(LCC_ERR_INVALID, "temperature phi outside [0, 1]");
   if (o.eps_den == 0) fail(LCC_ERR_INVALID, "eps_den = 0");
   if (o.max_levels <= 0 || o.max_levels > 1024) fail(LCC_ERR_INVALID, "max_levels outside [1, 1024]");
+  if (o.symmetry < LCC_SYM_AFTERBURNER || o.symmetry > LCC_SYM_MLH) fail(LCC_ERR_INVALID, "unknown symmetry mode");
 }
 
 uint64_t gcd64(uint64_t a, uint64_t b) {

@@ -19,7 +19,8 @@ namespace lcc {
 
 namespace {
 
-constexpr int HUB_CHUNK = 4096;
+constexpr int HUB_CHUNK = 2048;     // edges of a hub handled by one workgroup
+constexpr int HUB_LDS_BITS = 12;     // its LDS pre-aggregation table: 2 * HUB_CHUNK slots
 constexpr int HUB_BLOCK = 256;
 constexpr int BIG_BLOCK = 256;
 
@@ -627,6 +628,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, c
                                                           const int32_t* cons) {
   if (slot && slot->skip[pass]) return;
   constexpr int S = 2 * HUB_CHUNK;
+  static_assert(S == (1 << HUB_LDS_BITS), "the LDS table holds 2 slots per chunk edge");
   __shared__ int32_t lk[S];
   __shared__ uint32_t lv[S];
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
@@ -638,7 +640,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, c
   for (int s = threadIdx.x; s < S; s += HUB_BLOCK) { lk[s] = -1; lv[s] = 0; }
   __syncthreads();
   // own-cluster edges also go through the table here (the scan reads the hub's own weight from it)
-  const int64_t own = insert_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, -3, lk, lv, 13, cons, cons ? cons[v] : 0);
+  const int64_t own = insert_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, -3, lk, lv, HUB_LDS_BITS, cons, cons ? cons[v] : 0);
   (void)own;
   __syncthreads();
   uint32_t* tab = arena + 4 * base;
@@ -867,6 +869,24 @@ __global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs
     keep[v] = kp;
     hacc[k] = 0;
     if (kp) atomicAdd(&bc.ncand, 1ull);
+  }
+  counters_flush(&bc, &slot->nM[pass], nullptr);
+}
+
+// Ablations of the symmetry breaking (Table 2): every candidate kept (mode 1), or the minimum label heuristic
+// in odd passes (mode 2: kept only when moving to a lower cluster id or to a new singleton).
+__global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, int mode, int pass, uint8_t* keep,
+                            LMSlot* slot) {
+  __shared__ BlockCounters bc;
+  counters_init(&bc);
+  if (slot->skip[pass]) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = list[i];
+    const VState s = vs[v];
+    bool k = s.d != D_NONE;
+    if (k && mode == 2 && (pass & 1)) k = s.d == D_EMPTY || s.d < s.c;
+    keep[v] = k;
+    if (k) atomicAdd(&bc.ncand, 1ull);
   }
   counters_flush(&bc, &slot->nM[pass], nullptr);
 }
@@ -1347,10 +1367,16 @@ inline unsigned grid_for(int64_t n) {
   if (g > 65536) g = 65536;
   return (unsigned)g;
 }
+// kernels that end in one global atomic per workgroup on a shared counter: few workgroups, so the atomics
+// on that one address do not serialise behind each other
+inline unsigned red_blocks(int64_t n) {
+  int64_t g = cdiv(n, BLOCK);
+  return (unsigned)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
 
 // Persistent launches: workgroups loop over their share of the vertices.  Launching one short workgroup per
 // vertex (or per few vertices) is bound by the workgroup dispatch rate, not by memory.
-constexpr int64_t MAX_BLOCKS = 2048;
+constexpr int64_t MAX_BLOCKS = 4096;
 inline unsigned grp_blocks(int64_t cnt, int G) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(cnt, BLOCK / G), MAX_BLOCKS));
 }
@@ -1398,7 +1424,7 @@ void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, cons
 
 void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st, const int32_t* gid,
                     const uint8_t* gact) {
-  k_bucket_count<<<grid_for(n), BLOCK, 0, st>>>(off, n, ctrl, gid, gact);
+  k_bucket_count<<<red_blocks(n), BLOCK, 0, st>>>(off, n, ctrl, gid, gact);
   k_bucket_offsets<<<1, 1, 0, st>>>(ctrl);
   k_bucket_scatter<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4 * BLOCK), 8192)), BLOCK, 0, st>>>(off, n, list, ctrl, gid, gact);
 }
@@ -1411,7 +1437,7 @@ void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int3
 }
 
 void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st) {
-  k_vertex_sums<<<grid_for(n), BLOCK, 0, st>>>(vw, n, ctrl);
+  k_vertex_sums<<<red_blocks(n), BLOCK, 0, st>>>(vw, n, ctrl);
 }
 
 void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, hipStream_t st) {
@@ -1451,7 +1477,7 @@ void launch_objective(const DevGraph& g, const Buckets& b, const int32_t* C, con
   k_zero_i64<<<1, 1, 0, st>>>(&ctrl->obj_I);
   k_zero_i64<<<1, 1, 0, st>>>(&ctrl->obj_SW2);
   launch_internal(g, b, C, &ctrl->obj_I, nullptr, st);
-  k_sw2<<<grid_for(g.n), BLOCK, 0, st>>>(W, g.n, &ctrl->obj_SW2, nullptr, -1);
+  k_sw2<<<red_blocks(g.n), BLOCK, 0, st>>>(W, g.n, &ctrl->obj_SW2, nullptr, -1);
 }
 
 static const int32_t* L_hubs(const Buckets& b);
@@ -1499,8 +1525,8 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 2 : nullptr)))
   LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 3 : nullptr)))
   LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 4 : nullptr)))
-  LCC_ENUM(5, (k_enum_blk<256, LDS_SLOTS_B5><<<vtx_blocks(b.count[5]), 256, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 5 : nullptr)))
-  LCC_ENUM(6, (k_enum_blk<1024, LDS_SLOTS_B6><<<vtx_blocks(b.count[6], 512), 1024, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 6 : nullptr)))
+  LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 5 : nullptr)))
+  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b.count[6], 1024), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 6 : nullptr)))
 #undef LCC_ENUM
   if (n7) {
     unsigned nc = (unsigned)b.hub_chunks;
@@ -1574,7 +1600,7 @@ static void state_sums_sw2(const SegLM& sg, const int64_t* W, int64_t n, LMSlot*
     k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(W, 1, sg.vbase, G, sg.SW2 + (int64_t)k * G,
                                               k ? sg.SW2 + (int64_t)(k - 1) * G : nullptr, pass >= 0 ? slot : nullptr, pass);
   } else {
-    k_sw2<<<grid_for(n), BLOCK, 0, st>>>(W, n, &slot->SW2[k], pass >= 0 ? slot : nullptr, pass);
+    k_sw2<<<red_blocks(n), BLOCK, 0, st>>>(W, n, &slot->SW2[k], pass >= 0 ? slot : nullptr, pass);
   }
 }
 
@@ -1618,7 +1644,10 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
     k_hub_clear<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L_hubs(b), b.hub_chunk_off, b.count[7], g.off,
                                                              bufs.arena, nullptr, -1);
   for (int i = 1; i <= prm.pass_limit; ++i) {
-    int same_phi = i >= 2 && prm.phi_num[i] == prm.phi_num[i - 1] && prm.phi_den[i] == prm.phi_den[i - 1];
+    // a pass that kept no move repeats exactly when the next one has the same temperature (and, under the
+    // minimum label heuristic, never: its rule alternates between passes)
+    int same_phi = i >= 2 && prm.phi_num[i] == prm.phi_num[i - 1] && prm.phi_den[i] == prm.phi_den[i - 1] &&
+                   prm.symmetry != 2;
     k_pass_begin<<<1, 1, 0, st>>>(slot, i, same_phi);
     bool single_now = singleton && i == 1;
     launch_destinations(g, b, sc, prm.phi_num[i], prm.phi_den[i], 0, single_now, bufs, slot, i,
@@ -1628,7 +1657,12 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
                                                 i >= 2 ? sg.I + (int64_t)(i - 2) * G : nullptr, slot, i);
     // best-so-far check of the state this pass started from (state i-1)
     best_so_far(sg, slot, prm, bufs, n, i - 1, i, st);
-    launch_afterburner(g, b, sc, bufs, slot, i, hs, st);
+    if (prm.symmetry == 0) {
+      launch_afterburner(g, b, sc, bufs, slot, i, hs, st);
+    } else {
+      const int64_t nl = b.off[NBUCKET];
+      k_keep_rule<<<red_blocks(nl), BLOCK, 0, st>>>(b.list, nl, bufs.vs, prm.symmetry, i, bufs.keep, slot);
+    }
     apply_and_empty(g, bufs, sg, slot, i, st);
     state_sums_sw2(sg, bufs.W, n, slot, i, i, st);
   }

@@ -26,7 +26,12 @@ inline unsigned grid_for(int64_t n) {
   if (g > 65536) g = 65536;
   return (unsigned)g;
 }
-inline unsigned grp_blocks(int64_t cnt, int G) { return (unsigned)cdiv(cnt, BLOCK / G); }
+// persistent launches (at most 2048 workgroups looping over their share): one short workgroup per few
+// vertices is bound by the workgroup dispatch rate
+inline unsigned grp_blocks(int64_t cnt, int G) {
+  int64_t b = cdiv(cnt, BLOCK / G);
+  return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
 
 __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
   int64_t lo = 0, hi = n7;
@@ -54,22 +59,28 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_aB_grp(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* B,
                                                   const int64_t* WB, Score sc, int64_t* aB, uint8_t* inU,
                                                   int64_t* nU) {
+  __shared__ unsigned long long cu;  // |U| of this workgroup, one global atomic at the end
+  if (threadIdx.x == 0) cu = 0;
+  __syncthreads();
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
-  if (gid >= cnt) return;
-  const int32_t v = list[gid];
-  const int32_t bv = B[v];
-  int64_t s = 0;
-  for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G)
-    if (B[g.idx[j]] == bv) s += g.w[j];
-  s = gsum<G>(s);
-  if (gl == 0) {
-    aB[v] = s;
-    int64_t wv = g.vw[v];
-    bool u = sc.q * s - sc.p * wv * (WB[bv] - wv) >= 0;
-    inU[v] = u;
-    if (u) atomicAdd((unsigned long long*)nU, 1ull);
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
+    const int32_t v = list[gid];
+    const int32_t bv = B[v];
+    int64_t s = 0;
+    for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G)
+      if (B[g.idx[j]] == bv) s += g.w[j];
+    s = gsum<G>(s);
+    if (gl == 0) {
+      aB[v] = s;
+      int64_t wv = g.vw[v];
+      bool u = sc.q * s - sc.p * wv * (WB[bv] - wv) >= 0;
+      inU[v] = u;
+      if (u) atomicAdd(&cu, 1ull);
+    }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && cu) atomicAdd((unsigned long long*)nU, cu);
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_aB_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
@@ -93,13 +104,18 @@ __global__ void k_hub_zero64(const int32_t* hubs, int64_t n7, int64_t* a) {
 
 __global__ void k_hub_inU(const int32_t* hubs, int64_t n7, DevGraph g, const int32_t* B, const int64_t* WB,
                           Score sc, const int64_t* aB, uint8_t* inU, int64_t* nU) {
+  __shared__ unsigned long long cu;
+  if (threadIdx.x == 0) cu = 0;
+  __syncthreads();
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n7; k += (int64_t)gridDim.x * blockDim.x) {
     int32_t v = hubs[k];
     int64_t wv = g.vw[v];
     bool u = sc.q * aB[v] - sc.p * wv * (WB[B[v]] - wv) >= 0;
     inU[v] = u;
-    if (u) atomicAdd((unsigned long long*)nU, 1ull);
+    if (u) atomicAdd(&cu, 1ull);
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && cu) atomicAdd((unsigned long long*)nU, cu);
 }
 
 __device__ __forceinline__ bool qualifies(const DevGraph& g, const int32_t* B, const uint8_t* inU, const Score& sc,
@@ -113,7 +129,9 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_choose_grp(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* B,
                                                       const uint8_t* inU, Score sc, uint64_t st, int32_t* H) {
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
+  // the loop bound is the same for every lane of the workgroup: the ballots below see whole wavefronts
+  for (int64_t gbase0 = (int64_t)blockIdx.x * (BLOCK / G); gbase0 < cnt; gbase0 += (int64_t)gridDim.x * (BLOCK / G)) {
+  const int64_t gid = gbase0 + threadIdx.x / G;
   const bool active = gid < cnt;
   const int32_t v = active ? list[gid] : 0;
   const bool vin = active && inU[v];
@@ -161,6 +179,7 @@ __global__ __launch_bounds__(BLOCK) void k_choose_grp(const int32_t* list, int64
     } else if (gl == 0) {
       H[v] = v;
     }
+  }
   }
 }
 
@@ -303,19 +322,20 @@ __global__ __launch_bounds__(BLOCK) void k_aX_grp(const int32_t* list, int64_t c
                                                   const int32_t* root, uint32_t fseed, const uint8_t* flip,
                                                   int64_t* aX) {
   const int gl = threadIdx.x % G;
-  const int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G;
-  if (gid >= cnt) return;
-  const int32_t v = list[gid];
-  if (!member[v]) return;  // uniform within the group
-  const int32_t rv = root[v];
-  const uint64_t fv = fkey(v, fseed, flip);
-  int64_t s = 0;
-  for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) {
-    int32_t u = g.idx[j];
-    if (root[u] == rv && fkey(u, fseed, flip) < fv) s += g.w[j];
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
+    const int32_t v = list[gid];
+    if (!member[v]) continue;  // uniform within the group
+    const int32_t rv = root[v];
+    const uint64_t fv = fkey(v, fseed, flip);
+    int64_t s = 0;
+    for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) {
+      int32_t u = g.idx[j];
+      if (root[u] == rv && fkey(u, fseed, flip) < fv) s += g.w[j];
+    }
+    s = gsum<G>(s);
+    if (gl == 0) aX[v] = s;
   }
-  s = gsum<G>(s);
-  if (gl == 0) aX[v] = s;
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_aX_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,

@@ -32,8 +32,8 @@ EXPORTED = ["lcc_create", "lcc_destroy", "lcc_default_options", "lcc_workspace_b
 PROFILE_FAMILIES = ["enum_b0", "enum_b1", "enum_b2", "enum_b3", "enum_b4", "enum_b5", "enum_b6", "enum_b7",
                     "single", "afterburner"]
 FAMILY_KERNELS = {"enum_b0": "k_enum_grp<4>", "enum_b1": "k_enum_grp<8>", "enum_b2": "k_enum_grp<16>",
-                  "enum_b3": "k_enum_grp<32>", "enum_b4": "k_enum_wave<256>", "enum_b5": "k_enum_blk<256, 2048>",
-                  "enum_b6": "k_enum_blk<1024, 8192>", "enum_b7": "k_hub_insert+k_hub_scan+k_hub_final",
+                  "enum_b3": "k_enum_grp<32>", "enum_b4": "k_enum_wave<256>", "enum_b5": "k_enum_blk<128, 2048>",
+                  "enum_b6": "k_enum_blk<512, 8192>", "enum_b7": "k_hub_insert+k_hub_scan+k_hub_final",
                   "single": "k_single_*"}
 
 
@@ -55,7 +55,11 @@ class lcc_options(ctypes.Structure):
     _fields_ = [("pass_limit", ctypes.c_int32), ("n_phi", ctypes.c_int32), ("phi_num", ctypes.c_uint32 * 8),
                 ("phi_den", ctypes.c_uint32 * 8), ("phi_until", ctypes.c_uint32 * 8), ("eps_num", ctypes.c_uint32),
                 ("eps_den", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("max_levels", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("trace", ctypes.POINTER(lcc_trace))]
+                ("validate", ctypes.c_int32), ("trace", ctypes.POINTER(lcc_trace)), ("symmetry", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+LCC_SYM_AFTERBURNER, LCC_SYM_NONE, LCC_SYM_MLH = 0, 1, 2
 
 
 class lcc_kernel_stat(ctypes.Structure):

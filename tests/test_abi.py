@@ -28,14 +28,14 @@ def test_struct_layouts():
     assert ctypes.sizeof(lcc.lcc_graph) == 64
     assert ctypes.sizeof(lcc.lcc_lambda) == 24
     assert ctypes.sizeof(lcc.lcc_result) == 56
-    assert ctypes.sizeof(lcc.lcc_options) == 4 + 4 + 3 * 32 + 8 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(lcc.lcc_options) == 4 + 4 + 3 * 32 + 8 + 8 + 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(lcc.lcc_kernel_stat) == 32 + 8 + 8 + 8
 
 
 def test_host_only_entry_points():
     from paper_2608_01503_amd import lcc
     o = lcc.lcc_default_options()
-    assert (o.pass_limit, o.n_phi, o.eps_num, o.eps_den, o.max_levels) == (6, 2, 1, 10, 64)
+    assert (o.pass_limit, o.n_phi, o.eps_num, o.eps_den, o.max_levels, o.symmetry) == (6, 2, 1, 10, 64, 0)
     assert (o.phi_num[0], o.phi_den[0], o.phi_until[0], o.phi_num[1], o.phi_den[1], o.phi_until[1]) == (3, 4, 4, 1, 4, 6)
     assert lcc.lcc_workspace_bytes(1000, 10000) > 0
     assert lcc.lcc_status_string(-2) == "graph not symmetric"

@@ -128,3 +128,10 @@ def test_fused_knn_batch_full_size_sample():
         g = gg.Graph(n=graphs[i].n, off=off.cpu().numpy(), idx=idx.cpu().numpy(), w=w.cpu().numpy())
         ref = O.cluster(g, O.PLOUVAIN, lam=(1, 1, True), vw_mode=O.VW_WEIGHTED_DEGREE)
         assert np.array_equal(labs[i].cpu().numpy(), ref.labels) and ress[i].N == ref.N, i
+
+
+def test_fused_batch_with_ablation_options():
+    items = [(gg.rmat(11, 16, seed=50 + k), O.PLOUVAIN, *MOD, None) for k in range(3)] + \
+            [(gg.random_gnp(900, 0.006, 60, w_max=5), O.LOUVAIN, *CPM20, None)]
+    for sym in (1, 2):
+        _batch(items, opts_kw=dict(phases=((0, 1, 6),), symmetry=sym))

@@ -212,3 +212,13 @@ def test_iteration_input_errors():
         with pytest.raises(L.LccError) as e:
             U.run_gpu(g, variant, *MOD, **kw)
         assert e.value.status == -1
+
+
+@pytest.mark.parametrize("sym", [1, 2], ids=["none", "mlh"])
+def test_symmetry_breaking_ablations(sym):
+    """Table 2's ablations: no symmetry breaking, or the minimum label heuristic in odd passes; phi = 0."""
+    kw = dict(phases=((0, 1, 6),), symmetry=sym)
+    for g, obj in [(gg.config1_sbm(), MOD), (gg.rmat(13, 16, seed=5), MOD), (U.hub_graph(), CPM20),
+                   (gg.lattice(50, 40, 0.1, 100, 3), CPM20)]:
+        for v in (O.PLOUVAIN, O.PLEIDEN):
+            U.assert_parity(g, v, *obj, opts_kw=kw)

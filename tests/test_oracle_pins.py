@@ -672,3 +672,41 @@ def test_constrained_coarsening_stays_inside_constraint():
         r = O.cluster(g, O.LOUVAIN, constraint=B)
         for mem in defs.clusters_of(r.labels).values():
             assert len({int(B[v]) for v in mem}) == 1
+
+
+# ------------------------------------------------------------------------------------------------
+# symmetry-breaking ablations (Table 2): none, minimum label heuristic
+# ------------------------------------------------------------------------------------------------
+
+def test_no_symmetry_breaking_keeps_every_candidate():
+    for g in [gg.config1_sbm(), gg.random_gnp(400, 0.02, 61, w_max=5)]:
+        r = O.cluster(g, O.PLOUVAIN, opts=O.make_opts(phases=((0, 1, 6),), symmetry=O.SYM_NONE))
+        passes = [t for t in r.trace if t[0] == 1]
+        assert passes and all(t[4] == t[5] for t in passes)
+
+
+def test_minimum_label_heuristic_two_singletons():
+    """Two adjacent singletons that want each other: in an odd pass (heuristic active) only the vertex moving to
+    the lower id moves; in an even pass both move (no symmetry breaking)."""
+    g = gg.from_pairs(2, [(0, 1)])
+    vw, p, q = resolved(g, O.VW_UNIT, (0, 1, False))
+    odd = O.lm_pass(g, vw, p, q, [0, 1], phi=(0, 1), symmetry=O.SYM_MLH, pass_no=1)
+    assert list(odd["D"]) == [1, 0] and list(odd["keep"]) == [False, True] and list(odd["C"]) == [0, 0]
+    even = O.lm_pass(g, vw, p, q, [0, 1], phi=(0, 1), symmetry=O.SYM_MLH, pass_no=2)
+    assert list(even["keep"]) == [True, True] and list(even["C"]) == [1, 0]
+
+
+def test_minimum_label_heuristic_rule_on_random_graphs():
+    rng = np.random.default_rng(8)
+    for k, g in enumerate(tiny_graphs(12, 10, 40, seed=21)):
+        vw, p, q = resolved(g)
+        C = rng.integers(0, g.n, size=g.n).astype(np.int32)
+        for pass_no in (1, 2):
+            r = O.lm_pass(g, vw, p, q, C, phi=(0, 1), symmetry=O.SYM_MLH, pass_no=pass_no)
+            for v in range(g.n):
+                if not r["cand"][v]:
+                    assert not r["keep"][v]
+                elif pass_no == 2:
+                    assert r["keep"][v]
+                else:
+                    assert r["keep"][v] == (r["D"][v] == O.EMPTY or r["D"][v] < C[v])
