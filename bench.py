@@ -324,7 +324,10 @@ def main():
     if args.workload == "serve":
         bench_serve(args)
         return
+    t_gen = time.perf_counter()
     g, variant, lam, vw_mode, desc = workload(args.workload)
+    print(f"# {args.workload}: n={g.n} nnz={g.nnz} generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr,
+          flush=True)
     dev = torch.device("cuda:0")
     off = torch.from_numpy(g.off).to(dev)
     idx = torch.from_numpy(g.idx).to(dev)
@@ -337,8 +340,11 @@ def main():
     stream = torch.cuda.current_stream()
 
     res = None
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
+        tw = time.perf_counter()
         _, res = ctx.cluster(graph, lam, variant, opts, labels_out=labels, stream=stream)
+        torch.cuda.synchronize()
+        print(f"# warm-up call {k + 1}: {time.perf_counter() - tw:.2f} s", file=sys.stderr, flush=True)
     # roofline kernel: the single-kernel local-move family with the most time in one profiled (untimed) call
     single_kernel = [f for f in LL.PROFILE_FAMILIES if f in LL.FAMILY_KERNELS and "+" not in LL.FAMILY_KERNELS[f]]
     if args.family == "auto":
@@ -352,8 +358,11 @@ def main():
     ctx.profile_read(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         _, res = ctx.cluster(graph, lam, variant, opts, labels_out=labels, stream=stream)
+        if g.nnz > (1 << 30):  # long calls: a progress line per step (costs one synchronisation)
+            torch.cuda.synchronize()
+            print(f"# step {k + 1} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, kms, kbytes = ctx.profile_read(reset=True)[family]

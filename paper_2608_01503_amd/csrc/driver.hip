@@ -206,6 +206,9 @@ struct lcc_ctx {
     return pool.chunks.back().p;
   }
   void pool_reset() { pool.cur = 0; pool.off = 0; }
+  // scratch taken after a mark is handed out again after the release (the stream must be done with it)
+  std::pair<size_t, size_t> pool_mark() const { return {pool.cur, pool.off}; }
+  void pool_release(std::pair<size_t, size_t> m) { pool.cur = m.first; pool.off = m.second; }
 };
 
 thread_local lcc_ctx* g_prof_ctx = nullptr;  // context whose call runs on this thread, when profiling
@@ -316,8 +319,38 @@ struct Run {
   int32_t* gcopy = nullptr;
   uint8_t* gact = nullptr;
   int32_t* gtmp = nullptr;
+  // Variants without an uncoarsening local move (Louvain, pLeiden) need a coarse level's graph only until the
+  // next level is built: the coarse graphs then alternate between two buffers sized for the input, so the
+  // memory does not grow with the number of levels.  The maps and clusterings of every level stay.
+  bool pingpong = false;
+  char* ppbuf[2] = {nullptr, nullptr};
+  size_t ppcap = 0, ppoff = 0;
+  int ppcur = 0;
 
   Run(lcc_ctx* c, hipStream_t s) : ctx(c), st(s), w(c->w) {}
+
+  void use_pingpong(int64_t n, int64_t nnz) {
+    pingpong = true;
+    ppcap = align_up((size_t)(n + 1) * 8) + align_up((size_t)std::max<int64_t>(n, 1) * 8) +
+            2 * align_up((size_t)std::max<int64_t>(nnz, 1) * 4) + align_up((size_t)std::max<int64_t>(n, 1) * 4) +
+            align_up((size_t)(n + 1) * 4);
+  }
+  void level_begin(int l) {
+    if (!pingpong) return;
+    ppcur = l & 1;
+    if (!ppbuf[ppcur]) ppbuf[ppcur] = (char*)ctx->pool_take(ppcap);
+    ppoff = 0;
+  }
+  // storage of a coarse level's graph arrays
+  template <typename T>
+  T* level_take(int64_t count) {
+    if (!pingpong) return take<T>(ctx, count);
+    size_t b = align_up((size_t)std::max<int64_t>(count, 1) * sizeof(T));
+    if (ppoff + b > ppcap) fail(LCC_ERR_DEVICE, "internal: coarse level exceeds its buffer");
+    T* p = (T*)(ppbuf[ppcur] + ppoff);
+    ppoff += b;
+    return p;
+  }
 
   void sync(const char* what) {
     hip_check(hipGetLastError(), what);
@@ -464,8 +497,9 @@ struct Run {
       N.B = take<int32_t>(ctx, nc);
       launch_coarse_gid(L.map, L.B, n, N.B, st);
     }
-    int64_t* coff = take<int64_t>(ctx, nc + 1);
-    int64_t* cvw = take<int64_t>(ctx, nc);
+    level_begin(l + 1);
+    int64_t* coff = level_take<int64_t>(nc + 1);
+    int64_t* cvw = level_take<int64_t>(nc);
     fill_i64(cvw, 0, nc, st);
     launch_coarse_vw(L.map, L.g.vw, n, cvw, st);
     launch_cross_count(L.g, L.b, L.map, w.cnt, st);
@@ -494,12 +528,12 @@ struct Run {
       hip_check(hipMemcpyAsync(&nz, w.uid + E, sizeof(int32_t), hipMemcpyDeviceToHost, st), "coarse nnz");
       sync("coarse nnz");
       nnzc = nz;
-      cidx = take<int32_t>(ctx, nnzc);
-      cw = take<int32_t>(ctx, nnzc);
+      cidx = level_take<int32_t>(nnzc);
+      cw = level_take<int32_t>(nnzc);
       launch_coarse_write(ks, vs, w.head, w.uid, E, nnzc, nc, pref, hstart, w.ux, cidx, cw, coff, w.scan_temp, st);
     } else {
-      cidx = take<int32_t>(ctx, 1);
-      cw = take<int32_t>(ctx, 1);
+      cidx = level_take<int32_t>(1);
+      cw = level_take<int32_t>(1);
       fill_i64(coff, 0, nc + 1, st);
     }
     N.g.n = nc;
@@ -511,7 +545,7 @@ struct Run {
     N.C = take<int32_t>(ctx, nc);
     lv.push_back(N);
     Level& NL = lv.back();
-    prepare(NL, take<int32_t>(ctx, nc), take<int32_t>(ctx, nc + 1));
+    prepare(NL, level_take<int32_t>(nc), level_take<int32_t>(nc + 1));
   }
 
   // ---------------------------------------------------------------------------------------------------
@@ -632,13 +666,15 @@ struct Run {
         launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         if (nslot >= NSLOT) fail(LCC_ERR_INVALID, "too many local-move calls");
         int s2 = nslot++;
+        const auto mark = ctx->pool_mark();  // the alternate move's scratch is released below
         if (!lmalt(L.g, L.b, sc, B, w.slots + s2, w.ctrl, w.alt_list, w.alt_gain,
                    [this](size_t bytes) { return ctx->pool_take(bytes); }, st))
           fail(LCC_ERR_INVALID, "alternate local move with 2^30 or more movers is not supported");
         copy_i32(L.C, w.C, n, st);
         launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         launch_objective(L.g, L.b, w.C, w.W, w.ctrl, st);
-        read_ctrl("lmalt");
+        read_ctrl("lmalt");  // the stream is done with the scratch
+        ctx->pool_release(mark);
         N = q * ctx->h_ctrl->obj_I - p * (ctx->h_ctrl->obj_SW2 - L.sum_w2);
         rec(3, l, 0, 0, ctx->h_ctrl->lmalt_k, ctx->h_ctrl->lmalt_best_k, N, 0);
       }
@@ -934,6 +970,7 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
   }
   setup(R, g, lam, init_labels);
   R.lv[0].B = const_cast<int32_t*>(constraint);
+  if (variant == LCC_LOUVAIN || variant == LCC_PLEIDEN) R.use_pingpong(n, g->nnz);
   int top = 0;
   if (variant == LCC_LOUVAIN || variant == LCC_PLOUVAIN) top = R.louvain(variant == LCC_PLOUVAIN, init_labels);
   else top = R.leiden(variant == LCC_PLEIDEN_PLUS, init_labels);
