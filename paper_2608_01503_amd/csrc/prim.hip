@@ -95,6 +95,33 @@ __global__ __launch_bounds__(BLOCK) void k_tile_scan(const In* in, Out* out, int
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nt];
 }
 
+// Whole scan by one workgroup (tiles in sequence with a carry): small inputs take one launch instead of
+// three.
+template <typename In, typename Out>
+__global__ __launch_bounds__(BLOCK) void k_scan_small(const In* in, Out* out, int64_t n, const int64_t* cond) {
+  if (cond && *cond == 0) return;
+  Out carry = 0;
+  for (int64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+    const int64_t base = t0 + (int64_t)threadIdx.x * SCAN_ITEMS;
+    Out v[SCAN_ITEMS];
+    Out s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      v[k] = (base + k < n) ? (Out)in[base + k] : (Out)0;
+      s += v[k];
+    }
+    Out tot;
+    Out run = block_excl_scan<Out>(s, &tot) + carry;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
 template <typename T>
 __global__ void k_fill(T* p, T v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -106,6 +133,10 @@ void scan_impl(const In* in, Out* out, int64_t n, void* temp, const int64_t* con
   Out* sums = (Out*)temp;
   if (nt == 0) {
     k_fill<Out><<<1, 1, 0, st>>>(out, (Out)0, 1);
+    return;
+  }
+  if (nt <= 8) {
+    k_scan_small<In, Out><<<1, BLOCK, 0, st>>>(in, out, n, cond);
     return;
   }
   k_tile_reduce<In, Out><<<(unsigned)nt, BLOCK, 0, st>>>(in, n, sums, cond);
@@ -182,6 +213,76 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint64_t* kin, co
   }
 }
 
+// Whole sort of at most RADIX_TILE pairs by one workgroup in LDS: every pass is a histogram, a scan of the 256
+// digit counts and the stable ballot-ranked scatter above, between two LDS buffers.  The result is written to
+// (k0, v0).
+struct RadixShifts {
+  int s[8];
+};
+
+__global__ __launch_bounds__(BLOCK) void k_radix_small(uint64_t* k0, uint32_t* v0, int64_t m, RadixShifts sh,
+                                                       int npass) {
+  __shared__ uint64_t kb[2][RADIX_TILE];
+  __shared__ uint32_t vb[2][RADIX_TILE];
+  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[BLOCK / WAVE][256];
+  const int tid = threadIdx.x, wv = tid / WAVE, lane = tid & (WAVE - 1);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+  for (int64_t i = tid; i < m; i += BLOCK) { kb[0][i] = k0[i]; vb[0][i] = v0[i]; }
+  int cur = 0;
+  for (int p = 0; p < npass; ++p) {
+    const int shift = sh.s[p];
+    cnt[tid] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < m; i += BLOCK) atomicAdd(&cnt[(uint32_t)(kb[cur][i] >> shift) & 255u], 1u);
+    __syncthreads();
+    {
+      uint32_t tot;
+      run[tid] = block_excl_scan<uint32_t>(cnt[tid], &tot);
+    }
+    __syncthreads();
+    for (int64_t r0 = 0; r0 < m; r0 += BLOCK) {  // block-uniform
+#pragma unroll
+      for (int k = 0; k < BLOCK / WAVE; ++k) wcnt[k][tid] = 0;
+      __syncthreads();
+      const int64_t i = r0 + tid;
+      const bool valid = i < m;
+      const uint64_t key = valid ? kb[cur][i] : 0;
+      const uint32_t val = valid ? vb[cur][i] : 0;
+      const uint32_t d = (uint32_t)(key >> shift) & 255u;
+      uint64_t mask = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        uint64_t bal = __ballot((d >> b) & 1u);
+        mask &= ((d >> b) & 1u) ? bal : ~bal;
+      }
+      const uint32_t prank = (uint32_t)__popcll(mask & lt);
+      if (valid && prank == 0) wcnt[wv][d] = (uint32_t)__popcll(mask);
+      __syncthreads();
+      {
+        uint32_t rr = run[tid];
+#pragma unroll
+        for (int k = 0; k < BLOCK / WAVE; ++k) {
+          uint32_t c = wcnt[k][tid];
+          wcnt[k][tid] = rr;
+          rr += c;
+        }
+        run[tid] = rr;
+      }
+      __syncthreads();
+      if (valid) {
+        const uint32_t dst = wcnt[wv][d] + prank;
+        kb[cur ^ 1][dst] = key;
+        vb[cur ^ 1][dst] = val;
+      }
+      __syncthreads();
+    }
+    cur ^= 1;
+  }
+  for (int64_t i = tid; i < m; i += BLOCK) { k0[i] = kb[cur][i]; v0[i] = vb[cur][i]; }
+}
+
 __global__ void k_iota(int32_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = (int32_t)i;
@@ -236,6 +337,12 @@ size_t radix_temp_bytes(int64_t m) {
 int radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, const int* shifts,
                      int npass, void* temp, hipStream_t st) {
   if (m <= 0 || npass <= 0) return 0;
+  if (m <= RADIX_TILE && npass <= 8) {
+    RadixShifts sh{};
+    for (int p = 0; p < npass; ++p) sh.s[p] = shifts[p];
+    k_radix_small<<<1, BLOCK, 0, st>>>(k0, v0, m, sh, npass);
+    return 0;
+  }
   int64_t nt = cdiv(m, RADIX_TILE);
   size_t h = (size_t)(256 * nt + 1) * sizeof(uint32_t);
   h = (h + 255) & ~(size_t)255;
