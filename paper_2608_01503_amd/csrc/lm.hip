@@ -9,8 +9,8 @@
 //
 // Work decomposition per degree bucket (see common.h): groups of G lanes (G = 4..32, one neighbour per lane,
 // neighbour clusters aggregated by register shuffles), one wavefront per vertex with an LDS open-addressing
-// hash (degree <= 1024), one workgroup per vertex with an LDS hash (degree <= 4096), and hub vertices split
-// into 4096-edge chunks processed by independent workgroups with a global-memory hash in the edge arena.
+// hash (degree <= 128), one workgroup per vertex with an LDS hash (degree <= 1024: 128 threads, <= 4096: 512
+// threads), and hub vertices split into 2048-edge chunks processed by independent workgroups with a global-memory hash in the edge arena.
 #include <algorithm>
 
 #include "common.h"
@@ -599,9 +599,12 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
   counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
 }
 
-// Hubs: global-memory hash of 2 d slots (key, value) at slot offset 2 off[v] of the edge arena.  Chunk k
-// of a hub owns the 2 * HUB_CHUNK slots that start at 2 (off[v] + k HUB_CHUNK) for clearing and scanning;
-// insertions probe the whole table.
+// Hubs: global-memory hash of 2 d 64-bit slots (cluster << 32 | weight sum) at slot offset 2 off[v] of the
+// edge arena.  A hub's weight sums stay below 2^32 (the total edge weight does), so adding a weight to a slot
+// never carries into its key.  Chunk k of a hub owns the 2 * HUB_CHUNK slots that start at
+// 2 (off[v] + k HUB_CHUNK) for clearing and scanning; insertions probe the whole table.
+constexpr unsigned long long HUB_EMPTY = 0xFFFFFFFF00000000ull;
+
 __device__ __forceinline__ uint32_t hub_slot(int32_t c, int64_t cap) {
   return (uint32_t)(((uint64_t)fmix32((uint32_t)c) * (uint64_t)cap) >> 32);
 }
@@ -614,10 +617,8 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_clear(const int32_t* hubs, co
   const int32_t v = hubs[k];
   const int64_t s0 = 2 * (off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK);
   const int64_t s1 = min(2 * off[v + 1], s0 + 2 * HUB_CHUNK);
-  for (int64_t s = s0 + threadIdx.x; s < s1; s += HUB_BLOCK) {
-    arena[2 * s] = 0xFFFFFFFFu;
-    arena[2 * s + 1] = 0;
-  }
+  unsigned long long* tab = (unsigned long long*)arena;
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += HUB_BLOCK) tab[s] = HUB_EMPTY;
 }
 
 // Each chunk first aggregates its edges by cluster in LDS (a hub's neighbours often share few clusters), then
@@ -643,15 +644,22 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_insert(const int32_t* hubs, c
   const int64_t own = insert_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, -3, lk, lv, HUB_LDS_BITS, cons, cons ? cons[v] : 0);
   (void)own;
   __syncthreads();
-  uint32_t* tab = arena + 4 * base;
+  // one atomic per entry: an add when the slot already holds the key, else a compare-and-swap of the whole
+  // slot from empty (a slot read as empty may be stale; the swap then reports its real content)
+  unsigned long long* tab = (unsigned long long*)arena + 2 * base;
   for (int s = threadIdx.x; s < S; s += HUB_BLOCK) {
     int32_t c = lk[s];
     if (c < 0) continue;
-    uint32_t wt = lv[s];
+    const unsigned long long wt = lv[s];
+    const unsigned long long mine = ((unsigned long long)(uint32_t)c << 32) | wt;
     int64_t h = hub_slot(c, cap);
     for (int64_t probe = 0; probe < cap; ++probe) {
-      uint32_t prev = atomicCAS(&tab[2 * h], 0xFFFFFFFFu, (uint32_t)c);
-      if (prev == 0xFFFFFFFFu || prev == (uint32_t)c) { atomicAdd(&tab[2 * h + 1], wt); break; }
+      unsigned long long cur = tab[h];
+      if (cur == HUB_EMPTY) {
+        cur = atomicCAS(&tab[h], HUB_EMPTY, mine);
+        if (cur == HUB_EMPTY) break;
+      }
+      if ((uint32_t)(cur >> 32) == (uint32_t)c) { atomicAdd(&tab[h], wt); break; }
       if (++h == cap) h = 0;
     }
   }
@@ -673,13 +681,13 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
   const int64_t s1 = min(2 * g.off[v + 1], s0 + 2 * HUB_CHUNK);
   int64_t own = 0, bs = INT64_MIN, np_ = 0;
   int32_t bcl = INT32_MAX;
+  unsigned long long* tab = (unsigned long long*)arena;
   for (int64_t s = s0 + threadIdx.x; s < s1; s += HUB_BLOCK) {
-    uint32_t key = arena[2 * s];
-    if (key == 0xFFFFFFFFu) continue;
-    int32_t c = (int32_t)key;
-    int64_t a = (int64_t)arena[2 * s + 1];
-    arena[2 * s] = 0xFFFFFFFFu;
-    arena[2 * s + 1] = 0;
+    const unsigned long long e = tab[s];
+    if (e == HUB_EMPTY) continue;
+    tab[s] = HUB_EMPTY;
+    const int32_t c = (int32_t)(uint32_t)(e >> 32);
+    const int64_t a = (int64_t)(uint32_t)e;
     if (c == cv) { own = a; continue; }
     ++np_;
     int64_t sc_ = sc.q * a - sc.p * wvt * W[c];
