@@ -19,7 +19,7 @@ namespace lcc {
 
 namespace {
 
-constexpr int HUB_CHUNK = 2048;     // edges of a hub handled by one workgroup
+constexpr int HUB_CHUNK = (int)HUB_CHUNK_EDGES;  // edges of a hub handled by one workgroup
 constexpr int HUB_LDS_BITS = 12;     // its LDS pre-aggregation table: 2 * HUB_CHUNK slots
 constexpr int HUB_BLOCK = 256;
 constexpr int BIG_BLOCK = 256;
