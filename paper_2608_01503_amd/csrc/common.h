@@ -161,7 +161,6 @@ struct SegLM {
   int64_t* N0 = nullptr;            // [G]
   int32_t* copy = nullptr;          // [G] C_out <- C for this graph after the current best-so-far check
   int64_t* ownv = nullptr;          // per vertex scratch
-  uint8_t* fl = nullptr;            // per vertex scratch (free-id flags)
 };
 
 
@@ -260,6 +259,101 @@ void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int3
 constexpr int64_t HUB_CHUNK_EDGES = 2048;
 void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st);
 
+// Device arrays whose entries carry a 32-bit tag instead of being cleared before each use: the free-id marks
+// of the local move and the status words of single-pass scans.  `last` (host) is the last tag handed out;
+// all arrays start at zero (no tag) and are cleared again when the tags run out.
+struct Tagged {
+  uint32_t last = 0;
+  uint32_t* held = nullptr;              // per cluster id: the tag of the last pass that saw it held
+  int64_t held_cap = 0;
+  unsigned long long* status = nullptr;  // per scan tile: tag << 32 | inclusive << 31 | value
+  int64_t status_cap = 0;
+  uint32_t* ticket = nullptr;            // tile counter of single-pass scans, 0 between launches
+};
+uint32_t next_tag(Tagged& t, hipStream_t st);
+
+// Single-pass exclusive scan by decoupled look-back.  Tiles of LB_TILE items are drawn from a ticket counter
+// in launch order, so a tile waits only for tiles that a running workgroup already holds.  A tile publishes
+// its own total first, then walks back over its predecessors' words (64 per step, one per lane) until it
+// meets an inclusive prefix, and publishes its own inclusive prefix.  Values are below 2^31.
+constexpr int LB_ITEMS = 8;
+constexpr int LB_TILE = BLOCK * LB_ITEMS;  // 2048
+
+__device__ __forceinline__ unsigned long long lb_word(uint32_t tag, bool inclusive, uint32_t v) {
+  return ((unsigned long long)tag << 32) | ((unsigned long long)inclusive << 31) | (unsigned long long)v;
+}
+
+// Next tile of this workgroup.  Each workgroup stops at its first ticket past the last tile, so a launch
+// draws tiles + gridDim.x tickets; the workgroup that draws the last one returns the counter to 0.
+__device__ __forceinline__ uint32_t lb_next(uint32_t* ticket, uint32_t draws, uint32_t* sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = atomicAdd(ticket, 1u);
+    if (t == draws - 1) atomicExch(ticket, 0u);
+    *sh = t;
+  }
+  __syncthreads();
+  return *sh;
+}
+
+// Exclusive scan of one value per thread over the block (BLOCK threads); *total = block sum.
+__device__ __forceinline__ uint32_t lb_block_excl(uint32_t x, uint32_t* total, uint32_t* wsum) {
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, WAVE);
+    if (lane >= o) inc += y;
+  }
+  if (lane == WAVE - 1) wsum[wv] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < BLOCK / WAVE; ++k) {
+    const uint32_t s = wsum[k];
+    if (k < wv) before += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + inc - x;
+}
+
+// Exclusive prefix of tile t whose own total is agg (called by every thread of the block).
+__device__ __forceinline__ uint32_t lb_prefix(unsigned long long* status, uint32_t t, uint32_t tag, uint32_t agg,
+                                              uint32_t* sh) {
+  if (threadIdx.x < WAVE) {
+    const int lane = threadIdx.x;
+    uint32_t excl = 0;
+    if (lane == 0)
+      __hip_atomic_store(&status[t], lb_word(tag, t == 0, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t > 0) {
+      int64_t j = (int64_t)t - 1 - lane;  // lane k reads tile t-1-k
+      for (;;) {
+        unsigned long long s = lb_word(tag, true, 0);  // before tile 0: an inclusive prefix of 0
+        if (j >= 0) {
+          do {
+            s = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } while ((uint32_t)(s >> 32) != tag);
+        }
+        const unsigned long long pm = __ballot((s >> 31) & 1ull);
+        uint32_t val = (uint32_t)s & 0x7FFFFFFFu;
+        if (pm && lane > __ffsll((long long)pm) - 1) val = 0;  // beyond the nearest inclusive prefix
+#pragma unroll
+        for (int o = WAVE / 2; o > 0; o >>= 1) val += __shfl_xor(val, o, WAVE);
+        excl += val;
+        if (pm) break;
+        j -= WAVE;
+      }
+      if (lane == 0)
+        __hip_atomic_store(&status[t], lb_word(tag, true, excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) *sh = excl;
+  }
+  __syncthreads();
+  return *sh;
+}
+
 struct LMBuffers {
   int32_t* C;      // current clustering (labels in [0, n))
   int32_t* Cout;   // best-so-far clustering
@@ -273,6 +367,7 @@ struct LMBuffers {
   uint32_t* arena; // 2 * nnz (key, value) slots for the global-memory hash
   void* scan_temp;
   int64_t* pairs;  // per-bucket counters of enumerated (vertex, cluster) pairs, or null
+  Tagged* tg;      // free-id marks and single-pass scan state
 };
 
 struct LMParams {

@@ -75,6 +75,7 @@ struct WS {
   uint8_t *inU, *flip, *has_child, *member;
   int32_t *H, *par, *root, *tsz, *pos_of, *fail, *mpos, *alt_list;
   int32_t* gid0;  // union of graphs: graph of every level-0 vertex
+  Tagged tg;      // free-id marks and single-pass scan state (zeroed when the workspace is allocated)
   void* scan_temp;
   void* radix_temp;
 };
@@ -114,6 +115,11 @@ size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
   w.pos_of = c.take<int32_t>(n); w.fail = c.take<int32_t>(n); w.mpos = c.take<int32_t>(n + 1);
   w.alt_list = c.take<int32_t>(n);
   w.gid0 = c.take<int32_t>(n);
+  w.tg = Tagged{};
+  w.tg.held = c.take<uint32_t>(n); w.tg.held_cap = n;
+  w.tg.status_cap = (M + 1) / LB_TILE + 2;
+  w.tg.status = c.take<unsigned long long>(w.tg.status_cap);
+  w.tg.ticket = c.take<uint32_t>(1);
   w.scan_temp = c.take<char>((int64_t)scan_temp_bytes(M + 1));
   w.radix_temp = c.take<char>((int64_t)radix_temp_bytes(M));
   return c.off;
@@ -184,6 +190,10 @@ struct lcc_ctx {
     ws_base = (char*)dalloc(need);
     ws_bytes = need;
     carve(w, ws_base, nn, ne);
+    hip_check(hipMemset(w.tg.held, 0, (size_t)w.tg.held_cap * sizeof(uint32_t)), "workspace");
+    hip_check(hipMemset(w.tg.status, 0, (size_t)w.tg.status_cap * sizeof(unsigned long long)), "workspace");
+    hip_check(hipMemset(w.tg.ticket, 0, sizeof(uint32_t)), "workspace");
+    hip_check(hipDeviceSynchronize(), "workspace");
     ws_n = nn;
     ws_nnz = ne;
   }
@@ -399,6 +409,7 @@ struct Run {
     B.scan_a = w.scan_a; B.scan_b = w.scan_b; B.freelist = w.freelist; B.arena = (uint32_t*)w.k0;
     B.scan_temp = w.scan_temp;
     B.pairs = &w.ctrl->pairs[0];
+    B.tg = &w.tg;
     return B;
   }
 
@@ -428,7 +439,6 @@ struct Run {
       q.N0 = gN0;
       q.copy = gcopy;
       q.ownv = w.t64a;
-      q.fl = w.flip;
     }
     return P;
   }

@@ -944,34 +944,86 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
   if (threadIdx.x == 0 && ne) atomicAdd((unsigned long long*)&slot->n_empty, ne);
 }
 
-// free cluster ids = ids no vertex holds once every move except those to a new singleton is applied
-__global__ void k_free_init(int64_t n, uint8_t* fl, const LMSlot* slot) {
-  if (slot->n_empty == 0) return;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
-    fl[c] = 1;
-}
-
-__global__ void k_free_mark(int64_t n, const int32_t* C, const uint8_t* empty, uint8_t* fl, const LMSlot* slot) {
-  if (slot->n_empty == 0) return;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    if (!empty[v]) fl[C[v]] = 0;
-}
-
-__global__ void k_free_list(int64_t n, const uint8_t* fl, const int32_t* rank, int32_t* freelist,
+// Free cluster ids are the ids that no vertex holds once every move except those to a new singleton is
+// applied.  A held id is marked with this pass's tag (marks of earlier passes carry older tags).
+__global__ void k_free_mark(int64_t n, const int32_t* C, const uint8_t* empty, uint32_t* held, uint32_t tag,
                             const LMSlot* slot) {
   if (slot->n_empty == 0) return;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
-    if (fl[c]) freelist[rank[c]] = (int32_t)c;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    if (!empty[v]) held[C[v]] = tag;
 }
 
-__global__ void k_assign_empty(int64_t n, const uint8_t* empty, const int32_t* rank, const int32_t* freelist,
-                               const int64_t* vw, int32_t* C, int64_t* W, const LMSlot* slot) {
+// The free ids in ascending order (freelist) and, for a union, every id's rank among them (rank[n] = count).
+__global__ __launch_bounds__(BLOCK) void k_free_list(int64_t n, const uint32_t* held, uint32_t tag,
+                                                     int32_t* freelist, int32_t* rank, unsigned long long* status,
+                                                     uint32_t* ticket, uint32_t lbtag, uint32_t nt,
+                                                     const LMSlot* slot) {
   if (slot->n_empty == 0) return;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    if (!empty[v]) continue;
-    int32_t c = freelist[rank[v]];
-    C[v] = c;
-    W[c] = vw[v];  // a free id has weight 0
+  __shared__ uint32_t sh_t, sh_p, wsum[BLOCK / WAVE];
+  const uint32_t draws = nt + gridDim.x;
+  for (uint32_t t = lb_next(ticket, draws, &sh_t); t < nt; t = lb_next(ticket, draws, &sh_t)) {
+    const int64_t base = (int64_t)t * LB_TILE + (int64_t)threadIdx.x * LB_ITEMS;
+    uint32_t f[LB_ITEMS], s = 0;
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+      f[k] = (base + k < n && held[base + k] != tag) ? 1u : 0u;
+      s += f[k];
+    }
+    uint32_t tot;
+    const uint32_t ex = lb_block_excl(s, &tot, wsum);
+    uint32_t run = lb_prefix(status, t, lbtag, tot, &sh_p) + ex;
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+      if (base + k < n) {
+        if (rank) rank[base + k] = (int32_t)run;
+        if (f[k]) freelist[run] = (int32_t)(base + k);
+      }
+      run += f[k];
+    }
+    if (rank && base < n && base + LB_ITEMS >= n) rank[n] = (int32_t)run;
+  }
+}
+
+// Movers to a new singleton take the free ids in ascending vertex order: the i-th mover takes freelist[i].
+// For a union only the movers' ranks are written (rank, rank[n] = count); k_assign_empty_seg assigns.
+__global__ __launch_bounds__(BLOCK) void k_assign_empty(int64_t n, const uint8_t* empty, const int32_t* freelist,
+                                                        const int64_t* vw, int32_t* C, int64_t* W, int32_t* rank,
+                                                        unsigned long long* status, uint32_t* ticket,
+                                                        uint32_t lbtag, uint32_t nt, const LMSlot* slot) {
+  if (slot->n_empty == 0) return;
+  __shared__ uint32_t sh_t, sh_p, wsum[BLOCK / WAVE];
+  const uint32_t draws = nt + gridDim.x;
+  for (uint32_t t = lb_next(ticket, draws, &sh_t); t < nt; t = lb_next(ticket, draws, &sh_t)) {
+    const int64_t base = (int64_t)t * LB_TILE + (int64_t)threadIdx.x * LB_ITEMS;
+    uint32_t f[LB_ITEMS], s = 0;
+    if (base + LB_ITEMS <= n) {
+      const uint64_t e8 = *(const uint64_t*)(empty + base);  // base is a multiple of 8
+#pragma unroll
+      for (int k = 0; k < LB_ITEMS; ++k) f[k] = (uint32_t)(e8 >> (8 * k)) & 0xFFu ? 1u : 0u;
+    } else {
+#pragma unroll
+      for (int k = 0; k < LB_ITEMS; ++k) f[k] = (base + k < n && empty[base + k]) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) s += f[k];
+    uint32_t tot;
+    const uint32_t ex = lb_block_excl(s, &tot, wsum);
+    uint32_t run = lb_prefix(status, t, lbtag, tot, &sh_p) + ex;
+#pragma unroll
+    for (int k = 0; k < LB_ITEMS; ++k) {
+      const int64_t v = base + k;
+      if (v < n) {
+        if (rank) {
+          rank[v] = (int32_t)run;
+        } else if (f[k]) {
+          const int32_t c = freelist[run];
+          C[v] = c;
+          W[c] = vw[v];  // a free id has weight 0
+        }
+      }
+      run += f[k];
+    }
+    if (rank && base < n && base + LB_ITEMS >= n) rank[n] = (int32_t)run;
   }
 }
 
@@ -1391,6 +1443,8 @@ inline unsigned grp_blocks(int64_t cnt, int G) {
 inline unsigned vtx_blocks(int64_t cnt, int64_t cap = MAX_BLOCKS) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cnt, cap));
 }
+// persistent workgroups of a single-pass scan over nt tiles
+inline unsigned lb_blocks(uint32_t nt) { return (unsigned)std::max<uint32_t>(1, std::min<uint32_t>(nt, 1024)); }
 
 // Hub chunk scratch lives at the end of the per-chunk partial arrays.
 struct HubScratch {
@@ -1584,20 +1638,20 @@ static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, const SegLM& sg,
   unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 4096));
   k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass);
   // free ids and ranks of the movers to a new singleton; all no-ops unless some vertex moved to a new
-  // singleton in this pass.  A single graph reuses keep as the free-id flags; a union keeps keep intact (only
-  // the listed vertices rewrite it) and uses its own flags.
-  uint8_t* fl = sg.G ? sg.fl : bufs.keep;
-  k_free_init<<<grid_for(n), BLOCK, 0, st>>>(n, fl, slot);
-  k_free_mark<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.C, bufs.empty, fl, slot);
-  scan_u8_i32(fl, bufs.scan_a, n, bufs.scan_temp, &slot->n_empty, st);
-  k_free_list<<<grid_for(n), BLOCK, 0, st>>>(n, fl, bufs.scan_a, bufs.freelist, slot);
-  scan_u8_i32(bufs.empty, bufs.scan_b, n, bufs.scan_temp, &slot->n_empty, st);
+  // singleton in this pass
+  Tagged& tg = *bufs.tg;
+  const uint32_t mark = next_tag(tg, st);
+  k_free_mark<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.C, bufs.empty, tg.held, mark, slot);
+  const uint32_t nt = (uint32_t)cdiv(n, LB_TILE);
+  const unsigned gl = lb_blocks(nt);
+  k_free_list<<<gl, BLOCK, 0, st>>>(n, tg.held, mark, bufs.freelist, sg.G ? bufs.scan_a : nullptr, tg.status,
+                                    tg.ticket, next_tag(tg, st), nt, slot);
+  k_assign_empty<<<gl, BLOCK, 0, st>>>(n, bufs.empty, bufs.freelist, g.vw, bufs.C, bufs.W,
+                                       sg.G ? bufs.scan_b : nullptr, tg.status, tg.ticket, next_tag(tg, st), nt,
+                                       slot);
   if (sg.G)
     k_assign_empty_seg<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_a, bufs.scan_b, bufs.freelist, sg.gid,
                                                      sg.vbase, g.vw, bufs.C, bufs.W, slot);
-  else
-    k_assign_empty<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_b, bufs.freelist, g.vw, bufs.C, bufs.W,
-                                                 slot);
 }
 
 // Objective bookkeeping of state k after pass `pass` (union: per graph).
@@ -1688,6 +1742,15 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
   } else {
     best_so_far(sg, slot, prm, bufs, n, 0, -1, st);
   }
+}
+
+uint32_t next_tag(Tagged& t, hipStream_t st) {
+  if (t.last == UINT32_MAX) {  // every tag is used: clear the tagged words and number again from 1
+    zero_bytes(t.held, (size_t)t.held_cap * sizeof(uint32_t), st);
+    zero_bytes(t.status, (size_t)t.status_cap * sizeof(unsigned long long), st);
+    t.last = 0;
+  }
+  return ++t.last;
 }
 
 void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {
