@@ -27,22 +27,24 @@ METRIC = "full-pipeline edges/s + HBM GB/s fraction; batched vs plain p50/p99 la
 HBM_PEAK_GBS = 8000.0
 
 
-def workload(name):
+def workload(name, generate=True):
+    """(graph or None, variant, lambda, vertex-weight mode, description) of a named single-graph workload."""
     import graphgen as gg
     import paper_2608_01503_amd as L
-    if name == "rmat22":
-        return gg.config2_rmat(), L.LCC_PLOUVAIN, (1, 1, True), L.LCC_VW_WEIGHTED_DEGREE, \
-            "R-MAT scale 22, edge factor 16, (0.57,0.19,0.19,0.05), pLouvain+ (Louvain+), modularity"
-    if name == "sbm2000":
-        return gg.config1_sbm(), L.LCC_PLOUVAIN, (1, 1, True), L.LCC_VW_WEIGHTED_DEGREE, \
-            "SBM 20 x 100, p_in 0.1, p_out 0.002, pLouvain+ (Louvain+), modularity"
-    if name == "lattice4096":
-        return gg.config3a_lattice(), L.LCC_PLEIDEN, (1, 20, False), L.LCC_VW_UNIT, \
-            "4096 x 4096 lattice, 10% edges deleted, weights U[1,100], pLeiden, CPM lambda=1/20"
-    if name == "rmat26":
-        return gg.config3b_rmat(), L.LCC_PLEIDEN, (1, 20, False), L.LCC_VW_UNIT, \
-            "R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), pLeiden, CPM lambda=1/20"
-    raise SystemExit(f"unknown workload {name}")
+    specs = {
+        "rmat22": (gg.config2_rmat, L.LCC_PLOUVAIN, (1, 1, True), L.LCC_VW_WEIGHTED_DEGREE,
+                   "R-MAT scale 22, edge factor 16, (0.57,0.19,0.19,0.05), pLouvain+ (Louvain+), modularity"),
+        "sbm2000": (gg.config1_sbm, L.LCC_PLOUVAIN, (1, 1, True), L.LCC_VW_WEIGHTED_DEGREE,
+                    "SBM 20 x 100, p_in 0.1, p_out 0.002, pLouvain+ (Louvain+), modularity"),
+        "lattice4096": (gg.config3a_lattice, L.LCC_PLEIDEN, (1, 20, False), L.LCC_VW_UNIT,
+                        "4096 x 4096 lattice, 10% edges deleted, weights U[1,100], pLeiden, CPM lambda=1/20"),
+        "rmat26": (gg.config3b_rmat, L.LCC_PLEIDEN, (1, 20, False), L.LCC_VW_UNIT,
+                   "R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), pLeiden, CPM lambda=1/20"),
+    }
+    if name not in specs:
+        raise SystemExit(f"unknown workload {name}")
+    gen, variant, lam, mode, desc = specs[name]
+    return (gen() if generate else None), variant, lam, mode, desc
 
 
 def counter_traffic(family: str, workload_name: str):
@@ -67,6 +69,122 @@ def counter_traffic(family: str, workload_name: str):
         return float(rec["traffic_bytes_per_launch"])
     except (KeyError, OSError, ValueError):
         return None
+
+
+COUNTER_SOURCES = ["paper_2608_01503_amd/csrc/lm.hip", "paper_2608_01503_amd/csrc/common.h"]
+
+
+def write_counter_summary(run_dir: str, family: str, workload_name: str):
+    """Summarise four rocprofv3 counter runs under run_dir into profiles/counters_<family>_<workload>.txt:
+    fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of one pipeline step with --family), cal_fetch/ and cal_write/
+    (the same counters over --copy-calibration, a plain 1 GiB device copy, which fixes the scale of each
+    counter in bytes).  Runs on the host; reads only the CSV files."""
+    import csv
+    import glob
+    import re
+    import statistics
+    sys.path.insert(0, ROOT)
+    from paper_2608_01503_amd.lcc import FAMILY_KERNELS
+    kernel = FAMILY_KERNELS[family]
+
+    def rows(sub):
+        f = glob.glob(os.path.join(run_dir, sub, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {os.path.join(run_dir, sub)}")
+        return list(csv.DictReader(open(f[0])))
+
+    def copy_scale(sub):
+        v = max(float(r["Counter_Value"]) for r in rows(sub) if "copy" in r["Kernel_Name"].lower())
+        return (1 << 30) / (v * 1024.0), v
+
+    def per_dispatch(sub):
+        pat = re.compile(r"\b" + re.escape(kernel.split("<")[0]) + (re.escape("<" + kernel.split("<", 1)[1]) if "<" in kernel else r"\("))
+        return [float(r["Counter_Value"]) for r in rows(sub) if pat.search(r["Kernel_Name"])]
+
+    ff, fv = copy_scale("cal_fetch")
+    wf, wv = copy_scale("cal_write")
+    fk, wk = per_dispatch("fetch"), per_dispatch("write")
+    if not fk or len(fk) != len(wk):
+        raise SystemExit(f"dispatches of {kernel}: fetch {len(fk)}, write {len(wk)}")
+    fetch_b = statistics.mean(fk) * 1024 * ff
+    write_b = statistics.mean(wk) * 1024 * wf
+    h = hashlib.sha256()
+    for f in COUNTER_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    step = f"python -u bench.py --workload {workload_name} --steps 1 --warmup 0 --no-cpu-baseline --family {family}"
+    cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/fetch -o run -- {step}",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {run_dir}/write -o run -- {step}",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/cal_fetch -o run -- python -u bench.py --copy-calibration",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {run_dir}/cal_write -o run -- python -u bench.py --copy-calibration",
+            f"python bench.py --counter-summary {run_dir} --workload {workload_name} --family {family}"]
+    out = os.path.join(ROOT, "profiles", f"counters_{family}_{workload_name}.txt")
+    with open(out, "w") as o:
+        o.write(f"# HBM traffic of kernel family {family} ({kernel}) on workload {workload_name}\n")
+        o.write("# rocprofv3 counter runs (one pipeline step each), the plain 1 GiB device-copy calibration, the summary:\n")
+        for c in cmds:
+            o.write(f"#   {c}\n")
+        o.write(f"kernel: {kernel}\n")
+        o.write(f"dispatches: {len(fk)}\n")
+        o.write(f"fetch_kib_per_dispatch_raw: {statistics.mean(fk):.1f}\n")
+        o.write(f"write_kib_per_dispatch_raw: {statistics.mean(wk):.1f}\n")
+        o.write(f"copy_fetch_kib_raw_for_1GiB: {fv:.1f}\n")
+        o.write(f"copy_write_kib_raw_for_1GiB: {wv:.1f}\n")
+        o.write(f"fetch_scale: {ff:.4f}\n")
+        o.write(f"write_scale: {wf:.4f}\n")
+        o.write(f"fetch_bytes_per_launch: {fetch_b:.0f}\n")
+        o.write(f"write_bytes_per_launch: {write_b:.0f}\n")
+        o.write(f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}\n")
+        o.write(f"sources: {' '.join(COUNTER_SOURCES)}\n")
+        o.write(f"sources_sha256: {h.hexdigest()}\n")
+    print(open(out).read())
+
+
+def write_trace_summary(run_dir: str, workload_name: str, steps: int, warmup: int, family: str):
+    """Summarise a rocprofv3 --kernel-trace --stats run of `bench.py --steps S --warmup W --family F` (S + W
+    clustering calls) into profiles/kernels_<workload>.txt: time, launches and average duration per kernel,
+    per call.  Runs on the host; reads only the CSV file."""
+    import csv
+    import glob
+    import re
+    f = glob.glob(os.path.join(run_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_stats.csv under {run_dir}")
+    rows = list(csv.DictReader(open(f[0])))
+    calls = steps + warmup
+    _, _, _, _, desc = workload(workload_name, generate=False)
+
+    def short(name):
+        name = name.replace("lcc::(anonymous namespace)::", "").replace("lcc::", "")
+        name = re.sub(r"^void ", "", name)
+        depth, out = 0, []
+        for ch in name:  # drop the parameter list, keep template arguments
+            if ch == "(" and depth == 0:
+                break
+            depth += ch == "<"
+            depth -= ch == ">"
+            out.append(ch)
+        return "".join(out)
+
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows) / calls / 1e6
+    out = os.path.join(ROOT, "profiles", f"kernels_{workload_name}.txt")
+    with open(out, "w") as o:
+        o.write(f"# Kernel time per clustering call: {desc}\n")
+        o.write(f"# commands ({calls} clustering calls: {warmup} warm-up + {steps} timed, plus one objective check; "
+                "figures below are per clustering call):\n")
+        o.write(f"#   rocprofv3 --kernel-trace --stats --output-format csv -d {run_dir} -o run -- python -u bench.py "
+                f"--workload {workload_name} --steps {steps} --warmup {warmup} --no-cpu-baseline --family {family}\n")
+        o.write(f"#   python bench.py --trace-summary {run_dir} --workload {workload_name} --steps {steps} "
+                f"--warmup {warmup} --family {family}\n")
+        o.write(f"# total kernel time per call: {total:.2f} ms\n#\n")
+        o.write("# ms/call  calls/call  avg_us  max_us  kernel\n")
+        for r in rows:
+            ms = float(r["TotalDurationNs"]) / calls / 1e6
+            if ms < 0.005:
+                continue
+            o.write(f"{ms:8.2f} {int(r['Calls']) / calls:9.1f} {float(r['AverageNs']) / 1e3:9.1f} "
+                    f"{float(r['MaxNs']) / 1e3:9.1f}  {short(r['Name'])}\n")
+    print(open(out).read())
 
 
 def bench_knn_batch(args):
@@ -296,9 +414,19 @@ def main():
     ap.add_argument("--knn-count", type=int, default=4096, help="graphs of the kNN batch workload")
     ap.add_argument("--serve-count", type=int, default=240, help="measured requests of the served workload")
     ap.add_argument("--serve-warm", type=int, default=24, help="warm-up requests of the served workload")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="only summarise the rocprofv3 kernel-trace run under DIR into profiles/")
+    ap.add_argument("--counter-summary", metavar="DIR",
+                    help="only summarise the rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR into profiles/")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (counter calibration for HBM traffic)")
     args = ap.parse_args()
+    if args.trace_summary:
+        write_trace_summary(args.trace_summary, args.workload, args.steps, args.warmup, args.family)
+        return
+    if args.counter_summary:
+        write_counter_summary(args.counter_summary, args.family, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU path is not built",
               file=sys.stderr)
