@@ -154,7 +154,7 @@ def write_trace_summary(run_dir: str, workload_name: str, steps: int, warmup: in
     _, _, _, _, desc = workload(workload_name, generate=False)
 
     def short(name):
-        name = name.replace("lcc::(anonymous namespace)::", "").replace("lcc::", "")
+        name = name.replace("lcc::", "").replace("(anonymous namespace)::", "")
         name = re.sub(r"^void ", "", name)
         depth, out = 0, []
         for ch in name:  # drop the parameter list, keep template arguments
