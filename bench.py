@@ -508,6 +508,10 @@ def main():
                 "avg_launch_ms": kms / launches if launches else None,
                 "bytes_per_launch": kbytes / launches if launches else None,
                 "traffic_over_algorithmic": traffic / (kbytes / launches) if traffic and launches else None,
+                # counted HBM bytes per launch over the same live launch time (the fraction by bytes moved)
+                "traffic_gbs": traffic / (kms / launches) / 1e6 if traffic and launches and kms > 0 else None,
+                "traffic_frac": traffic / (kms / launches) / 1e6 / HBM_PEAK_GBS if traffic and launches and kms > 0
+                else None,
                 "share_of_step": (kms / max(args.steps, 1)) / (sec * 1e3)}
 
     out = {
