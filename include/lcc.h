@@ -199,6 +199,36 @@ lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda
 lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, const int32_t* labels,
                          void* stream, lcc_result* res);
 
+/* Launch tuning of a context.  Every setting gives bit-identical results; only the work decomposition
+ * changes.  bucket_max[k] is the largest row degree put in degree bucket k (0-3: groups of 4/8/16/32 lanes,
+ * 4: a wavefront with a 256-slot LDS hash, 5 and 6: workgroups with 2048- and 8192-slot LDS hashes; rows above
+ * bucket_max[6] go to the hub path of 2048-edge chunks).  A bucket's kernels serve rows up to their default
+ * bound {4, 8, 16, 32, 128, 1024, 4096}, so a tuning may lower the bounds (non-decreasing in k, >= 0) but not
+ * raise them; equal neighbouring bounds leave a bucket empty.  grid_cap (64..65536, default 2048) bounds the
+ * workgroups of the persistent per-vertex launches.  lcc_set_tuning returns LCC_ERR_INVALID for a setting
+ * outside these limits and leaves the context unchanged; the tuning applies to later calls on the context
+ * (and to the execution slots of servers created afterwards). */
+typedef struct {
+  int64_t bucket_max[7];
+  int32_t grid_cap;
+  int32_t reserved;  /* 0 */
+} lcc_tuning;
+
+void lcc_default_tuning(lcc_tuning* t);
+lcc_status lcc_set_tuning(lcc_ctx* ctx, const lcc_tuning* t);
+lcc_status lcc_get_tuning(lcc_ctx* ctx, lcc_tuning* t);
+
+/* Autotuner: times a fixed list of candidate tunings (three grid caps with the current bounds, then bucket
+ * layouts that move rows to larger-capacity buckets with the best cap) on the given graphs, `trials` timed
+ * runs each after one warm-up run (the fastest run counts), and keeps the fastest tuning on the context.
+ * Each run is one lcc_cluster_batch call over the graphs (lcc_cluster when count == 1) on `stream`; graphs,
+ * lambdas, variants and opts are as for lcc_cluster_batch, and labels are written to scratch the tuner owns.
+ * *best receives the chosen tuning and *best_ms (may be NULL) its time per run.  On a failing run its status
+ * is returned and the context keeps the tuning it had. */
+lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lambdas, const lcc_variant* variants,
+                        int64_t count, const lcc_options* opts, void* stream, int32_t trials, lcc_tuning* best,
+                        double* best_ms);
+
 /* Continuous-batching server over one context (its device and allocator).  The server runs 8 execution
  * slots, each with its own context and HIP stream, so admitted jobs run concurrently on the GPU.  A free slot
  * admits the oldest queued job whose footprint (lcc_workspace_bytes) fits the unreserved part of hbm_budget

@@ -5,4 +5,4 @@ The computation lives in the HIP library ``liblcc.so`` (hand-written gfx950 kern
 """
 from .lcc import (LCC_LOUVAIN, LCC_PLEIDEN, LCC_PLEIDEN_PLUS, LCC_PLOUVAIN, LCC_VW_GIVEN, LCC_VW_UNIT,  # noqa: F401
                   LCC_VW_WEIGHTED_DEGREE, Context, LccError, Result, Server, lcc_default_options,
-                  lcc_workspace_bytes, load, make_graph)
+                  lcc_default_tuning, lcc_workspace_bytes, load, make_graph, tuning_dict)

@@ -19,15 +19,21 @@ constexpr int32_t D_EMPTY = -2;  // destination = a new singleton cluster
 // Degree buckets (upper bounds, inclusive).  Buckets 0-3 are handled by sub-wave groups of 4/8/16/32 lanes
 // (one neighbour per lane), 4-5 by one wavefront per vertex, 6-7 by one workgroup per vertex.  The local-move
 // kernels aggregate neighbour clusters with register shuffles (0-3), an LDS hash (4-6) or a global-memory
-// hash inside the edge arena (7).
-constexpr int64_t BUCKET_MAX[NBUCKET] = {4, 8, 16, 32, 128, 1024, 4096, INT64_MAX};
+// hash inside the edge arena (7).  BUCKET_CAP holds the largest row each of buckets 0-6 can serve (the lane
+// count of its group, half the slots of its LDS hash); a tuning may set lower bounds, never higher ones, and
+// every setting gives the same results.
+constexpr int64_t BUCKET_CAP[NBUCKET - 1] = {4, 8, 16, 32, 128, 1024, 4096};
 constexpr int LDS_SLOTS_B4 = 256;
 constexpr int LDS_SLOTS_B5 = 2048;
 constexpr int LDS_SLOTS_B6 = 8192;
 
-__host__ __device__ inline int bucket_of(int64_t d) {
+struct BucketBounds {
+  int64_t max[NBUCKET - 1];  // upper degree bound of buckets 0..6; bucket 7 takes the rest
+};
+
+__host__ __device__ inline int bucket_of(int64_t d, const BucketBounds& bb) {
   int b = 0;
-  while (b < NBUCKET - 1 && d > BUCKET_MAX[b]) ++b;
+  while (b < NBUCKET - 1 && d > bb.max[b]) ++b;
   return b;
 }
 
@@ -108,6 +114,7 @@ struct DevGraph {
 // Vertex lists of the degree buckets of one level (all buckets in one array, bucket b at [off[b], off[b+1])).
 struct Buckets {
   const int32_t* list = nullptr;
+  int32_t grid_cap = 2048;  // workgroups of the persistent per-vertex launches (a result-neutral tuning)
   int64_t count[NBUCKET] = {};
   int64_t off[NBUCKET + 1] = {};
   // hub (last bucket) vertices are processed in fixed-size edge chunks: chunk range of hub k is
@@ -246,7 +253,7 @@ void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, cons
                           int64_t* vw_out, Ctrl* ctrl, hipStream_t st, const int32_t* gid = nullptr,
                           const int8_t* gmode = nullptr, int64_t* rowsum = nullptr);
 // Degree buckets of the vertices of a level; with gid/gact only the vertices whose graph has gact set.
-void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st,
+void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, const BucketBounds& bb, hipStream_t st,
                     const int32_t* gid = nullptr, const uint8_t* gact = nullptr);
 // out[k] = sum of x[i] (or x[i]^2) over i in [vbase[k], vbase[k+1]), k < G
 void launch_seg_sum(const int64_t* x, int square, const int32_t* vbase, int64_t G, int64_t* out, hipStream_t st);

@@ -22,9 +22,9 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)g;
 }
 // persistent launches (at most 2048 workgroups looping over their share of the vertices)
-inline unsigned grp_blocks(int64_t cnt, int G) {
+inline unsigned grp_blocks(const Buckets& bk, int64_t cnt, int G) {
   int64_t b = cdiv(cnt, BLOCK / G);
-  return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+  return (unsigned)(b < 1 ? 1 : (b > bk.grid_cap ? bk.grid_cap : b));
 }
 
 __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
@@ -288,12 +288,12 @@ void launch_coarse_vw(const int32_t* map, const int64_t* vw, int64_t n, int64_t*
 
 void launch_cross_count(const DevGraph& g, const Buckets& b, const int32_t* map, int32_t* cnt, hipStream_t st) {
   const int32_t* L = b.list;
-  if (b.count[0]) k_cross_count_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, map, cnt);
-  if (b.count[1]) k_cross_count_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, map, cnt);
-  if (b.count[2]) k_cross_count_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, map, cnt);
-  if (b.count[3]) k_cross_count_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, map, cnt);
+  if (b.count[0]) k_cross_count_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, map, cnt);
+  if (b.count[1]) k_cross_count_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, map, cnt);
+  if (b.count[2]) k_cross_count_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, map, cnt);
+  if (b.count[3]) k_cross_count_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, map, cnt);
   int64_t nw = b.count[4] + b.count[5] + b.count[6];
-  if (nw) k_cross_count_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, map, cnt);
+  if (nw) k_cross_count_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, map, cnt);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
     k_zero_hub_counts<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], cnt);
@@ -305,12 +305,12 @@ void launch_cross_count(const DevGraph& g, const Buckets& b, const int32_t* map,
 void launch_cross_emit(const DevGraph& g, const Buckets& b, const int32_t* map, int64_t* cursor, uint64_t* keys,
                        uint32_t* vals, hipStream_t st) {
   const int32_t* L = b.list;
-  if (b.count[0]) k_cross_emit_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, map, cursor, keys, vals);
-  if (b.count[1]) k_cross_emit_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, map, cursor, keys, vals);
-  if (b.count[2]) k_cross_emit_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, map, cursor, keys, vals);
-  if (b.count[3]) k_cross_emit_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, map, cursor, keys, vals);
+  if (b.count[0]) k_cross_emit_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, map, cursor, keys, vals);
+  if (b.count[1]) k_cross_emit_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, map, cursor, keys, vals);
+  if (b.count[2]) k_cross_emit_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, map, cursor, keys, vals);
+  if (b.count[3]) k_cross_emit_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, map, cursor, keys, vals);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_cross_emit_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, map, cursor, keys, vals);
+  if (nw) k_cross_emit_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, map, cursor, keys, vals);
   if (b.count[6]) k_cross_emit_chunk<<<(unsigned)b.count[6], HUB_BLOCK, 0, st>>>(L + b.off[6], nullptr, b.count[6], 0, g, map, cursor, keys, vals);
   if (b.count[7]) k_cross_emit_chunk<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], HUB_CHUNK_EDGES, g, map, cursor, keys, vals);
 }

@@ -6,6 +6,7 @@
 // call is queued on the caller's stream; the host synchronises only where a size decides the next launch
 // (bucket counts, cluster counts, coarse entry counts) -- a handful of times per level.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
@@ -142,6 +143,12 @@ size_t level_bytes(int64_t n, int64_t nnz) {
 
 struct lcc_ctx {
   int device = 0;
+  lcc_tuning tune{{4, 8, 16, 32, 128, 1024, 4096}, 2048, 0};  // result-neutral launch tuning
+  BucketBounds bounds() const {
+    BucketBounds b;
+    for (int k = 0; k < NBUCKET - 1; ++k) b.max[k] = tune.bucket_max[k];
+    return b;
+  }
   lcc_alloc_fn alloc = nullptr;
   lcc_free_fn freef = nullptr;
   void* user = nullptr;
@@ -381,7 +388,7 @@ struct Run {
   void prepare(Level& L, int32_t* list, int32_t* hub_off, const uint8_t* act = nullptr, Buckets* into = nullptr) {
     const int64_t n = L.g.n;
     k_reset_level_counters<<<1, 1, 0, st>>>(w.ctrl);
-    launch_buckets(L.g.off, n, list, w.ctrl, st, G ? L.gid : nullptr, act);
+    launch_buckets(L.g.off, n, list, w.ctrl, ctx->bounds(), st, G ? L.gid : nullptr, act);
     if (!into) launch_vertex_sums(L.g.vw, n, w.ctrl, st);
     if (G && !into) {
       L.sumw2g = take<int64_t>(ctx, G);
@@ -399,6 +406,7 @@ struct Run {
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = hub_off;
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    b.grid_cap = ctx->tune.grid_cap;
     if (!into) L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
     if (b.count[NBUCKET - 1]) launch_hub_chunks(list + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, hub_off, w.scan_temp, st);
   }
@@ -818,7 +826,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   {
     // prepare() reads vertex sums, which are not derived yet: buckets first, sums after the row pass
     k_reset_level_counters<<<1, 1, 0, st>>>(w.ctrl);
-    launch_buckets(L.g.off, n, w.list0, w.ctrl, st);
+    launch_buckets(L.g.off, n, w.list0, w.ctrl, ctx->bounds(), st);
     R.read_ctrl("buckets");
     Buckets& b = L.b;
     b.list = w.list0;
@@ -831,6 +839,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = w.hub_off0;
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    b.grid_cap = ctx->tune.grid_cap;
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
@@ -1194,7 +1203,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   Level& L = R.lv[0];
   {
     k_reset_level_counters<<<1, 1, 0, st>>>(w.ctrl);
-    launch_buckets(L.g.off, n, w.list0, w.ctrl, st);
+    launch_buckets(L.g.off, n, w.list0, w.ctrl, ctx->bounds(), st);
     R.read_ctrl("buckets");
     Buckets& b = L.b;
     b.list = w.list0;
@@ -1207,6 +1216,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = w.hub_off0;
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    b.grid_cap = ctx->tune.grid_cap;
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
@@ -1375,6 +1385,132 @@ lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda
     }
     return LCC_OK;
   });
+}
+
+void lcc_default_tuning(lcc_tuning* t) {
+  if (!t) return;
+  memset(t, 0, sizeof(*t));
+  for (int k = 0; k < NBUCKET - 1; ++k) t->bucket_max[k] = BUCKET_CAP[k];
+  t->grid_cap = 2048;
+}
+
+lcc_status lcc_set_tuning(lcc_ctx* ctx, const lcc_tuning* t) {
+  return guarded([&]() -> lcc_status {
+    if (!ctx || !t) fail(LCC_ERR_INVALID, "bad arguments");
+    for (int k = 0; k < NBUCKET - 1; ++k) {
+      if (t->bucket_max[k] < 0 || t->bucket_max[k] > BUCKET_CAP[k])
+        fail(LCC_ERR_INVALID, "bucket bound " + std::to_string(k) + " outside [0, " + std::to_string(BUCKET_CAP[k]) + "]");
+      if (k > 0 && t->bucket_max[k] < t->bucket_max[k - 1]) fail(LCC_ERR_INVALID, "bucket bounds must not decrease");
+    }
+    if (t->grid_cap < 64 || t->grid_cap > 65536) fail(LCC_ERR_INVALID, "grid_cap outside [64, 65536]");
+    if (t->reserved != 0) fail(LCC_ERR_INVALID, "reserved must be 0");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->tune = *t;
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_get_tuning(lcc_ctx* ctx, lcc_tuning* t) {
+  return guarded([&]() -> lcc_status {
+    if (!ctx || !t) fail(LCC_ERR_INVALID, "bad arguments");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    *t = ctx->tune;
+    return LCC_OK;
+  });
+}
+
+lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lambdas, const lcc_variant* variants,
+                        int64_t count, const lcc_options* opts, void* stream, int32_t trials, lcc_tuning* best,
+                        double* best_ms) {
+  lcc_tuning start{};
+  bool started = false;
+  lcc_status st = guarded([&]() -> lcc_status {
+    if (!ctx || !gs || !lambdas || !variants || !best || count < 1 || trials < 1)
+      fail(LCC_ERR_INVALID, "bad autotune arguments");
+    {
+      std::lock_guard<std::mutex> lock(ctx->mu);
+      start = ctx->tune;
+      started = true;
+    }
+    // label scratch in each graph's memory space
+    std::vector<int32_t*> outs((size_t)count);
+    std::vector<std::vector<int32_t>> host_out((size_t)count);
+    std::vector<lcc_result> res((size_t)count);
+    int64_t dev_n = 0;
+    for (int64_t i = 0; i < count; ++i)
+      if (gs[i].mem == LCC_MEM_DEVICE) dev_n += std::max<int64_t>(gs[i].n, 1);
+    int32_t* dev = dev_n ? (int32_t*)ctx->dalloc((size_t)dev_n * 4) : nullptr;
+    struct Free { lcc_ctx* c; void* p; ~Free() { if (p) { (void)hipDeviceSynchronize(); c->dfree(p); } } } fr{ctx, dev};
+    for (int64_t i = 0, o = 0; i < count; ++i) {
+      if (gs[i].mem == LCC_MEM_DEVICE) {
+        outs[(size_t)i] = dev + o;
+        o += std::max<int64_t>(gs[i].n, 1);
+      } else {
+        host_out[(size_t)i].resize((size_t)std::max<int64_t>(gs[i].n, 1));
+        outs[(size_t)i] = host_out[(size_t)i].data();
+      }
+    }
+    auto run = [&](const lcc_tuning& t) -> double {
+      {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        ctx->tune = t;
+      }
+      double ms = 0;
+      for (int r = 0; r <= trials; ++r) {  // run 0 is the warm-up
+        auto t0 = std::chrono::steady_clock::now();
+        lcc_status s = count == 1 ? lcc_cluster(ctx, &gs[0], lambdas[0], variants[0], opts, stream, outs[0], &res[0])
+                                  : lcc_cluster_batch(ctx, gs, lambdas, variants, count, opts, stream, outs.data(),
+                                                      res.data());
+        if (s != LCC_OK) fail(s, std::string("autotune run: ") + (lcc_last_error() ? lcc_last_error() : ""));
+        double d = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (r == 1 || (r > 1 && d < ms)) ms = d;
+      }
+      return ms;
+    };
+    lcc_tuning cur = start, win = start;
+    double win_ms = run(start);
+    for (int32_t cap : {1024, 2048, 4096}) {  // workgroup caps with the current bounds
+      if (cap == start.grid_cap) continue;
+      lcc_tuning t = start;
+      t.grid_cap = cap;
+      double ms = run(t);
+      if (ms < win_ms) { win_ms = ms; win = t; }
+    }
+    cur = win;
+    // bucket layouts: each moves one class of rows to a bucket of larger capacity
+    static const int64_t layouts[][NBUCKET - 1] = {
+        {4, 8, 16, 32, 128, 1024, 4096},   // the default
+        {0, 8, 16, 32, 128, 1024, 4096},   // no 4-lane groups
+        {4, 8, 16, 16, 128, 1024, 4096},   // no 32-lane groups: degrees 17-32 to a wavefront
+        {4, 8, 16, 32, 64, 1024, 4096},    // wavefront hash only up to degree 64
+        {4, 8, 16, 32, 128, 512, 4096},    // the 8192-slot workgroups from degree 513
+        {4, 8, 16, 32, 128, 1024, 2048},   // hub chunks from degree 2049
+        {4, 8, 16, 32, 128, 1024, 1024},   // no 8192-slot workgroups: hub chunks from degree 1025
+    };
+    for (const auto& lay : layouts) {
+      lcc_tuning t = cur;
+      bool same = true;
+      for (int k = 0; k < NBUCKET - 1; ++k) {
+        same = same && t.bucket_max[k] == lay[k];
+        t.bucket_max[k] = lay[k];
+      }
+      if (same) continue;
+      double ms = run(t);
+      if (ms < win_ms) { win_ms = ms; win = t; }
+    }
+    {
+      std::lock_guard<std::mutex> lock(ctx->mu);
+      ctx->tune = win;
+    }
+    *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return LCC_OK;
+  });
+  if (st != LCC_OK && started) {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->tune = start;
+  }
+  return st;
 }
 
 lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const int32_t* labels, void* stream,

@@ -1202,7 +1202,8 @@ __global__ void k_zero_i64(int64_t* p) {
 // ---------------------------------------------------------------------------------------------------------
 // Degree buckets
 // ---------------------------------------------------------------------------------------------------------
-__global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl, const int32_t* gid, const uint8_t* gact) {
+__global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl, const int32_t* gid, const uint8_t* gact,
+                               BucketBounds bb) {
   __shared__ unsigned long long cnt[NBUCKET], edg[NBUCKET];
   __shared__ unsigned long long chunks;
   if (threadIdx.x < NBUCKET) { cnt[threadIdx.x] = 0; edg[threadIdx.x] = 0; }
@@ -1211,7 +1212,7 @@ __global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl, const 
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     if (gact && !gact[gid[v]]) continue;
     int64_t d = off[v + 1] - off[v];
-    int b = bucket_of(d);
+    int b = bucket_of(d, bb);
     atomicAdd(&cnt[b], 1ull);
     if (d) atomicAdd(&edg[b], (unsigned long long)d);
     if (b == NBUCKET - 1) atomicAdd(&chunks, (unsigned long long)cdiv(d, HUB_CHUNK));
@@ -1238,7 +1239,8 @@ __global__ void k_bucket_offsets(Ctrl* ctrl) {
 // Bucket lists: per workgroup tile, LDS counts per bucket, one global atomic per bucket, positions inside
 // the tile from LDS atomics (the order inside a bucket does not affect any result).
 __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(const int64_t* off, int64_t n, int32_t* list,
-                                                          Ctrl* ctrl, const int32_t* gid, const uint8_t* gact) {
+                                                          Ctrl* ctrl, const int32_t* gid, const uint8_t* gact,
+                                                          BucketBounds bb) {
   __shared__ uint32_t cnt[NBUCKET];
   __shared__ int64_t base[NBUCKET];
   constexpr int T = 4 * BLOCK;
@@ -1250,7 +1252,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(const int64_t* off, in
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       int64_t v = t0 + k * BLOCK + threadIdx.x;
-      b[k] = (v < n && (!gact || gact[gid[v]])) ? bucket_of(off[v + 1] - off[v]) : -1;
+      b[k] = (v < n && (!gact || gact[gid[v]])) ? bucket_of(off[v + 1] - off[v], bb) : -1;
       if (b[k] >= 0) r[k] = atomicAdd(&cnt[b[k]], 1u);
     }
     __syncthreads();
@@ -1436,12 +1438,13 @@ inline unsigned red_blocks(int64_t n) {
 
 // Persistent launches: workgroups loop over their share of the vertices.  Launching one short workgroup per
 // vertex (or per few vertices) is bound by the workgroup dispatch rate, not by memory.
-constexpr int64_t MAX_BLOCKS = 4096;
-inline unsigned grp_blocks(int64_t cnt, int G) {
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(cnt, BLOCK / G), MAX_BLOCKS));
+// The local move takes twice the level's grid cap (4096 workgroups by default); the workgroup-per-vertex
+// kernels of bucket 6 take a quarter of that.
+inline unsigned grp_blocks(const Buckets& b, int64_t cnt, int G) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(cnt, BLOCK / G), 2 * (int64_t)b.grid_cap));
 }
-inline unsigned vtx_blocks(int64_t cnt, int64_t cap = MAX_BLOCKS) {
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cnt, cap));
+inline unsigned vtx_blocks(const Buckets& b, int64_t cnt, int64_t cap_div = 1) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cnt, 2 * (int64_t)b.grid_cap / cap_div));
 }
 // persistent workgroups of a single-pass scan over nt tiles
 inline unsigned lb_blocks(uint32_t nt) { return (unsigned)std::max<uint32_t>(1, std::min<uint32_t>(nt, 1024)); }
@@ -1469,13 +1472,13 @@ void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, cons
                           int64_t* rowsum) {
   const int32_t* L = b.list;
   const VwSrc vm{vw_mode, gid, gmode, rowsum};
-  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vm, vw_given, vw_out, ctrl);
-  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vm, vw_given, vw_out, ctrl);
-  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vm, vw_given, vw_out, ctrl);
-  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vm, vw_given, vw_out, ctrl);
+  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vm, vw_given, vw_out, ctrl);
+  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vm, vw_given, vw_out, ctrl);
+  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vm, vw_given, vw_out, ctrl);
+  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vm, vw_given, vw_out, ctrl);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_validate_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vm, vw_given, vw_out, ctrl);
-  if (b.count[6]) k_validate_blk<<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vm, vw_given, vw_out, ctrl);
+  if (nw) k_validate_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vm, vw_given, vw_out, ctrl);
+  if (b.count[6]) k_validate_blk<<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vm, vw_given, vw_out, ctrl);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
     fill_i64(b.hub_acc, 0, b.count[7], st);
@@ -1484,11 +1487,11 @@ void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, cons
   }
 }
 
-void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, hipStream_t st, const int32_t* gid,
-                    const uint8_t* gact) {
-  k_bucket_count<<<red_blocks(n), BLOCK, 0, st>>>(off, n, ctrl, gid, gact);
+void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, const BucketBounds& bb, hipStream_t st,
+                    const int32_t* gid, const uint8_t* gact) {
+  k_bucket_count<<<red_blocks(n), BLOCK, 0, st>>>(off, n, ctrl, gid, gact, bb);
   k_bucket_offsets<<<1, 1, 0, st>>>(ctrl);
-  k_bucket_scatter<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4 * BLOCK), 8192)), BLOCK, 0, st>>>(off, n, list, ctrl, gid, gact);
+  k_bucket_scatter<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4 * BLOCK), 8192)), BLOCK, 0, st>>>(off, n, list, ctrl, gid, gact, bb);
 }
 
 void launch_hub_chunks(const int32_t* hubs, int64_t n7, const int64_t* off, int32_t* cnt, int32_t* chunk_off,
@@ -1510,13 +1513,13 @@ void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int6
 static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
                             const int32_t* skip, hipStream_t st, int64_t* per_v = nullptr) {
   const int32_t* L = b.list;
-  if (b.count[0]) k_internal_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, out, skip, per_v);
-  if (b.count[1]) k_internal_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, out, skip, per_v);
-  if (b.count[2]) k_internal_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, out, skip, per_v);
-  if (b.count[3]) k_internal_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, out, skip, per_v);
+  if (b.count[0]) k_internal_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, out, skip, per_v);
+  if (b.count[1]) k_internal_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, out, skip, per_v);
+  if (b.count[2]) k_internal_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, out, skip, per_v);
+  if (b.count[3]) k_internal_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, out, skip, per_v);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_internal_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, out, skip, per_v);
-  if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, out, skip, per_v);
+  if (nw) k_internal_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, out, skip, per_v);
+  if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, out, skip, per_v);
   if (b.count[7]) {
     if (per_v) k_zero_listed<<<grid_for(b.count[7]), BLOCK, 0, st>>>(L + b.off[7], b.count[7], per_v, skip);
     k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, out, skip, per_v);
@@ -1528,7 +1531,7 @@ void launch_internal_per_vertex(const DevGraph& g, const Buckets& b, const int32
   launch_internal(g, b, C, nullptr, nullptr, st, out);
 }
 
-static unsigned seg_blocks(int64_t G) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(G, MAX_BLOCKS)); }
+static unsigned seg_blocks(int64_t G) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(G, 4096)); }
 
 void launch_seg_sum(const int64_t* x, int square, const int32_t* vbase, int64_t G, int64_t* out, hipStream_t st) {
   if (G > 0) k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(x, square, vbase, G, out, nullptr, nullptr, -1);
@@ -1559,13 +1562,13 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
     double sb = 0;
     for (int k = 0; k < NBUCKET; ++k) sb += 16.0 * (double)b.edges[k] + 48.0 * (double)b.count[k];
     prof_begin(PF_SINGLE, st);
-    if (b.count[0]) k_single_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, sc, pa, pb, vs, slot, pass);
-    if (b.count[1]) k_single_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, sc, pa, pb, vs, slot, pass);
-    if (b.count[2]) k_single_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, sc, pa, pb, vs, slot, pass);
-    if (b.count[3]) k_single_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[0]) k_single_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[1]) k_single_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[2]) k_single_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[3]) k_single_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, sc, pa, pb, vs, slot, pass);
     int64_t nw = b.count[4] + b.count[5];
-    if (nw) k_single_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, sc, pa, pb, vs, slot, pass);
-    if (b.count[6]) k_single_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass);
+    if (nw) k_single_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, sc, pa, pb, vs, slot, pass);
+    if (b.count[6]) k_single_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass);
     if (n7) {
       k_single_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, sc, hs.ps, hs.pc);
       k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, nullptr, nullptr, sc, pa, pb, 0,
@@ -1582,13 +1585,13 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
     launch;                                      \
     prof_end(PF_ENUM_B0 + k, eb(k), st);         \
   }
-  LCC_ENUM(0, (k_enum_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 0 : nullptr)))
-  LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 1 : nullptr)))
-  LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 2 : nullptr)))
-  LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 3 : nullptr)))
-  LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 4 : nullptr)))
-  LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 5 : nullptr)))
-  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b.count[6], 1024), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 6 : nullptr)))
+  LCC_ENUM(0, (k_enum_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 0 : nullptr)))
+  LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 1 : nullptr)))
+  LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 2 : nullptr)))
+  LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 3 : nullptr)))
+  LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 4 : nullptr)))
+  LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 5 : nullptr)))
+  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 6 : nullptr)))
 #undef LCC_ENUM
   if (n7) {
     unsigned nc = (unsigned)b.hub_chunks;
@@ -1618,13 +1621,13 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const ScoreS
   const int32_t* L = b.list;
   const VState* vs = bufs.vs;
   uint8_t* keep = bufs.keep;
-  if (b.count[0]) k_ab_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vs, sc, keep, slot, pass);
-  if (b.count[1]) k_ab_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vs, sc, keep, slot, pass);
-  if (b.count[2]) k_ab_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vs, sc, keep, slot, pass);
-  if (b.count[3]) k_ab_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass);
+  if (b.count[0]) k_ab_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vs, sc, keep, slot, pass);
+  if (b.count[1]) k_ab_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vs, sc, keep, slot, pass);
+  if (b.count[2]) k_ab_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vs, sc, keep, slot, pass);
+  if (b.count[3]) k_ab_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_ab_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vs, sc, keep, slot, pass);
-  if (b.count[6]) k_ab_blk<BIG_BLOCK><<<vtx_blocks(b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vs, sc, keep, slot, pass);
+  if (nw) k_ab_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vs, sc, keep, slot, pass);
+  if (b.count[6]) k_ab_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vs, sc, keep, slot, pass);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
     k_ab_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, vs, sc, hs.hacc, slot, pass);

@@ -28,9 +28,9 @@ inline unsigned grid_for(int64_t n) {
 }
 // persistent launches (at most 2048 workgroups looping over their share): one short workgroup per few
 // vertices is bound by the workgroup dispatch rate
-inline unsigned grp_blocks(int64_t cnt, int G) {
+inline unsigned grp_blocks(const Buckets& bk, int64_t cnt, int G) {
   int64_t b = cdiv(cnt, BLOCK / G);
-  return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+  return (unsigned)(b < 1 ? 1 : (b > bk.grid_cap ? bk.grid_cap : b));
 }
 
 __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
@@ -405,12 +405,12 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
   // constraint-cluster weights and U
   launch_cluster_weights(B, g.vw, n, rb.WB, st);
   k_set_i64<<<1, 1, 0, st>>>(&ctrl->refine_U, 0);
-  if (b.count[0]) k_aB_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
-  if (b.count[1]) k_aB_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
-  if (b.count[2]) k_aB_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
-  if (b.count[3]) k_aB_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[0]) k_aB_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[1]) k_aB_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[2]) k_aB_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[3]) k_aB_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
   int64_t nw = b.count[4] + b.count[5] + b.count[6];
-  if (nw) k_aB_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+  if (nw) k_aB_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
   const int32_t* hubs = L + b.off[7];
   const int64_t n7 = b.count[7];
   if (n7) {
@@ -419,11 +419,11 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
     k_hub_inU<<<grid_for(n7), BLOCK, 0, st>>>(hubs, n7, g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
   }
   // random candidate edge
-  if (b.count[0]) k_choose_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.inU, sc, s_t, rb.H);
-  if (b.count[1]) k_choose_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.inU, sc, s_t, rb.H);
-  if (b.count[2]) k_choose_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.inU, sc, s_t, rb.H);
-  if (b.count[3]) k_choose_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.inU, sc, s_t, rb.H);
-  if (nw) k_choose_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.inU, sc, s_t, rb.H);
+  if (b.count[0]) k_choose_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.inU, sc, s_t, rb.H);
+  if (b.count[1]) k_choose_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.inU, sc, s_t, rb.H);
+  if (b.count[2]) k_choose_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.inU, sc, s_t, rb.H);
+  if (b.count[3]) k_choose_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.inU, sc, s_t, rb.H);
+  if (nw) k_choose_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.inU, sc, s_t, rb.H);
   if (n7) {
     k_choose_hub_count<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, B, rb.inU, sc, b.hub_ps);
     k_choose_hub_pick<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, rb.inU, s_t, b.hub_ps, b.hub_acc, rb.H);
@@ -457,11 +457,11 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
     const uint32_t* sv = which ? rb.v1 : rb.v0;
     // a(v, X_{<v}) for tree members
     fill_i64(rb.aX, 0, n, st);
-    if (b.count[0]) k_aX_grp<4><<<grp_blocks(b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (b.count[1]) k_aX_grp<8><<<grp_blocks(b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (b.count[2]) k_aX_grp<16><<<grp_blocks(b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (b.count[3]) k_aX_grp<32><<<grp_blocks(b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (nw) k_aX_grp<64><<<grp_blocks(nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, rb.member, rb.root, fseed, rb.flip, rb.aX);
+    if (b.count[0]) k_aX_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
+    if (b.count[1]) k_aX_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
+    if (b.count[2]) k_aX_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
+    if (b.count[3]) k_aX_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
+    if (nw) k_aX_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, rb.member, rb.root, fseed, rb.flip, rb.aX);
     if (n7) k_aX_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, rb.member, rb.root, fseed, rb.flip, rb.aX);
     k_sorted_terms<<<grid_for(m), BLOCK, 0, st>>>(m, sv, g.vw, rb.aB, rb.aX, rb.tmp64a, rb.tmp64b, rb.pos_of);
     scan_i64_i64(rb.tmp64a, rb.pw, m, rb.scan_temp, st);

@@ -207,6 +207,8 @@ lcc_status lcc_server_create(lcc_ctx* ctx, size_t hbm_budget, lcc_server** out) 
   void* user;
   lcc_ctx_allocator_internal(ctx, &a, &f, &user);
   if (hipSetDevice(dev) != hipSuccess) { delete s; return LCC_ERR_DEVICE; }
+  lcc_tuning tune;
+  if (lcc_get_tuning(ctx, &tune) != LCC_OK) lcc_default_tuning(&tune);
   for (int k = 0; k < SLOTS; ++k) {
     lcc_ctx* c = nullptr;
     hipStream_t st = nullptr;
@@ -217,6 +219,7 @@ lcc_status lcc_server_create(lcc_ctx* ctx, size_t hbm_budget, lcc_server** out) 
       delete s;
       return LCC_ERR_DEVICE;
     }
+    (void)lcc_set_tuning(c, &tune);  // the slots run with the parent context's launch tuning
     s->ctxs.push_back(c);
     s->streams.push_back(st);
   }

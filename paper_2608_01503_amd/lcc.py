@@ -26,7 +26,8 @@ LCC_FLAG_LEVEL_CAP, LCC_FLAG_REFINE_NO_PROGRESS = 1, 2
 
 EXPORTED = ["lcc_create", "lcc_destroy", "lcc_default_options", "lcc_workspace_bytes", "lcc_cluster",
             "lcc_cluster_ex", "lcc_cluster_batch", "lcc_objective", "lcc_server_create", "lcc_submit", "lcc_poll",
-            "lcc_server_destroy", "lcc_profile_enable", "lcc_profile_read", "lcc_status_string", "lcc_last_error"]
+            "lcc_server_destroy", "lcc_profile_enable", "lcc_profile_read", "lcc_status_string", "lcc_last_error",
+            "lcc_default_tuning", "lcc_set_tuning", "lcc_get_tuning", "lcc_autotune"]
 
 # kernel families of lcc_profile_enable (bit = index) and the kernel each one times
 PROFILE_FAMILIES = ["enum_b0", "enum_b1", "enum_b2", "enum_b3", "enum_b4", "enum_b5", "enum_b6", "enum_b7",
@@ -60,6 +61,10 @@ class lcc_options(ctypes.Structure):
 
 
 LCC_SYM_AFTERBURNER, LCC_SYM_NONE, LCC_SYM_MLH = 0, 1, 2
+
+
+class lcc_tuning(ctypes.Structure):
+    _fields_ = [("bucket_max", ctypes.c_int64 * 7), ("grid_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lcc_kernel_stat(ctypes.Structure):
@@ -123,6 +128,15 @@ def load():
     lib.lcc_profile_enable.argtypes = [v, u64]
     lib.lcc_profile_read.restype = st
     lib.lcc_profile_read.argtypes = [v, P(lcc_kernel_stat), ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32]
+    lib.lcc_default_tuning.restype = None
+    lib.lcc_default_tuning.argtypes = [P(lcc_tuning)]
+    lib.lcc_set_tuning.restype = st
+    lib.lcc_set_tuning.argtypes = [v, P(lcc_tuning)]
+    lib.lcc_get_tuning.restype = st
+    lib.lcc_get_tuning.argtypes = [v, P(lcc_tuning)]
+    lib.lcc_autotune.restype = st
+    lib.lcc_autotune.argtypes = [v, P(lcc_graph), P(lcc_lambda), P(ctypes.c_int), i64, P(lcc_options), v,
+                                 ctypes.c_int32, P(lcc_tuning), P(ctypes.c_double)]
     lib.lcc_status_string.restype = ctypes.c_char_p
     lib.lcc_status_string.argtypes = [ctypes.c_int]
     lib.lcc_last_error.restype = ctypes.c_char_p
@@ -159,6 +173,22 @@ def lcc_default_options(**kw) -> lcc_options:
         else:
             setattr(o, k, val)
     return o
+
+
+def lcc_default_tuning(bucket_max=None, grid_cap=None) -> lcc_tuning:
+    """The default launch tuning, with the given fields replaced (bucket_max: 7 bounds)."""
+    t = lcc_tuning()
+    load().lcc_default_tuning(ctypes.byref(t))
+    if bucket_max is not None:
+        for k, b in enumerate(bucket_max):
+            t.bucket_max[k] = int(b)
+    if grid_cap is not None:
+        t.grid_cap = int(grid_cap)
+    return t
+
+
+def tuning_dict(t: lcc_tuning) -> dict:
+    return {"bucket_max": [int(x) for x in t.bucket_max], "grid_cap": int(t.grid_cap)}
 
 
 def lcc_workspace_bytes(n: int, nnz: int, variant: int = LCC_PLOUVAIN) -> int:
@@ -318,6 +348,29 @@ class Context:
         st = _stream_handle(stream, graphs[0] if graphs else None)
         _check(lib.lcc_cluster_batch(self.handle, G, L, V, k, ctypes.byref(o), st, P, R))
         return [lab[:g.n] for lab, g in zip(labels_out, graphs)], [_result(R[i]) for i in range(k)]
+
+    def set_tuning(self, t: lcc_tuning):
+        _check(load().lcc_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_tuning(self) -> lcc_tuning:
+        t = lcc_tuning()
+        _check(load().lcc_get_tuning(self.handle, ctypes.byref(t)))
+        return t
+
+    def autotune(self, graphs, lams, variants, opts=None, stream=None, trials: int = 1):
+        """Run the library's autotuner on these graphs; the chosen tuning stays on the context.
+        Returns (tuning, ms per run)."""
+        lib = load()
+        k = len(graphs)
+        G = (lcc_graph * k)(*graphs)
+        L = (lcc_lambda * k)(*[lam_of(x) for x in lams])
+        V = (ctypes.c_int * k)(*variants)
+        o = opts if opts is not None else lcc_default_options()
+        best = lcc_tuning()
+        ms = ctypes.c_double(0.0)
+        _check(lib.lcc_autotune(self.handle, G, L, V, k, ctypes.byref(o), _stream_handle(stream, graphs[0]),
+                                int(trials), ctypes.byref(best), ctypes.byref(ms)))
+        return best, ms.value
 
     def profile_enable(self, families):
         """Time the named kernel families (see PROFILE_FAMILIES) in subsequent calls; [] disables."""

@@ -30,6 +30,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(lcc.lcc_result) == 56
     assert ctypes.sizeof(lcc.lcc_options) == 4 + 4 + 3 * 32 + 8 + 8 + 4 + 4 + 8 + 4 + 4
     assert ctypes.sizeof(lcc.lcc_kernel_stat) == 32 + 8 + 8 + 8
+    assert ctypes.sizeof(lcc.lcc_tuning) == 7 * 8 + 4 + 4
 
 
 def test_host_only_entry_points():
@@ -39,3 +40,6 @@ def test_host_only_entry_points():
     assert (o.phi_num[0], o.phi_den[0], o.phi_until[0], o.phi_num[1], o.phi_den[1], o.phi_until[1]) == (3, 4, 4, 1, 4, 6)
     assert lcc.lcc_workspace_bytes(1000, 10000) > 0
     assert lcc.lcc_status_string(-2) == "graph not symmetric"
+    t = lcc.lcc_default_tuning()
+    assert lcc.tuning_dict(t) == {"bucket_max": [4, 8, 16, 32, 128, 1024, 4096], "grid_cap": 2048}
+    assert lcc.tuning_dict(lcc.lcc_default_tuning(grid_cap=512))["grid_cap"] == 512
