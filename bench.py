@@ -214,6 +214,16 @@ def bench_knn_batch(args):
     lam = [(1, 1, True)] * len(graphs)
     var = [L.LCC_PLOUVAIN] * len(graphs)
     outs = [torch.empty(gr.n, dtype=torch.int32, device=dev) for gr in graphs]
+    # launch tuning from the autotuner on every 16th graph (one fused batch per candidate); both the plain
+    # and the fused runs below use it
+    tuning, tune_s = None, 0.0
+    if args.autotune != "off":
+        ta = time.perf_counter()
+        sample = graphs[::16]
+        best, _ = ctx.autotune(sample, lam[:len(sample)], var[:len(sample)], opts=opts, trials=1)
+        tune_s = time.perf_counter() - ta
+        tuning = L.tuning_dict(best)
+        print(f"# autotuned on {len(sample)} graphs in {tune_s:.1f} s: {tuning}", file=sys.stderr, flush=True)
     # plain: one call per graph (warm the workspace on the largest graph first)
     big = max(range(len(graphs)), key=lambda i: graphs[i].nnz)
     ctx.cluster(graphs[big], (1, 1, True), L.LCC_PLOUVAIN, opts, labels_out=outs[big])
@@ -249,7 +259,8 @@ def bench_knn_batch(args):
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"{len(graphs)} kNN graphs (k=15, 50-D Gaussian mixtures with 5-40 components, "
                                f"n log-uniform in [500, 50000]), pLouvain+ modularity, one fused batch call",
-                   "graphs": len(graphs), "vertices": nv, "nnz": nnz, "generation_s": gen_s},
+                   "graphs": len(graphs), "vertices": nv, "nnz": nnz, "generation_s": gen_s,
+                   "tuning": tuning, "autotune_s": tune_s},
         "batched": {"wall_s": fused_wall, "p50_latency_s": fused_wall, "p99_latency_s": fused_wall,
                     "edges_per_s": nnz / fused_wall, "walls_s": walls},
         "plain": {"wall_s": plain_wall, "p50_latency_s": pct(done, 50), "p99_latency_s": pct(done, 99),
@@ -412,6 +423,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--family", default="auto", help="kernel family timed live for the roofline")
     ap.add_argument("--knn-count", type=int, default=4096, help="graphs of the kNN batch workload")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="run the library's autotuner before timing (auto: on for the kNN batch, off for single "
+                         "graphs, whose committed counter profiles are taken with the default tuning)")
     ap.add_argument("--serve-count", type=int, default=240, help="measured requests of the served workload")
     ap.add_argument("--serve-warm", type=int, default=24, help="warm-up requests of the served workload")
     ap.add_argument("--trace-summary", metavar="DIR",
@@ -466,6 +480,11 @@ def main():
     ctx = L.Context(0, allocator="hip" if g.nnz > (1 << 30) else "torch")
     opts = L.lcc_default_options()
     stream = torch.cuda.current_stream()
+    tuning = None
+    if args.autotune == "on":
+        best, _ = ctx.autotune([graph], [lam], [variant], opts=opts, stream=stream, trials=2)
+        tuning = L.tuning_dict(best)
+        print(f"# autotuned: {tuning}", file=sys.stderr, flush=True)
 
     res = None
     for k in range(args.warmup):
@@ -529,7 +548,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "clusters": res.num_clusters if res else None,
                    "modularity": res.modularity if res else None, "levels": res.levels if res else None,
-                   "flags": res.flags if res else None, "objective_consistent": objective_consistent},
+                   "flags": res.flags if res else None, "objective_consistent": objective_consistent,
+                   "tuning": tuning},
         "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.cpu_scale),
     }
