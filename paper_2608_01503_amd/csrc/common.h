@@ -115,6 +115,7 @@ struct DevGraph {
 struct Buckets {
   const int32_t* list = nullptr;
   int32_t grid_cap = 2048;  // workgroups of the persistent per-vertex launches (a result-neutral tuning)
+  int64_t hub_deg = 4096;   // rows longer than this are in the hub bucket (its lower bound, exclusive)
   int64_t count[NBUCKET] = {};
   int64_t off[NBUCKET + 1] = {};
   // hub (last bucket) vertices are processed in fixed-size edge chunks: chunk range of hub k is

@@ -407,6 +407,7 @@ struct Run {
     b.hub_chunk_off = hub_off;
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
     b.grid_cap = ctx->tune.grid_cap;
+    b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     if (!into) L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
     if (b.count[NBUCKET - 1]) launch_hub_chunks(list + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, hub_off, w.scan_temp, st);
   }
@@ -840,6 +841,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     b.hub_chunk_off = w.hub_off0;
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
     b.grid_cap = ctx->tune.grid_cap;
+    b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
@@ -1217,6 +1219,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     b.hub_chunk_off = w.hub_off0;
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
     b.grid_cap = ctx->tune.grid_cap;
+    b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }

@@ -51,13 +51,15 @@ __device__ __forceinline__ int pattern(int32_t cv, int32_t dv, int32_t cu, int32
 }
 
 // q-free adjacent part: adj[i] = sum over earlier adjacent movers u of w(u, v_i) s(u, v_i); one wavefront
-// per mover (grid-stride), lanes over the row
+// per mover (grid-stride), lanes over the row.  Rows of the hub bucket are left to k_gain_adj_hub.
 __global__ __launch_bounds__(BLOCK) void k_gain_adj(const int32_t* list, int64_t k, DevGraph g, const VState* vs,
-                                                    const uint8_t* mv, const int32_t* pos, int64_t* adj) {
+                                                    const uint8_t* mv, const int32_t* pos, int64_t hub_deg,
+                                                    int64_t* adj) {
   const int lane = threadIdx.x & (WAVE - 1);
   for (int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE; i < k;
        i += (int64_t)gridDim.x * (BLOCK / WAVE)) {
     const int32_t v = list[i];
+    if (g.off[v + 1] - g.off[v] > hub_deg) continue;  // uniform over the wavefront
     const VState me = vs[v];
     int64_t acc = 0;
     for (int64_t j = g.off[v] + lane; j < g.off[v + 1]; j += WAVE) {
@@ -72,22 +74,55 @@ __global__ __launch_bounds__(BLOCK) void k_gain_adj(const int32_t* list, int64_t
   }
 }
 
+__device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
+  int64_t lo = 0, hi = n7;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (chunk_off[mid] <= blk) lo = mid; else hi = mid;
+  }
+  return (int)lo;
+}
+
+// hub rows: one workgroup per edge chunk of a hub that is a mover, added into adj (zeroed beforehand)
+__global__ __launch_bounds__(BLOCK) void k_gain_adj_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
+                                                        DevGraph g, const VState* vs, const uint8_t* mv,
+                                                        const int32_t* pos, int64_t* adj) {
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  if (!mv[v]) return;
+  const int64_t i = pos[v];
+  const VState me = vs[v];
+  const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK_EDGES;
+  const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK_EDGES);
+  int64_t acc = 0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += BLOCK) {
+    const int32_t u = g.idx[j];
+    if (!mv[u] || pos[u] >= i) continue;
+    const VState o = vs[u];
+    acc += (int64_t)pattern(me.c, me.d, o.c, o.d) * g.w[j];
+  }
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && acc) atomicAdd((unsigned long long*)&adj[i], (unsigned long long)acc);
+}
+
 // Records of mover j (4 j .. 4 j + 3): event "leaves C" (-w), event "enters D" (+w), query at D, query at C.
-// key = cluster << 33 | j << 1 | (event ? 1 : 0); unused records (D = new singleton) get the largest key.
+// key = cluster << cs | j << 1 | (event ? 1 : 0) with cs = bits(k) + 1, so real keys use bits(n) + cs bits and
+// the sort runs over one bit more; unused records (D = new singleton) get the largest key.
 constexpr uint64_t NO_KEY = ~0ull;
 
-__global__ void k_alt_records(const int32_t* list, int64_t k, const VState* vs, const int64_t* vw, uint64_t* key,
-                              uint32_t* val, int64_t* evw) {
+__global__ void k_alt_records(const int32_t* list, int64_t k, int cs, const VState* vs, const int64_t* vw,
+                              uint64_t* key, uint32_t* val, int64_t* evw) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < k; j += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = list[j];
     const VState s = vs[v];
     const int64_t w = vw[v];
     const uint64_t jj = (uint64_t)j << 1;
     const bool fresh = s.d == D_EMPTY;
-    key[4 * j + 0] = ((uint64_t)(uint32_t)s.c << 33) | jj | 1;
-    key[4 * j + 1] = fresh ? NO_KEY : (((uint64_t)(uint32_t)s.d << 33) | jj | 1);
-    key[4 * j + 2] = fresh ? NO_KEY : (((uint64_t)(uint32_t)s.d << 33) | jj);
-    key[4 * j + 3] = ((uint64_t)(uint32_t)s.c << 33) | jj;
+    key[4 * j + 0] = ((uint64_t)(uint32_t)s.c << cs) | jj | 1;
+    key[4 * j + 1] = fresh ? NO_KEY : (((uint64_t)(uint32_t)s.d << cs) | jj | 1);
+    key[4 * j + 2] = fresh ? NO_KEY : (((uint64_t)(uint32_t)s.d << cs) | jj);
+    key[4 * j + 3] = ((uint64_t)(uint32_t)s.c << cs) | jj;
     for (int t = 0; t < 4; ++t) val[4 * j + t] = (uint32_t)(4 * j + t);
     evw[4 * j + 0] = -w;
     evw[4 * j + 1] = fresh ? 0 : w;
@@ -97,11 +132,11 @@ __global__ void k_alt_records(const int32_t* list, int64_t k, const VState* vs, 
 }
 
 // sorted position p: x = the event weight (0 for queries), head = first record of a cluster
-__global__ void k_alt_gather(const uint64_t* key, const uint32_t* val, const int64_t* evw, int64_t m, int64_t* x,
-                             uint8_t* head) {
+__global__ void k_alt_gather(const uint64_t* key, const uint32_t* val, const int64_t* evw, int64_t m, int cs,
+                             int64_t* x, uint8_t* head) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
     x[p] = (key[p] & 1) ? evw[val[p]] : 0;
-    head[p] = p == 0 || (key[p] >> 33) != (key[p - 1] >> 33);
+    head[p] = p == 0 || (key[p] >> cs) != (key[p - 1] >> cs);
   }
 }
 
@@ -127,42 +162,29 @@ __global__ void k_gain(const int32_t* list, int64_t k, const VState* vs, const i
   }
 }
 
-// shortest prefix with the largest positive running sum (one workgroup)
-__global__ __launch_bounds__(BLOCK) void k_best_prefix(const int64_t* gain, int64_t k, Ctrl* ctrl) {
-  __shared__ int64_t wsum[BLOCK / WAVE];
-  __shared__ int64_t s_carry, s_best, s_bestk;
-  if (threadIdx.x == 0) { s_carry = 0; s_best = 0; s_bestk = 0; }
-  __syncthreads();
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  for (int64_t b0 = 0; b0 < k; b0 += BLOCK) {
-    int64_t i = b0 + threadIdx.x;
-    int64_t x = i < k ? gain[i] : 0;
-    int64_t inc = x;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      int64_t y = __shfl_up(inc, o, WAVE);
-      if (lane >= o) inc += y;
-    }
-    if (lane == WAVE - 1) wsum[wv] = inc;
-    __syncthreads();
-    int64_t before = s_carry;
-    for (int w = 0; w < wv; ++w) before += wsum[w];
-    int64_t run = before + inc;  // running sum through item i
-    __syncthreads();
-    // serial max over this chunk in item order (ties keep the earliest)
-    __shared__ int64_t runs[BLOCK];
-    runs[threadIdx.x] = run;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int t = 0; t < BLOCK && b0 + t < k; ++t)
-        if (runs[t] > s_best) { s_best = runs[t]; s_bestk = b0 + t + 1; }
-      s_carry = runs[min((int64_t)BLOCK, k - b0) - 1];
-    }
-    __syncthreads();
+// Shortest prefix with the largest strictly positive running sum.  S is the exclusive scan of the gains
+// (S[i + 1] = running sum through mover i); one workgroup reduces (largest sum, then smallest index).
+constexpr int BP_BLOCK = 1024;
+__global__ __launch_bounds__(BP_BLOCK) void k_best_prefix(const int64_t* S, int64_t k, Ctrl* ctrl) {
+  __shared__ int64_t sv[BP_BLOCK / WAVE], si[BP_BLOCK / WAVE];
+  int64_t bv = 0, bi = INT64_MAX;  // no prefix yet; a prefix must beat 0
+  for (int64_t i = threadIdx.x; i < k; i += BP_BLOCK) {
+    const int64_t r = S[i + 1];
+    if (r > bv || (r == bv && r > 0 && i < bi)) { bv = r; bi = i; }
   }
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int64_t ov = __shfl_xor(bv, o, WAVE), oi = __shfl_xor(bi, o, WAVE);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  if (lane == 0) { sv[wv] = bv; si[wv] = bi; }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    ctrl->lmalt_best_k = s_bestk;
-    ctrl->lmalt_best = s_best;
+    for (int w = 1; w < BP_BLOCK / WAVE; ++w)
+      if (sv[w] > bv || (sv[w] == bv && si[w] < bi)) { bv = sv[w]; bi = si[w]; }
+    ctrl->lmalt_best_k = bv > 0 ? bi + 1 : 0;
+    ctrl->lmalt_best = bv > 0 ? bv : 0;
   }
 }
 
@@ -216,21 +238,33 @@ bool lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs
   auto* adj = (int64_t*)take((size_t)k * 8);
   void* stemp = take(scan_temp_bytes(m + 1));
   void* rtemp = take(radix_temp_bytes(m));
+  auto* S2 = (int64_t*)take((size_t)(k + 1) * 8);
   const unsigned gw = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(k, BLOCK / WAVE), 2048));
-  k_gain_adj<<<gw, BLOCK, 0, st>>>(list, k, g, bufs.vs, bufs.keep, bufs.scan_a, adj);
-  k_alt_records<<<grid_for(k), BLOCK, 0, st>>>(list, k, bufs.vs, g.vw, key0, val0, evw);
-  int shifts[8];
-  for (int t = 0; t < 8; ++t) shifts[t] = 8 * t;
-  const int which = radix_sort_pairs(key0, val0, key1, val1, m, shifts, 8, rtemp, st);
+  const int32_t* hubs = b.list + b.off[NBUCKET - 1];
+  const int64_t n7 = b.count[NBUCKET - 1];
+  if (n7) fill_i64(adj, 0, k, st);
+  k_gain_adj<<<gw, BLOCK, 0, st>>>(list, k, g, bufs.vs, bufs.keep, bufs.scan_a, b.hub_deg, adj);
+  if (n7) k_gain_adj_hub<<<(unsigned)b.hub_chunks, BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, bufs.vs, bufs.keep,
+                                                                bufs.scan_a, adj);
+  int kb = 1, nb = 1;
+  while (((int64_t)1 << kb) < k) ++kb;
+  while (((int64_t)1 << nb) < n) ++nb;
+  const int cs = kb + 1;
+  // real keys are below 2^(cs + nb); one more bit keeps NO_KEY (all ones in the sorted bits) strictly last
+  int shifts[8], np = 0;
+  for (int t = 0; t < cs + nb + 1 && np < 8; t += 8) shifts[np++] = t;
+  k_alt_records<<<grid_for(k), BLOCK, 0, st>>>(list, k, cs, bufs.vs, g.vw, key0, val0, evw);
+  const int which = radix_sort_pairs(key0, val0, key1, val1, m, shifts, np, rtemp, st);
   const uint64_t* ks = which ? key1 : key0;
   const uint32_t* vs_ = which ? val1 : val0;
-  k_alt_gather<<<grid_for(m), BLOCK, 0, st>>>(ks, vs_, evw, m, x, head);
+  k_alt_gather<<<grid_for(m), BLOCK, 0, st>>>(ks, vs_, evw, m, cs, x, head);
   scan_i64_i64(x, S, m, stemp, st);
   scan_u8_i32(head, H, m, stemp, nullptr, st);
   k_alt_base<<<grid_for(m), BLOCK, 0, st>>>(head, H, S, m, base);
   k_alt_query<<<grid_for(m), BLOCK, 0, st>>>(ks, vs_, head, H, S, base, m, F);
   k_gain<<<grid_for(k), BLOCK, 0, st>>>(list, k, bufs.vs, g.vw, sc, adj, F, gain);
-  k_best_prefix<<<1, BLOCK, 0, st>>>(gain, k, ctrl);
+  scan_i64_i64(gain, S2, k, stemp, st);
+  k_best_prefix<<<1, BP_BLOCK, 0, st>>>(S2, k, ctrl);
   k_commit_prefix<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, ctrl);
   launch_apply_and_empty(g, bufs, slot, st);
   return true;
