@@ -438,10 +438,27 @@ struct RefineBuffers {
   uint8_t* flip; uint8_t* has_child; int32_t* tsz; uint8_t* member; int32_t* mpos;
   uint64_t* k0; uint32_t* v0; uint64_t* k1; uint32_t* v1;
   int64_t* pw; int64_t* pc; int64_t* tmp64a; int64_t* tmp64b; int32_t* pos_of; int32_t* fail;
-  void* scan_temp; void* radix_temp;
+  void* scan_temp;
 };
+// Throws the library's device error (LCC_ERR_DEVICE with the HIP message) when e is not hipSuccess.
+void device_check(hipError_t e, const char* what);
+
+// segsort.hip: grouped placement and segmented sorting.
+// out[grp[i]] += cnt[i] over items with grp[i] >= 0.
+void launch_group_sum(const int32_t* grp, const int32_t* cnt, int64_t n, int64_t* out, hipStream_t st);
+// pos[i] = the start of cnt[i] (1 when cnt is null) positions of item i inside segment grp[i], for items with
+// grp[i] >= 0 (and mask[i] set when mask is given); segment s starts at start[s]; cursor: nseg scratch.
+void launch_group_place(const int32_t* grp, const int32_t* cnt, const uint8_t* mask, int64_t n, const int64_t* start,
+                        int64_t nseg, unsigned long long* cursor, int64_t* pos, hipStream_t st);
+// (kout, vout) = (kin, vin) with the m items of every segment [off[s], off[s+1]) sorted by key.  Every key of
+// segment s is (s << seg_shift) | low with low < 2^low_bits (low_bits <= seg_shift), so the whole output is
+// sorted.  take() hands out stream-ordered scratch.
+void segsort_pairs(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t m,
+                   const int64_t* off, int64_t nseg, int low_bits, int seg_shift, void* scan_temp,
+                   const std::function<void*(size_t)>& take, hipStream_t st);
+
 void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t* B, uint64_t seed, uint64_t t,
-            int32_t* R, RefineBuffers& rb, Ctrl* ctrl, hipStream_t st);
+            int32_t* R, RefineBuffers& rb, Ctrl* ctrl, const std::function<void*(size_t)>& take, hipStream_t st);
 
 // lmalt.hip: LocalMoveAlt (Sec. V-A)
 // Returns false (nothing done) when the mover count is 2^30 or more.

@@ -76,9 +76,9 @@ struct WS {
   uint8_t *inU, *flip, *has_child, *member;
   int32_t *H, *par, *root, *tsz, *pos_of, *fail, *mpos, *alt_list;
   int32_t* gid0;  // union of graphs: graph of every level-0 vertex
+  int64_t *seg0, *seg1;  // contraction: entries per coarse row (then the rows' cursors) and the rows' starts
   Tagged tg;      // free-id marks and single-pass scan state (zeroed when the workspace is allocated)
   void* scan_temp;
-  void* radix_temp;
 };
 
 size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
@@ -116,13 +116,13 @@ size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
   w.pos_of = c.take<int32_t>(n); w.fail = c.take<int32_t>(n); w.mpos = c.take<int32_t>(n + 1);
   w.alt_list = c.take<int32_t>(n);
   w.gid0 = c.take<int32_t>(n);
+  w.seg0 = c.take<int64_t>(n + 1); w.seg1 = c.take<int64_t>(n + 1);
   w.tg = Tagged{};
   w.tg.held = c.take<uint32_t>(n); w.tg.held_cap = n;
   w.tg.status_cap = (M + 1) / LB_TILE + 2;
   w.tg.status = c.take<unsigned long long>(w.tg.status_cap);
   w.tg.ticket = c.take<uint32_t>(1);
   w.scan_temp = c.take<char>((int64_t)scan_temp_bytes(M + 1));
-  w.radix_temp = c.take<char>((int64_t)radix_temp_bytes(M));
   return c.off;
 }
 
@@ -248,6 +248,7 @@ void prof_end(int family, double bytes, hipStream_t st) {
   c->prof_recs.push_back({family, c->prof_open[family], e, bytes});
   c->prof_open[family] = nullptr;
 }
+void device_check(hipError_t e, const char* what) { hip_check(e, what); }
 }  // namespace lcc
 
 namespace {
@@ -521,26 +522,36 @@ struct Run {
     int64_t* cvw = level_take<int64_t>(nc);
     fill_i64(cvw, 0, nc, st);
     launch_coarse_vw(L.map, L.g.vw, n, cvw, st);
+    // cross entries per fine vertex and per coarse row; row x's entries take the range [xoff[x], xoff[x+1])
+    // and every fine vertex claims its share of its row's range
     launch_cross_count(L.g, L.b, L.map, w.cnt, st);
-    scan_i32_i64(w.cnt, w.pos, n, w.scan_temp, st);
+    int64_t* ecnt = w.seg0;
+    int64_t* xoff = w.seg1;
+    fill_i64(ecnt, 0, nc, st);
+    launch_group_sum(L.map, w.cnt, n, ecnt, st);
+    scan_i64_i64(ecnt, xoff, nc, w.scan_temp, st);
     int64_t E = 0;
-    hip_check(hipMemcpyAsync(&E, w.pos + n, sizeof(int64_t), hipMemcpyDeviceToHost, st), "entries");
+    hip_check(hipMemcpyAsync(&E, xoff + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st), "entries");
     sync("entries");
     int64_t nnzc = 0;
     int32_t* cidx;
     int32_t* cw;
     if (E > 0) {
+      launch_group_place(L.map, w.cnt, nullptr, n, xoff, nc, (unsigned long long*)ecnt, w.pos, st);
       launch_cross_emit(L.g, L.b, L.map, w.pos, w.k0, w.v0, st);
+      // each row sorted by neighbour: the whole array is then in (x, y) order
       int ybits = 1;
       while (((int64_t)1 << ybits) < nc) ++ybits;
-      int shifts[8], np = 0;
-      for (int s = 0; s < ybits; s += 8) shifts[np++] = s;
-      for (int s = 0; s < ybits; s += 8) shifts[np++] = 32 + s;
-      int which = radix_sort_pairs(w.k0, w.v0, w.k1, w.v1, E, shifts, np, w.radix_temp, st);
-      const uint64_t* ks = which ? w.k1 : w.k0;
-      const uint32_t* vs = which ? w.v1 : w.v0;
-      int64_t* pref = (int64_t*)(which ? w.k0 : w.k1);  // the other key buffer is free
-      int32_t* hstart = (int32_t*)(which ? w.v0 : w.v1);
+      {
+        const auto mk = ctx->pool_mark();
+        segsort_pairs(w.k0, w.v0, w.k1, w.v1, E, xoff, nc, ybits, 32, w.scan_temp,
+                      [&](size_t by) { return ctx->pool_take(by); }, st);
+        ctx->pool_release(mk);
+      }
+      const uint64_t* ks = w.k1;
+      const uint32_t* vs = w.v1;
+      int64_t* pref = (int64_t*)w.k0;  // the input key buffer is free
+      int32_t* hstart = (int32_t*)w.v0;
       launch_heads(ks, E, w.head, st);
       scan_u8_i32(w.head, w.uid, E, w.scan_temp, nullptr, st);
       int32_t nz = 0;
@@ -662,7 +673,7 @@ struct Run {
     r.flip = w.flip; r.has_child = w.has_child; r.tsz = w.tsz; r.member = w.member; r.mpos = w.mpos;
     r.k0 = w.k0; r.v0 = w.v0; r.k1 = w.k1; r.v1 = w.v1;
     r.pw = w.pw; r.pc = w.pc; r.tmp64a = w.t64a; r.tmp64b = w.t64b; r.pos_of = w.pos_of; r.fail = w.fail;
-    r.scan_temp = w.scan_temp; r.radix_temp = w.radix_temp;
+    r.scan_temp = w.scan_temp;
     return r;
   }
 
@@ -704,7 +715,12 @@ struct Run {
       // refinement R of B = C_l; compaction of B for the downsampled clustering
       int32_t* R = w.in_labels;
       RefineBuffers rb = rbufs();
-      refine(L.g, L.b, sc, L.C, o.seed, refine_calls, R, rb, w.ctrl, st);
+      {
+        const auto mk = ctx->pool_mark();  // the refinement's sort scratch is released right after
+        refine(L.g, L.b, sc, L.C, o.seed, refine_calls, R, rb, w.ctrl, [&](size_t by) { return ctx->pool_take(by); },
+               st);
+        ctx->pool_release(mk);
+      }
       int64_t nR = count_labels(R, n);
       read_ctrl("refine");
       if (ctx->h_ctrl->err_bits & ERRB_INTERNAL) fail(LCC_ERR_DEVICE, "refinement produced a parent cycle");

@@ -306,11 +306,17 @@ __global__ void k_members(int64_t n, const int32_t* root, const int32_t* tsz, ui
     member[v] = tsz[root[v]] > 1;
 }
 
-__global__ void k_tree_keys(int64_t n, const uint8_t* member, const int32_t* mpos, const int32_t* root,
+// positions of the trees of two or more members: the tree of root r gets tsz[r] of them
+__global__ void k_tree_sizes(int64_t n, const int32_t* root, const int32_t* tsz, int32_t* gs) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    gs[v] = (root[v] == (int32_t)v && tsz[v] >= 2) ? tsz[v] : 0;
+}
+
+__global__ void k_tree_keys(int64_t n, const uint8_t* member, const int64_t* tpos, const int32_t* root,
                             uint32_t fseed, const uint8_t* flip, uint64_t* keys, uint32_t* vals) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     if (!member[v]) continue;
-    int32_t p = mpos[v];
+    const int64_t p = tpos[v];
     keys[p] = ((uint64_t)(uint32_t)root[v] << 33) | fkey((int32_t)v, fseed, flip);
     vals[p] = (uint32_t)v;
   }
@@ -397,7 +403,7 @@ __global__ void k_set_i64(int64_t* p, int64_t v) {
 }  // namespace
 
 void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t* B, uint64_t seed, uint64_t t,
-            int32_t* R, RefineBuffers& rb, Ctrl* ctrl, hipStream_t st) {
+            int32_t* R, RefineBuffers& rb, Ctrl* ctrl, const std::function<void*(size_t)>& take, hipStream_t st) {
   const int64_t n = g.n;
   const int32_t* L = b.list;
   const uint64_t s_t = seed_stream(seed, t);
@@ -438,23 +444,24 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
   fill_i32(rb.tsz, 0, n, st);
   k_roots<<<grid_for(n), BLOCK, 0, st>>>(n, rb.par, rb.root, rb.tsz, ctrl);
   k_members<<<grid_for(n), BLOCK, 0, st>>>(n, rb.root, rb.tsz, rb.member);
-  scan_u8_i32(rb.member, rb.mpos, n, rb.scan_temp, nullptr, st);
+  // members grouped by tree (each tree's range from a scan of the tree sizes), then every tree sorted by f;
+  // pw, tmp64a and tmp64b serve as scratch here and get their own contents below
+  int64_t* toff = rb.pw;
+  auto* cursor = (unsigned long long*)rb.tmp64a;
+  int64_t* tpos = rb.tmp64b;
+  k_tree_sizes<<<grid_for(n), BLOCK, 0, st>>>(n, rb.root, rb.tsz, rb.mpos);
+  scan_i32_i64(rb.mpos, toff, n, rb.scan_temp, st);
   // the member count is needed on the host to size the sort
-  int32_t m32 = 0;
-  hipMemcpyAsync(&m32, rb.mpos + n, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-  hipStreamSynchronize(st);
-  const int64_t m = m32;
+  int64_t m = 0;
+  device_check(hipMemcpyAsync(&m, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st), "tree members");
+  device_check(hipStreamSynchronize(st), "tree members");
   k_set_i64<<<1, 1, 0, st>>>(&ctrl->refine_m, m);
   fill_i32(rb.fail, INT32_MAX, n, st);
   if (m > 0) {
-    k_tree_keys<<<grid_for(n), BLOCK, 0, st>>>(n, rb.member, rb.mpos, rb.root, fseed, rb.flip, rb.k0, rb.v0);
-    int bits = 33;
-    while (((int64_t)1 << (bits - 33)) < n) ++bits;
-    int shifts[8];
-    int np = 0;
-    for (int s = 0; s < bits && np < 8; s += 8) shifts[np++] = s;
-    int which = radix_sort_pairs(rb.k0, rb.v0, rb.k1, rb.v1, m, shifts, np, rb.radix_temp, st);
-    const uint32_t* sv = which ? rb.v1 : rb.v0;
+    launch_group_place(rb.root, nullptr, rb.member, n, toff, n, cursor, tpos, st);
+    k_tree_keys<<<grid_for(n), BLOCK, 0, st>>>(n, rb.member, tpos, rb.root, fseed, rb.flip, rb.k0, rb.v0);
+    segsort_pairs(rb.k0, rb.v0, rb.k1, rb.v1, m, toff, n, 33, 33, rb.scan_temp, take, st);
+    const uint32_t* sv = rb.v1;
     // a(v, X_{<v}) for tree members
     fill_i64(rb.aX, 0, n, st);
     if (b.count[0]) k_aX_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, rb.member, rb.root, fseed, rb.flip, rb.aX);

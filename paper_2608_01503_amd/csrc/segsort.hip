@@ -1,0 +1,296 @@
+// Grouped placement and segmented sorting, for the two sorts of the hot path whose keys are (segment, key
+// inside the segment): the contraction's (coarse row x, neighbour y) entries (Alg. 4) and pLeidenR's tree
+// members by (root, ordering f) (Alg. 6).
+//
+// Instead of an LSD radix sort over every key bit, the items are first placed into their segment's range
+// (sizes are known up front, so the range of segment s starts at an exclusive scan of the sizes; items of one
+// tile claim space with one global atomic per distinct segment), and then each segment is sorted on its own,
+// by size class: up to 16 or 64 items by ranking in a group of 16 or 64 lanes (shuffles, no LDS), up to 2048
+// by a bitonic network in LDS (one workgroup per segment), and the longer segments together by an LSD radix
+// sort over (segment rank, key inside the segment) whose output goes back into each segment's range.
+// Equal keys may end in any order; the callers either have unique keys or sum equal keys' values.
+#include <algorithm>
+#include <functional>
+
+#include "common.h"
+
+namespace lcc {
+
+namespace {
+
+constexpr int PL_TILE = 2048;            // items per placement tile
+constexpr int PL_SLOTS = 2 * PL_TILE;    // LDS hash of the tile's segments
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = cdiv(n, BLOCK);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+inline unsigned tile_blocks(int64_t tiles, int64_t cap) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, cap));
+}
+
+// out[grp[i]] += cnt[i] for grp[i] >= 0
+__global__ __launch_bounds__(BLOCK) void k_group_sum(const int32_t* grp, const int32_t* cnt, int64_t n,
+                                                     int64_t* out) {
+  __shared__ int32_t ak[PL_SLOTS];
+  __shared__ unsigned long long av[PL_SLOTS];
+  LdsAgg<PL_SLOTS> agg{ak, av};
+  for (int64_t t0 = (int64_t)blockIdx.x * PL_TILE; t0 < n; t0 += (int64_t)gridDim.x * PL_TILE) {
+    agg.clear();
+    __syncthreads();
+    for (int k = threadIdx.x; k < PL_TILE; k += BLOCK) {
+      const int64_t i = t0 + k;
+      if (i >= n) break;
+      if (grp[i] >= 0 && cnt[i] > 0) agg.add(grp[i], cnt[i]);
+    }
+    __syncthreads();
+    agg.flush(out);
+    __syncthreads();
+  }
+}
+
+// Item i (grp[i] >= 0, mask[i] set when mask is given) receives pos[i], the start of cnt[i] positions (1 when
+// cnt is null) inside its segment; cursor[s] starts at segment s's first position and is advanced.
+__global__ __launch_bounds__(BLOCK) void k_group_place(const int32_t* grp, const int32_t* cnt, const uint8_t* mask,
+                                                       int64_t n, unsigned long long* cursor, int64_t* pos) {
+  __shared__ int32_t hk[PL_SLOTS];
+  __shared__ unsigned long long hs[PL_SLOTS];  // the tile's total per segment, then the base it claimed
+  constexpr int IPT = PL_TILE / BLOCK;
+  for (int64_t t0 = (int64_t)blockIdx.x * PL_TILE; t0 < n; t0 += (int64_t)gridDim.x * PL_TILE) {
+    for (int s = threadIdx.x; s < PL_SLOTS; s += BLOCK) { hk[s] = -1; hs[s] = 0; }
+    __syncthreads();
+    int slot[IPT];
+    unsigned long long in_tile[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const int64_t i = t0 + (int64_t)k * BLOCK + threadIdx.x;
+      slot[k] = -1;
+      in_tile[k] = 0;
+      if (i >= n || (mask && !mask[i])) continue;
+      const int32_t g = grp[i];
+      const unsigned long long c = cnt ? (unsigned long long)(cnt[i] > 0 ? cnt[i] : 0) : 1ull;
+      if (g < 0 || c == 0) continue;
+      uint32_t h = fmix32((uint32_t)g) & (PL_SLOTS - 1);
+      for (int probe = 0; probe < PL_SLOTS; ++probe) {
+        const int32_t prev = atomicCAS(&hk[h], -1, g);
+        if (prev == -1 || prev == g) break;
+        h = (h + 1) & (PL_SLOTS - 1);
+      }
+      slot[k] = (int)h;
+      in_tile[k] = atomicAdd(&hs[h], c);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < PL_SLOTS; s += BLOCK)
+      if (hk[s] >= 0) hs[s] = atomicAdd(&cursor[hk[s]], hs[s]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+      if (slot[k] >= 0) pos[t0 + (int64_t)k * BLOCK + threadIdx.x] = (int64_t)(hs[slot[k]] + in_tile[k]);
+    __syncthreads();
+  }
+}
+
+__global__ void k_copy_u64(const int64_t* src, int64_t n, unsigned long long* dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (unsigned long long)src[i];
+}
+
+// Segments by size class: 1 (1..16 items), 2 (17..64), 3 (65..SEG_MED), 4 (longer); empty ones need nothing.
+constexpr int SEG_MED = 2048;
+constexpr int NCLASS = 5;
+
+__device__ __forceinline__ int seg_class(int64_t sz) {
+  return sz <= 0 ? 0 : sz <= 16 ? 1 : sz <= 64 ? 2 : sz <= SEG_MED ? 3 : 4;
+}
+
+// lists[c][..] = the segments of class c (in any order); counts[c] = their number
+__global__ __launch_bounds__(BLOCK) void k_seg_classify(const int64_t* off, int64_t nseg, int32_t* lists,
+                                                        unsigned long long* counts) {
+  __shared__ unsigned int lc[NCLASS];
+  __shared__ unsigned long long base[NCLASS];
+  for (int64_t s0 = (int64_t)blockIdx.x * BLOCK; s0 < nseg; s0 += (int64_t)gridDim.x * BLOCK) {
+    if (threadIdx.x < NCLASS) lc[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t s = s0 + threadIdx.x;
+    int c = 0;
+    unsigned int r = 0;
+    if (s < nseg) {
+      c = seg_class(off[s + 1] - off[s]);
+      if (c) r = atomicAdd(&lc[c], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x > 0 && threadIdx.x < NCLASS && lc[threadIdx.x])
+      base[threadIdx.x] = atomicAdd(&counts[threadIdx.x], (unsigned long long)lc[threadIdx.x]);
+    __syncthreads();
+    if (c) lists[(int64_t)c * nseg + (int64_t)(base[c] + r)] = (int32_t)s;
+    __syncthreads();
+  }
+}
+
+// Segments of at most G items, one group of G lanes each: every item's rank in its segment is the number of
+// smaller keys (ties by position), found with G shuffles.
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_seg_rank(const int32_t* list, const unsigned long long* count,
+                                                    const int64_t* off, const uint64_t* kin, const uint32_t* vin,
+                                                    uint64_t* kout, uint32_t* vout) {
+  const int64_t cnt = (int64_t)*count;
+  const int gl = threadIdx.x % G;
+  for (int64_t q = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / G; q < cnt; q += (int64_t)gridDim.x * (BLOCK / G)) {
+    const int64_t s = list[q];
+    const int64_t b = off[s], sz = off[s + 1] - b;
+    const bool in = gl < sz;
+    const uint64_t key = in ? kin[b + gl] : ~0ull;
+    const uint32_t val = in ? vin[b + gl] : 0u;
+    int rank = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const uint64_t kk = __shfl(key, k, G);
+      rank += (kk < key) || (kk == key && k < gl);
+    }
+    if (in) {
+      kout[b + rank] = key;
+      vout[b + rank] = val;
+    }
+  }
+}
+
+// ascending bitonic sort of N (a power of two, <= SEG_MED) keys with their values, in LDS
+__device__ __forceinline__ void bitonic_lds(uint64_t* k, uint32_t* v, int N) {
+  for (int size = 2; size <= N; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < N / 2; i += BLOCK) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t a = k[lo], b = k[hi];
+        if ((a > b) == asc) {
+          k[lo] = b;
+          k[hi] = a;
+          const uint32_t t = v[lo];
+          v[lo] = v[hi];
+          v[hi] = t;
+        }
+      }
+    }
+  __syncthreads();
+}
+
+// Segments of 65..SEG_MED items, one workgroup each, bitonic in LDS.
+__global__ __launch_bounds__(BLOCK) void k_seg_bitonic(const int32_t* list, const unsigned long long* count,
+                                                       const int64_t* off, const uint64_t* kin, const uint32_t* vin,
+                                                       uint64_t* kout, uint32_t* vout) {
+  __shared__ uint64_t sk[SEG_MED];
+  __shared__ uint32_t sv[SEG_MED];
+  const int64_t cnt = (int64_t)*count;
+  for (int64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+    const int64_t s = list[q];
+    const int64_t b = off[s], sz = off[s + 1] - b;
+    int N = 1;
+    while (N < sz) N <<= 1;
+    for (int i = threadIdx.x; i < N; i += BLOCK) {
+      sk[i] = i < sz ? kin[b + i] : ~0ull;
+      sv[i] = i < sz ? vin[b + i] : 0u;
+    }
+    bitonic_lds(sk, sv, N);
+    for (int i = threadIdx.x; i < sz; i += BLOCK) {
+      kout[b + i] = sk[i];
+      vout[b + i] = sv[i];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_seg_long_sizes(const int32_t* list, int64_t nlong, const int64_t* off, int64_t* size) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nlong; r += (int64_t)gridDim.x * blockDim.x)
+    size[r] = off[list[r] + 1] - off[list[r]];
+}
+
+// long-segment item i: key (rank r << low_bits | key inside its segment), its value
+__global__ void k_seg_long_gather(const uint64_t* kin, const uint32_t* vin, const int64_t* off, const int32_t* list,
+                                  const int64_t* loff, int64_t nlong, int64_t mlong, int low_bits, uint64_t* ka,
+                                  uint32_t* va) {
+  const uint64_t low = (1ull << low_bits) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mlong; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nlong - 1;  // last r with loff[r] <= i
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (loff[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int64_t src = off[list[lo]] + (i - loff[lo]);
+    ka[i] = ((uint64_t)lo << low_bits) | (kin[src] & low);
+    va[i] = vin[src];
+  }
+}
+
+// sorted item i goes back into its segment's range with its key rebuilt (segment << seg_shift | low part)
+__global__ void k_seg_long_scatter(const uint64_t* ka, const uint32_t* va, const int64_t* off, const int32_t* list,
+                                   const int64_t* loff, int64_t mlong, int low_bits, int seg_shift, uint64_t* kout,
+                                   uint32_t* vout) {
+  const uint64_t low = (1ull << low_bits) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mlong; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = (int64_t)(ka[i] >> low_bits);
+    const int64_t seg = list[r];
+    const int64_t dst = off[seg] + (i - loff[r]);
+    kout[dst] = ((uint64_t)seg << seg_shift) | (ka[i] & low);
+    vout[dst] = va[i];
+  }
+}
+
+}  // namespace
+
+void launch_group_sum(const int32_t* grp, const int32_t* cnt, int64_t n, int64_t* out, hipStream_t st) {
+  k_group_sum<<<tile_blocks(cdiv(n, PL_TILE), 4096), BLOCK, 0, st>>>(grp, cnt, n, out);
+}
+
+void launch_group_place(const int32_t* grp, const int32_t* cnt, const uint8_t* mask, int64_t n, const int64_t* start,
+                        int64_t nseg, unsigned long long* cursor, int64_t* pos, hipStream_t st) {
+  k_copy_u64<<<grid_for(nseg), BLOCK, 0, st>>>(start, nseg, cursor);
+  k_group_place<<<tile_blocks(cdiv(n, PL_TILE), 4096), BLOCK, 0, st>>>(grp, cnt, mask, n, cursor, pos);
+}
+
+void segsort_pairs(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t m,
+                   const int64_t* off, int64_t nseg, int low_bits, int seg_shift, void* scan_temp,
+                   const std::function<void*(size_t)>& take, hipStream_t st) {
+  if (m <= 0 || nseg <= 0) return;
+  auto* counts = (unsigned long long*)take(NCLASS * sizeof(unsigned long long));
+  auto* lists = (int32_t*)take((size_t)NCLASS * nseg * sizeof(int32_t));
+  zero_bytes(counts, NCLASS * sizeof(unsigned long long), st);
+  k_seg_classify<<<tile_blocks(cdiv(nseg, BLOCK), 4096), BLOCK, 0, st>>>(off, nseg, lists, counts);
+  unsigned long long hc[NCLASS] = {};
+  device_check(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st), "segment classes");
+  device_check(hipStreamSynchronize(st), "segment classes");
+  if (hc[1]) k_seg_rank<16><<<tile_blocks(cdiv((int64_t)hc[1], BLOCK / 16), 4096), BLOCK, 0, st>>>(
+      lists + 1 * nseg, counts + 1, off, kin, vin, kout, vout);
+  if (hc[2]) k_seg_rank<64><<<tile_blocks(cdiv((int64_t)hc[2], BLOCK / 64), 4096), BLOCK, 0, st>>>(
+      lists + 2 * nseg, counts + 2, off, kin, vin, kout, vout);
+  if (hc[3]) k_seg_bitonic<<<tile_blocks((int64_t)hc[3], 2048), BLOCK, 0, st>>>(lists + 3 * nseg, counts + 3, off,
+                                                                                 kin, vin, kout, vout);
+  const int64_t nlong = (int64_t)hc[4];
+  if (nlong == 0) return;
+  const int32_t* list = lists + 4 * nseg;
+  auto* size = (int64_t*)take((size_t)nlong * 8);
+  auto* loff = (int64_t*)take((size_t)(nlong + 1) * 8);
+  k_seg_long_sizes<<<grid_for(nlong), BLOCK, 0, st>>>(list, nlong, off, size);
+  scan_i64_i64(size, loff, nlong, scan_temp, st);
+  int64_t mlong = 0;
+  device_check(hipMemcpyAsync(&mlong, loff + nlong, sizeof(int64_t), hipMemcpyDeviceToHost, st), "long items");
+  device_check(hipStreamSynchronize(st), "long items");
+  auto* ka = (uint64_t*)take((size_t)mlong * 8);
+  auto* kb = (uint64_t*)take((size_t)mlong * 8);
+  auto* va = (uint32_t*)take((size_t)mlong * 4);
+  auto* vb = (uint32_t*)take((size_t)mlong * 4);
+  void* rtemp = take(radix_temp_bytes(mlong));
+  k_seg_long_gather<<<grid_for(mlong), BLOCK, 0, st>>>(kin, vin, off, list, loff, nlong, mlong, low_bits, ka, va);
+  int rbits = 1;
+  while (((int64_t)1 << rbits) < nlong) ++rbits;
+  int shifts[8], np = 0;
+  for (int b = 0; b < low_bits + rbits && np < 8; b += 8) shifts[np++] = b;
+  const int which = radix_sort_pairs(ka, va, kb, vb, mlong, shifts, np, rtemp, st);
+  k_seg_long_scatter<<<grid_for(mlong), BLOCK, 0, st>>>(which ? kb : ka, which ? vb : va, off, list, loff, mlong,
+                                                         low_bits, seg_shift, kout, vout);
+}
+
+}  // namespace lcc
