@@ -451,11 +451,12 @@ void launch_group_sum(const int32_t* grp, const int32_t* cnt, int64_t n, int64_t
 void launch_group_place(const int32_t* grp, const int32_t* cnt, const uint8_t* mask, int64_t n, const int64_t* start,
                         int64_t nseg, unsigned long long* cursor, int64_t* pos, hipStream_t st);
 // (kout, vout) = (kin, vin) with the m items of every segment [off[s], off[s+1]) sorted by key.  Every key of
-// segment s is (s << seg_shift) | low with low < 2^low_bits (low_bits <= seg_shift), so the whole output is
-// sorted.  take() hands out stream-ordered scratch.
-void segsort_pairs(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t m,
-                   const int64_t* off, int64_t nseg, int low_bits, int seg_shift, void* scan_temp,
-                   const std::function<void*(size_t)>& take, hipStream_t st);
+// segment s is below every key of segment s + 1, and keys inside a segment differ only in their low
+// `low_bits` bits, so the whole output is sorted.  (kin, vin) are clobbered (the second buffer of the long
+// segments' passes); m < 2^32.  take() hands out stream-ordered scratch.
+void segsort_pairs(uint64_t* kin, uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t m, const int64_t* off,
+                   int64_t nseg, int low_bits, void* scan_temp, const std::function<void*(size_t)>& take,
+                   hipStream_t st);
 
 void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t* B, uint64_t seed, uint64_t t,
             int32_t* R, RefineBuffers& rb, Ctrl* ctrl, const std::function<void*(size_t)>& take, hipStream_t st);

@@ -544,7 +544,7 @@ struct Run {
       while (((int64_t)1 << ybits) < nc) ++ybits;
       {
         const auto mk = ctx->pool_mark();
-        segsort_pairs(w.k0, w.v0, w.k1, w.v1, E, xoff, nc, ybits, 32, w.scan_temp,
+        segsort_pairs(w.k0, w.v0, w.k1, w.v1, E, xoff, nc, ybits, w.scan_temp,
                       [&](size_t by) { return ctx->pool_take(by); }, st);
         ctx->pool_release(mk);
       }

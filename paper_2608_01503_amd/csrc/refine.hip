@@ -460,7 +460,7 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
   if (m > 0) {
     launch_group_place(rb.root, nullptr, rb.member, n, toff, n, cursor, tpos, st);
     k_tree_keys<<<grid_for(n), BLOCK, 0, st>>>(n, rb.member, tpos, rb.root, fseed, rb.flip, rb.k0, rb.v0);
-    segsort_pairs(rb.k0, rb.v0, rb.k1, rb.v1, m, toff, n, 33, 33, rb.scan_temp, take, st);
+    segsort_pairs(rb.k0, rb.v0, rb.k1, rb.v1, m, toff, n, 33, rb.scan_temp, take, st);
     const uint32_t* sv = rb.v1;
     // a(v, X_{<v}) for tree members
     fill_i64(rb.aX, 0, n, st);

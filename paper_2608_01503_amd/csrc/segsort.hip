@@ -6,8 +6,8 @@
 // (sizes are known up front, so the range of segment s starts at an exclusive scan of the sizes; items of one
 // tile claim space with one global atomic per distinct segment), and then each segment is sorted on its own,
 // by size class: up to 16 or 64 items by ranking in a group of 16 or 64 lanes (shuffles, no LDS), up to 2048
-// by a bitonic network in LDS (one workgroup per segment), and the longer segments together by an LSD radix
-// sort over (segment rank, key inside the segment) whose output goes back into each segment's range.
+// by a bitonic network in LDS (one workgroup per segment), and the longer segments in place by an LSD radix
+// sort over the key bits inside the segment (tile histograms laid out by segment).
 // Equal keys may end in any order; the callers either have unique keys or sum equal keys' values.
 #include <algorithm>
 #include <functional>
@@ -203,39 +203,113 @@ __global__ __launch_bounds__(BLOCK) void k_seg_bitonic(const int32_t* list, cons
   }
 }
 
-__global__ void k_seg_long_sizes(const int32_t* list, int64_t nlong, const int64_t* off, int64_t* size) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nlong; r += (int64_t)gridDim.x * blockDim.x)
-    size[r] = off[list[r] + 1] - off[list[r]];
-}
+// Long segments are sorted in place by an LSD radix sort over the key bits inside the segment only: the
+// tiles of every long segment keep per-tile digit counts laid out as (segment rank, digit, tile), so one
+// exclusive scan over them gives each item's position in the concatenation of the long segments, which maps
+// back into its own segment's range.
+constexpr int SR_TILE = 4096;
 
-// long-segment item i: key (rank r << low_bits | key inside its segment), its value
-__global__ void k_seg_long_gather(const uint64_t* kin, const uint32_t* vin, const int64_t* off, const int32_t* list,
-                                  const int64_t* loff, int64_t nlong, int64_t mlong, int low_bits, uint64_t* ka,
-                                  uint32_t* va) {
-  const uint64_t low = (1ull << low_bits) - 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mlong; i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t lo = 0, hi = nlong - 1;  // last r with loff[r] <= i
-    while (lo < hi) {
-      const int64_t mid = (lo + hi + 1) >> 1;
-      if (loff[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    const int64_t src = off[list[lo]] + (i - loff[lo]);
-    ka[i] = ((uint64_t)lo << low_bits) | (kin[src] & low);
-    va[i] = vin[src];
+__global__ void k_seg_long_sizes(const int32_t* list, int64_t nlong, const int64_t* off, int64_t* size,
+                                 int64_t* ntile) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nlong; r += (int64_t)gridDim.x * blockDim.x) {
+    size[r] = off[list[r] + 1] - off[list[r]];
+    ntile[r] = cdiv(size[r], SR_TILE);
   }
 }
 
-// sorted item i goes back into its segment's range with its key rebuilt (segment << seg_shift | low part)
-__global__ void k_seg_long_scatter(const uint64_t* ka, const uint32_t* va, const int64_t* off, const int32_t* list,
-                                   const int64_t* loff, int64_t mlong, int low_bits, int seg_shift, uint64_t* kout,
-                                   uint32_t* vout) {
-  const uint64_t low = (1ull << low_bits) - 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mlong; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = (int64_t)(ka[i] >> low_bits);
-    const int64_t seg = list[r];
-    const int64_t dst = off[seg] + (i - loff[r]);
-    kout[dst] = ((uint64_t)seg << seg_shift) | (ka[i] & low);
-    vout[dst] = va[i];
+struct LongTile {
+  int64_t r, t, nt, b, e;  // segment rank, tile of the segment, tiles of the segment, item range
+};
+
+__device__ __forceinline__ LongTile long_tile(int64_t g, const int64_t* toff, int64_t nlong, const int32_t* list,
+                                              const int64_t* off) {
+  int64_t lo = 0, hi = nlong - 1;  // last r with toff[r] <= g
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (toff[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  LongTile lt;
+  lt.r = lo;
+  lt.t = g - toff[lo];
+  lt.nt = toff[lo + 1] - toff[lo];
+  const int64_t s = list[lo];
+  lt.b = off[s] + lt.t * SR_TILE;
+  lt.e = min(off[s + 1], lt.b + SR_TILE);
+  return lt;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_segradix_hist(const uint64_t* keys, const int64_t* off, const int32_t* list,
+                                                         const int64_t* toff, int64_t nlong, int shift,
+                                                         uint32_t* hist) {
+  __shared__ uint32_t cnt[256];
+  const LongTile lt = long_tile(blockIdx.x, toff, nlong, list, off);
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = lt.b + threadIdx.x; i < lt.e; i += BLOCK) atomicAdd(&cnt[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  hist[256 * toff[lt.r] + (int64_t)threadIdx.x * lt.nt + lt.t] = cnt[threadIdx.x];
+}
+
+// Stable scatter of one tile: items in rounds of 256 in index order; a lane's rank among same-digit items of
+// its round is the count of lower lanes of its wavefront with the same digit (ballot match) plus the counts of
+// the earlier wavefronts.
+__global__ __launch_bounds__(BLOCK) void k_segradix_scatter(const uint64_t* kin, const uint32_t* vin,
+                                                            const int64_t* off, const int32_t* list,
+                                                            const int64_t* toff, const int64_t* loff, int64_t nlong,
+                                                            int shift, const uint32_t* offs, uint64_t* kout,
+                                                            uint32_t* vout) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[BLOCK / WAVE][256];
+  const int tid = threadIdx.x, wv = tid / WAVE, lane = tid & (WAVE - 1);
+  const LongTile lt = long_tile(blockIdx.x, toff, nlong, list, off);
+  base[tid] = offs[256 * toff[lt.r] + (int64_t)tid * lt.nt + lt.t];
+  const int64_t to_array = off[list[lt.r]] - loff[lt.r];  // position in the concatenation -> in the array
+  const uint64_t lm = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+  for (int64_t r0 = lt.b; r0 < lt.e; r0 += BLOCK) {  // block-uniform
+#pragma unroll
+    for (int k = 0; k < BLOCK / WAVE; ++k) wcnt[k][tid] = 0;
+    __syncthreads();
+    const int64_t i = r0 + tid;
+    const bool valid = i < lt.e;
+    const uint64_t key = valid ? kin[i] : 0;
+    const uint32_t val = valid ? vin[i] : 0;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint64_t mask = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot((d >> b) & 1u);
+      mask &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    const uint32_t prank = (uint32_t)__popcll(mask & lm);
+    if (valid && prank == 0) wcnt[wv][d] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    {
+      uint32_t run = base[tid];
+#pragma unroll
+      for (int k = 0; k < BLOCK / WAVE; ++k) {
+        const uint32_t c = wcnt[k][tid];
+        wcnt[k][tid] = run;
+        run += c;
+      }
+      base[tid] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const int64_t dst = to_array + (int64_t)(wcnt[wv][d] + prank);
+      kout[dst] = key;
+      vout[dst] = val;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_seg_long_copy(const uint64_t* kin, const uint32_t* vin, const int64_t* off,
+                                                         const int32_t* list, const int64_t* toff, int64_t nlong,
+                                                         uint64_t* kout, uint32_t* vout) {
+  const LongTile lt = long_tile(blockIdx.x, toff, nlong, list, off);
+  for (int64_t i = lt.b + threadIdx.x; i < lt.e; i += BLOCK) {
+    kout[i] = kin[i];
+    vout[i] = vin[i];
   }
 }
 
@@ -251,8 +325,8 @@ void launch_group_place(const int32_t* grp, const int32_t* cnt, const uint8_t* m
   k_group_place<<<tile_blocks(cdiv(n, PL_TILE), 4096), BLOCK, 0, st>>>(grp, cnt, mask, n, cursor, pos);
 }
 
-void segsort_pairs(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t m,
-                   const int64_t* off, int64_t nseg, int low_bits, int seg_shift, void* scan_temp,
+void segsort_pairs(uint64_t* kin, uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t m,
+                   const int64_t* off, int64_t nseg, int low_bits, void* scan_temp,
                    const std::function<void*(size_t)>& take, hipStream_t st) {
   if (m <= 0 || nseg <= 0) return;
   auto* counts = (unsigned long long*)take(NCLASS * sizeof(unsigned long long));
@@ -270,27 +344,33 @@ void segsort_pairs(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uin
                                                                                  kin, vin, kout, vout);
   const int64_t nlong = (int64_t)hc[4];
   if (nlong == 0) return;
+  // long segments, in place: passes alternate between (kin, vin) and (kout, vout) on their ranges
   const int32_t* list = lists + 4 * nseg;
   auto* size = (int64_t*)take((size_t)nlong * 8);
+  auto* ntile = (int64_t*)take((size_t)nlong * 8);
   auto* loff = (int64_t*)take((size_t)(nlong + 1) * 8);
-  k_seg_long_sizes<<<grid_for(nlong), BLOCK, 0, st>>>(list, nlong, off, size);
+  auto* toff = (int64_t*)take((size_t)(nlong + 1) * 8);
+  k_seg_long_sizes<<<grid_for(nlong), BLOCK, 0, st>>>(list, nlong, off, size, ntile);
   scan_i64_i64(size, loff, nlong, scan_temp, st);
-  int64_t mlong = 0;
-  device_check(hipMemcpyAsync(&mlong, loff + nlong, sizeof(int64_t), hipMemcpyDeviceToHost, st), "long items");
-  device_check(hipStreamSynchronize(st), "long items");
-  auto* ka = (uint64_t*)take((size_t)mlong * 8);
-  auto* kb = (uint64_t*)take((size_t)mlong * 8);
-  auto* va = (uint32_t*)take((size_t)mlong * 4);
-  auto* vb = (uint32_t*)take((size_t)mlong * 4);
-  void* rtemp = take(radix_temp_bytes(mlong));
-  k_seg_long_gather<<<grid_for(mlong), BLOCK, 0, st>>>(kin, vin, off, list, loff, nlong, mlong, low_bits, ka, va);
-  int rbits = 1;
-  while (((int64_t)1 << rbits) < nlong) ++rbits;
-  int shifts[8], np = 0;
-  for (int b = 0; b < low_bits + rbits && np < 8; b += 8) shifts[np++] = b;
-  const int which = radix_sort_pairs(ka, va, kb, vb, mlong, shifts, np, rtemp, st);
-  k_seg_long_scatter<<<grid_for(mlong), BLOCK, 0, st>>>(which ? kb : ka, which ? vb : va, off, list, loff, mlong,
-                                                         low_bits, seg_shift, kout, vout);
+  scan_i64_i64(ntile, toff, nlong, scan_temp, st);
+  int64_t T = 0;
+  device_check(hipMemcpyAsync(&T, toff + nlong, sizeof(int64_t), hipMemcpyDeviceToHost, st), "long tiles");
+  device_check(hipStreamSynchronize(st), "long tiles");
+  auto* hist = (uint32_t*)take((size_t)(256 * T + 1) * 4);
+  auto* offs = (uint32_t*)take((size_t)(256 * T + 1) * 4);
+  uint64_t* ka = kin;
+  uint32_t* va = vin;
+  uint64_t* kb = kout;
+  uint32_t* vb = vout;
+  int np = 0;
+  for (int sh = 0; sh < low_bits; sh += 8, ++np) {
+    k_segradix_hist<<<(unsigned)T, BLOCK, 0, st>>>(ka, off, list, toff, nlong, sh, hist);
+    scan_u32_u32(hist, offs, 256 * T, scan_temp, st);
+    k_segradix_scatter<<<(unsigned)T, BLOCK, 0, st>>>(ka, va, off, list, toff, loff, nlong, sh, offs, kb, vb);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != kout) k_seg_long_copy<<<(unsigned)T, BLOCK, 0, st>>>(ka, va, off, list, toff, nlong, kout, vout);
 }
 
 }  // namespace lcc
