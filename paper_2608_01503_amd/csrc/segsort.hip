@@ -5,7 +5,7 @@
 // Instead of an LSD radix sort over every key bit, the items are first placed into their segment's range
 // (sizes are known up front, so the range of segment s starts at an exclusive scan of the sizes; items of one
 // tile claim space with one global atomic per distinct segment), and then each segment is sorted on its own,
-// by size class: up to 16 or 64 items by ranking in a group of 16 or 64 lanes (shuffles, no LDS), up to 2048
+// by size class: up to 16 or 64 items by ranking in a group of 16 or 64 lanes (shuffles, no LDS), up to 512
 // by a bitonic network in LDS (one workgroup per segment), and the longer segments in place by an LSD radix
 // sort over the key bits inside the segment (tile histograms laid out by segment).
 // Equal keys may end in any order; the callers either have unique keys or sum equal keys' values.
@@ -98,7 +98,7 @@ __global__ void k_copy_u64(const int64_t* src, int64_t n, unsigned long long* ds
 }
 
 // Segments by size class: 1 (1..16 items), 2 (17..64), 3 (65..SEG_MED), 4 (longer); empty ones need nothing.
-constexpr int SEG_MED = 2048;
+constexpr int SEG_MED = 512;
 constexpr int NCLASS = 5;
 
 __device__ __forceinline__ int seg_class(int64_t sz) {
@@ -178,7 +178,8 @@ __device__ __forceinline__ void bitonic_lds(uint64_t* k, uint32_t* v, int N) {
   __syncthreads();
 }
 
-// Segments of 65..SEG_MED items, one workgroup each, bitonic in LDS.
+// Segments of 65..SEG_MED items, one workgroup each, bitonic in LDS (the radix passes of the long segments
+// beat the network beyond a few hundred items).
 __global__ __launch_bounds__(BLOCK) void k_seg_bitonic(const int32_t* list, const unsigned long long* count,
                                                        const int64_t* off, const uint64_t* kin, const uint32_t* vin,
                                                        uint64_t* kout, uint32_t* vout) {
