@@ -367,7 +367,7 @@ __global__ void k_pass_begin(LMSlot* s, int i, int same_phi) {
     s->nL[i] = 0;
     s->nM[i] = 0;
     s->I[i - 1] = 0;
-    s->SW2[i] = 0;
+    s->SW2[i] = s->SW2[i - 1];  // a single graph's moves add their change (a union recomputes it)
   }
 }
 
@@ -907,10 +907,12 @@ __global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, 
 constexpr int APPLY_TILE = 1024;   // vertices per workgroup tile (4 per thread)
 constexpr int AGG_SLOTS = 4096;    // > 2 * APPLY_TILE distinct cluster ids per tile
 
+// sq (optional) receives the change of sum_c W_c^2 made by the moves (a single graph's state bookkeeping).
 __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep, const VState* vs,
                                                  const int64_t* vw, int32_t* C, int64_t* W, uint8_t* empty,
-                                                 LMSlot* slot, int pass) {
+                                                 LMSlot* slot, int pass, int64_t* sq) {
   if (slot && slot->skip[pass]) return;
+  int64_t dsq = 0;
   __shared__ int32_t ak[AGG_SLOTS];
   __shared__ unsigned long long av[AGG_SLOTS];
   __shared__ unsigned long long ne;
@@ -938,10 +940,14 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
       empty[v] = e;
     }
     __syncthreads();
-    agg.flush(W);
+    if (sq) dsq += agg.flush_sq(W); else agg.flush(W);
     __syncthreads();
   }
   if (threadIdx.x == 0 && ne) atomicAdd((unsigned long long*)&slot->n_empty, ne);
+  if (sq) {
+    dsq = sum_reduce<BLOCK>(dsq);
+    if (threadIdx.x == 0 && dsq) atomicAdd((unsigned long long*)sq, (unsigned long long)dsq);
+  }
 }
 
 // Free cluster ids are the ids that no vertex holds once every move except those to a new singleton is
@@ -989,8 +995,10 @@ __global__ __launch_bounds__(BLOCK) void k_free_list(int64_t n, const uint32_t* 
 __global__ __launch_bounds__(BLOCK) void k_assign_empty(int64_t n, const uint8_t* empty, const int32_t* freelist,
                                                         const int64_t* vw, int32_t* C, int64_t* W, int32_t* rank,
                                                         unsigned long long* status, uint32_t* ticket,
-                                                        uint32_t lbtag, uint32_t nt, const LMSlot* slot) {
+                                                        uint32_t lbtag, uint32_t nt, const LMSlot* slot,
+                                                        int64_t* sq) {
   if (slot->n_empty == 0) return;
+  int64_t dsq = 0;  // each new singleton adds w(v)^2 to sum_c W_c^2
   __shared__ uint32_t sh_t, sh_p, wsum[BLOCK / WAVE];
   const uint32_t draws = nt + gridDim.x;
   for (uint32_t t = lb_next(ticket, draws, &sh_t); t < nt; t = lb_next(ticket, draws, &sh_t)) {
@@ -1019,11 +1027,16 @@ __global__ __launch_bounds__(BLOCK) void k_assign_empty(int64_t n, const uint8_t
           const int32_t c = freelist[run];
           C[v] = c;
           W[c] = vw[v];  // a free id has weight 0
+          dsq += vw[v] * vw[v];
         }
       }
       run += f[k];
     }
     if (rank && base < n && base + LB_ITEMS >= n) rank[n] = (int32_t)run;
+  }
+  if (sq) {
+    dsq = sum_reduce<BLOCK>(dsq);
+    if (threadIdx.x == 0 && dsq) atomicAdd((unsigned long long*)sq, (unsigned long long)dsq);
   }
 }
 
@@ -1635,11 +1648,14 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const ScoreS
   }
 }
 
+// track_sq: keep slot->SW2[pass] (set to the previous state's value by k_pass_begin) up to date from the
+// moves instead of recomputing it from all cluster weights
 static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, const SegLM& sg, LMSlot* slot, int pass,
-                            hipStream_t st) {
+                            bool track_sq, hipStream_t st) {
   const int64_t n = g.n;
+  int64_t* sq = track_sq ? &slot->SW2[pass] : nullptr;
   unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 4096));
-  k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass);
+  k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass, sq);
   // free ids and ranks of the movers to a new singleton; all no-ops unless some vertex moved to a new
   // singleton in this pass
   Tagged& tg = *bufs.tg;
@@ -1651,7 +1667,7 @@ static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, const SegLM& sg,
                                     tg.ticket, next_tag(tg, st), nt, slot);
   k_assign_empty<<<gl, BLOCK, 0, st>>>(n, bufs.empty, bufs.freelist, g.vw, bufs.C, bufs.W,
                                        sg.G ? bufs.scan_b : nullptr, tg.status, tg.ticket, next_tag(tg, st), nt,
-                                       slot);
+                                       slot, sq);
   if (sg.G)
     k_assign_empty_seg<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_a, bufs.scan_b, bufs.freelist, sg.gid,
                                                      sg.vbase, g.vw, bufs.C, bufs.W, slot);
@@ -1664,8 +1680,8 @@ static void state_sums_sw2(const SegLM& sg, const int64_t* W, int64_t n, LMSlot*
     const int64_t G = sg.G;
     k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(W, 1, sg.vbase, G, sg.SW2 + (int64_t)k * G,
                                               k ? sg.SW2 + (int64_t)(k - 1) * G : nullptr, pass >= 0 ? slot : nullptr, pass);
-  } else {
-    k_sw2<<<red_blocks(n), BLOCK, 0, st>>>(W, n, &slot->SW2[k], pass >= 0 ? slot : nullptr, pass);
+  } else if (pass < 0) {  // the starting state; later states follow from the moves (apply_and_empty)
+    k_sw2<<<red_blocks(n), BLOCK, 0, st>>>(W, n, &slot->SW2[k], nullptr, pass);
   }
 }
 
@@ -1728,7 +1744,7 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
       const int64_t nl = b.off[NBUCKET];
       k_keep_rule<<<red_blocks(nl), BLOCK, 0, st>>>(b.list, nl, bufs.vs, prm.symmetry, i, bufs.keep, slot);
     }
-    apply_and_empty(g, bufs, sg, slot, i, st);
+    apply_and_empty(g, bufs, sg, slot, i, G == 0, st);
     state_sums_sw2(sg, bufs.W, n, slot, i, i, st);
   }
   const int last = prm.pass_limit;
@@ -1757,7 +1773,7 @@ uint32_t next_tag(Tagged& t, hipStream_t st) {
 }
 
 void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {
-  apply_and_empty(g, bufs, SegLM{}, slot, 0, st);
+  apply_and_empty(g, bufs, SegLM{}, slot, 0, false, st);
 }
 
 void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
