@@ -141,9 +141,16 @@ size_t level_bytes(int64_t n, int64_t nnz) {
 
 }  // namespace
 
+static lcc_tuning initial_tuning() {
+  lcc_tuning t{};
+  for (int k = 0; k < NBUCKET - 1; ++k) t.bucket_max[k] = BUCKET_CAP[k];
+  t.grid_cap = 2048;
+  return t;
+}
+
 struct lcc_ctx {
   int device = 0;
-  lcc_tuning tune{{4, 8, 16, 32, 128, 1024, 4096}, 2048, 0};  // result-neutral launch tuning
+  lcc_tuning tune = initial_tuning();  // result-neutral launch tuning
   BucketBounds bounds() const {
     BucketBounds b;
     for (int k = 0; k < NBUCKET - 1; ++k) b.max[k] = tune.bucket_max[k];
@@ -1407,10 +1414,7 @@ lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda
 }
 
 void lcc_default_tuning(lcc_tuning* t) {
-  if (!t) return;
-  memset(t, 0, sizeof(*t));
-  for (int k = 0; k < NBUCKET - 1; ++k) t->bucket_max[k] = BUCKET_CAP[k];
-  t->grid_cap = 2048;
+  if (t) *t = initial_tuning();
 }
 
 lcc_status lcc_set_tuning(lcc_ctx* ctx, const lcc_tuning* t) {
