@@ -449,7 +449,8 @@ void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* ma
 // refine.hip: pLeidenR (Alg. 6)
 struct RefineBuffers {
   int64_t* WB; int64_t* aB; int64_t* aX; uint8_t* inU; int32_t* H; int32_t* par; int32_t* root;
-  uint8_t* flip; uint8_t* has_child; int32_t* tsz; uint8_t* member; int32_t* mpos;
+  uint8_t* flip; uint8_t* has_child; int32_t* tsz; uint8_t* member;
+  int32_t* tree_sz;  // n + 1: per root, its tree's size when it has 2 or more members
   uint64_t* k0; uint32_t* v0; uint64_t* k1; uint32_t* v1;
   int64_t* pw; int64_t* pc; int64_t* tmp64a; int64_t* tmp64b; int32_t* pos_of; int32_t* fail;
   void* scan_temp;

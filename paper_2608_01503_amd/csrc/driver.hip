@@ -74,7 +74,7 @@ struct WS {
   uint8_t* head; int32_t* uid; int32_t* ux;
   int64_t *WB, *aB, *aX, *pw, *pc, *t64a, *t64b, *alt_gain;
   uint8_t *inU, *flip, *has_child, *member;
-  int32_t *H, *par, *root, *tsz, *pos_of, *fail, *mpos, *alt_list;
+  int32_t *H, *par, *root, *tsz, *pos_of, *fail, *tree_sz, *alt_list;
   int32_t* gid0;  // union of graphs: graph of every level-0 vertex
   int64_t *seg0, *seg1;  // contraction: entries per coarse row (then the rows' cursors) and the rows' starts
   Tagged tg;      // free-id marks and single-pass scan state (zeroed when the workspace is allocated)
@@ -113,7 +113,7 @@ size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
   w.inU = c.take<uint8_t>(n); w.flip = c.take<uint8_t>(n); w.has_child = c.take<uint8_t>(n);
   w.member = c.take<uint8_t>(n);
   w.H = c.take<int32_t>(n); w.par = c.take<int32_t>(n); w.root = c.take<int32_t>(n); w.tsz = c.take<int32_t>(n);
-  w.pos_of = c.take<int32_t>(n); w.fail = c.take<int32_t>(n); w.mpos = c.take<int32_t>(n + 1);
+  w.pos_of = c.take<int32_t>(n); w.fail = c.take<int32_t>(n); w.tree_sz = c.take<int32_t>(n + 1);
   w.alt_list = c.take<int32_t>(n);
   w.gid0 = c.take<int32_t>(n);
   w.seg0 = c.take<int64_t>(n + 1); w.seg1 = c.take<int64_t>(n + 1);
@@ -677,7 +677,7 @@ struct Run {
   RefineBuffers rbufs() {
     RefineBuffers r{};
     r.WB = w.WB; r.aB = w.aB; r.aX = w.aX; r.inU = w.inU; r.H = w.H; r.par = w.par; r.root = w.root;
-    r.flip = w.flip; r.has_child = w.has_child; r.tsz = w.tsz; r.member = w.member; r.mpos = w.mpos;
+    r.flip = w.flip; r.has_child = w.has_child; r.tsz = w.tsz; r.member = w.member; r.tree_sz = w.tree_sz;
     r.k0 = w.k0; r.v0 = w.v0; r.k1 = w.k1; r.v1 = w.v1;
     r.pw = w.pw; r.pc = w.pc; r.tmp64a = w.t64a; r.tmp64b = w.t64b; r.pos_of = w.pos_of; r.fail = w.fail;
     r.scan_temp = w.scan_temp;

@@ -449,8 +449,8 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
   int64_t* toff = rb.pw;
   auto* cursor = (unsigned long long*)rb.tmp64a;
   int64_t* tpos = rb.tmp64b;
-  k_tree_sizes<<<grid_for(n), BLOCK, 0, st>>>(n, rb.root, rb.tsz, rb.mpos);
-  scan_i32_i64(rb.mpos, toff, n, rb.scan_temp, st);
+  k_tree_sizes<<<grid_for(n), BLOCK, 0, st>>>(n, rb.root, rb.tsz, rb.tree_sz);
+  scan_i32_i64(rb.tree_sz, toff, n, rb.scan_temp, st);
   // the member count is needed on the host to size the sort
   int64_t m = 0;
   device_check(hipMemcpyAsync(&m, toff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st), "tree members");
