@@ -201,6 +201,11 @@ struct lcc_ctx {
     WS tmp{};
     size_t need = carve(tmp, nullptr, nn, ne);
     if (ws_base) { (void)hipDeviceSynchronize(); dfree(ws_base); ws_base = nullptr; }
+    // until the new workspace is in place the context has none: a failed allocation must not leave the sizes
+    // of the freed one behind for the next call
+    ws_n = ws_nnz = -1;
+    ws_bytes = 0;
+    w = WS{};
     ws_base = (char*)dalloc(need);
     ws_bytes = need;
     carve(w, ws_base, nn, ne);

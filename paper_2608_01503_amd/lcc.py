@@ -254,14 +254,32 @@ def _result(r: lcc_result, trace=None) -> Result:
 
 
 class Context:
-    """One lcc_ctx on a HIP device.  allocator: "torch" (torch's caching allocator) or "hip" (hipMalloc)."""
+    """One lcc_ctx on a HIP device.  allocator: "torch" (torch's caching allocator), "hip" (hipMalloc), or a
+    pair of callables (alloc(nbytes) -> device pointer as int, or None when out of memory; free(pointer))."""
 
-    def __init__(self, device: int = 0, allocator: str = "torch"):
+    def __init__(self, device: int = 0, allocator="torch"):
         lib = load()
         self.device = device
         self._alloc_cb = ALLOC_FN(0)
         self._free_cb = FREE_FN(0)
-        if allocator == "torch":
+        if isinstance(allocator, tuple):
+            user_alloc, user_free = allocator
+
+            def _ua(nbytes, user):
+                try:
+                    return user_alloc(int(nbytes))
+                except Exception:  # reported by the library as LCC_ERR_OOM
+                    return None
+
+            def _uf(p, user):
+                try:
+                    user_free(p)
+                except Exception:
+                    pass
+
+            self._alloc_cb = ALLOC_FN(_ua)
+            self._free_cb = FREE_FN(_uf)
+        elif allocator == "torch":
             import torch
 
             def _a(nbytes, user):
