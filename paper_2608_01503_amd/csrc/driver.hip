@@ -995,7 +995,15 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
   } prof_guard(ctx);
   ctx->ensure_ws(g->n, g->nnz);
   ctx->pool_reset();
-  struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
+  // on every exit, also a failure half-way: the stream is drained before the level pool is handed out again
+  struct PoolGuard {
+    lcc_ctx* c;
+    hipStream_t s;
+    ~PoolGuard() {
+      (void)hipStreamSynchronize(s);
+      c->pool_reset();
+    }
+  } guard{ctx, st};
   const int64_t n = g->n;
   if (n == 0) {  // lambda is still checked (modularity is undefined without weight); one level, no cluster
     Score s0{};
@@ -1169,7 +1177,15 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   }
   ctx->ensure_ws(n, nnz);
   ctx->pool_reset();
-  struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
+  // on every exit, also a failure half-way: the stream is drained before the level pool is handed out again
+  struct PoolGuard {
+    lcc_ctx* c;
+    hipStream_t s;
+    ~PoolGuard() {
+      (void)hipStreamSynchronize(s);
+      c->pool_reset();
+    }
+  } guard{ctx, st};
   WS& w = R.w;
   R.G = G;
   R.lv.reserve((size_t)R.o.max_levels + 2);
@@ -1554,7 +1570,15 @@ lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const
     default_opts(&R.o);
     ctx->ensure_ws(g->n, g->nnz);
     ctx->pool_reset();
-    struct PoolGuard { lcc_ctx* c; ~PoolGuard() { c->pool_reset(); } } guard{ctx};
+    // on every exit, also a failure half-way: the stream is drained before the level pool is handed out again
+  struct PoolGuard {
+    lcc_ctx* c;
+    hipStream_t s;
+    ~PoolGuard() {
+      (void)hipStreamSynchronize(s);
+      c->pool_reset();
+    }
+  } guard{ctx, st};
     if (g->n == 0) {
       fill_result(res, 0, 0, 0, 1, 0, 0, false, 0, 0);
       return LCC_OK;
