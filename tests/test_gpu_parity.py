@@ -222,3 +222,21 @@ def test_symmetry_breaking_ablations(sym):
                    (gg.lattice(50, 40, 0.1, 100, 3), CPM20)]:
         for v in (O.PLOUVAIN, O.PLEIDEN):
             U.assert_parity(g, v, *obj, opts_kw=kw)
+
+
+def test_tag_wraparound(monkeypatch):
+    """Free-id marks and single-pass scans tag their words instead of clearing them; when the 32-bit tags run
+    out the arrays are cleared and numbering restarts.  Starting the sequence just before its end makes every
+    call cross the wrap-around; results must not change."""
+    import paper_2608_01503_amd as L
+    monkeypatch.setenv("LCC_TAG_BASE", str(2 ** 32 - 7))
+    ctx = L.Context(0)  # a fresh context: the variable is read when its workspace is allocated
+    for g, v, lam, mode in [(U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=8), L.LCC_PLEIDEN_PLUS,
+                             (1, 20, False), L.LCC_VW_UNIT),
+                            (gg.random_gnp(3000, 0.004, 77, w_max=4), L.LCC_PLOUVAIN, (1, 1, True),
+                             L.LCC_VW_WEIGHTED_DEGREE)]:
+        ref = U.run_oracle(g, v, lam, mode)
+        lab, res = ctx.cluster(U.device_graph(g, mode), lam, v, trace_capacity=1 << 14)
+        assert np.array_equal(lab.cpu().numpy(), ref.labels) and res.N == ref.N
+        assert np.array_equal(res.trace, ref.trace)
+    ctx.close()
