@@ -240,3 +240,12 @@ def test_tag_wraparound(monkeypatch):
         assert np.array_equal(lab.cpu().numpy(), ref.labels) and res.N == ref.N
         assert np.array_equal(res.trace, ref.trace)
     ctx.close()
+
+
+@pytest.mark.parametrize("variant,lam,mode", [(O.PLOUVAIN, (1, 1, True), O.VW_WEIGHTED_DEGREE),
+                                              (O.PLEIDEN, (1, 50, False), O.VW_UNIT)])
+def test_dense_cross_rows(variant, lam, mode):
+    """Few coarse rows with tens of thousands of cross entries each: the contraction's per-row sort takes its
+    long-row path with many tiles per row and a single radix pass (fewer than 257 coarse vertices)."""
+    g = gg.sbm(20, 500, 0.1, 0.01, seed=23)
+    U.assert_parity(g, variant, lam, mode)
