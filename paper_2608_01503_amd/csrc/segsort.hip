@@ -5,9 +5,10 @@
 // Instead of an LSD radix sort over every key bit, the items are first placed into their segment's range
 // (sizes are known up front, so the range of segment s starts at an exclusive scan of the sizes; items of one
 // tile claim space with one global atomic per distinct segment), and then each segment is sorted on its own,
-// by size class: up to 16 or 64 items by ranking in a group of 16 or 64 lanes (shuffles, no LDS), up to 512
-// by a bitonic network in LDS (one workgroup per segment), and the longer segments in place by an LSD radix
-// sort over the key bits inside the segment (tile histograms laid out by segment).
+// by size class: up to 16 or 64 items by ranking in a group of 16 or 64 lanes (shuffles, no LDS), up to 128 by
+// a bitonic network in the registers of one wavefront, up to 512 by a bitonic network in LDS (one workgroup),
+// and the longer segments in place by an LSD radix sort over the key bits inside the segment (tile histograms
+// laid out by segment).
 // Equal keys may end in any order; the callers either have unique keys or sum equal keys' values.
 #include <algorithm>
 #include <functional>
@@ -97,12 +98,14 @@ __global__ void k_copy_u64(const int64_t* src, int64_t n, unsigned long long* ds
     dst[i] = (unsigned long long)src[i];
 }
 
-// Segments by size class: 1 (1..16 items), 2 (17..64), 3 (65..SEG_MED), 4 (longer); empty ones need nothing.
+// Segments by size class: 1 (1..16 items), 2 (17..64), 3 (65..128), 4 (129..SEG_MED), 5 (longer); empty ones
+// need nothing.
 constexpr int SEG_MED = 512;
-constexpr int NCLASS = 5;
+constexpr int NCLASS = 6;
+constexpr int C_LONG = NCLASS - 1;
 
 __device__ __forceinline__ int seg_class(int64_t sz) {
-  return sz <= 0 ? 0 : sz <= 16 ? 1 : sz <= 64 ? 2 : sz <= SEG_MED ? 3 : 4;
+  return sz <= 0 ? 0 : sz <= 16 ? 1 : sz <= 64 ? 2 : sz <= 128 ? 3 : sz <= SEG_MED ? 4 : C_LONG;
 }
 
 // lists[c][..] = the segments of class c (in any order); counts[c] = their number
@@ -156,6 +159,46 @@ __global__ __launch_bounds__(BLOCK) void k_seg_rank(const int32_t* list, const u
   }
 }
 
+// Segments of 65..128 items, one wavefront each, bitonic in registers: lane l holds items l and l + 64, pairs
+// 64 apart meet inside a lane, closer pairs across lanes by shuffles.  Padding keys are all ones.
+__global__ __launch_bounds__(BLOCK) void k_seg_wave_bitonic(const int32_t* list, const unsigned long long* count,
+                                                            const int64_t* off, const uint64_t* kin,
+                                                            const uint32_t* vin, uint64_t* kout, uint32_t* vout) {
+  const int64_t cnt = (int64_t)*count;
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (int64_t q = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) / WAVE; q < cnt; q += (int64_t)gridDim.x * (BLOCK / WAVE)) {
+    const int64_t s = list[q];
+    const int64_t b = off[s], sz = off[s + 1] - b;
+    uint64_t k0 = lane < sz ? kin[b + lane] : ~0ull, k1 = lane + WAVE < sz ? kin[b + lane + WAVE] : ~0ull;
+    uint32_t v0 = lane < sz ? vin[b + lane] : 0u, v1 = lane + WAVE < sz ? vin[b + lane + WAVE] : 0u;
+    for (int size = 2; size <= 2 * WAVE; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        if (stride == WAVE) {  // items l and l + 64: ascending, since (l & 128) == 0
+          if (k0 > k1) {
+            const uint64_t tk = k0; k0 = k1; k1 = tk;
+            const uint32_t tv = v0; v0 = v1; v1 = tv;
+          }
+        } else {
+          const bool lower = (lane & stride) == 0;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            uint64_t& k = h ? k1 : k0;
+            uint32_t& v = h ? v1 : v0;
+            const int i = lane + h * WAVE;
+            const uint64_t pk = __shfl_xor(k, stride, WAVE);
+            const uint32_t pv = __shfl_xor(v, stride, WAVE);
+            const bool asc = (i & size) == 0;
+            const bool take = lower == asc ? pk < k : pk > k;  // the lower slot keeps the min when ascending
+            if (take) { k = pk; v = pv; }
+          }
+        }
+      }
+    }
+    if (lane < sz) { kout[b + lane] = k0; vout[b + lane] = v0; }
+    if (lane + WAVE < sz) { kout[b + lane + WAVE] = k1; vout[b + lane + WAVE] = v1; }
+  }
+}
+
 // ascending bitonic sort of N (a power of two, <= SEG_MED) keys with their values, in LDS
 __device__ __forceinline__ void bitonic_lds(uint64_t* k, uint32_t* v, int N) {
   for (int size = 2; size <= N; size <<= 1)
@@ -178,7 +221,7 @@ __device__ __forceinline__ void bitonic_lds(uint64_t* k, uint32_t* v, int N) {
   __syncthreads();
 }
 
-// Segments of 65..SEG_MED items, one workgroup each, bitonic in LDS (the radix passes of the long segments
+// Segments of 129..SEG_MED items, one workgroup each, bitonic in LDS (the radix passes of the long segments
 // beat the network beyond a few hundred items).
 __global__ __launch_bounds__(BLOCK) void k_seg_bitonic(const int32_t* list, const unsigned long long* count,
                                                        const int64_t* off, const uint64_t* kin, const uint32_t* vin,
@@ -341,12 +384,14 @@ void segsort_pairs(uint64_t* kin, uint32_t* vin, uint64_t* kout, uint32_t* vout,
       lists + 1 * nseg, counts + 1, off, kin, vin, kout, vout);
   if (hc[2]) k_seg_rank<64><<<tile_blocks(cdiv((int64_t)hc[2], BLOCK / 64), 4096), BLOCK, 0, st>>>(
       lists + 2 * nseg, counts + 2, off, kin, vin, kout, vout);
-  if (hc[3]) k_seg_bitonic<<<tile_blocks((int64_t)hc[3], 2048), BLOCK, 0, st>>>(lists + 3 * nseg, counts + 3, off,
+  if (hc[3]) k_seg_wave_bitonic<<<tile_blocks(cdiv((int64_t)hc[3], BLOCK / WAVE), 4096), BLOCK, 0, st>>>(
+      lists + 3 * nseg, counts + 3, off, kin, vin, kout, vout);
+  if (hc[4]) k_seg_bitonic<<<tile_blocks((int64_t)hc[4], 2048), BLOCK, 0, st>>>(lists + 4 * nseg, counts + 4, off,
                                                                                  kin, vin, kout, vout);
-  const int64_t nlong = (int64_t)hc[4];
+  const int64_t nlong = (int64_t)hc[C_LONG];
   if (nlong == 0) return;
   // long segments, in place: passes alternate between (kin, vin) and (kout, vout) on their ranges
-  const int32_t* list = lists + 4 * nseg;
+  const int32_t* list = lists + C_LONG * nseg;
   auto* size = (int64_t*)take((size_t)nlong * 8);
   auto* ntile = (int64_t*)take((size_t)nlong * 8);
   auto* loff = (int64_t*)take((size_t)(nlong + 1) * 8);
