@@ -1,10 +1,11 @@
 // Graph contraction (Alg. 4) as relabel + sort + segmented reduce, and the projections between levels.
 //
 // Coarse vertex x = rank of cluster id among the ids in use (ascending compaction by prefix scan).  Every
-// fine entry (v, u, w) with map[v] != map[u] is emitted as key (map[v] << 32 | map[u]), value w; an LSD radix
-// sort over the used key bits brings equal keys together in (x, y) order; run heads become the coarse
-// entries (neighbours ascending, weights summed with integer atomics, self-loops dropped).  The result is
-// the canonical coarse CSR independent of scheduling.
+// fine entry (v, u, w) with map[v] != map[u] is emitted as key (map[v] << 32 | map[u]), value w, into coarse
+// row x's range (per-row entry counts and grouped placement, segsort.hip); each row is then sorted by y, which
+// brings equal keys together in (x, y) order; run heads become the coarse entries (neighbours ascending,
+// weights summed from a prefix scan of the values, self-loops dropped).  The result is the canonical coarse
+// CSR independent of scheduling.
 #include "common.h"
 
 namespace lcc {
