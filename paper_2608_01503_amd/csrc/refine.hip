@@ -5,7 +5,7 @@
 //          r = fmix64(s_t ^ 2v) mod |A_v|, s_t = t-th splitmix64 output of the seed (t counts refinement calls)
 //   f(v) = fmix32(v ^ (s_t >> 32)), a bijection, K = 2^32; the edge to H[v] is kept iff f(H[v]) < f(v)
 //   roots without children take f <- 2K - 1 - f and their own edge is tested again with the new values
-//   trees: roots by following parents; members of non-trivial trees sorted by (root, f) with a radix sort
+//   trees: roots by following parents; members of non-trivial trees grouped by root and each tree sorted by f
 //   commit: along each sorted tree, v_i is valid iff w'(v_i, X_{i-1}) >= 0 and w'(X_{i-1}, B) >= 0 where X_{i-1}
 //          is the earlier part of the tree; w(X) and w(X, B \ X) come from prefix sums over the sorted order
 //          (w(X_i, B \ X_i) = sum_{j <= i} a(v_j, B \ v_j) - 2 a(v_j, X_{j-1})); the longest all-valid prefix
