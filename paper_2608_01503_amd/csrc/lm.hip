@@ -167,6 +167,20 @@ __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_
 // ---------------------------------------------------------------------------------------------------------
 constexpr int U = 4;
 
+// Sum of x over the 64 lanes of a fully active wavefront, returned to every lane.  A row-local Hillis-Steele
+// scan by DPP row shifts (1, 2, 4, 8), then the two row broadcasts carry rows 0-2 into rows 1-3, so lane 63
+// holds the total: register-to-register moves only, no LDS round trips.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  int v = (int)x;
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1 and 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2 and 3
+  return (uint32_t)__builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ __forceinline__ void lds_insert(int32_t* hk, uint32_t* hv, int bits, int32_t c, uint32_t wt) {
   const uint32_t mask = (1u << bits) - 1;
   uint32_t h = hslot(c, bits);
@@ -217,12 +231,10 @@ __device__ __forceinline__ int64_t insert_row(const DevGraph& g, const int32_t* 
         uint64_t act = __ballot(key >= 0);
         if (!act) break;
         int lead = __ffsll((unsigned long long)act) - 1;
-        int32_t lk = __shfl(key, lead, WAVE);
+        int32_t lk = __builtin_amdgcn_readlane(key, lead);
         uint64_t m = __ballot(key == lk);
         if (__popcll(m) < 2) break;  // no sharing left worth combining
-        uint32_t part = key == lk ? val : 0u;
-#pragma unroll
-        for (int o = WAVE / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, WAVE);
+        uint32_t part = wave_sum_u32(key == lk ? val : 0u);
         if (lane == lead) lds_insert(hk, hv, bits, lk, part);
         if (key == lk) key = -1;
       }
@@ -247,11 +259,16 @@ __device__ __forceinline__ void scan_table(const int32_t* hk, const uint32_t* hv
   for (int s0 = t; s0 < cap; s0 += S * U) {
     int32_t ks[U];
     int64_t as[U], Ws[U];
+    // every read stays inside the table (clamped slot) and is issued unconditionally, so the 2 U LDS reads
+    // go out back to back and are waited for once; slots past the end are then masked off
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      int sl = s0 + k * S;
-      ks[k] = sl < cap ? hk[sl] : -1;
-      as[k] = ks[k] >= 0 ? (int64_t)hv[sl] : 0;
+      const int sl = s0 + k * S;
+      const int slc = sl < cap ? sl : cap - 1;
+      const int32_t kk = hk[slc];
+      const uint32_t vv = hv[slc];
+      ks[k] = sl < cap ? kk : -1;
+      as[k] = ks[k] >= 0 ? (int64_t)vv : 0;
     }
 #pragma unroll
     for (int k = 0; k < U; ++k) Ws[k] = (ks[k] >= 0 && ks[k] != cv) ? W[ks[k]] : 0;
