@@ -13,6 +13,22 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
 constexpr int NBUCKET = 8;
 constexpr int MAX_PASSES = 32;
+// Per-workgroup counter partials.  Thousands of workgroups each adding a partial to one global address
+// serialise on that address (about 12 ns per atomic on MI355X, so 4096 workgroups cost about 50 us); workgroup
+// b adds instead into stripe b mod NSTRIPE of the counter (stripes 128 bytes apart), and a one-workgroup fold
+// kernel adds the stripes of each counter into its destination and clears them.
+constexpr int NSTRIPE = 1024;
+constexpr int STRIPE_W = 16;  // int64 slots per stripe, one per counter id
+enum : int {
+  CT_NCAND = 0,   // candidates of a pass
+  CT_OWN = 1,     // sum of own-cluster weights
+  CT_PAIRS = 2,   // CT_PAIRS + bucket: enumerated (vertex, other cluster) pairs
+  CT_NM = 10,     // kept moves
+  CT_EMPTY = 11,  // movers to a new singleton
+  CT_SQ = 12,     // change of the sum of squared cluster weights
+  CT_INT = 13,    // internal edge weight
+  CT_COUNT = 14
+};
 constexpr int32_t D_NONE = -1;   // no destination
 constexpr int32_t D_EMPTY = -2;  // destination = a new singleton cluster
 
@@ -127,6 +143,7 @@ struct Buckets {
   int32_t* hub_pc = nullptr;
   int64_t* hub_pown = nullptr;
   int64_t* hub_acc = nullptr;
+  int64_t* stripes = nullptr;  // NSTRIPE * STRIPE_W counter partials, all zero between folds
 };
 
 // Scoring parameters of a level: lambda = p / q; phi = phi_a / phi_b; tie window threshold on |delta_u -
@@ -414,7 +431,7 @@ void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int6
 // Exact objective pieces of clustering C: ctrl->obj_I and ctrl->obj_SW2 (W must hold C's cluster weights).
 void launch_objective(const DevGraph& g, const Buckets& b, const int32_t* C, const int64_t* W,
                       Ctrl* ctrl, hipStream_t st);
-void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hipStream_t st);
+void launch_apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, LMSlot* slot, hipStream_t st);
 
 // contract.hip
 // used flags of labels -> rank (compact map) : rank[c] for c in [0, n), count at rank[n].

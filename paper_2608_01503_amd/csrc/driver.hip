@@ -79,6 +79,7 @@ struct WS {
   int32_t* gid0;  // union of graphs: graph of every level-0 vertex
   int64_t *seg0, *seg1;  // contraction: entries per coarse row (then the rows' cursors) and the rows' starts
   Tagged tg;      // free-id marks and single-pass scan state (zeroed when the workspace is allocated)
+  int64_t* stripes;  // per-workgroup counter partials (zeroed when the workspace is allocated)
   void* scan_temp;
 };
 
@@ -123,6 +124,7 @@ size_t carve(WS& w, char* base, int64_t n, int64_t nnz) {
   w.tg.status_cap = (M + 1) / LB_TILE + 2;
   w.tg.status = c.take<unsigned long long>(w.tg.status_cap);
   w.tg.ticket = c.take<uint32_t>(1);
+  w.stripes = c.take<int64_t>((int64_t)NSTRIPE * STRIPE_W);
   w.scan_temp = c.take<char>((int64_t)scan_temp_bytes(M + 1));
   return c.off;
 }
@@ -213,6 +215,7 @@ struct lcc_ctx {
     hip_check(hipMemset(w.tg.held, 0, (size_t)w.tg.held_cap * sizeof(uint32_t)), "workspace");
     hip_check(hipMemset(w.tg.status, 0, (size_t)w.tg.status_cap * sizeof(unsigned long long)), "workspace");
     hip_check(hipMemset(w.tg.ticket, 0, sizeof(uint32_t)), "workspace");
+    hip_check(hipMemset(w.stripes, 0, (size_t)NSTRIPE * STRIPE_W * sizeof(int64_t)), "workspace");
     hip_check(hipDeviceSynchronize(), "workspace");
     // tags are result-neutral; LCC_TAG_BASE starts their sequence elsewhere (tests use it to reach the
     // wrap-around, which otherwise takes billions of passes)
@@ -422,7 +425,7 @@ struct Run {
     b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = hub_off;
-    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc; b.stripes = w.stripes;
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     if (!into) L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
@@ -871,7 +874,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = w.hub_off0;
-    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc; b.stripes = w.stripes;
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     if (b.count[NBUCKET - 1])
@@ -1265,7 +1268,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     b.off[NBUCKET] = ctx->h_ctrl->bucket_off[NBUCKET];
     b.hub_chunks = ctx->h_ctrl->count3;
     b.hub_chunk_off = w.hub_off0;
-    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc;
+    b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc; b.stripes = w.stripes;
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     if (b.count[NBUCKET - 1])

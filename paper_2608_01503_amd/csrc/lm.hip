@@ -12,6 +12,8 @@
 // hash (degree <= 128), one workgroup per vertex with an LDS hash (degree <= 1024: 128 threads, <= 4096: 512
 // threads), and hub vertices split into 2048-edge chunks processed by independent workgroups with a global-memory hash in the edge arena.
 #include <algorithm>
+#include <initializer_list>
+#include <utility>
 
 #include "common.h"
 
@@ -114,13 +116,18 @@ __device__ __forceinline__ void counters_init(BlockCounters* bc) {
   if (threadIdx.x == 0) { bc->ncand = 0; bc->own = 0; bc->pairs = 0; }
   __syncthreads();
 }
-__device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* ncand, int64_t* own,
-                                               int64_t* pairs = nullptr) {
+// this workgroup's stripe of the counter partials (see NSTRIPE)
+__device__ __forceinline__ unsigned long long* stripe(int64_t* S, int ct) {
+  return (unsigned long long*)&S[(int64_t)(blockIdx.x & (NSTRIPE - 1)) * STRIPE_W + ct];
+}
+// counter ids < 0 are not counted
+__device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* S, int ct_ncand, int ct_own,
+                                               int ct_pairs = -1) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (bc->ncand && ncand) atomicAdd((unsigned long long*)ncand, bc->ncand);
-    if (bc->own && own) atomicAdd((unsigned long long*)own, bc->own);
-    if (bc->pairs && pairs) atomicAdd((unsigned long long*)pairs, bc->pairs);
+    if (bc->ncand && ct_ncand >= 0) atomicAdd(stripe(S, ct_ncand), bc->ncand);
+    if (bc->own && ct_own >= 0) atomicAdd(stripe(S, ct_own), bc->own);
+    if (bc->pairs && ct_pairs >= 0) atomicAdd(stripe(S, ct_pairs), bc->pairs);
   }
 }
 
@@ -204,27 +211,30 @@ __device__ __forceinline__ int64_t insert_row(const DevGraph& g, const int32_t* 
   const int64_t tw = t - lane;  // first lane of this wavefront
   int64_t own = 0;
   for (int64_t j0 = b + t, jw = b + tw; jw < e; j0 += (int64_t)S * U, jw += (int64_t)S * U) {
-    int32_t cs[U];
+    // Lanes past the end read the row's last entry (jw < e, so it exists) and drop it afterwards: every load
+    // and gather is issued unconditionally, back to back, with no per-load branch.
+    int32_t us[U], cs[U];
     uint32_t ws[U];
+    bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      int64_t j = j0 + (int64_t)k * S;
-      cs[k] = -1;
-      ws[k] = 0;
-      if (j < e) { cs[k] = g.idx[j]; ws[k] = (uint32_t)g.w[j]; }
+      const int64_t j = j0 + (int64_t)k * S;
+      ok[k] = j < e;
+      const int64_t jc = ok[k] ? j : e - 1;
+      us[k] = g.idx[jc];
+      ws[k] = (uint32_t)g.w[jc];
     }
     if (cons) {
 #pragma unroll
       for (int k = 0; k < U; ++k)
-        if (cs[k] >= 0 && cons[cs[k]] != bv) cs[k] = -1;
+        if (cons[us[k]] != bv) ok[k] = false;
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k)
-      if (cs[k] >= 0) cs[k] = C[cs[k]];
+    for (int k = 0; k < U; ++k) cs[k] = C[us[k]];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      int32_t key = cs[k];
-      uint32_t val = ws[k];
+      int32_t key = ok[k] ? cs[k] : -1;
+      uint32_t val = ok[k] ? ws[k] : 0u;
       if (key == cv) { own += val; key = -1; }
 #pragma unroll
       for (int round = 0; round < 2; ++round) {
@@ -271,7 +281,7 @@ __device__ __forceinline__ void scan_table(const int32_t* hk, const uint32_t* hv
       as[k] = ks[k] >= 0 ? (int64_t)vv : 0;
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k) Ws[k] = (ks[k] >= 0 && ks[k] != cv) ? W[ks[k]] : 0;
+    for (int k = 0; k < U; ++k) Ws[k] = W[ks[k] >= 0 ? ks[k] : cv];  // empty slots read W[cv] and are skipped
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       if (ks[k] < 0) continue;
@@ -314,25 +324,28 @@ __device__ __forceinline__ void best_reduce(Best& r) {
 __device__ __forceinline__ void single_row(const DevGraph& g, const Score& sc, int64_t b, int64_t e, int t, int S,
                                            int64_t wv, Best& r, const int32_t* cons, int32_t bv) {
   for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+    // lanes past the end read the row's last entry (j0 < e) and drop it: loads issued without branches
     int32_t us[U];
     int64_t ws[U], vu[U];
+    bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      int64_t j = j0 + (int64_t)k * S;
-      us[k] = -1;
-      ws[k] = 0;
-      if (j < e) { us[k] = g.idx[j]; ws[k] = g.w[j]; }
+      const int64_t j = j0 + (int64_t)k * S;
+      ok[k] = j < e;
+      const int64_t jc = ok[k] ? j : e - 1;
+      us[k] = g.idx[jc];
+      ws[k] = g.w[jc];
     }
     if (cons) {
 #pragma unroll
       for (int k = 0; k < U; ++k)
-        if (us[k] >= 0 && cons[us[k]] != bv) us[k] = -1;
+        if (cons[us[k]] != bv) ok[k] = false;
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k) vu[k] = us[k] >= 0 ? g.vw[us[k]] : 0;
+    for (int k = 0; k < U; ++k) vu[k] = g.vw[us[k]];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      if (us[k] < 0) continue;
+      if (!ok[k]) continue;
       int64_t val = sc.q * ws[k] - sc.p * wv * vu[k];
       if (better(val, us[k], r.s, r.c)) { r.s = val; r.c = us[k]; }
     }
@@ -344,21 +357,23 @@ __device__ __forceinline__ int64_t internal_row(const DevGraph& g, const int32_t
                                                 int S, int32_t cv) {
   int64_t acc = 0;
   for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+    // lanes past the end read the row's last entry (j0 < e) and drop it: loads issued without branches
     int32_t cs[U];
     int64_t ws[U];
+    bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      int64_t j = j0 + (int64_t)k * S;
-      cs[k] = -1;
-      ws[k] = 0;
-      if (j < e) { cs[k] = g.idx[j]; ws[k] = g.w[j]; }
+      const int64_t j = j0 + (int64_t)k * S;
+      ok[k] = j < e;
+      const int64_t jc = ok[k] ? j : e - 1;
+      cs[k] = g.idx[jc];
+      ws[k] = g.w[jc];
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k)
-      if (cs[k] >= 0) cs[k] = C[cs[k]];
+    for (int k = 0; k < U; ++k) cs[k] = C[cs[k]];
 #pragma unroll
     for (int k = 0; k < U; ++k)
-      if (cs[k] == cv) acc += ws[k];
+      if (ok[k] && cs[k] == cv) acc += ws[k];
   }
   return acc;
 }
@@ -422,7 +437,7 @@ __global__ void k_final_state(LMSlot* s, int last) {
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64_t cnt, DevGraph g, ScoreSrc ss,
                                                       uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot,
-                                                      int pass) {
+                                                      int pass, int64_t* S) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   const int gl = threadIdx.x % G;
@@ -436,12 +451,13 @@ __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64
     best_reduce<G>(r);
     if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
   }
-  counters_flush(&bc, &slot->nL[pass], nullptr);
+  counters_flush(&bc, S, CT_NCAND, -1);
 }
 
 template <int G>
 __global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t cnt, DevGraph g, ScoreSrc ss,
-                                                  uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot, int pass) {
+                                                  uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot, int pass,
+                                                  int64_t* S) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
@@ -454,7 +470,7 @@ __global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t c
     if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
     __syncthreads();
   }
-  counters_flush(&bc, &slot->nL[pass], nullptr);
+  counters_flush(&bc, S, CT_NCAND, -1);
 }
 
 // Hub chunk of the singleton pass: partial argmax per chunk.
@@ -489,7 +505,7 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t cnt, DevGraph g,
                                                     const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
                                                     uint32_t pb, int strict, VState* vs, LMSlot* slot, int pass,
-                                                    int64_t* own_sum, int64_t* pairs) {
+                                                    int64_t* S, int ct_own, int ct_pairs) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot && slot->skip[pass]) return;
@@ -529,7 +545,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
     own = sum_reduce<G>(own);
     if (gl == 0) finish_vertex(v, cv, wv, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
   }
-  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
+  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
 
 // One wavefront per vertex, LDS open-addressing hash of capacity pow2ceil(2 d) <= SLOTS.
@@ -537,7 +553,7 @@ template <int SLOTS>
 __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_t cnt, DevGraph g,
                                                      const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
                                                      uint32_t pb, int strict, VState* vs, LMSlot* slot,
-                                                     int pass, int64_t* own_sum, int64_t* pairs) {
+                                                     int pass, int64_t* S, int ct_own, int ct_pairs) {
   __shared__ int32_t hk[BLOCK / WAVE][SLOTS];
   __shared__ uint32_t hv[BLOCK / WAVE][SLOTS];
   __shared__ BlockCounters bc;
@@ -577,7 +593,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
     }
     __syncthreads();
   }
-  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
+  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
 
 // One workgroup of BS threads per vertex sharing an LDS hash of capacity pow2ceil(2 d) <= SLOTS.
@@ -585,7 +601,7 @@ template <int BS, int SLOTS>
 __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
                                                  const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb,
                                                  int strict, VState* vs, LMSlot* slot, int pass,
-                                                 int64_t* own_sum, int64_t* pairs) {
+                                                 int64_t* S, int ct_own, int ct_pairs) {
   __shared__ int32_t hk[SLOTS];
   __shared__ uint32_t hv[SLOTS];
   __shared__ BlockCounters bc;
@@ -613,7 +629,7 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
     }
     __syncthreads();
   }
-  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum, pairs);
+  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
 
 // Hubs: global-memory hash of 2 d 64-bit slots (cluster << 32 | weight sum) at slot offset 2 off[v] of the
@@ -687,7 +703,8 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
                                                         int64_t n7, DevGraph g, const int32_t* C,
                                                         const int64_t* W, ScoreSrc ss, uint32_t* arena,
                                                         int64_t* ps, int32_t* pc, int64_t* pown,
-                                                        const LMSlot* slot, int pass, int64_t* pairs) {
+                                                        const LMSlot* slot, int pass, int64_t* S,
+                                                        int ct_pairs) {
   if (slot && slot->skip[pass]) return;
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
@@ -715,7 +732,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
   np_ = sum_reduce<HUB_BLOCK>(np_);
   if (threadIdx.x == 0) {
     ps[blockIdx.x] = bs; pc[blockIdx.x] = bcl; pown[blockIdx.x] = own;
-    if (pairs && np_) atomicAdd((unsigned long long*)pairs, (unsigned long long)np_);
+    if (ct_pairs >= 0 && np_) atomicAdd(stripe(S, ct_pairs), (unsigned long long)np_);
   }
 }
 
@@ -723,7 +740,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
 __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64_t n7, const int64_t* vw,
                             const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb, int strict,
                             const int64_t* ps, const int32_t* pc, const int64_t* pown, VState* vs,
-                            LMSlot* slot, int pass, int64_t* own_sum) {
+                            LMSlot* slot, int pass, int64_t* S, int ct_own) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot && slot->skip[pass]) return;
@@ -739,7 +756,7 @@ __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64
     int32_t cv = C ? C[v] : v;
     finish_vertex(v, cv, vw[v], own, bs, bcl, ss.at(v), C ? W : vw, pa, pb, strict, vs, &bc, ss.ownv);
   }
-  counters_flush(&bc, slot ? &slot->nL[pass] : nullptr, own_sum);
+  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -783,26 +800,26 @@ __device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, c
                                           int64_t wv) {
   int64_t acc = 0;
   for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+    // lanes past the end read the row's last entry (j0 < e) and drop it: loads issued without branches
     int32_t us[U];
     int64_t ws[U];
+    bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      int64_t j = j0 + (int64_t)k * S;
-      us[k] = -1;
-      ws[k] = 0;
-      if (j < e) { us[k] = g.idx[j]; ws[k] = g.w[j]; }
+      const int64_t j = j0 + (int64_t)k * S;
+      ok[k] = j < e;
+      const int64_t jc = ok[k] ? j : e - 1;
+      us[k] = g.idx[jc];
+      ws[k] = g.w[jc];
     }
     VState os[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-      os[k] = VState{0, D_NONE, 0};
-      if (us[k] >= 0) os[k] = vs[us[k]];
-    }
+    for (int k = 0; k < U; ++k) os[k] = vs[us[k]];
     int pat[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       pat[k] = 0;
-      if (os[k].d != D_NONE && before(us[k] - base, os[k].delta, v - base, me.delta, sc.tie))
+      if (ok[k] && os[k].d != D_NONE && before(us[k] - base, os[k].delta, v - base, me.delta, sc.tie))
         pat[k] = ab_pattern(me.c, me.d, os[k].c, os[k].d);
     }
     int64_t vu[U];
@@ -817,7 +834,8 @@ __device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, c
 
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
-                                                  ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass) {
+                                                  ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass,
+                                                  int64_t* S) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot->skip[pass]) return;
@@ -838,12 +856,13 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
       }
     }
   }
-  counters_flush(&bc, &slot->nM[pass], nullptr);
+  counters_flush(&bc, S, CT_NM, -1);
 }
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
-                                               ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass) {
+                                               ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass,
+                                               int64_t* S) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot->skip[pass]) return;
@@ -862,7 +881,7 @@ __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt,
       if (k) atomicAdd(&bc.ncand, 1ull);
     }
   }
-  counters_flush(&bc, &slot->nM[pass], nullptr);
+  counters_flush(&bc, S, CT_NM, -1);
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
@@ -882,7 +901,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const
 }
 
 __global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs, int64_t* hacc, uint8_t* keep,
-                               LMSlot* slot, int pass) {
+                               LMSlot* slot, int pass, int64_t* S) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot->skip[pass]) return;
@@ -895,13 +914,13 @@ __global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs
     hacc[k] = 0;
     if (kp) atomicAdd(&bc.ncand, 1ull);
   }
-  counters_flush(&bc, &slot->nM[pass], nullptr);
+  counters_flush(&bc, S, CT_NM, -1);
 }
 
 // Ablations of the symmetry breaking (Table 2): every candidate kept (mode 1), or the minimum label heuristic
 // in odd passes (mode 2: kept only when moving to a lower cluster id or to a new singleton).
 __global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, int mode, int pass, uint8_t* keep,
-                            LMSlot* slot) {
+                            LMSlot* slot, int64_t* S) {
   __shared__ BlockCounters bc;
   counters_init(&bc);
   if (slot->skip[pass]) return;
@@ -913,7 +932,7 @@ __global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, 
     keep[v] = k;
     if (k) atomicAdd(&bc.ncand, 1ull);
   }
-  counters_flush(&bc, &slot->nM[pass], nullptr);
+  counters_flush(&bc, S, CT_NM, -1);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -927,7 +946,7 @@ constexpr int AGG_SLOTS = 4096;    // > 2 * APPLY_TILE distinct cluster ids per 
 // sq (optional) receives the change of sum_c W_c^2 made by the moves (a single graph's state bookkeeping).
 __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep, const VState* vs,
                                                  const int64_t* vw, int32_t* C, int64_t* W, uint8_t* empty,
-                                                 LMSlot* slot, int pass, int64_t* sq) {
+                                                 LMSlot* slot, int pass, int64_t* S, int track_sq) {
   if (slot && slot->skip[pass]) return;
   int64_t dsq = 0;
   __shared__ int32_t ak[AGG_SLOTS];
@@ -957,13 +976,13 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
       empty[v] = e;
     }
     __syncthreads();
-    if (sq) dsq += agg.flush_sq(W); else agg.flush(W);
+    if (track_sq) dsq += agg.flush_sq(W); else agg.flush(W);
     __syncthreads();
   }
-  if (threadIdx.x == 0 && ne) atomicAdd((unsigned long long*)&slot->n_empty, ne);
-  if (sq) {
+  if (threadIdx.x == 0 && ne) atomicAdd(stripe(S, CT_EMPTY), ne);
+  if (track_sq) {
     dsq = sum_reduce<BLOCK>(dsq);
-    if (threadIdx.x == 0 && dsq) atomicAdd((unsigned long long*)sq, (unsigned long long)dsq);
+    if (threadIdx.x == 0 && dsq) atomicAdd(stripe(S, CT_SQ), (unsigned long long)dsq);
   }
 }
 
@@ -1072,10 +1091,10 @@ __global__ void k_sw2(const int64_t* W, int64_t n, int64_t* out, const LMSlot* s
 // ---------------------------------------------------------------------------------------------------------
 // Objective: ordered internal edge weight I(C) = sum over edges (u,v) with C[u] = C[v] of w(u,v)
 // ---------------------------------------------------------------------------------------------------------
-// out: one total over all rows (atomic), or per_v[v] per row when per_v is not null
+// one total over all rows (counter CT_INT of the stripes S), or per_v[v] per row when per_v is not null
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_internal_grp(const int32_t* list, int64_t cnt, DevGraph g,
-                                                        const int32_t* C, int64_t* out, const int32_t* skip,
+                                                        const int32_t* C, int64_t* S, const int32_t* skip,
                                                         int64_t* per_v) {
   if (skip && *skip) return;
   const int gl = threadIdx.x % G;
@@ -1093,12 +1112,12 @@ __global__ __launch_bounds__(BLOCK) void k_internal_grp(const int32_t* list, int
   }
   if (per_v) return;
   s = sum_reduce<BLOCK>(s);
-  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
+  if (threadIdx.x == 0 && s) atomicAdd(stripe(S, CT_INT), (unsigned long long)s);
 }
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_internal_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
-                                                     int64_t* out, const int32_t* skip, int64_t* per_v) {
+                                                     int64_t* S, const int32_t* skip, int64_t* per_v) {
   if (skip && *skip) return;
   int64_t s = 0;
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
@@ -1113,11 +1132,11 @@ __global__ __launch_bounds__(BS) void k_internal_blk(const int32_t* list, int64_
   }
   if (per_v) return;
   s = sum_reduce<BS>(s);
-  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)out, (unsigned long long)s);
+  if (threadIdx.x == 0 && s) atomicAdd(stripe(S, CT_INT), (unsigned long long)s);
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_internal_hub(const int32_t* hubs, const int32_t* chunk_off,
-                                                            int64_t n7, DevGraph g, const int32_t* C, int64_t* out,
+                                                            int64_t n7, DevGraph g, const int32_t* C, int64_t* S,
                                                             const int32_t* skip, int64_t* per_v) {
   if (skip && *skip) return;
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
@@ -1127,7 +1146,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_internal_hub(const int32_t* hubs,
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   int64_t s = internal_row(g, C, j0, j1, threadIdx.x, HUB_BLOCK, cv);
   s = sum_reduce<HUB_BLOCK>(s);
-  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)(per_v ? &per_v[v] : out), (unsigned long long)s);
+  if (threadIdx.x == 0 && s) atomicAdd(per_v ? (unsigned long long*)&per_v[v] : stripe(S, CT_INT), (unsigned long long)s);
 }
 
 // per_v[hubs[k]] = 0 before the hub chunks add into it
@@ -1453,6 +1472,24 @@ __global__ void k_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl) {
   }
 }
 
+// Adds the stripes of every counter that has a destination into it and clears those stripes.
+struct FoldDst {
+  int64_t* d[CT_COUNT];
+};
+__global__ __launch_bounds__(1024) void k_fold(int64_t* S, FoldDst f) {
+  for (int ct = 0; ct < CT_COUNT; ++ct) {
+    if (!f.d[ct]) continue;  // uniform over the workgroup
+    int64_t x = 0;
+    for (int s = threadIdx.x; s < NSTRIPE; s += 1024) {
+      int64_t* p = &S[(int64_t)s * STRIPE_W + ct];
+      x += *p;
+      *p = 0;
+    }
+    x = sum_reduce<1024>(x);
+    if (threadIdx.x == 0 && x) *f.d[ct] += x;
+  }
+}
+
 inline unsigned grid_for(int64_t n) {
   int64_t g = cdiv(n, BLOCK);
   if (g < 1) g = 1;
@@ -1478,6 +1515,15 @@ inline unsigned vtx_blocks(const Buckets& b, int64_t cnt, int64_t cap_div = 1) {
 }
 // persistent workgroups of a single-pass scan over nt tiles
 inline unsigned lb_blocks(uint32_t nt) { return (unsigned)std::max<uint32_t>(1, std::min<uint32_t>(nt, 1024)); }
+
+// fold the listed counters (id, destination; a null destination folds nothing) of the stripes S
+void fold(int64_t* S, std::initializer_list<std::pair<int, int64_t*>> m, hipStream_t st) {
+  FoldDst f{};
+  bool any = false;
+  for (const auto& e : m)
+    if (e.second) { f.d[e.first] = e.second; any = true; }
+  if (any) k_fold<<<1, 1024, 0, st>>>(S, f);
+}
 
 // Hub chunk scratch lives at the end of the per-chunk partial arrays.
 struct HubScratch {
@@ -1543,17 +1589,19 @@ void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int6
 static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
                             const int32_t* skip, hipStream_t st, int64_t* per_v = nullptr) {
   const int32_t* L = b.list;
-  if (b.count[0]) k_internal_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, out, skip, per_v);
-  if (b.count[1]) k_internal_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, out, skip, per_v);
-  if (b.count[2]) k_internal_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, out, skip, per_v);
-  if (b.count[3]) k_internal_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, out, skip, per_v);
+  int64_t* S = b.stripes;
+  if (b.count[0]) k_internal_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, S, skip, per_v);
+  if (b.count[1]) k_internal_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, S, skip, per_v);
+  if (b.count[2]) k_internal_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, S, skip, per_v);
+  if (b.count[3]) k_internal_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, S, skip, per_v);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_internal_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, out, skip, per_v);
-  if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, out, skip, per_v);
+  if (nw) k_internal_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, S, skip, per_v);
+  if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, S, skip, per_v);
   if (b.count[7]) {
     if (per_v) k_zero_listed<<<grid_for(b.count[7]), BLOCK, 0, st>>>(L + b.off[7], b.count[7], per_v, skip);
-    k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, out, skip, per_v);
+    k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, S, skip, per_v);
   }
+  if (!per_v) fold(S, {{CT_INT, out}}, st);
 }
 
 void launch_internal_per_vertex(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
@@ -1588,26 +1636,30 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   VState* vs = bufs.vs;
   const int32_t* hubs = L + b.off[7];
   const int64_t n7 = b.count[7];
+  int64_t* S = b.stripes;
   if (singleton) {
     double sb = 0;
     for (int k = 0; k < NBUCKET; ++k) sb += 16.0 * (double)b.edges[k] + 48.0 * (double)b.count[k];
     prof_begin(PF_SINGLE, st);
-    if (b.count[0]) k_single_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, sc, pa, pb, vs, slot, pass);
-    if (b.count[1]) k_single_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, sc, pa, pb, vs, slot, pass);
-    if (b.count[2]) k_single_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, sc, pa, pb, vs, slot, pass);
-    if (b.count[3]) k_single_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, sc, pa, pb, vs, slot, pass);
+    if (b.count[0]) k_single_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, sc, pa, pb, vs, slot, pass, S);
+    if (b.count[1]) k_single_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, sc, pa, pb, vs, slot, pass, S);
+    if (b.count[2]) k_single_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, sc, pa, pb, vs, slot, pass, S);
+    if (b.count[3]) k_single_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, sc, pa, pb, vs, slot, pass, S);
     int64_t nw = b.count[4] + b.count[5];
-    if (nw) k_single_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, sc, pa, pb, vs, slot, pass);
-    if (b.count[6]) k_single_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass);
+    if (nw) k_single_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, sc, pa, pb, vs, slot, pass, S);
+    if (b.count[6]) k_single_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass, S);
     if (n7) {
       k_single_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, sc, hs.ps, hs.pc);
       k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, nullptr, nullptr, sc, pa, pb, 0,
-                                                 hs.ps, hs.pc, nullptr, vs, slot, pass, nullptr);
+                                                 hs.ps, hs.pc, nullptr, vs, slot, pass, S, -1);
     }
     prof_end(PF_SINGLE, sb, st);
+    fold(S, {{CT_NCAND, &slot->nL[pass]}}, st);
     return;
   }
   int64_t* P = strict ? nullptr : bufs.pairs;  // distinct-pair counters (diagnostics), per bucket
+  const int co = own_sum ? CT_OWN : -1;
+  auto cp = [&](int k) { return P ? CT_PAIRS + k : -1; };
   auto eb = [&](int k) { return 12.0 * (double)b.edges[k] + 56.0 * (double)b.count[k]; };
 #define LCC_ENUM(k, launch)                      \
   if (b.count[k]) {                              \
@@ -1615,24 +1667,28 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
     launch;                                      \
     prof_end(PF_ENUM_B0 + k, eb(k), st);         \
   }
-  LCC_ENUM(0, (k_enum_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 0 : nullptr)))
-  LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 1 : nullptr)))
-  LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 2 : nullptr)))
-  LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 3 : nullptr)))
-  LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 4 : nullptr)))
-  LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 5 : nullptr)))
-  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, own_sum, P ? P + 6 : nullptr)))
+  LCC_ENUM(0, (k_enum_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(0))))
+  LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(1))))
+  LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(2))))
+  LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(3))))
+  LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(4))))
+  LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(5))))
+  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6))))
 #undef LCC_ENUM
   if (n7) {
     unsigned nc = (unsigned)b.hub_chunks;
     prof_begin(PF_ENUM_B0 + 7, st);
     k_hub_insert<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, bufs.arena, slot, pass, sc.cons);
     k_hub_scan<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, W, sc, bufs.arena, hs.ps, hs.pc, hs.pown, slot, pass,
-                                         P ? P + 7 : nullptr);
+                                         S, cp(7));
     k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, C, W, sc, pa, pb, strict, hs.ps,
-                                               hs.pc, hs.pown, vs, slot, pass, own_sum);
+                                               hs.pc, hs.pown, vs, slot, pass, S, co);
     prof_end(PF_ENUM_B0 + 7, eb(7), st);
   }
+  fold(S, {{CT_NCAND, slot ? &slot->nL[pass] : nullptr}, {CT_OWN, own_sum}, {CT_PAIRS + 0, P ? P + 0 : nullptr},
+           {CT_PAIRS + 1, P ? P + 1 : nullptr}, {CT_PAIRS + 2, P ? P + 2 : nullptr}, {CT_PAIRS + 3, P ? P + 3 : nullptr},
+           {CT_PAIRS + 4, P ? P + 4 : nullptr}, {CT_PAIRS + 5, P ? P + 5 : nullptr}, {CT_PAIRS + 6, P ? P + 6 : nullptr},
+           {CT_PAIRS + 7, P ? P + 7 : nullptr}}, st);
 }
 
 static const int32_t* L_hubs(const Buckets& b) { return b.list + b.off[7]; }
@@ -1651,28 +1707,32 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const ScoreS
   const int32_t* L = b.list;
   const VState* vs = bufs.vs;
   uint8_t* keep = bufs.keep;
-  if (b.count[0]) k_ab_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vs, sc, keep, slot, pass);
-  if (b.count[1]) k_ab_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vs, sc, keep, slot, pass);
-  if (b.count[2]) k_ab_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vs, sc, keep, slot, pass);
-  if (b.count[3]) k_ab_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass);
+  if (b.count[0]) k_ab_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vs, sc, keep, slot, pass, b.stripes);
+  if (b.count[1]) k_ab_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vs, sc, keep, slot, pass, b.stripes);
+  if (b.count[2]) k_ab_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vs, sc, keep, slot, pass, b.stripes);
+  if (b.count[3]) k_ab_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass, b.stripes);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_ab_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vs, sc, keep, slot, pass);
-  if (b.count[6]) k_ab_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vs, sc, keep, slot, pass);
+  if (nw) k_ab_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vs, sc, keep, slot, pass, b.stripes);
+  if (b.count[6]) k_ab_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vs, sc, keep, slot, pass, b.stripes);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
     k_ab_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, vs, sc, hs.hacc, slot, pass);
-    k_ab_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vs, hs.hacc, keep, slot, pass);
+    k_ab_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vs, hs.hacc, keep, slot, pass, b.stripes);
   }
 }
 
 // track_sq: keep slot->SW2[pass] (set to the previous state's value by k_pass_begin) up to date from the
 // moves instead of recomputing it from all cluster weights
-static void apply_and_empty(const DevGraph& g, LMBuffers& bufs, const SegLM& sg, LMSlot* slot, int pass,
-                            bool track_sq, hipStream_t st) {
+static void apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, const SegLM& sg, LMSlot* slot,
+                            int pass, bool track_sq, hipStream_t st) {
   const int64_t n = g.n;
   int64_t* sq = track_sq ? &slot->SW2[pass] : nullptr;
   unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 4096));
-  k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass, sq);
+  k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass, b.stripes,
+                                track_sq ? 1 : 0);
+  // the kept moves (afterburner or keep rule), the movers to a new singleton and the sum-of-squares change
+  fold(b.stripes, {{CT_NM, slot ? &slot->nM[pass] : nullptr}, {CT_EMPTY, slot ? &slot->n_empty : nullptr}, {CT_SQ, sq}},
+       st);
   // free ids and ranks of the movers to a new singleton; all no-ops unless some vertex moved to a new
   // singleton in this pass
   Tagged& tg = *bufs.tg;
@@ -1759,9 +1819,10 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
       launch_afterburner(g, b, sc, bufs, slot, i, hs, st);
     } else {
       const int64_t nl = b.off[NBUCKET];
-      k_keep_rule<<<red_blocks(nl), BLOCK, 0, st>>>(b.list, nl, bufs.vs, prm.symmetry, i, bufs.keep, slot);
+      k_keep_rule<<<red_blocks(nl), BLOCK, 0, st>>>(b.list, nl, bufs.vs, prm.symmetry, i, bufs.keep, slot,
+                                                    b.stripes);
     }
-    apply_and_empty(g, bufs, sg, slot, i, G == 0, st);
+    apply_and_empty(g, b, bufs, sg, slot, i, G == 0, st);
     state_sums_sw2(sg, bufs.W, n, slot, i, i, st);
   }
   const int last = prm.pass_limit;
@@ -1789,8 +1850,8 @@ uint32_t next_tag(Tagged& t, hipStream_t st) {
   return ++t.last;
 }
 
-void launch_apply_and_empty(const DevGraph& g, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {
-  apply_and_empty(g, bufs, SegLM{}, slot, 0, false, st);
+void launch_apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {
+  apply_and_empty(g, b, bufs, SegLM{}, slot, 0, false, st);
 }
 
 void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,

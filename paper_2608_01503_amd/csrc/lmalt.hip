@@ -266,7 +266,7 @@ bool lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs
   scan_i64_i64(gain, S2, k, stemp, st);
   k_best_prefix<<<1, BP_BLOCK, 0, st>>>(S2, k, ctrl);
   k_commit_prefix<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, ctrl);
-  launch_apply_and_empty(g, bufs, slot, st);
+  launch_apply_and_empty(g, b, bufs, slot, st);
   return true;
 }
 
