@@ -200,13 +200,15 @@ struct LdsAgg {
   __device__ __forceinline__ void clear() {
     for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) { keys[s] = -1; vals[s] = 0; }
   }
-  __device__ __forceinline__ void add(int32_t k, int64_t v) {
+  // returns 1 when k took a new slot
+  __device__ __forceinline__ int add(int32_t k, int64_t v) {
     uint32_t h = ((uint32_t)k * 2654435761u) & (SLOTS - 1);
     for (int probe = 0; probe < SLOTS; ++probe) {
       int32_t prev = atomicCAS(&keys[h], -1, k);
-      if (prev == -1 || prev == k) { atomicAdd(&vals[h], (unsigned long long)v); return; }
+      if (prev == -1 || prev == k) { atomicAdd(&vals[h], (unsigned long long)v); return prev == -1; }
       h = (h + 1) & (SLOTS - 1);
     }
+    return 0;
   }
   __device__ __forceinline__ void flush(int64_t* out) {
     for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {

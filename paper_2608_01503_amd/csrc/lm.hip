@@ -936,12 +936,17 @@ __global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, 
 }
 
 // ---------------------------------------------------------------------------------------------------------
-// Update (Alg. 2 line "C <- Update(L, C, D)"): simultaneous moves with integer atomics on the cluster
+// Update (the update step of Alg. 2): simultaneous moves with integer atomics on the cluster
 // weights and sizes.  Movers to a new singleton take the ids left unused by all other moves, smallest first,
 // in ascending vertex order.
 // ---------------------------------------------------------------------------------------------------------
-constexpr int APPLY_TILE = 1024;   // vertices per workgroup tile (4 per thread)
-constexpr int AGG_SLOTS = 4096;    // > 2 * APPLY_TILE distinct cluster ids per tile
+constexpr int APPLY_TILE = BLOCK;  // vertices per workgroup tile (one per thread)
+constexpr int AGG_SLOTS = 2048;    // LDS aggregation table of the cluster-weight changes
+// The table keeps accumulating over a workgroup's tiles and is flushed only before it could pass half full (a
+// tile adds at most 2 APPLY_TILE keys): a heavy cluster then receives one global atomic per workgroup, not per
+// tile (same-address atomics serialise).
+constexpr int AGG_FLUSH_AT = AGG_SLOTS / 2 - 2 * APPLY_TILE;
+static_assert(AGG_FLUSH_AT >= 0, "the table must hold the keys of a tile");
 
 // sq (optional) receives the change of sum_c W_c^2 made by the moves (a single graph's state bookkeeping).
 __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep, const VState* vs,
@@ -954,31 +959,41 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
   __shared__ unsigned long long ne;
   LdsAgg<AGG_SLOTS> agg{ak, av};
   if (threadIdx.x == 0) ne = 0;
+  agg.clear();
+  __syncthreads();
+  int used = 0;  // distinct keys in the table (uniform over the workgroup)
   for (int64_t t0 = (int64_t)blockIdx.x * APPLY_TILE; t0 < n; t0 += (int64_t)gridDim.x * APPLY_TILE) {
-    agg.clear();
-    __syncthreads();
-    for (int k = threadIdx.x; k < APPLY_TILE; k += BLOCK) {
-      int64_t v = t0 + k;
-      if (v >= n) break;
+    const int64_t v = t0 + threadIdx.x;
+    int64_t claims = 0;
+    if (v < n) {
       uint8_t e = 0;
       if (keep[v]) {
-        VState s = vs[v];
-        int64_t wv = vw[v];
-        agg.add(s.c, -wv);
+        const VState s = vs[v];
+        const int64_t wv = vw[v];
+        claims += agg.add(s.c, -wv);
         if (s.d == D_EMPTY) {
           e = 1;
           atomicAdd(&ne, 1ull);
         } else {
           C[v] = s.d;
-          agg.add(s.d, wv);
+          claims += agg.add(s.d, wv);
         }
       }
       empty[v] = e;
     }
-    __syncthreads();
-    if (track_sq) dsq += agg.flush_sq(W); else agg.flush(W);
-    __syncthreads();
+    used += (int)sum_reduce<BLOCK>(claims);  // its barriers also complete this tile's table updates
+    if (used > AGG_FLUSH_AT) {
+      if (track_sq) dsq += agg.flush_sq(W); else agg.flush(W);
+      __syncthreads();
+      agg.clear();
+      __syncthreads();
+      used = 0;
+    }
   }
+  if (used) {
+    if (track_sq) dsq += agg.flush_sq(W); else agg.flush(W);
+  }
+  __syncthreads();
   if (threadIdx.x == 0 && ne) atomicAdd(stripe(S, CT_EMPTY), ne);
   if (track_sq) {
     dsq = sum_reduce<BLOCK>(dsq);
@@ -1224,19 +1239,23 @@ __global__ __launch_bounds__(BLOCK) void k_cluster_weights(const int32_t* C, con
   __shared__ int32_t ak[AGG_SLOTS];
   __shared__ unsigned long long av[AGG_SLOTS];
   LdsAgg<AGG_SLOTS> agg{ak, av};
-  constexpr int T = 2048;
-  for (int64_t t0 = (int64_t)blockIdx.x * T; t0 < n; t0 += (int64_t)gridDim.x * T) {
-    agg.clear();
-    __syncthreads();
-    for (int k = threadIdx.x; k < T; k += BLOCK) {
-      int64_t v = t0 + k;
-      if (v >= n) break;
-      agg.add(C[v], vw[v]);
+  agg.clear();
+  __syncthreads();
+  int used = 0;  // as in k_apply: flushed before the table could pass half full
+  for (int64_t t0 = (int64_t)blockIdx.x * APPLY_TILE; t0 < n; t0 += (int64_t)gridDim.x * APPLY_TILE) {
+    const int64_t v = t0 + threadIdx.x;
+    int64_t claims = 0;
+    if (v < n) claims = agg.add(C[v], vw[v]);
+    used += (int)sum_reduce<BLOCK>(claims);
+    if (used > AGG_FLUSH_AT) {
+      agg.flush(W);
+      __syncthreads();
+      agg.clear();
+      __syncthreads();
+      used = 0;
     }
-    __syncthreads();
-    agg.flush(W);
-    __syncthreads();
   }
+  if (used) agg.flush(W);
 }
 
 __global__ void k_copy_vw(const int64_t* vw, int64_t* W, int64_t n) {
@@ -1583,7 +1602,7 @@ void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st
 
 void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, hipStream_t st) {
   fill_i64(W, 0, n, st);
-  k_cluster_weights<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 2048), 4096)), BLOCK, 0, st>>>(C, vw, n, W);
+  k_cluster_weights<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 1024)), BLOCK, 0, st>>>(C, vw, n, W);
 }
 
 static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
@@ -1727,7 +1746,7 @@ static void apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs
                             int pass, bool track_sq, hipStream_t st) {
   const int64_t n = g.n;
   int64_t* sq = track_sq ? &slot->SW2[pass] : nullptr;
-  unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 4096));
+  unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 1024));
   k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass, b.stripes,
                                 track_sq ? 1 : 0);
   // the kept moves (afterburner or keep rule), the movers to a new singleton and the sum-of-squares change
