@@ -548,7 +548,18 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
   counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
 
-// One wavefront per vertex, LDS open-addressing hash of capacity pow2ceil(2 d) <= SLOTS.
+// Orders a wavefront's own LDS accesses around a phase change of its private table: every LDS operation of
+// the wavefront has completed (lgkmcnt 0) and the compiler moves no memory access across.  No other wavefront
+// is involved, so no workgroup barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), vmcnt and expcnt left at their maximum
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront per vertex, LDS open-addressing hash of capacity pow2ceil(2 d) <= SLOTS.  Every wavefront owns
+// its table and walks its own vertices: the wavefronts of a workgroup never wait for each other.
 template <int SLOTS>
 __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_t cnt, DevGraph g,
                                                      const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
@@ -560,38 +571,30 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
   counters_init(&bc);
   if (slot && slot->skip[pass]) return;
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-  for (int64_t base = (int64_t)blockIdx.x * (BLOCK / WAVE); base < cnt; base += (int64_t)gridDim.x * (BLOCK / WAVE)) {
-    const int64_t gid = base + wv;
-    const bool active = gid < cnt;
-    int32_t v = 0, cv = 0;
-    int64_t b = 0, e = 0, wvt = 0;
-    int bits = 1;
-    if (active) {
-      v = list[gid];
-      b = g.off[v];
-      e = g.off[v + 1];
-      cv = C[v];
-      wvt = g.vw[v];
-      bits = ceil_log2(2 * (e - b));
-      if (bits < 1) bits = 1;
-      for (int sl = lane; sl < (1 << bits); sl += WAVE) { hk[wv][sl] = -1; hv[wv][sl] = 0; }
+  int32_t* tk = hk[wv];
+  uint32_t* tv = hv[wv];
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / WAVE) + wv; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / WAVE)) {
+    const int32_t v = list[gid];
+    const int64_t b = g.off[v], e = g.off[v + 1];
+    const int32_t cv = C[v];
+    const int64_t wvt = g.vw[v];
+    int bits = ceil_log2(2 * (e - b));
+    if (bits < 1) bits = 1;
+    for (int sl = lane; sl < (1 << bits); sl += WAVE) { tk[sl] = -1; tv[sl] = 0; }
+    wave_lds_sync();
+    const int64_t own_reg = insert_row(g, C, b, e, lane, WAVE, cv, tk, tv, bits, ss.cons, ss.con(v));
+    wave_lds_sync();
+    const Score sc = ss.at(v);
+    Best r = best_init();
+    scan_table(tk, tv, 1 << bits, lane, WAVE, cv, wvt, W, sc, r);
+    r.own += own_reg;
+    best_reduce<WAVE>(r);
+    if (lane == 0) {
+      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
+      if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
     }
-    __syncthreads();
-    int64_t own_reg = 0;
-    if (active) own_reg = insert_row(g, C, b, e, lane, WAVE, cv, hk[wv], hv[wv], bits, ss.cons, ss.con(v));
-    __syncthreads();
-    if (active) {
-      const Score sc = ss.at(v);
-      Best r = best_init();
-      scan_table(hk[wv], hv[wv], 1 << bits, lane, WAVE, cv, wvt, W, sc, r);
-      r.own += own_reg;
-      best_reduce<WAVE>(r);
-      if (lane == 0) {
-        finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
-        if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
-      }
-    }
-    __syncthreads();
+    wave_lds_sync();  // the scan's reads are done before the next vertex clears the table
   }
   counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
