@@ -35,15 +35,65 @@ __device__ __forceinline__ bool better(int64_t s2, int32_t c2, int64_t s, int32_
   return s2 > s || (s2 == s && c2 < c);
 }
 
+// Partner of butterfly step K (K = 0, 1, ...) inside aligned groups of G lanes.  Groups of at most 16 lanes
+// use DPP lane moves (register to register, no LDS): two quad permutations (lane ^ 1, lane ^ 2), the row half
+// mirror (lane i of an 8-lane half-row <-> lane 7 - i) and the row mirror (i <-> 15 - i).  The mirror partners
+// are not xor partners, but each step pairs every lane with one in the other half of its 2^(K+1)-lane block,
+// whose lanes all hold the same value after the earlier steps: an all-reduction of a commutative and
+// associative operation gets the same result.  Wider groups use shuffles.
+constexpr int DPP_GROUP_STEP[4] = {0xB1, 0x4E, 0x141, 0x140};
+
+template <int G, int K>
+__device__ __forceinline__ int32_t gx32(int32_t x) {
+  if constexpr (G <= 16) return __builtin_amdgcn_update_dpp(0, x, DPP_GROUP_STEP[K], 0xf, 0xf, false);
+  else return __shfl_xor(x, 1 << K, G);
+}
+template <int G, int K>
+__device__ __forceinline__ int64_t gx64(int64_t x) {
+  if constexpr (G <= 16) {
+    const int32_t lo = gx32<G, K>((int32_t)(uint32_t)(uint64_t)x);
+    const int32_t hi = gx32<G, K>((int32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+  } else {
+    return __shfl_xor(x, 1 << K, G);
+  }
+}
+
+// Lane K of every aligned group of G lanes (G = 4: quad permutation; 8 and 16: row broadcasts; else shuffle).
+template <int G, int K>
+__device__ __forceinline__ int32_t gbcast32(int32_t x) {
+  if constexpr (G == 4) {
+    return __builtin_amdgcn_update_dpp(0, x, K | (K << 2) | (K << 4) | (K << 6), 0xf, 0xf, false);
+  } else if constexpr (G == 8) {
+    const int32_t lo = __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xf, 0xf, false);      // row_newbcast:K
+    const int32_t hi = __builtin_amdgcn_update_dpp(0, x, 0x150 + K + 8, 0xf, 0xf, false);  // row_newbcast:K+8
+    return (threadIdx.x & 8) ? hi : lo;
+  } else if constexpr (G == 16) {
+    return __builtin_amdgcn_update_dpp(0, x, 0x150 + K, 0xf, 0xf, false);
+  } else {
+    return __shfl(x, K, G);
+  }
+}
+
+template <int G, int K = 0>
+__device__ __forceinline__ void argmax_steps(int64_t& s, int32_t& c) {
+  if constexpr ((1 << K) < G) {
+    const int64_t s2 = gx64<G, K>(s);
+    const int32_t c2 = gx32<G, K>(c);
+    if (better(s2, c2, s, c)) { s = s2; c = c2; }
+    argmax_steps<G, K + 1>(s, c);
+  }
+}
+template <int G, int K = 0>
+__device__ __forceinline__ int64_t sum_steps(int64_t x) {
+  if constexpr ((1 << K) < G) return sum_steps<G, K + 1>(x + gx64<G, K>(x));
+  else return x;
+}
+
 template <int G>
 __device__ __forceinline__ void argmax_reduce(int64_t& s, int32_t& c) {
   if constexpr (G <= WAVE) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-      int64_t s2 = __shfl_xor(s, o, G);
-      int32_t c2 = __shfl_xor(c, o, G);
-      if (better(s2, c2, s, c)) { s = s2; c = c2; }
-    }
+    argmax_steps<G>(s, c);
   } else {
     __shared__ int64_t ss[G / WAVE];
     __shared__ int32_t cc[G / WAVE];
@@ -62,9 +112,7 @@ __device__ __forceinline__ void argmax_reduce(int64_t& s, int32_t& c) {
 template <int G>
 __device__ __forceinline__ int64_t sum_reduce(int64_t x) {
   if constexpr (G <= WAVE) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
-    return x;
+    return sum_steps<G>(x);
   } else {
     __shared__ int64_t ss[G / WAVE];
     x = sum_reduce<WAVE>(x);
@@ -294,17 +342,22 @@ __device__ __forceinline__ void scan_table(const int32_t* hk, const uint32_t* hv
 }
 
 // reduction of Best over G lanes (G <= 64) or a block of G threads; the result is valid in lane / thread 0
+template <int G, int K = 0>
+__device__ __forceinline__ void best_steps(Best& r) {
+  if constexpr ((1 << K) < G) {
+    const int64_t s2 = gx64<G, K>(r.s);
+    const int32_t c2 = gx32<G, K>(r.c);
+    r.own += gx64<G, K>(r.own);
+    r.np += gx64<G, K>(r.np);
+    if (better(s2, c2, r.s, r.c)) { r.s = s2; r.c = c2; }
+    best_steps<G, K + 1>(r);
+  }
+}
+
 template <int G>
 __device__ __forceinline__ void best_reduce(Best& r) {
   constexpr int WD = G < WAVE ? G : WAVE;
-#pragma unroll
-  for (int o = WD / 2; o > 0; o >>= 1) {
-    int64_t s2 = __shfl_xor(r.s, o, WD);
-    int32_t c2 = __shfl_xor(r.c, o, WD);
-    r.own += __shfl_xor(r.own, o, WD);
-    r.np += __shfl_xor(r.np, o, WD);
-    if (better(s2, c2, r.s, r.c)) { r.s = s2; r.c = c2; }
-  }
+  best_steps<WD>(r);
   if constexpr (G > WAVE) {
     __shared__ Best sb[G / WAVE];
     if ((threadIdx.x & (WAVE - 1)) == 0) sb[threadIdx.x / WAVE] = r;
@@ -500,7 +553,22 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_single_hub(const int32_t* hubs, c
 // General pass: enumerate neighbour clusters and take the argmax (Alg. 2 with DS = Enumerate(G, C))
 // ---------------------------------------------------------------------------------------------------------
 
-// degree <= G: lane l holds neighbour l; clusters aggregated by an all-pairs shuffle sweep of the group.
+// Every lane of the group sees every lane's (cluster, weight) in turn and sums the weights of its own cluster;
+// a lane stays leader when no earlier lane holds its cluster.
+template <int G, int K = 0>
+__device__ __forceinline__ void pair_sweep(int32_t c, int32_t wt, bool has, int gl, int64_t& acc, bool& leader) {
+  if constexpr (K < G) {
+    const int32_t ck = gbcast32<G, K>(c);
+    const int32_t wk = gbcast32<G, K>(wt);
+    if (has && ck == c) {
+      acc += wk;
+      if (K < gl) leader = false;
+    }
+    pair_sweep<G, K + 1>(c, wt, has, gl, acc, leader);
+  }
+}
+
+// degree <= G: lane l holds neighbour l; clusters aggregated by an all-pairs sweep of the group.
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t cnt, DevGraph g,
                                                     const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
@@ -521,18 +589,10 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
     const int32_t u = gl < d ? g.idx[b + gl] : -1;
     const bool has = u >= 0 && (!ss.cons || ss.cons[u] == ss.cons[v]);
     const int32_t c = has ? C[u] : -1;
-    const int64_t wt = has ? (int64_t)g.w[b + gl] : 0;
+    const int32_t wt = has ? g.w[b + gl] : 0;
     int64_t acc = 0;
     bool leader = has;
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      int32_t ck = __shfl(c, k, G);
-      int64_t wk = __shfl(wt, k, G);
-      if (has && ck == c) {
-        acc += wk;
-        if (k < gl) leader = false;
-      }
-    }
+    pair_sweep<G>(c, wt, has, gl, acc, leader);
     int64_t own = (leader && c == cv) ? acc : 0;
     int64_t bs = INT64_MIN;
     int32_t bcl = INT32_MAX;
@@ -943,8 +1003,10 @@ __global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, 
 // weights and sizes.  Movers to a new singleton take the ids left unused by all other moves, smallest first,
 // in ascending vertex order.
 // ---------------------------------------------------------------------------------------------------------
-constexpr int APPLY_TILE = BLOCK;  // vertices per workgroup tile (one per thread)
-constexpr int AGG_SLOTS = 2048;    // LDS aggregation table of the cluster-weight changes
+constexpr int APPLY_PER = 2;                   // vertices per thread and tile (their loads overlap)
+constexpr int APPLY_TILE = APPLY_PER * BLOCK;  // vertices per workgroup tile
+constexpr int AGG_SLOTS = 4096;                // LDS aggregation table of the cluster-weight changes
+constexpr int AGG_BLOCKS = 768;                // workgroups of the aggregating kernels (3 per CU fit the LDS)
 // The table keeps accumulating over a workgroup's tiles and is flushed only before it could pass half full (a
 // tile adds at most 2 APPLY_TILE keys): a heavy cluster then receives one global atomic per workgroup, not per
 // tile (same-address atomics serialise).
@@ -966,20 +1028,33 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
   __syncthreads();
   int used = 0;  // distinct keys in the table (uniform over the workgroup)
   for (int64_t t0 = (int64_t)blockIdx.x * APPLY_TILE; t0 < n; t0 += (int64_t)gridDim.x * APPLY_TILE) {
-    const int64_t v = t0 + threadIdx.x;
+    uint8_t kp[APPLY_PER];
+#pragma unroll
+    for (int k = 0; k < APPLY_PER; ++k) {
+      const int64_t v = t0 + k * BLOCK + threadIdx.x;
+      kp[k] = v < n ? keep[v] : 0;
+    }
+    VState sv[APPLY_PER];
+    int64_t wv[APPLY_PER];
+#pragma unroll
+    for (int k = 0; k < APPLY_PER; ++k) {
+      const int64_t v = t0 + k * BLOCK + threadIdx.x;
+      if (kp[k]) { sv[k] = vs[v]; wv[k] = vw[v]; }
+    }
     int64_t claims = 0;
-    if (v < n) {
+#pragma unroll
+    for (int k = 0; k < APPLY_PER; ++k) {
+      const int64_t v = t0 + k * BLOCK + threadIdx.x;
+      if (v >= n) continue;
       uint8_t e = 0;
-      if (keep[v]) {
-        const VState s = vs[v];
-        const int64_t wv = vw[v];
-        claims += agg.add(s.c, -wv);
-        if (s.d == D_EMPTY) {
+      if (kp[k]) {
+        claims += agg.add(sv[k].c, -wv[k]);
+        if (sv[k].d == D_EMPTY) {
           e = 1;
           atomicAdd(&ne, 1ull);
         } else {
-          C[v] = s.d;
-          claims += agg.add(s.d, wv);
+          C[v] = sv[k].d;
+          claims += agg.add(sv[k].d, wv[k]);
         }
       }
       empty[v] = e;
@@ -1239,18 +1314,29 @@ __global__ void k_assign_empty_seg(int64_t n, const uint8_t* empty, const int32_
 
 __global__ __launch_bounds__(BLOCK) void k_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n,
                                                            int64_t* W) {
+  constexpr int PER = 4, T = PER * BLOCK;  // one key per vertex: a tile adds at most T keys
+  static_assert(AGG_SLOTS / 2 - T >= 0, "the table must hold the keys of a tile");
   __shared__ int32_t ak[AGG_SLOTS];
   __shared__ unsigned long long av[AGG_SLOTS];
   LdsAgg<AGG_SLOTS> agg{ak, av};
   agg.clear();
   __syncthreads();
   int used = 0;  // as in k_apply: flushed before the table could pass half full
-  for (int64_t t0 = (int64_t)blockIdx.x * APPLY_TILE; t0 < n; t0 += (int64_t)gridDim.x * APPLY_TILE) {
-    const int64_t v = t0 + threadIdx.x;
+  for (int64_t t0 = (int64_t)blockIdx.x * T; t0 < n; t0 += (int64_t)gridDim.x * T) {
+    int32_t c[PER];
+    int64_t w[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int64_t v = t0 + k * BLOCK + threadIdx.x;
+      c[k] = v < n ? C[v] : -1;
+      w[k] = v < n ? vw[v] : 0;
+    }
     int64_t claims = 0;
-    if (v < n) claims = agg.add(C[v], vw[v]);
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (c[k] >= 0) claims += agg.add(c[k], w[k]);
     used += (int)sum_reduce<BLOCK>(claims);
-    if (used > AGG_FLUSH_AT) {
+    if (used > AGG_SLOTS / 2 - T) {
       agg.flush(W);
       __syncthreads();
       agg.clear();
@@ -1494,21 +1580,37 @@ __global__ void k_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl) {
   }
 }
 
-// Adds the stripes of every counter that has a destination into it and clears those stripes.
 struct FoldDst {
   int64_t* d[CT_COUNT];
 };
+
+// Adds the stripes of every counter that has a destination into it and clears those stripes.  Thread t reads
+// and clears stripe t whole (one 128-byte row), so every load is issued up front; one workgroup reduction
+// covers all counters.
 __global__ __launch_bounds__(1024) void k_fold(int64_t* S, FoldDst f) {
+  static_assert(NSTRIPE == 1024 && STRIPE_W == 16 && CT_COUNT <= STRIPE_W, "one stripe row per thread");
+  __shared__ int64_t part[1024 / WAVE][CT_COUNT];
+  int64_t* row = S + (int64_t)threadIdx.x * STRIPE_W;
+  int64_t x[CT_COUNT];
+#pragma unroll
+  for (int ct = 0; ct < CT_COUNT; ++ct) x[ct] = f.d[ct] ? row[ct] : 0;
+#pragma unroll
+  for (int ct = 0; ct < CT_COUNT; ++ct)
+    if (f.d[ct]) row[ct] = 0;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+#pragma unroll
   for (int ct = 0; ct < CT_COUNT; ++ct) {
-    if (!f.d[ct]) continue;  // uniform over the workgroup
-    int64_t x = 0;
-    for (int s = threadIdx.x; s < NSTRIPE; s += 1024) {
-      int64_t* p = &S[(int64_t)s * STRIPE_W + ct];
-      x += *p;
-      *p = 0;
-    }
-    x = sum_reduce<1024>(x);
-    if (threadIdx.x == 0 && x) *f.d[ct] += x;
+    int64_t v = x[ct];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    if (lane == 0) part[wv][ct] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < CT_COUNT && f.d[threadIdx.x]) {
+    int64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < 1024 / WAVE; ++k) t += part[k][threadIdx.x];
+    if (t) *f.d[threadIdx.x] += t;
   }
 }
 
@@ -1605,7 +1707,7 @@ void launch_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl, hipStream_t st
 
 void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, hipStream_t st) {
   fill_i64(W, 0, n, st);
-  k_cluster_weights<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 1024)), BLOCK, 0, st>>>(C, vw, n, W);
+  k_cluster_weights<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 4 * BLOCK), AGG_BLOCKS)), BLOCK, 0, st>>>(C, vw, n, W);
 }
 
 static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
@@ -1749,7 +1851,7 @@ static void apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs
                             int pass, bool track_sq, hipStream_t st) {
   const int64_t n = g.n;
   int64_t* sq = track_sq ? &slot->SW2[pass] : nullptr;
-  unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), 1024));
+  unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), AGG_BLOCKS));
   k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass, b.stripes,
                                 track_sq ? 1 : 0);
   // the kept moves (afterburner or keep rule), the movers to a new singleton and the sum-of-squares change
