@@ -15,19 +15,19 @@ constexpr int NBUCKET = 8;
 constexpr int MAX_PASSES = 32;
 // Per-workgroup counter partials.  Thousands of workgroups each adding a partial to one global address
 // serialise on that address (about 12 ns per atomic on MI355X, so 4096 workgroups cost about 50 us); workgroup
-// b adds instead into stripe b mod NSTRIPE of the counter (stripes 128 bytes apart), and a one-workgroup fold
-// kernel adds the stripes of each counter into its destination and clears them.
+// b adds instead into stripe b mod NSTRIPE of the counter (stripes 128 bytes apart), and one workgroup later
+// adds the stripes of each counter into its destination and clears them (a fold kernel, or the prologue of
+// the next single-workgroup bookkeeping kernel of the local move).
 constexpr int NSTRIPE = 1024;
 constexpr int STRIPE_W = 16;  // int64 slots per stripe, one per counter id
 enum : int {
-  CT_NCAND = 0,   // candidates of a pass
-  CT_OWN = 1,     // sum of own-cluster weights
-  CT_PAIRS = 2,   // CT_PAIRS + bucket: enumerated (vertex, other cluster) pairs
-  CT_NM = 10,     // kept moves
-  CT_EMPTY = 11,  // movers to a new singleton
-  CT_SQ = 12,     // change of the sum of squared cluster weights
-  CT_INT = 13,    // internal edge weight
-  CT_COUNT = 14
+  CT_NCAND = 0,  // candidates of a pass
+  CT_OWN = 1,    // sum of own-cluster weights
+  CT_PAIRS = 2,  // CT_PAIRS + bucket: enumerated (vertex, other cluster) pairs
+  CT_NM = 10,    // kept moves
+  CT_SQ = 11,    // change of the sum of squared cluster weights
+  CT_INT = 12,   // internal edge weight
+  CT_COUNT = 13
 };
 constexpr int32_t D_NONE = -1;   // no destination
 constexpr int32_t D_EMPTY = -2;  // destination = a new singleton cluster

@@ -179,6 +179,43 @@ __device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* S, in
   }
 }
 
+// Destinations of the counters a fold adds up (null: not folded; its stripes stay as they are).
+struct FoldDst {
+  int64_t* d[CT_COUNT];
+};
+
+// Adds the stripes of every counter that has a destination into it and clears those stripes; run by one
+// workgroup of 1024 threads.  Thread t reads and clears stripe t whole (one 128-byte row), so every load is
+// issued up front; one workgroup reduction covers all counters.  Ends with a barrier: the destinations are
+// final for every thread afterwards.
+__device__ __forceinline__ void fold_block(int64_t* S, const FoldDst& f) {
+  static_assert(NSTRIPE == 1024 && STRIPE_W == 16 && CT_COUNT <= STRIPE_W, "one stripe row per thread");
+  __shared__ int64_t part[1024 / WAVE][CT_COUNT];
+  int64_t* row = S + (int64_t)threadIdx.x * STRIPE_W;
+  int64_t x[CT_COUNT];
+#pragma unroll
+  for (int ct = 0; ct < CT_COUNT; ++ct) x[ct] = f.d[ct] ? row[ct] : 0;
+#pragma unroll
+  for (int ct = 0; ct < CT_COUNT; ++ct)
+    if (f.d[ct]) row[ct] = 0;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int ct = 0; ct < CT_COUNT; ++ct) {
+    int64_t v = x[ct];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    if (lane == 0) part[wv][ct] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < CT_COUNT && f.d[threadIdx.x]) {
+    int64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < 1024 / WAVE; ++k) t += part[k][threadIdx.x];
+    if (t) *f.d[threadIdx.x] += t;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void finish_vertex(int32_t v, int32_t cv, int64_t wv, int64_t own, int64_t sbest,
                                               int32_t cbest, const Score& sc, const int64_t* W, uint32_t pa,
                                               uint32_t pb, int strict, VState* vs, BlockCounters* bc,
@@ -437,8 +474,10 @@ __device__ __forceinline__ int64_t internal_row(const DevGraph& g, const int32_t
 
 // Start of pass i: decide whether it repeats pass i-1 exactly (pass i-1 moved nothing and the temperature
 // is unchanged), and reset the pass counters.
-__global__ void k_pass_begin(LMSlot* s, int i, int same_phi) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Launched with one workgroup of 1024 threads: first folds the counters the previous pass left in the stripes.
+__global__ __launch_bounds__(1024) void k_pass_begin(LMSlot* s, int i, int same_phi, int64_t* S, FoldDst f) {
+  fold_block(S, f);
+  if (threadIdx.x != 0) return;
   s->copy = 0;
   s->n_empty = 0;
   if (i >= 2 && same_phi && s->nM[i - 1] == 0) {
@@ -458,8 +497,11 @@ __global__ void k_pass_begin(LMSlot* s, int i, int same_phi) {
 
 // Best-so-far check of state k (Alg. 2: C_out <- C when lambdaCC(C) > lambdaCC(C_out)).  Skipped when state
 // k equals state k-1, which was checked already.
-__global__ void k_best(LMSlot* s, int k, int skipk, int64_t p, int64_t q, int64_t sum_w2) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One workgroup of 1024 threads: first folds the counters the state's sums are waiting for.
+__global__ __launch_bounds__(1024) void k_best(LMSlot* s, int k, int skipk, int64_t p, int64_t q, int64_t sum_w2,
+                                               int64_t* S, FoldDst f) {
+  fold_block(S, f);
+  if (threadIdx.x != 0) return;
   s->copy = 0;
   if (skipk >= 0 && s->skip[skipk]) return;
   int64_t N = q * s->I[k] - p * (s->SW2[k] - sum_w2);
@@ -478,8 +520,10 @@ __global__ void k_copy_if(const LMSlot* s, const int32_t* C, int32_t* Cout, int6
     Cout[i] = C[i];
 }
 
-__global__ void k_final_state(LMSlot* s, int last) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One workgroup of 1024 threads: first folds the counters of the last pass.
+__global__ __launch_bounds__(1024) void k_final_state(LMSlot* s, int last, int64_t* S, FoldDst f) {
+  fold_block(S, f);
+  if (threadIdx.x != 0) return;
   if (s->skip[last]) s->I[last] = s->I[last - 1];
   else s->I[last] = 0;
 }
@@ -1013,7 +1057,8 @@ constexpr int AGG_BLOCKS = 768;                // workgroups of the aggregating 
 constexpr int AGG_FLUSH_AT = AGG_SLOTS / 2 - 2 * APPLY_TILE;
 static_assert(AGG_FLUSH_AT >= 0, "the table must hold the keys of a tile");
 
-// sq (optional) receives the change of sum_c W_c^2 made by the moves (a single graph's state bookkeeping).
+// sq (optional) receives the change of sum_c W_c^2 made by the moves (a single graph's state bookkeeping);
+// slot->n_empty becomes nonzero when some kept move goes to a new singleton.
 __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep, const VState* vs,
                                                  const int64_t* vw, int32_t* C, int64_t* W, uint8_t* empty,
                                                  LMSlot* slot, int pass, int64_t* S, int track_sq) {
@@ -1072,7 +1117,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
     if (track_sq) dsq += agg.flush_sq(W); else agg.flush(W);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && ne) atomicAdd(stripe(S, CT_EMPTY), ne);
+  if (threadIdx.x == 0 && ne && slot) slot->n_empty = 1;  // consumers only test it against zero
   if (track_sq) {
     dsq = sum_reduce<BLOCK>(dsq);
     if (threadIdx.x == 0 && dsq) atomicAdd(stripe(S, CT_SQ), (unsigned long long)dsq);
@@ -1580,39 +1625,7 @@ __global__ void k_vertex_sums(const int64_t* vw, int64_t n, Ctrl* ctrl) {
   }
 }
 
-struct FoldDst {
-  int64_t* d[CT_COUNT];
-};
-
-// Adds the stripes of every counter that has a destination into it and clears those stripes.  Thread t reads
-// and clears stripe t whole (one 128-byte row), so every load is issued up front; one workgroup reduction
-// covers all counters.
-__global__ __launch_bounds__(1024) void k_fold(int64_t* S, FoldDst f) {
-  static_assert(NSTRIPE == 1024 && STRIPE_W == 16 && CT_COUNT <= STRIPE_W, "one stripe row per thread");
-  __shared__ int64_t part[1024 / WAVE][CT_COUNT];
-  int64_t* row = S + (int64_t)threadIdx.x * STRIPE_W;
-  int64_t x[CT_COUNT];
-#pragma unroll
-  for (int ct = 0; ct < CT_COUNT; ++ct) x[ct] = f.d[ct] ? row[ct] : 0;
-#pragma unroll
-  for (int ct = 0; ct < CT_COUNT; ++ct)
-    if (f.d[ct]) row[ct] = 0;
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-#pragma unroll
-  for (int ct = 0; ct < CT_COUNT; ++ct) {
-    int64_t v = x[ct];
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    if (lane == 0) part[wv][ct] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < CT_COUNT && f.d[threadIdx.x]) {
-    int64_t t = 0;
-#pragma unroll
-    for (int k = 0; k < 1024 / WAVE; ++k) t += part[k][threadIdx.x];
-    if (t) *f.d[threadIdx.x] += t;
-  }
-}
+__global__ __launch_bounds__(1024) void k_fold(int64_t* S, FoldDst f) { fold_block(S, f); }
 
 inline unsigned grid_for(int64_t n) {
   int64_t g = cdiv(n, BLOCK);
@@ -1640,13 +1653,20 @@ inline unsigned vtx_blocks(const Buckets& b, int64_t cnt, int64_t cap_div = 1) {
 // persistent workgroups of a single-pass scan over nt tiles
 inline unsigned lb_blocks(uint32_t nt) { return (unsigned)std::max<uint32_t>(1, std::min<uint32_t>(nt, 1024)); }
 
-// fold the listed counters (id, destination; a null destination folds nothing) of the stripes S
-void fold(int64_t* S, std::initializer_list<std::pair<int, int64_t*>> m, hipStream_t st) {
+// Fold the listed counters (id, destination; a null destination folds nothing) of the stripes S: now, with a
+// fold kernel, or, when `pending` is given, by the next bookkeeping kernel (k_pass_begin, k_best or
+// k_final_state), which folds its FoldDst before anything reads the destinations.
+void fold(int64_t* S, std::initializer_list<std::pair<int, int64_t*>> m, hipStream_t st, FoldDst* pending = nullptr) {
   FoldDst f{};
   bool any = false;
   for (const auto& e : m)
     if (e.second) { f.d[e.first] = e.second; any = true; }
-  if (any) k_fold<<<1, 1024, 0, st>>>(S, f);
+  if (pending) {
+    for (int ct = 0; ct < CT_COUNT; ++ct)
+      if (f.d[ct]) pending->d[ct] = f.d[ct];
+  } else if (any) {
+    k_fold<<<1, 1024, 0, st>>>(S, f);
+  }
 }
 
 // Hub chunk scratch lives at the end of the per-chunk partial arrays.
@@ -1711,7 +1731,8 @@ void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int6
 }
 
 static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
-                            const int32_t* skip, hipStream_t st, int64_t* per_v = nullptr) {
+                            const int32_t* skip, hipStream_t st, int64_t* per_v = nullptr,
+                            FoldDst* pending = nullptr) {
   const int32_t* L = b.list;
   int64_t* S = b.stripes;
   if (b.count[0]) k_internal_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, S, skip, per_v);
@@ -1725,7 +1746,7 @@ static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* 
     if (per_v) k_zero_listed<<<grid_for(b.count[7]), BLOCK, 0, st>>>(L + b.off[7], b.count[7], per_v, skip);
     k_internal_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L + b.off[7], b.hub_chunk_off, b.count[7], g, C, S, skip, per_v);
   }
-  if (!per_v) fold(S, {{CT_INT, out}}, st);
+  if (!per_v) fold(S, {{CT_INT, out}}, st, pending);
 }
 
 void launch_internal_per_vertex(const DevGraph& g, const Buckets& b, const int32_t* C, int64_t* out,
@@ -1753,7 +1774,8 @@ static HubScratch hub_scratch(const Buckets& b);
 // One pass of destinations + candidacy.  singleton: first coarsening pass (C = identity).
 static void launch_destinations(const DevGraph& g, const Buckets& b, const ScoreSrc& sc, uint32_t pa, uint32_t pb,
                                 int strict, bool singleton, LMBuffers& bufs, LMSlot* slot, int pass,
-                                int64_t* own_sum, const HubScratch& hs, hipStream_t st) {
+                                int64_t* own_sum, const HubScratch& hs, hipStream_t st,
+                                FoldDst* pending = nullptr) {
   const int32_t* L = b.list;
   const int32_t* C = bufs.C;
   const int64_t* W = bufs.W;
@@ -1778,7 +1800,7 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
                                                  hs.ps, hs.pc, nullptr, vs, slot, pass, S, -1);
     }
     prof_end(PF_SINGLE, sb, st);
-    fold(S, {{CT_NCAND, &slot->nL[pass]}}, st);
+    fold(S, {{CT_NCAND, &slot->nL[pass]}}, st, pending);
     return;
   }
   int64_t* P = strict ? nullptr : bufs.pairs;  // distinct-pair counters (diagnostics), per bucket
@@ -1812,7 +1834,7 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   fold(S, {{CT_NCAND, slot ? &slot->nL[pass] : nullptr}, {CT_OWN, own_sum}, {CT_PAIRS + 0, P ? P + 0 : nullptr},
            {CT_PAIRS + 1, P ? P + 1 : nullptr}, {CT_PAIRS + 2, P ? P + 2 : nullptr}, {CT_PAIRS + 3, P ? P + 3 : nullptr},
            {CT_PAIRS + 4, P ? P + 4 : nullptr}, {CT_PAIRS + 5, P ? P + 5 : nullptr}, {CT_PAIRS + 6, P ? P + 6 : nullptr},
-           {CT_PAIRS + 7, P ? P + 7 : nullptr}}, st);
+           {CT_PAIRS + 7, P ? P + 7 : nullptr}}, st, pending);
 }
 
 static const int32_t* L_hubs(const Buckets& b) { return b.list + b.off[7]; }
@@ -1848,15 +1870,14 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const ScoreS
 // track_sq: keep slot->SW2[pass] (set to the previous state's value by k_pass_begin) up to date from the
 // moves instead of recomputing it from all cluster weights
 static void apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, const SegLM& sg, LMSlot* slot,
-                            int pass, bool track_sq, hipStream_t st) {
+                            int pass, bool track_sq, hipStream_t st, FoldDst* pending = nullptr) {
   const int64_t n = g.n;
   int64_t* sq = track_sq ? &slot->SW2[pass] : nullptr;
   unsigned ga = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, APPLY_TILE), AGG_BLOCKS));
   k_apply<<<ga, BLOCK, 0, st>>>(n, bufs.keep, bufs.vs, g.vw, bufs.C, bufs.W, bufs.empty, slot, pass, b.stripes,
                                 track_sq ? 1 : 0);
-  // the kept moves (afterburner or keep rule), the movers to a new singleton and the sum-of-squares change
-  fold(b.stripes, {{CT_NM, slot ? &slot->nM[pass] : nullptr}, {CT_EMPTY, slot ? &slot->n_empty : nullptr}, {CT_SQ, sq}},
-       st);
+  // the kept moves (afterburner or keep rule) and the sum-of-squares change
+  fold(b.stripes, {{CT_NM, slot ? &slot->nM[pass] : nullptr}, {CT_SQ, sq}}, st, pending);
   // free ids and ranks of the movers to a new singleton; all no-ops unless some vertex moved to a new
   // singleton in this pass
   Tagged& tg = *bufs.tg;
@@ -1886,13 +1907,19 @@ static void state_sums_sw2(const SegLM& sg, const int64_t* W, int64_t n, LMSlot*
   }
 }
 
+// pend: counters still in the stripes that this check's sums need (folded here, then cleared)
 static void best_so_far(const SegLM& sg, LMSlot* slot, const LMParams& prm, LMBuffers& bufs, int64_t n, int k,
-                        int skipk, hipStream_t st) {
+                        int skipk, hipStream_t st, int64_t* S, FoldDst& pend) {
   if (sg.G) {
+    bool any = false;
+    for (int ct = 0; ct < CT_COUNT; ++ct) any = any || pend.d[ct];
+    if (any) k_fold<<<1, 1024, 0, st>>>(S, pend);
+    pend = FoldDst{};
     k_best_seg<<<grid_for(sg.G), BLOCK, 0, st>>>(sg, slot, k, skipk);
     if (k > 0) k_copy_if_seg<<<grid_for(n), BLOCK, 0, st>>>(sg.copy, sg.gid, bufs.C, bufs.Cout, n);
   } else {
-    k_best<<<1, 1, 0, st>>>(slot, k, skipk, prm.sc.p, prm.sc.q, prm.sum_w2);
+    k_best<<<1, 1024, 0, st>>>(slot, k, skipk, prm.sc.p, prm.sc.q, prm.sum_w2, S, pend);
+    pend = FoldDst{};
     if (k > 0) k_copy_if<<<grid_for(n), BLOCK, 0, st>>>(slot, bufs.C, bufs.Cout, n);
   }
 }
@@ -1925,20 +1952,26 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
   if (b.count[7])
     k_hub_clear<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L_hubs(b), b.hub_chunk_off, b.count[7], g.off,
                                                              bufs.arena, nullptr, -1);
+  // Counters the kernels leave in the stripes are folded by the next bookkeeping kernel of a single graph
+  // (no launch of their own); a union folds them at once.
+  int64_t* S = b.stripes;
+  FoldDst pend{};
+  FoldDst* pp = G ? nullptr : &pend;
   for (int i = 1; i <= prm.pass_limit; ++i) {
     // a pass that kept no move repeats exactly when the next one has the same temperature (and, under the
     // minimum label heuristic, never: its rule alternates between passes)
     int same_phi = i >= 2 && prm.phi_num[i] == prm.phi_num[i - 1] && prm.phi_den[i] == prm.phi_den[i - 1] &&
                    prm.symmetry != 2;
-    k_pass_begin<<<1, 1, 0, st>>>(slot, i, same_phi);
+    k_pass_begin<<<1, 1024, 0, st>>>(slot, i, same_phi, S, pend);
+    pend = FoldDst{};
     bool single_now = singleton && i == 1;
     launch_destinations(g, b, sc, prm.phi_num[i], prm.phi_den[i], 0, single_now, bufs, slot, i,
-                        &slot->I[i - 1], hs, st);
+                        &slot->I[i - 1], hs, st, pp);
     if (G)  // internal weight of state i-1 per graph, from the own-cluster weights the pass just summed
       k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(sg.ownv, 0, sg.vbase, G, sg.I + (int64_t)(i - 1) * G,
                                                 i >= 2 ? sg.I + (int64_t)(i - 2) * G : nullptr, slot, i);
     // best-so-far check of the state this pass started from (state i-1)
-    best_so_far(sg, slot, prm, bufs, n, i - 1, i, st);
+    best_so_far(sg, slot, prm, bufs, n, i - 1, i, st, S, pend);
     if (prm.symmetry == 0) {
       launch_afterburner(g, b, sc, bufs, slot, i, hs, st);
     } else {
@@ -1946,22 +1979,23 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
       k_keep_rule<<<red_blocks(nl), BLOCK, 0, st>>>(b.list, nl, bufs.vs, prm.symmetry, i, bufs.keep, slot,
                                                     b.stripes);
     }
-    apply_and_empty(g, b, bufs, sg, slot, i, G == 0, st);
+    apply_and_empty(g, b, bufs, sg, slot, i, G == 0, st, pp);
     state_sums_sw2(sg, bufs.W, n, slot, i, i, st);
   }
   const int last = prm.pass_limit;
   if (last >= 1) {
-    k_final_state<<<1, 1, 0, st>>>(slot, last);
+    k_final_state<<<1, 1024, 0, st>>>(slot, last, S, pend);
+    pend = FoldDst{};
     if (G) {
       launch_internal(g, b, bufs.C, nullptr, &slot->skip[last], st, sg.ownv);
       k_seg_sum<<<seg_blocks(G), BLOCK, 0, st>>>(sg.ownv, 0, sg.vbase, G, sg.I + (int64_t)last * G,
                                                 sg.I + (int64_t)(last - 1) * G, slot, last);
     } else {
-      launch_internal(g, b, bufs.C, &slot->I[last], &slot->skip[last], st);
+      launch_internal(g, b, bufs.C, &slot->I[last], &slot->skip[last], st, nullptr, &pend);
     }
-    best_so_far(sg, slot, prm, bufs, n, last, last, st);
+    best_so_far(sg, slot, prm, bufs, n, last, last, st, S, pend);
   } else {
-    best_so_far(sg, slot, prm, bufs, n, 0, -1, st);
+    best_so_far(sg, slot, prm, bufs, n, 0, -1, st, S, pend);
   }
 }
 
