@@ -197,13 +197,15 @@ __device__ __forceinline__ void fold_block(int64_t* S, const FoldDst& f) {
   for (int ct = 0; ct < CT_COUNT; ++ct) x[ct] = f.d[ct] ? row[ct] : 0;
 #pragma unroll
   for (int ct = 0; ct < CT_COUNT; ++ct)
-    if (f.d[ct]) row[ct] = 0;
+    if (x[ct]) row[ct] = 0;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
 #pragma unroll
   for (int ct = 0; ct < CT_COUNT; ++ct) {
     int64_t v = x[ct];
+    if (__ballot(v != 0)) {  // stripes past the launches' workgroup counts are zero: most wavefronts skip
 #pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+      for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    }
     if (lane == 0) part[wv][ct] = v;
   }
   __syncthreads();
