@@ -185,35 +185,51 @@ struct FoldDst {
 };
 
 // Adds the stripes of every counter that has a destination into it and clears those stripes; run by one
-// workgroup of 1024 threads.  Thread t reads and clears stripe t whole (one 128-byte row), so every load is
-// issued up front; one workgroup reduction covers all counters.  Ends with a barrier: the destinations are
-// final for every thread afterwards.
+// workgroup of 1024 threads.  The stripes are read as 8192 pieces of 16 bytes, thread t taking pieces t,
+// t + 1024, ..., t + 7168: every load instruction of a wavefront covers 1 KB of consecutive bytes, and piece p
+// holds counters 2 (p mod 8) and 2 (p mod 8) + 1 of stripe p / 8, so a thread always sees the same two
+// counters.  Ends with a barrier: the destinations are final for every thread afterwards.
 __device__ __forceinline__ void fold_block(int64_t* S, const FoldDst& f) {
-  static_assert(NSTRIPE == 1024 && STRIPE_W == 16 && CT_COUNT <= STRIPE_W, "one stripe row per thread");
-  __shared__ int64_t part[1024 / WAVE][CT_COUNT];
-  int64_t* row = S + (int64_t)threadIdx.x * STRIPE_W;
-  int64_t x[CT_COUNT];
+  static_assert(NSTRIPE == 1024 && STRIPE_W == 16 && CT_COUNT <= STRIPE_W, "8 pieces per stripe, 8 per thread");
+  __shared__ int64_t part[1024 / WAVE][STRIPE_W];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+  const int c0 = 2 * (t & 7), c1 = c0 + 1;
+  const bool f0 = c0 < CT_COUNT && f.d[c0], f1 = c1 < CT_COUNT && f.d[c1];
+  int64_t a0 = 0, a1 = 0;
+  if (f0 || f1) {
+    longlong2* P = (longlong2*)S;
+    longlong2 v[8];
 #pragma unroll
-  for (int ct = 0; ct < CT_COUNT; ++ct) x[ct] = f.d[ct] ? row[ct] : 0;
+    for (int k = 0; k < 8; ++k) v[k] = P[t + 1024 * k];
 #pragma unroll
-  for (int ct = 0; ct < CT_COUNT; ++ct)
-    if (x[ct]) row[ct] = 0;
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-#pragma unroll
-  for (int ct = 0; ct < CT_COUNT; ++ct) {
-    int64_t v = x[ct];
-    if (__ballot(v != 0)) {  // stripes past the launches' workgroup counts are zero: most wavefronts skip
-#pragma unroll
-      for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    for (int k = 0; k < 8; ++k) {
+      if (f0) a0 += v[k].x;
+      if (f1) a1 += v[k].y;
     }
-    if (lane == 0) part[wv][ct] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < CT_COUNT && f.d[threadIdx.x]) {
-    int64_t t = 0;
 #pragma unroll
-    for (int k = 0; k < 1024 / WAVE; ++k) t += part[k][threadIdx.x];
-    if (t) *f.d[threadIdx.x] += t;
+    for (int k = 0; k < 8; ++k) {
+      if ((f0 && v[k].x) || (f1 && v[k].y)) {
+        longlong2 z = v[k];
+        if (f0) z.x = 0;
+        if (f1) z.y = 0;
+        P[t + 1024 * k] = z;
+      }
+    }
+  }
+  if (__ballot(a0 != 0 || a1 != 0)) {  // stripes past the launches' workgroup counts are zero: most skip
+#pragma unroll
+    for (int o = 8; o < WAVE; o <<= 1) {  // lanes with equal t mod 8 hold the same two counters
+      a0 += __shfl_xor(a0, o, WAVE);
+      a1 += __shfl_xor(a1, o, WAVE);
+    }
+  }
+  if (lane < 8) { part[wv][c0] = a0; part[wv][c1] = a1; }
+  __syncthreads();
+  if (t < CT_COUNT && f.d[t]) {
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 1024 / WAVE; ++k) s += part[k][t];
+    if (s) *f.d[t] += s;
   }
   __syncthreads();
 }
