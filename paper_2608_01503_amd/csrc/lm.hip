@@ -1757,8 +1757,8 @@ static void launch_internal(const DevGraph& g, const Buckets& b, const int32_t* 
   if (b.count[1]) k_internal_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, S, skip, per_v);
   if (b.count[2]) k_internal_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, S, skip, per_v);
   if (b.count[3]) k_internal_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, S, skip, per_v);
-  int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_internal_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, C, S, skip, per_v);
+  if (b.count[4]) k_internal_grp<32><<<grp_blocks(b, b.count[4], 32), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, S, skip, per_v);
+  if (b.count[5]) k_internal_grp<64><<<grp_blocks(b, b.count[5], 64), BLOCK, 0, st>>>(L + b.off[5], b.count[5], g, C, S, skip, per_v);
   if (b.count[6]) k_internal_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, C, S, skip, per_v);
   if (b.count[7]) {
     if (per_v) k_zero_listed<<<grid_for(b.count[7]), BLOCK, 0, st>>>(L + b.off[7], b.count[7], per_v, skip);
@@ -1809,8 +1809,8 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
     if (b.count[1]) k_single_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, sc, pa, pb, vs, slot, pass, S);
     if (b.count[2]) k_single_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, sc, pa, pb, vs, slot, pass, S);
     if (b.count[3]) k_single_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, sc, pa, pb, vs, slot, pass, S);
-    int64_t nw = b.count[4] + b.count[5];
-    if (nw) k_single_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, sc, pa, pb, vs, slot, pass, S);
+    if (b.count[4]) k_single_grp<32><<<grp_blocks(b, b.count[4], 32), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, sc, pa, pb, vs, slot, pass, S);
+    if (b.count[5]) k_single_grp<64><<<grp_blocks(b, b.count[5], 64), BLOCK, 0, st>>>(L + b.off[5], b.count[5], g, sc, pa, pb, vs, slot, pass, S);
     if (b.count[6]) k_single_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, sc, pa, pb, vs, slot, pass, S);
     if (n7) {
       k_single_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, sc, hs.ps, hs.pc);
@@ -1875,8 +1875,9 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const ScoreS
   if (b.count[1]) k_ab_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vs, sc, keep, slot, pass, b.stripes);
   if (b.count[2]) k_ab_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vs, sc, keep, slot, pass, b.stripes);
   if (b.count[3]) k_ab_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass, b.stripes);
-  int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_ab_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vs, sc, keep, slot, pass, b.stripes);
+  // degree 33-128 rows in half-wavefront groups (one pass of U = 4 loads covers them), longer ones per wavefront
+  if (b.count[4]) k_ab_grp<32><<<grp_blocks(b, b.count[4], 32), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, vs, sc, keep, slot, pass, b.stripes);
+  if (b.count[5]) k_ab_grp<64><<<grp_blocks(b, b.count[5], 64), BLOCK, 0, st>>>(L + b.off[5], b.count[5], g, vs, sc, keep, slot, pass, b.stripes);
   if (b.count[6]) k_ab_blk<BIG_BLOCK><<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vs, sc, keep, slot, pass, b.stripes);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
