@@ -1075,6 +1075,66 @@ constexpr int AGG_BLOCKS = 768;                // workgroups of the aggregating 
 constexpr int AGG_FLUSH_AT = AGG_SLOTS / 2 - 2 * APPLY_TILE;
 static_assert(AGG_FLUSH_AT >= 0, "the table must hold the keys of a tile");
 
+// LDS aggregation table that also lists its occupied slots: a flush visits only those and leaves the table
+// empty behind it, so neither the flush nor the next tile pays for the whole table.
+struct AggList {
+  int32_t* keys;
+  unsigned long long* vals;
+  uint16_t* used;  // occupied slots, in claim order (the table stays at most half full)
+  int* nused;
+  __device__ __forceinline__ void clear_all() {
+    for (int s = threadIdx.x; s < AGG_SLOTS; s += blockDim.x) { keys[s] = -1; vals[s] = 0; }
+    if (threadIdx.x == 0) *nused = 0;
+  }
+  // Adds v to key k when act; called by every lane of a converged wavefront.  Returns 1 when k took a new
+  // slot; the new slots of the wavefront are appended to the list with one LDS atomic.
+  __device__ __forceinline__ int add(bool act, int32_t k, int64_t v) {
+    int claimed = 0;
+    uint32_t h = 0;
+    if (act) {
+      h = ((uint32_t)k * 2654435761u) & (AGG_SLOTS - 1);
+      for (int probe = 0; probe < AGG_SLOTS; ++probe) {
+        const int32_t prev = atomicCAS(&keys[h], -1, k);
+        if (prev == -1 || prev == k) {
+          atomicAdd(&vals[h], (unsigned long long)v);
+          claimed = prev == -1;
+          break;
+        }
+        h = (h + 1) & (AGG_SLOTS - 1);
+      }
+    }
+    const uint64_t m = __ballot(claimed);
+    if (m) {
+      const int lane = threadIdx.x & (WAVE - 1);
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(nused, __popcll(m));
+      base = __shfl(base, leader, WAVE);
+      if (claimed) used[base + __popcll(m & ((1ull << lane) - 1))] = (uint16_t)h;
+    }
+    return claimed;
+  }
+  // Adds every listed entry into out (sq: also returns this thread's share of the change of the sum of
+  // squares, as LdsAgg::flush_sq) and empties those slots.  Call between workgroup barriers; the caller then
+  // resets the list count.
+  __device__ __forceinline__ int64_t flush(int64_t* out, bool sq) {
+    const int n = *nused;
+    int64_t d = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int s = used[i];
+      const int32_t k = keys[s];
+      const unsigned long long v = vals[s];
+      if (v) {
+        const int64_t old = (int64_t)atomicAdd((unsigned long long*)&out[k], v);
+        if (sq) d += 2 * old * (int64_t)v + (int64_t)v * (int64_t)v;
+      }
+      keys[s] = -1;
+      vals[s] = 0;
+    }
+    return d;
+  }
+};
+
 // sq (optional) receives the change of sum_c W_c^2 made by the moves (a single graph's state bookkeeping);
 // slot->n_empty becomes nonzero when some kept move goes to a new singleton.
 __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep, const VState* vs,
@@ -1084,10 +1144,12 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
   int64_t dsq = 0;
   __shared__ int32_t ak[AGG_SLOTS];
   __shared__ unsigned long long av[AGG_SLOTS];
+  __shared__ uint16_t au[AGG_SLOTS / 2];
+  __shared__ int an;
   __shared__ unsigned long long ne;
-  LdsAgg<AGG_SLOTS> agg{ak, av};
+  AggList agg{ak, av, au, &an};
   if (threadIdx.x == 0) ne = 0;
-  agg.clear();
+  agg.clear_all();
   __syncthreads();
   int used = 0;  // distinct keys in the table (uniform over the workgroup)
   for (int64_t t0 = (int64_t)blockIdx.x * APPLY_TILE; t0 < n; t0 += (int64_t)gridDim.x * APPLY_TILE) {
@@ -1102,38 +1164,33 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
 #pragma unroll
     for (int k = 0; k < APPLY_PER; ++k) {
       const int64_t v = t0 + k * BLOCK + threadIdx.x;
+      sv[k] = VState{0, D_NONE, 0};
+      wv[k] = 0;
       if (kp[k]) { sv[k] = vs[v]; wv[k] = vw[v]; }
     }
     int64_t claims = 0;
 #pragma unroll
     for (int k = 0; k < APPLY_PER; ++k) {
       const int64_t v = t0 + k * BLOCK + threadIdx.x;
-      if (v >= n) continue;
-      uint8_t e = 0;
-      if (kp[k]) {
-        claims += agg.add(sv[k].c, -wv[k]);
-        if (sv[k].d == D_EMPTY) {
-          e = 1;
-          atomicAdd(&ne, 1ull);
-        } else {
-          C[v] = sv[k].d;
-          claims += agg.add(sv[k].d, wv[k]);
-        }
+      const bool mv = kp[k] && sv[k].d != D_EMPTY;  // a move into an existing cluster
+      claims += agg.add(kp[k], sv[k].c, -wv[k]);
+      claims += agg.add(mv, sv[k].d, wv[k]);
+      if (v < n) {
+        if (mv) C[v] = sv[k].d;
+        if (kp[k] && !mv) atomicAdd(&ne, 1ull);
+        empty[v] = (uint8_t)(kp[k] && !mv);
       }
-      empty[v] = e;
     }
     used += (int)sum_reduce<BLOCK>(claims);  // its barriers also complete this tile's table updates
     if (used > AGG_FLUSH_AT) {
-      if (track_sq) dsq += agg.flush_sq(W); else agg.flush(W);
+      dsq += agg.flush(W, track_sq);
       __syncthreads();
-      agg.clear();
+      if (threadIdx.x == 0) an = 0;
       __syncthreads();
       used = 0;
     }
   }
-  if (used) {
-    if (track_sq) dsq += agg.flush_sq(W); else agg.flush(W);
-  }
+  if (used) dsq += agg.flush(W, track_sq);
   __syncthreads();
   if (threadIdx.x == 0 && ne && slot) slot->n_empty = 1;  // consumers only test it against zero
   if (track_sq) {
@@ -1381,8 +1438,10 @@ __global__ __launch_bounds__(BLOCK) void k_cluster_weights(const int32_t* C, con
   static_assert(AGG_SLOTS / 2 - T >= 0, "the table must hold the keys of a tile");
   __shared__ int32_t ak[AGG_SLOTS];
   __shared__ unsigned long long av[AGG_SLOTS];
-  LdsAgg<AGG_SLOTS> agg{ak, av};
-  agg.clear();
+  __shared__ uint16_t au[AGG_SLOTS / 2];
+  __shared__ int an;
+  AggList agg{ak, av, au, &an};
+  agg.clear_all();
   __syncthreads();
   int used = 0;  // as in k_apply: flushed before the table could pass half full
   for (int64_t t0 = (int64_t)blockIdx.x * T; t0 < n; t0 += (int64_t)gridDim.x * T) {
@@ -1396,18 +1455,17 @@ __global__ __launch_bounds__(BLOCK) void k_cluster_weights(const int32_t* C, con
     }
     int64_t claims = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k)
-      if (c[k] >= 0) claims += agg.add(c[k], w[k]);
+    for (int k = 0; k < PER; ++k) claims += agg.add(c[k] >= 0, c[k], w[k]);
     used += (int)sum_reduce<BLOCK>(claims);
     if (used > AGG_SLOTS / 2 - T) {
-      agg.flush(W);
+      agg.flush(W, false);
       __syncthreads();
-      agg.clear();
+      if (threadIdx.x == 0) an = 0;
       __syncthreads();
       used = 0;
     }
   }
-  if (used) agg.flush(W);
+  if (used) agg.flush(W, false);
 }
 
 __global__ void k_copy_vw(const int64_t* vw, int64_t* W, int64_t n) {
