@@ -108,27 +108,46 @@ __device__ __forceinline__ int seg_class(int64_t sz) {
   return sz <= 0 ? 0 : sz <= 16 ? 1 : sz <= 64 ? 2 : sz <= 128 ? 3 : sz <= SEG_MED ? 4 : C_LONG;
 }
 
-// lists[c][..] = the segments of class c (in any order); counts[c] = their number
+// lists[c][..] = the segments of class c (in any order); counts[c] = their number.  Each workgroup counts the
+// classes of all its segments first and claims one range per class with one global atomic (same-address
+// atomics serialise, so not one per tile), then writes its segments into those ranges.  Within a wavefront,
+// the lanes of a class are counted by ballot and added with one LDS atomic.
 __global__ __launch_bounds__(BLOCK) void k_seg_classify(const int64_t* off, int64_t nseg, int32_t* lists,
                                                         unsigned long long* counts) {
   __shared__ unsigned int lc[NCLASS];
   __shared__ unsigned long long base[NCLASS];
-  for (int64_t s0 = (int64_t)blockIdx.x * BLOCK; s0 < nseg; s0 += (int64_t)gridDim.x * BLOCK) {
-    if (threadIdx.x < NCLASS) lc[threadIdx.x] = 0;
-    __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1);
+  const uint64_t lt = (1ull << lane) - 1;
+  if (threadIdx.x < NCLASS) lc[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t s0 = (int64_t)blockIdx.x * BLOCK; s0 < nseg; s0 += (int64_t)gridDim.x * BLOCK) {  // uniform
     const int64_t s = s0 + threadIdx.x;
-    int c = 0;
-    unsigned int r = 0;
-    if (s < nseg) {
-      c = seg_class(off[s + 1] - off[s]);
-      if (c) r = atomicAdd(&lc[c], 1u);
+    const int c = s < nseg ? seg_class(off[s + 1] - off[s]) : 0;
+#pragma unroll
+    for (int k = 1; k < NCLASS; ++k) {
+      const uint64_t m = __ballot(c == k);
+      if (lane == 0 && m) atomicAdd(&lc[k], (unsigned int)__popcll(m));
     }
-    __syncthreads();
-    if (threadIdx.x > 0 && threadIdx.x < NCLASS && lc[threadIdx.x])
-      base[threadIdx.x] = atomicAdd(&counts[threadIdx.x], (unsigned long long)lc[threadIdx.x]);
-    __syncthreads();
-    if (c) lists[(int64_t)c * nseg + (int64_t)(base[c] + r)] = (int32_t)s;
-    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x > 0 && threadIdx.x < NCLASS) {
+    base[threadIdx.x] = lc[threadIdx.x] ? atomicAdd(&counts[threadIdx.x], (unsigned long long)lc[threadIdx.x]) : 0;
+    lc[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  for (int64_t s0 = (int64_t)blockIdx.x * BLOCK; s0 < nseg; s0 += (int64_t)gridDim.x * BLOCK) {
+    const int64_t s = s0 + threadIdx.x;
+    const int c = s < nseg ? seg_class(off[s + 1] - off[s]) : 0;
+#pragma unroll
+    for (int k = 1; k < NCLASS; ++k) {
+      const uint64_t m = __ballot(c == k);
+      if (!m) continue;  // uniform over the wavefront
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      unsigned int b = 0;
+      if (lane == leader) b = atomicAdd(&lc[k], (unsigned int)__popcll(m));
+      b = __shfl(b, leader, WAVE);
+      if (c == k) lists[(int64_t)k * nseg + (int64_t)(base[k] + b + (unsigned int)__popcll(m & lt))] = (int32_t)s;
+    }
   }
 }
 
@@ -376,7 +395,7 @@ void segsort_pairs(uint64_t* kin, uint32_t* vin, uint64_t* kout, uint32_t* vout,
   auto* counts = (unsigned long long*)take(NCLASS * sizeof(unsigned long long));
   auto* lists = (int32_t*)take((size_t)NCLASS * nseg * sizeof(int32_t));
   zero_bytes(counts, NCLASS * sizeof(unsigned long long), st);
-  k_seg_classify<<<tile_blocks(cdiv(nseg, BLOCK), 4096), BLOCK, 0, st>>>(off, nseg, lists, counts);
+  k_seg_classify<<<tile_blocks(cdiv(nseg, BLOCK), 512), BLOCK, 0, st>>>(off, nseg, lists, counts);
   unsigned long long hc[NCLASS] = {};
   device_check(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st), "segment classes");
   device_check(hipStreamSynchronize(st), "segment classes");
