@@ -32,22 +32,63 @@ inline unsigned tile_blocks(int64_t tiles, int64_t cap) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, cap));
 }
 
+// The tile's LDS hash also lists its occupied slots (each wavefront appends its new slots with one LDS
+// atomic): the per-tile flush and the reset for the next tile visit only those, not the whole table.
+// Probes key g into the table; returns the slot, and whether g took a new one, for a converged wavefront
+// (lanes with act false probe nothing).
+__device__ __forceinline__ int pl_claim(int32_t* hk, uint16_t* hl, int* hn, bool act, int32_t g) {
+  int h = -1, claimed = 0;
+  if (act) {
+    uint32_t x = fmix32((uint32_t)g) & (PL_SLOTS - 1);
+    for (int probe = 0; probe < PL_SLOTS; ++probe) {
+      const int32_t prev = atomicCAS(&hk[x], -1, g);
+      if (prev == -1 || prev == g) { claimed = prev == -1; break; }
+      x = (x + 1) & (PL_SLOTS - 1);
+    }
+    h = (int)x;
+  }
+  const uint64_t m = __ballot(claimed);
+  if (m) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(hn, __popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (claimed) hl[base + __popcll(m & ((1ull << lane) - 1))] = (uint16_t)h;
+  }
+  return h;
+}
+
 // out[grp[i]] += cnt[i] for grp[i] >= 0
 __global__ __launch_bounds__(BLOCK) void k_group_sum(const int32_t* grp, const int32_t* cnt, int64_t n,
                                                      int64_t* out) {
-  __shared__ int32_t ak[PL_SLOTS];
-  __shared__ unsigned long long av[PL_SLOTS];
-  LdsAgg<PL_SLOTS> agg{ak, av};
-  for (int64_t t0 = (int64_t)blockIdx.x * PL_TILE; t0 < n; t0 += (int64_t)gridDim.x * PL_TILE) {
-    agg.clear();
-    __syncthreads();
-    for (int k = threadIdx.x; k < PL_TILE; k += BLOCK) {
-      const int64_t i = t0 + k;
-      if (i >= n) break;
-      if (grp[i] >= 0 && cnt[i] > 0) agg.add(grp[i], cnt[i]);
+  __shared__ int32_t hk[PL_SLOTS];
+  __shared__ unsigned long long hv[PL_SLOTS];
+  __shared__ uint16_t hl[PL_TILE];  // a tile has at most PL_TILE distinct keys
+  __shared__ int hn;
+  constexpr int IPT = PL_TILE / BLOCK;
+  for (int s = threadIdx.x; s < PL_SLOTS; s += BLOCK) { hk[s] = -1; hv[s] = 0; }
+  if (threadIdx.x == 0) hn = 0;
+  __syncthreads();
+  for (int64_t t0 = (int64_t)blockIdx.x * PL_TILE; t0 < n; t0 += (int64_t)gridDim.x * PL_TILE) {  // uniform
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const int64_t i = t0 + (int64_t)k * BLOCK + threadIdx.x;
+      const int32_t g = i < n ? grp[i] : -1;
+      const int32_t c = i < n ? cnt[i] : 0;
+      const bool act = g >= 0 && c > 0;
+      const int h = pl_claim(hk, hl, &hn, act, g);
+      if (act) atomicAdd(&hv[h], (unsigned long long)c);
     }
     __syncthreads();
-    agg.flush(out);
+    for (int j = threadIdx.x; j < hn; j += BLOCK) {
+      const int sl = hl[j];
+      atomicAdd((unsigned long long*)&out[hk[sl]], hv[sl]);
+      hk[sl] = -1;
+      hv[sl] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) hn = 0;
     __syncthreads();
   }
 }
@@ -58,37 +99,43 @@ __global__ __launch_bounds__(BLOCK) void k_group_place(const int32_t* grp, const
                                                        int64_t n, unsigned long long* cursor, int64_t* pos) {
   __shared__ int32_t hk[PL_SLOTS];
   __shared__ unsigned long long hs[PL_SLOTS];  // the tile's total per segment, then the base it claimed
+  __shared__ uint16_t hl[PL_TILE];
+  __shared__ int hn;
   constexpr int IPT = PL_TILE / BLOCK;
-  for (int64_t t0 = (int64_t)blockIdx.x * PL_TILE; t0 < n; t0 += (int64_t)gridDim.x * PL_TILE) {
-    for (int s = threadIdx.x; s < PL_SLOTS; s += BLOCK) { hk[s] = -1; hs[s] = 0; }
-    __syncthreads();
+  for (int s = threadIdx.x; s < PL_SLOTS; s += BLOCK) { hk[s] = -1; hs[s] = 0; }
+  if (threadIdx.x == 0) hn = 0;
+  __syncthreads();
+  for (int64_t t0 = (int64_t)blockIdx.x * PL_TILE; t0 < n; t0 += (int64_t)gridDim.x * PL_TILE) {  // uniform
     int slot[IPT];
     unsigned long long in_tile[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       const int64_t i = t0 + (int64_t)k * BLOCK + threadIdx.x;
-      slot[k] = -1;
-      in_tile[k] = 0;
-      if (i >= n || (mask && !mask[i])) continue;
-      const int32_t g = grp[i];
-      const unsigned long long c = cnt ? (unsigned long long)(cnt[i] > 0 ? cnt[i] : 0) : 1ull;
-      if (g < 0 || c == 0) continue;
-      uint32_t h = fmix32((uint32_t)g) & (PL_SLOTS - 1);
-      for (int probe = 0; probe < PL_SLOTS; ++probe) {
-        const int32_t prev = atomicCAS(&hk[h], -1, g);
-        if (prev == -1 || prev == g) break;
-        h = (h + 1) & (PL_SLOTS - 1);
-      }
-      slot[k] = (int)h;
-      in_tile[k] = atomicAdd(&hs[h], c);
+      bool act = i < n && (!mask || mask[i]);
+      const int32_t g = act ? grp[i] : -1;
+      const unsigned long long c = !act ? 0ull : cnt ? (unsigned long long)(cnt[i] > 0 ? cnt[i] : 0) : 1ull;
+      act = act && g >= 0 && c != 0;
+      const int h = pl_claim(hk, hl, &hn, act, g);
+      slot[k] = act ? h : -1;
+      in_tile[k] = act ? atomicAdd(&hs[h], c) : 0ull;
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < PL_SLOTS; s += BLOCK)
-      if (hk[s] >= 0) hs[s] = atomicAdd(&cursor[hk[s]], hs[s]);
+    for (int j = threadIdx.x; j < hn; j += BLOCK) {
+      const int sl = hl[j];
+      hs[sl] = atomicAdd(&cursor[hk[sl]], hs[sl]);
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < IPT; ++k)
       if (slot[k] >= 0) pos[t0 + (int64_t)k * BLOCK + threadIdx.x] = (int64_t)(hs[slot[k]] + in_tile[k]);
+    __syncthreads();
+    for (int j = threadIdx.x; j < hn; j += BLOCK) {
+      const int sl = hl[j];
+      hk[sl] = -1;
+      hs[sl] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) hn = 0;
     __syncthreads();
   }
 }
