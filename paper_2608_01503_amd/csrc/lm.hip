@@ -429,15 +429,16 @@ __device__ __forceinline__ void best_reduce(Best& r) {
 }
 
 // singleton pass: best neighbour u by S = q w(u,v) - p w(v) w(u)
+template <int UU = U>
 __device__ __forceinline__ void single_row(const DevGraph& g, const Score& sc, int64_t b, int64_t e, int t, int S,
                                            int64_t wv, Best& r, const int32_t* cons, int32_t bv) {
-  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * UU) {
     // lanes past the end read the row's last entry (j0 < e) and drop it: loads issued without branches
-    int32_t us[U];
-    int64_t ws[U], vu[U];
-    bool ok[U];
+    int32_t us[UU];
+    int64_t ws[UU], vu[UU];
+    bool ok[UU];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
+    for (int k = 0; k < UU; ++k) {
       const int64_t j = j0 + (int64_t)k * S;
       ok[k] = j < e;
       const int64_t jc = ok[k] ? j : e - 1;
@@ -446,13 +447,13 @@ __device__ __forceinline__ void single_row(const DevGraph& g, const Score& sc, i
     }
     if (cons) {
 #pragma unroll
-      for (int k = 0; k < U; ++k)
+      for (int k = 0; k < UU; ++k)
         if (cons[us[k]] != bv) ok[k] = false;
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k) vu[k] = g.vw[us[k]];
+    for (int k = 0; k < UU; ++k) vu[k] = g.vw[us[k]];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
+    for (int k = 0; k < UU; ++k) {
       if (!ok[k]) continue;
       int64_t val = sc.q * ws[k] - sc.p * wv * vu[k];
       if (better(val, us[k], r.s, r.c)) { r.s = val; r.c = us[k]; }
@@ -461,16 +462,17 @@ __device__ __forceinline__ void single_row(const DevGraph& g, const Score& sc, i
 }
 
 // internal weight of v: sum of w(u,v) over neighbours in v's cluster
+template <int UU = U>
 __device__ __forceinline__ int64_t internal_row(const DevGraph& g, const int32_t* C, int64_t b, int64_t e, int t,
                                                 int S, int32_t cv) {
   int64_t acc = 0;
-  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * UU) {
     // lanes past the end read the row's last entry (j0 < e) and drop it: loads issued without branches
-    int32_t cs[U];
-    int64_t ws[U];
-    bool ok[U];
+    int32_t cs[UU];
+    int64_t ws[UU];
+    bool ok[UU];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
+    for (int k = 0; k < UU; ++k) {
       const int64_t j = j0 + (int64_t)k * S;
       ok[k] = j < e;
       const int64_t jc = ok[k] ? j : e - 1;
@@ -478,9 +480,9 @@ __device__ __forceinline__ int64_t internal_row(const DevGraph& g, const int32_t
       ws[k] = g.w[jc];
     }
 #pragma unroll
-    for (int k = 0; k < U; ++k) cs[k] = C[cs[k]];
+    for (int k = 0; k < UU; ++k) cs[k] = C[cs[k]];
 #pragma unroll
-    for (int k = 0; k < U; ++k)
+    for (int k = 0; k < UU; ++k)
       if (ok[k] && cs[k] == cv) acc += ws[k];
   }
   return acc;
@@ -562,7 +564,7 @@ __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64
     const int64_t wv = g.vw[v];
     const Score sc = ss.at(v);
     Best r = best_init();
-    single_row(g, sc, g.off[v], g.off[v + 1], gl, G, wv, r, ss.cons, ss.con(v));
+    single_row<G <= 16 ? 1 : U>(g, sc, g.off[v], g.off[v + 1], gl, G, wv, r, ss.cons, ss.con(v));
     best_reduce<G>(r);
     if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
   }
@@ -920,38 +922,39 @@ __device__ __forceinline__ int ab_pattern(int32_t cv, int32_t dv, int32_t cu, in
 }
 
 // sum of the adjustments of candidate v over the edges b + t, b + t + S, ... < e
+template <int UU = U>
 __device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, const Score& sc, int32_t base,
                                           int64_t b, int64_t e, int t, int S, int32_t v, const VState& me,
                                           int64_t wv) {
   int64_t acc = 0;
-  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * U) {
+  for (int64_t j0 = b + t; j0 < e; j0 += (int64_t)S * UU) {
     // lanes past the end read the row's last entry (j0 < e) and drop it: loads issued without branches
-    int32_t us[U];
-    int64_t ws[U];
-    bool ok[U];
+    int32_t us[UU];
+    int64_t ws[UU];
+    bool ok[UU];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
+    for (int k = 0; k < UU; ++k) {
       const int64_t j = j0 + (int64_t)k * S;
       ok[k] = j < e;
       const int64_t jc = ok[k] ? j : e - 1;
       us[k] = g.idx[jc];
       ws[k] = g.w[jc];
     }
-    VState os[U];
+    VState os[UU];
 #pragma unroll
-    for (int k = 0; k < U; ++k) os[k] = vs[us[k]];
-    int pat[U];
+    for (int k = 0; k < UU; ++k) os[k] = vs[us[k]];
+    int pat[UU];
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
+    for (int k = 0; k < UU; ++k) {
       pat[k] = 0;
       if (ok[k] && os[k].d != D_NONE && before(us[k] - base, os[k].delta, v - base, me.delta, sc.tie))
         pat[k] = ab_pattern(me.c, me.d, os[k].c, os[k].d);
     }
-    int64_t vu[U];
+    int64_t vu[UU];
 #pragma unroll
-    for (int k = 0; k < U; ++k) vu[k] = pat[k] ? g.vw[us[k]] : 0;
+    for (int k = 0; k < UU; ++k) vu[k] = pat[k] ? g.vw[us[k]] : 0;
 #pragma unroll
-    for (int k = 0; k < U; ++k)
+    for (int k = 0; k < UU; ++k)
       if (pat[k]) acc += (int64_t)pat[k] * (sc.q * ws[k] - sc.p * vu[k] * wv);
   }
   return acc;
@@ -972,7 +975,7 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
     if (me.d == D_NONE) {
       if (gl == 0) keep[v] = 0;
     } else {
-      int64_t acc = ab_row(g, vs, ss.at(v), ss.base(v), g.off[v], g.off[v + 1], gl, G, v, me, g.vw[v]);
+      int64_t acc = ab_row<G <= 16 ? 1 : U>(g, vs, ss.at(v), ss.base(v), g.off[v], g.off[v + 1], gl, G, v, me, g.vw[v]);
       acc = sum_reduce<G>(acc);
       if (gl == 0) {
         bool k = me.delta + acc >= 0;
@@ -1315,7 +1318,7 @@ __global__ __launch_bounds__(BLOCK) void k_internal_grp(const int32_t* list, int
   for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
        gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
-    int64_t x = internal_row(g, C, g.off[v], g.off[v + 1], gl, G, C[v]);
+    int64_t x = internal_row<G <= 16 ? 1 : U>(g, C, g.off[v], g.off[v + 1], gl, G, C[v]);
     if (per_v) {
       x = sum_reduce<G>(x);
       if (gl == 0) per_v[v] = x;
