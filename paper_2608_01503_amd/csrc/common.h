@@ -38,10 +38,13 @@ constexpr int32_t D_EMPTY = -2;  // destination = a new singleton cluster
 // hash inside the edge arena (7).  BUCKET_CAP holds the largest row each of buckets 0-6 can serve (the lane
 // count of its group, half the slots of its LDS hash); a tuning may set lower bounds, never higher ones, and
 // every setting gives the same results.
-constexpr int64_t BUCKET_CAP[NBUCKET - 1] = {4, 8, 16, 32, 128, 1024, 4096};
+constexpr int64_t BUCKET_CAP[NBUCKET - 1] = {4, 8, 16, 32, 128, 1024, 8192};
+// default bounds (bucket 6 rows above 4096 are a tuning choice: they help graphs with many such rows)
+constexpr int64_t BUCKET_DEFAULT[NBUCKET - 1] = {4, 8, 16, 32, 128, 1024, 4096};
 constexpr int LDS_SLOTS_B4 = 256;
 constexpr int LDS_SLOTS_B5 = 2048;
-constexpr int LDS_SLOTS_B6 = 8192;
+constexpr int LDS_SLOTS_B6 = 8192;    // bucket 6 rows up to 4096 (512 threads)
+constexpr int LDS_SLOTS_B6X = 16384;  // bucket 6 rows 4097-8192 (1024 threads, 128 KB of LDS)
 
 struct BucketBounds {
   int64_t max[NBUCKET - 1];  // upper degree bound of buckets 0..6; bucket 7 takes the rest

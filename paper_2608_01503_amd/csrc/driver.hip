@@ -146,7 +146,7 @@ size_t level_bytes(int64_t n, int64_t nnz) {
 
 static lcc_tuning initial_tuning() {
   lcc_tuning t{};
-  for (int k = 0; k < NBUCKET - 1; ++k) t.bucket_max[k] = BUCKET_CAP[k];
+  for (int k = 0; k < NBUCKET - 1; ++k) t.bucket_max[k] = BUCKET_DEFAULT[k];
   t.grid_cap = 2048;
   return t;
 }
@@ -1537,6 +1537,7 @@ lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lam
         {4, 8, 16, 32, 128, 512, 4096},    // the 8192-slot workgroups from degree 513
         {4, 8, 16, 32, 128, 1024, 2048},   // hub chunks from degree 2049
         {4, 8, 16, 32, 128, 1024, 1024},   // no 8192-slot workgroups: hub chunks from degree 1025
+        {4, 8, 16, 32, 128, 1024, 8192},   // rows up to 8192 in LDS (16384-slot workgroups above 4096)
     };
     for (const auto& lay : layouts) {
       lcc_tuning t = cur;

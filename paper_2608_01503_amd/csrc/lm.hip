@@ -728,7 +728,8 @@ template <int BS, int SLOTS>
 __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
                                                  const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb,
                                                  int strict, VState* vs, LMSlot* slot, int pass,
-                                                 int64_t* S, int ct_own, int ct_pairs) {
+                                                 int64_t* S, int ct_own, int ct_pairs, int64_t dlo = -1,
+                                                 int64_t dhi = INT64_MAX) {
   __shared__ int32_t hk[SLOTS];
   __shared__ uint32_t hv[SLOTS];
   __shared__ BlockCounters bc;
@@ -737,6 +738,7 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
     const int64_t b = g.off[v], e = g.off[v + 1];
+    if (e - b <= dlo || e - b > dhi) continue;  // rows of the other launch over this bucket (uniform)
     const int32_t cv = C[v];
     const int64_t wvt = g.vw[v];
     int bits = ceil_log2(2 * (e - b));
@@ -1898,7 +1900,14 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(3))))
   LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(4))))
   LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(5))))
-  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6))))
+  // bucket 6: rows up to 4096 on 512 threads and an 8192-slot table; when a tuning raises the bucket's bound,
+  // longer rows on 1024 threads and a 16384-slot table (a second launch over the bucket)
+  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), -1, LDS_SLOTS_B6 / 2)))
+  if (b.count[6] && b.hub_deg > LDS_SLOTS_B6 / 2) {  // the bucket's bytes are counted with the first launch
+    prof_begin(PF_ENUM_B0 + 6, st);
+    k_enum_blk<1024, LDS_SLOTS_B6X><<<vtx_blocks(b, b.count[6], 4), 1024, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), LDS_SLOTS_B6 / 2, INT64_MAX);
+    prof_end(PF_ENUM_B0 + 6, 0.0, st);
+  }
 #undef LCC_ENUM
   if (n7) {
     unsigned nc = (unsigned)b.hub_chunks;

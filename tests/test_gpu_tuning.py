@@ -17,6 +17,7 @@ TUNINGS = [
     dict(bucket_max=[4, 8, 16, 32, 64, 512, 2048], grid_cap=4096),
     dict(bucket_max=[0, 8, 8, 32, 32, 1024, 1024], grid_cap=65536),
     dict(bucket_max=[4, 4, 4, 4, 128, 128, 128]),         # no 8/16/32-lane groups, no workgroup hashes
+    dict(bucket_max=[4, 8, 16, 32, 128, 1024, 8192]),     # rows 4097-8192 on the 16384-slot workgroups
 ]
 
 CASES = [
@@ -76,7 +77,7 @@ def test_set_tuning_rejects_out_of_range_settings():
     ctx = U.ctx()
     before = L.tuning_dict(ctx.get_tuning())
     bad = [dict(bucket_max=[5, 8, 16, 32, 128, 1024, 4096]),     # above a bucket's capacity
-           dict(bucket_max=[4, 8, 16, 32, 128, 1024, 4097]),
+           dict(bucket_max=[4, 8, 16, 32, 128, 1024, 8193]),
            dict(bucket_max=[4, 8, 6, 32, 128, 1024, 4096]),      # decreasing
            dict(bucket_max=[-1, 8, 16, 32, 128, 1024, 4096]),
            dict(grid_cap=32), dict(grid_cap=70000)]
@@ -97,7 +98,7 @@ def test_autotune_keeps_a_valid_tuning_and_results():
     assert ms > 0
     t = L.tuning_dict(best)
     assert t == L.tuning_dict(ctx.get_tuning())
-    caps = [4, 8, 16, 32, 128, 1024, 4096]
+    caps = [4, 8, 16, 32, 128, 1024, 8192]
     assert all(0 <= b <= c for b, c in zip(t["bucket_max"], caps)) and 64 <= t["grid_cap"] <= 65536
     after, ares = ctx.cluster(graph, (1, 1, True), L.LCC_PLOUVAIN)
     assert np.array_equal(before.cpu().numpy(), after.cpu().numpy()) and ares.N == bres.N
