@@ -315,6 +315,8 @@ struct Tagged {
   uint32_t* ticket = nullptr;            // tile counter of single-pass scans, 0 between launches
 };
 uint32_t next_tag(Tagged& t, hipStream_t st);
+// k consecutive tags in out[0..k); when fewer than k remain, the tagged words are cleared first (on st)
+void next_tags(Tagged& t, int k, uint32_t* out, hipStream_t st);
 
 // Single-pass exclusive scan by decoupled look-back.  Tiles of LB_TILE items are drawn from a ticket counter
 // in launch order, so a tile waits only for tiles that a running workgroup already holds.  A tile publishes

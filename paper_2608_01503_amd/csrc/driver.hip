@@ -891,7 +891,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
   if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
   if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
-  if (R.o.validate && c.count0 != 0) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
+  if ((e & ERRB_NOT_SYMMETRIC) || (R.o.validate && c.count0 != 0)) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
   if (c.sum_we >= ((uint64_t)1 << 32)) fail(LCC_ERR_OVERFLOW, "total edge weight >= 2^32");
   if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
   L.sum_w2 = (int64_t)c.sum_w2;
@@ -1290,7 +1290,8 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
   if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
   if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
-  if (R.o.validate && c.count0 != 0) fail(LCC_ERR_NOT_SYMMETRIC, "a graph of the batch is not symmetric");
+  if ((e & ERRB_NOT_SYMMETRIC) || (R.o.validate && c.count0 != 0))
+    fail(LCC_ERR_NOT_SYMMETRIC, "a graph of the batch is not symmetric");
   if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
   std::vector<Score> sc((size_t)G);
   for (int64_t i = 0; i < G; ++i) {

@@ -1571,16 +1571,25 @@ __global__ void k_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, C
     if (off[v + 1] < off[v]) atomicOr(&ctrl->err_bits, ERRB_INVALID);
 }
 
-__device__ __forceinline__ uint64_t fp_h(uint32_t a, uint32_t b, uint32_t w) {
-  uint64_t key = ((uint64_t)a << 32) | b;
-  return fmix64(key ^ ((uint64_t)w * 0x9E3779B97F4A7C15ULL));
-}
-
+// Exact symmetry: every entry (v, u) with u > v must find (u, v) of the same weight in row u (binary search,
+// rows ascending), and the entries with u > v must be exactly as many as those with u < v.  The first
+// condition maps the upper entries one-to-one onto lower entries of equal weight (rows hold no duplicate);
+// with equal counts that map is onto, so every lower entry has its reverse too.  A row that is not ascending
+// is reported as unsorted first, whatever the search finds in it.
 struct EdgeCheck {
   uint32_t err = 0;
-  uint64_t f1 = 0;
+  int64_t balance = 0;  // upper entries minus lower entries
   int64_t ws = 0;
 };
+
+__device__ __forceinline__ bool has_reverse(const DevGraph& g, int32_t u, int32_t v, int32_t wt) {
+  int64_t lo = g.off[u], hi = g.off[u + 1];
+  while (lo < hi) {  // first position of row u holding an id >= v
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (g.idx[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo < g.off[u + 1] && g.idx[lo] == v && g.w[lo] == wt;
+}
 
 __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t j, int64_t rb, EdgeCheck& ec) {
   int32_t u = g.idx[j];
@@ -1590,7 +1599,12 @@ __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t
   if (u == v) ec.err |= ERRB_SELF_LOOP;
   if (j > rb && g.idx[j - 1] >= u) ec.err |= ERRB_UNSORTED;
   if (wt <= 0) ec.err |= ERRB_WEIGHT;
-  ec.f1 += fp_h((uint32_t)v, (uint32_t)u, (uint32_t)wt) - fp_h((uint32_t)u, (uint32_t)v, (uint32_t)wt);
+  if (u > v) {
+    ++ec.balance;
+    if (!has_reverse(g, u, v, wt)) ec.err |= ERRB_NOT_SYMMETRIC;
+  } else if (u < v) {
+    --ec.balance;
+  }
 }
 
 // vertex-weight mode of a vertex (per graph in a union), and the optional per-vertex weighted-degree output
@@ -1614,11 +1628,11 @@ __device__ __forceinline__ int64_t vertex_weight(int vw_mode, int64_t ws, const 
 
 __device__ __forceinline__ void flush_check(EdgeCheck ec, int64_t wsum, Ctrl* ctrl) {
   // block-wide: every thread calls this
-  uint64_t f1 = (uint64_t)sum_reduce<BLOCK>((int64_t)ec.f1);
+  const int64_t bal = sum_reduce<BLOCK>(ec.balance);
   wsum = sum_reduce<BLOCK>(wsum);
   if (ec.err) atomicOr(&ctrl->err_bits, ec.err);
   if (threadIdx.x == 0) {
-    if (f1) atomicAdd((unsigned long long*)&ctrl->count0, (unsigned long long)f1);
+    if (bal) atomicAdd((unsigned long long*)&ctrl->count0, (unsigned long long)bal);
     if (wsum) atomicAdd((unsigned long long*)&ctrl->sum_we, (unsigned long long)wsum);
   }
 }
@@ -1969,15 +1983,19 @@ static void apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs
   fold(b.stripes, {{CT_NM, slot ? &slot->nM[pass] : nullptr}, {CT_SQ, sq}}, st, pending);
   // free ids and ranks of the movers to a new singleton; all no-ops unless some vertex moved to a new
   // singleton in this pass
+  // all three tags are taken before the first launch: a wrap-around (which clears the tagged words) can then
+  // only come before the marks are written, never between the marks and their readers
   Tagged& tg = *bufs.tg;
-  const uint32_t mark = next_tag(tg, st);
+  uint32_t tags[3];
+  next_tags(tg, 3, tags, st);
+  const uint32_t mark = tags[0];
   k_free_mark<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.C, bufs.empty, tg.held, mark, slot);
   const uint32_t nt = (uint32_t)cdiv(n, LB_TILE);
   const unsigned gl = lb_blocks(nt);
   k_free_list<<<gl, BLOCK, 0, st>>>(n, tg.held, mark, bufs.freelist, sg.G ? bufs.scan_a : nullptr, tg.status,
-                                    tg.ticket, next_tag(tg, st), nt, slot);
+                                    tg.ticket, tags[1], nt, slot);
   k_assign_empty<<<gl, BLOCK, 0, st>>>(n, bufs.empty, bufs.freelist, g.vw, bufs.C, bufs.W,
-                                       sg.G ? bufs.scan_b : nullptr, tg.status, tg.ticket, next_tag(tg, st), nt,
+                                       sg.G ? bufs.scan_b : nullptr, tg.status, tg.ticket, tags[2], nt,
                                        slot, sq);
   if (sg.G)
     k_assign_empty_seg<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.empty, bufs.scan_a, bufs.scan_b, bufs.freelist, sg.gid,
@@ -2088,13 +2106,19 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
   }
 }
 
-uint32_t next_tag(Tagged& t, hipStream_t st) {
-  if (t.last == UINT32_MAX) {  // every tag is used: clear the tagged words and number again from 1
+void next_tags(Tagged& t, int k, uint32_t* out, hipStream_t st) {
+  if (t.last > UINT32_MAX - (uint32_t)k) {  // fewer than k tags left: clear the tagged words, number from 1
     zero_bytes(t.held, (size_t)t.held_cap * sizeof(uint32_t), st);
     zero_bytes(t.status, (size_t)t.status_cap * sizeof(unsigned long long), st);
     t.last = 0;
   }
-  return ++t.last;
+  for (int i = 0; i < k; ++i) out[i] = ++t.last;
+}
+
+uint32_t next_tag(Tagged& t, hipStream_t st) {
+  uint32_t x;
+  next_tags(t, 1, &x, st);
+  return x;
 }
 
 void launch_apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {

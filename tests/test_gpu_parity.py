@@ -126,11 +126,38 @@ def test_error_statuses_match_oracle():
         (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [1, 1, 2, 2]), ((1, 0, False), O.VW_UNIT)),   # zero denominator
         (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [2 ** 31 - 1] * 4), MOD),       # total edge weight >= 2^32
         (G(3, [0, 0, 0, 0], [], []), MOD),                        # modularity with no edges: W = 0
+        (G(4, [0, 1, 2, 3, 4], [2, 3, 1, 0], [1, 1, 1, 1]), MOD), # as many upper as lower entries, no reverses
     ]
     for g, (lam, mode) in cases:
         ref = O.cluster(g, O.PLOUVAIN, lam=lam, vw_mode=mode)
         assert ref.status != 0
         assert _status_gpu(g, lam, mode) == ref.status, (g, lam)
+
+
+@pytest.mark.parametrize("where", ["hub", "wave", "group"])
+def test_symmetry_check_is_exact(where):
+    """One entry's weight changed (or one reverse entry moved to another neighbour) in a hub row, a mid-degree
+    row or a short row: the device check compares every entry with its reverse, so each is NOT_SYMMETRIC, as
+    in the oracle; the unmodified graph passes."""
+    g = U.hub_graph(n=6000, hub_deg=(5000, 2000, 700), seed=12)
+    deg = np.diff(g.off)
+    v = {"hub": 0, "wave": int(np.nonzero((deg > 32) & (deg <= 128))[0][0]),
+         "group": int(np.nonzero((deg > 1) & (deg <= 4))[0][0])}[where]
+    assert _status_gpu(g, *MOD) == 0
+    w = g.w.copy()
+    w[g.off[v] + 1] += 1
+    bad = gg.Graph(n=g.n, off=g.off, idx=g.idx, w=w)
+    assert O.cluster(bad, O.PLOUVAIN, lam=MOD[0], vw_mode=MOD[1]).status == -2
+    assert _status_gpu(bad, *MOD) == -2
+    # the last entry of row v moved to a larger id whose row has no entry for v (the row stays ascending)
+    idx = g.idx.copy()
+    j = g.off[v + 1] - 1
+    cand = [u for u in range(idx[j] + 1, g.n) if u != v]
+    if cand:
+        idx[j] = cand[0]
+        bad2 = gg.Graph(n=g.n, off=g.off, idx=idx, w=g.w)
+        assert O.cluster(bad2, O.PLOUVAIN, lam=MOD[0], vw_mode=MOD[1]).status == -2
+        assert _status_gpu(bad2, *MOD) == -2
 
 
 def test_deterministic_repeat():
@@ -224,12 +251,14 @@ def test_symmetry_breaking_ablations(sym):
             U.assert_parity(g, v, *obj, opts_kw=kw)
 
 
-def test_tag_wraparound(monkeypatch):
+@pytest.mark.parametrize("base", [2 ** 32 - 7, 2 ** 32 - 4, 2 ** 32 - 2])
+def test_tag_wraparound(monkeypatch, base):
     """Free-id marks and single-pass scans tag their words instead of clearing them; when the 32-bit tags run
     out the arrays are cleared and numbering restarts.  Starting the sequence just before its end makes every
-    call cross the wrap-around; results must not change."""
+    call cross the wrap-around (at each offset of the three tags a pass takes, including a mark tag of 2^32 - 1);
+    results must not change."""
     import paper_2608_01503_amd as L
-    monkeypatch.setenv("LCC_TAG_BASE", str(2 ** 32 - 7))
+    monkeypatch.setenv("LCC_TAG_BASE", str(base))
     ctx = L.Context(0)  # a fresh context: the variable is read when its workspace is allocated
     for g, v, lam, mode in [(U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=8), L.LCC_PLEIDEN_PLUS,
                              (1, 20, False), L.LCC_VW_UNIT),
