@@ -167,6 +167,26 @@ lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size
 lcc_status lcc_cluster(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
                        const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res);
 
+/* Size in bytes of the device array that lcc_cluster_noalloc works in (one per device, per process). */
+#define LCC_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* lcc_cluster for callers that cannot allocate device memory (serving loops, harnesses that forbid it).
+ * Arguments, results, ownership and errors are those of lcc_cluster, with these differences:
+ *   - every device buffer of the call (workspace and coarse levels) is carved from a static device array of
+ *     LCC_NOALLOC_SCRATCH_BYTES that each device holds from the library's load until the process ends; the
+ *     call makes no device allocation (no hipMalloc, no hipFree, no use of the context's allocator) and leaves
+ *     the context's own workspace as it was;
+ *   - limit: the graph is accepted iff lcc_workspace_bytes(n, nnz, variant) <= LCC_NOALLOC_SCRATCH_BYTES,
+ *     else LCC_ERR_INVALID is returned before any device work; LCC_ERR_OOM if the coarse levels of a run
+ *     outgrow the array (nothing is written then);
+ *   - all calls on one device share its array: the library serialises them (a call holds the array until
+ *     its stream has completed).  The array keeps the last call's contents; each call clears what must start
+ *     at zero;
+ *   - the call synchronises its stream (as lcc_cluster does), so it cannot be captured into a HIP graph;
+ *     kernel timing (lcc_profile_enable) does not apply to it. */
+lcc_status lcc_cluster_noalloc(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                               const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res);
+
 /* lcc_cluster with the iteration inputs of the paper (Sec. II-B, Sec. IV-D), each optional (NULL = none),
  * n int32 in the same memory space as the graph, borrowed for the call:
  *   init_labels  labels in [0, n) (LCC_ERR_INVALID otherwise).  pLeiden / pLeiden+ start from this clustering

@@ -142,6 +142,46 @@ size_t level_bytes(int64_t n, int64_t nnz) {
          4 * align_up((size_t)n * 4) + align_up((size_t)(n + 2) * 4);
 }
 
+// Scratch of lcc_cluster_noalloc: a fixed device array that holds that entry point's workspace and level pool,
+// for callers that cannot allocate device memory.  Every device the library runs on holds its own copy until
+// the process ends.  Host code never uses the array's name as an address (it is a host-side stand-in): the
+// device address comes from hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t NOALLOC_BYTES = (size_t)LCC_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+struct ScratchDev {
+  std::mutex setup_mu;     // guards ptr / err / done
+  std::mutex call_mu;      // one no-allocation call at a time on the device: they share its array
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+  bool done = false;
+};
+constexpr int MAX_DEVICES = 64;
+ScratchDev g_scratch[MAX_DEVICES];
+
+// Device address of `scratch` on `device` (which must be current); taken at the first request per device.
+void* scratch_address(int device, hipError_t* err) {
+  ScratchDev& s = g_scratch[device];
+  std::lock_guard<std::mutex> lk(s.setup_mu);
+  if (!s.done) {
+    void* p = nullptr;
+    s.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    s.ptr = s.err == hipSuccess ? p : nullptr;
+    s.done = true;
+  }
+  *err = s.err;
+  return s.ptr;
+}
+
+// No-allocation mode of a context: the workspace and the level pool are bump-allocated from the device's
+// scratch array instead of the context's allocator.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  size_t ws_end = 0;
+};
+
 }  // namespace
 
 static lcc_tuning initial_tuning() {
@@ -167,6 +207,7 @@ struct lcc_ctx {
   int64_t ws_n = -1, ws_nnz = -1;
   WS w{};
   Pool pool;
+  Arena* arena = nullptr;       // set for the duration of a no-allocation call
   Ctrl* h_ctrl = nullptr;       // pinned mirror
   LMSlot* h_slots = nullptr;    // pinned mirror
   std::mutex mu;
@@ -199,6 +240,19 @@ struct lcc_ctx {
     else (void)hipFree(p);
   }
   void ensure_ws(int64_t n, int64_t nnz) {
+    if (arena) {  // carved from the scratch array for exactly this graph (the caller checked the size)
+      WS tmp{};
+      const size_t need = carve(tmp, nullptr, n, nnz);
+      if (need > arena->cap) fail(LCC_ERR_INVALID, "graph exceeds the no-allocation scratch");
+      w = WS{};
+      carve(w, arena->base, n, nnz);
+      ws_base = arena->base;
+      ws_bytes = need;
+      ws_n = n;
+      ws_nnz = nnz;
+      arena->ws_end = arena->off = align_up(need);
+      return;
+    }
     if (n <= ws_n && nnz <= ws_nnz) return;
     int64_t nn = std::max(n, ws_n), ne = std::max(nnz, ws_nnz);
     WS tmp{};
@@ -225,6 +279,13 @@ struct lcc_ctx {
   }
   void* pool_take(size_t bytes) {
     bytes = align_up(bytes);
+    if (arena) {
+      if (bytes > arena->cap - arena->off)
+        fail(LCC_ERR_OOM, "no-allocation scratch of " + std::to_string(arena->cap) + " bytes exhausted by the coarse levels");
+      void* p = arena->base + arena->off;
+      arena->off += bytes;
+      return p;
+    }
     while (pool.cur < pool.chunks.size()) {
       auto& c = pool.chunks[pool.cur];
       if (pool.off + bytes <= c.cap) {
@@ -241,10 +302,21 @@ struct lcc_ctx {
     pool.off = bytes;
     return pool.chunks.back().p;
   }
-  void pool_reset() { pool.cur = 0; pool.off = 0; }
+  void pool_reset() {
+    if (arena) { arena->off = arena->ws_end; return; }
+    pool.cur = 0;
+    pool.off = 0;
+  }
   // scratch taken after a mark is handed out again after the release (the stream must be done with it)
-  std::pair<size_t, size_t> pool_mark() const { return {pool.cur, pool.off}; }
-  void pool_release(std::pair<size_t, size_t> m) { pool.cur = m.first; pool.off = m.second; }
+  std::pair<size_t, size_t> pool_mark() const {
+    if (arena) return {0, arena->off};
+    return {pool.cur, pool.off};
+  }
+  void pool_release(std::pair<size_t, size_t> m) {
+    if (arena) { arena->off = m.second; return; }
+    pool.cur = m.first;
+    pool.off = m.second;
+  }
 };
 
 thread_local lcc_ctx* g_prof_ctx = nullptr;  // context whose call runs on this thread, when profiling
@@ -974,9 +1046,35 @@ void check_graph_args(const lcc_graph* g) {
   if (g->mem != LCC_MEM_HOST && g->mem != LCC_MEM_DEVICE) fail(LCC_ERR_INVALID, "unknown memory kind");
 }
 
+// Footprint bound of one call (workspace + coarse levels), the admission figure of lcc_workspace_bytes.
+size_t call_bytes(int64_t n, int64_t nnz) {
+  WS tmp{};
+  return carve(tmp, nullptr, n, nnz) + 2 * level_bytes(n, nnz);
+}
+
+// Puts a context into no-allocation mode for one call and restores its own workspace afterwards.
+struct ArenaSwap {
+  lcc_ctx* c;
+  bool on = false;
+  WS w{};
+  char* base = nullptr;
+  size_t bytes = 0;
+  int64_t n = -1, nnz = -1;
+  void engage(Arena* a) {
+    w = c->w; base = c->ws_base; bytes = c->ws_bytes; n = c->ws_n; nnz = c->ws_nnz;
+    c->arena = a;
+    on = true;
+  }
+  ~ArenaSwap() {
+    if (!on) return;
+    c->arena = nullptr;
+    c->w = w; c->ws_base = base; c->ws_bytes = bytes; c->ws_n = n; c->ws_nnz = nnz;
+  }
+};
+
 lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_variant variant,
                         const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res,
-                        const int32_t* init_labels, const int32_t* constraint = nullptr) {
+                        const int32_t* init_labels, const int32_t* constraint = nullptr, bool noalloc = false) {
   if (!ctx) fail(LCC_ERR_INVALID, "context is NULL");
   check_graph_args(g);
   if (!res) fail(LCC_ERR_INVALID, "result is NULL");
@@ -984,15 +1082,34 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
   if (variant < LCC_LOUVAIN || variant > LCC_PLEIDEN_PLUS) fail(LCC_ERR_INVALID, "unknown variant");
   if (constraint && (init_labels || variant == LCC_PLEIDEN || variant == LCC_PLEIDEN_PLUS))
     fail(LCC_ERR_INVALID, "a constraint clustering applies to Louvain variants without initial labels");
+  std::unique_lock<std::mutex> call_lock;  // no-allocation calls on one device share its scratch array
+  if (noalloc) {
+    const size_t need = call_bytes(g->n, g->nnz);
+    if (need > NOALLOC_BYTES)
+      fail(LCC_ERR_INVALID, "graph too large for the no-allocation scratch: lcc_workspace_bytes = " +
+                                std::to_string(need) + " > " + std::to_string(NOALLOC_BYTES));
+    if (ctx->device >= MAX_DEVICES) fail(LCC_ERR_INVALID, "no-allocation scratch: device index beyond 63");
+    call_lock = std::unique_lock<std::mutex>(g_scratch[ctx->device].call_mu);
+  }
   std::lock_guard<std::mutex> lock(ctx->mu);
   hip_check(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
+  Arena arena;
+  ArenaSwap swap{ctx};  // declared before the pool guard below: restores the context after the stream drained
+  if (noalloc) {
+    hipError_t e = hipSuccess;
+    void* p = scratch_address(ctx->device, &e);
+    if (!p) fail(LCC_ERR_DEVICE, std::string("address of the no-allocation scratch: ") + hipGetErrorString(e));
+    arena.base = (char*)p;
+    arena.cap = NOALLOC_BYTES;
+    swap.engage(&arena);
+  }
   Run R(ctx, st);
   if (opts) R.o = *opts; else default_opts(&R.o);
   check_opts(R.o);
   struct ProfGuard {
     lcc_ctx* c;
-    explicit ProfGuard(lcc_ctx* x) : c(x) { g_prof_ctx = x->prof_mask ? x : nullptr; }
+    explicit ProfGuard(lcc_ctx* x) : c(x) { g_prof_ctx = (x->prof_mask && !x->arena) ? x : nullptr; }
     ~ProfGuard() {
       g_prof_ctx = nullptr;
       for (auto& r : c->prof_recs) { c->ev_pool.push_back(r.a); c->ev_pool.push_back(r.b); }
@@ -1001,6 +1118,14 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
     }
   } prof_guard(ctx);
   ctx->ensure_ws(g->n, g->nnz);
+  if (noalloc) {  // the array keeps the previous call's contents: clear what must start at zero
+    WS& w = ctx->w;
+    zero_bytes(w.tg.held, (size_t)w.tg.held_cap * sizeof(uint32_t), st);
+    zero_bytes(w.tg.status, (size_t)w.tg.status_cap * sizeof(unsigned long long), st);
+    zero_bytes(w.tg.ticket, sizeof(uint32_t), st);
+    zero_bytes(w.stripes, (size_t)NSTRIPE * STRIPE_W * sizeof(int64_t), st);
+    w.tg.last = 0;
+  }
   ctx->pool_reset();
   // on every exit, also a failure half-way: the stream is drained before the level pool is handed out again
   struct PoolGuard {
@@ -1370,6 +1495,10 @@ lcc_status lcc_create(int device, lcc_alloc_fn alloc, lcc_free_fn free_fn, void*
     hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
     if (device < 0 || device >= ndev) fail(LCC_ERR_INVALID, "no such device");
     hip_check(hipSetDevice(device), "hipSetDevice");
+    if (device < MAX_DEVICES) {  // the no-allocation scratch's address on this device (its call reports errors)
+      hipError_t e = hipSuccess;
+      (void)scratch_address(device, &e);
+    }
     lcc_ctx* c = new lcc_ctx();
     c->device = device;
     c->alloc = alloc;
@@ -1412,10 +1541,8 @@ lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size
   return guarded([&]() -> lcc_status {
     if (!bytes || n < 0 || nnz < 0) fail(LCC_ERR_INVALID, "bad arguments");
     if (variant < LCC_LOUVAIN || variant > LCC_PLEIDEN_PLUS) fail(LCC_ERR_INVALID, "unknown variant");
-    WS tmp{};
-    size_t ws = carve(tmp, nullptr, n, nnz);
     // coarse levels: bounded by twice the input (geometric coarsening); the pool grows beyond on demand
-    *bytes = ws + 2 * level_bytes(n, nnz);
+    *bytes = call_bytes(n, nnz);
     return LCC_OK;
   });
 }
@@ -1423,6 +1550,13 @@ lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size
 lcc_status lcc_cluster(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
                        const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res) {
   return guarded([&]() { return cluster_impl(ctx, g, lambda, variant, opts, stream, labels_out, res, nullptr); });
+}
+
+lcc_status lcc_cluster_noalloc(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, lcc_variant variant,
+                               const lcc_options* opts, void* stream, int32_t* labels_out, lcc_result* res) {
+  return guarded([&]() {
+    return cluster_impl(ctx, g, lambda, variant, opts, stream, labels_out, res, nullptr, nullptr, true);
+  });
 }
 
 lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lambdas,

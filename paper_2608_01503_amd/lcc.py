@@ -23,9 +23,10 @@ LCC_LOUVAIN, LCC_PLOUVAIN, LCC_PLEIDEN, LCC_PLEIDEN_PLUS = 0, 1, 2, 3
 LCC_VW_GIVEN, LCC_VW_WEIGHTED_DEGREE, LCC_VW_UNIT = 0, 1, 2
 LCC_MEM_HOST, LCC_MEM_DEVICE = 0, 1
 LCC_FLAG_LEVEL_CAP, LCC_FLAG_REFINE_NO_PROGRESS = 1, 2
+LCC_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ["lcc_create", "lcc_destroy", "lcc_default_options", "lcc_workspace_bytes", "lcc_cluster",
-            "lcc_cluster_ex", "lcc_cluster_batch", "lcc_objective", "lcc_server_create", "lcc_submit", "lcc_poll",
+            "lcc_cluster_ex", "lcc_cluster_noalloc", "lcc_cluster_batch", "lcc_objective", "lcc_server_create", "lcc_submit", "lcc_poll",
             "lcc_server_destroy", "lcc_profile_enable", "lcc_profile_read", "lcc_status_string", "lcc_last_error",
             "lcc_default_tuning", "lcc_set_tuning", "lcc_get_tuning", "lcc_autotune"]
 
@@ -108,6 +109,9 @@ def load():
     lib.lcc_workspace_bytes.argtypes = [i64, i64, ctypes.c_int, P(ctypes.c_size_t)]
     lib.lcc_cluster.restype = st
     lib.lcc_cluster.argtypes = [v, P(lcc_graph), lcc_lambda, ctypes.c_int, P(lcc_options), v, v, P(lcc_result)]
+    lib.lcc_cluster_noalloc.restype = st
+    lib.lcc_cluster_noalloc.argtypes = [v, P(lcc_graph), lcc_lambda, ctypes.c_int, P(lcc_options), v, v,
+                                        P(lcc_result)]
     lib.lcc_cluster_ex.restype = st
     lib.lcc_cluster_ex.argtypes = [v, P(lcc_graph), lcc_lambda, ctypes.c_int, P(lcc_options), v, v, v, v,
                                    P(lcc_result)]
@@ -312,11 +316,14 @@ class Context:
             pass
 
     def cluster(self, graph: lcc_graph, lam=(1, 1, True), variant=LCC_PLOUVAIN, opts: lcc_options | None = None,
-                labels_out=None, stream=None, trace_capacity: int = 0, init=None, constraint=None):
+                labels_out=None, stream=None, trace_capacity: int = 0, init=None, constraint=None,
+                noalloc: bool = False):
         """Cluster one graph.  Returns (labels, Result).  labels_out defaults to a new int32 array in the
         graph's memory space (torch tensor on the device, numpy on the host).  init / constraint: optional
-        int32 arrays in the graph's memory space (lcc_cluster_ex)."""
+        int32 arrays in the graph's memory space (lcc_cluster_ex).  noalloc: lcc_cluster_noalloc."""
         lib = load()
+        if noalloc and (init is not None or constraint is not None):
+            raise ValueError("lcc_cluster_noalloc takes no initial or constraint clustering")
         n = graph.n
         if labels_out is None:
             if graph.mem == LCC_MEM_DEVICE:
@@ -333,7 +340,10 @@ class Context:
             o.trace = ctypes.pointer(tr)
         res = lcc_result()
         st = _stream_handle(stream, graph)
-        if init is None and constraint is None:
+        if noalloc:
+            _check(lib.lcc_cluster_noalloc(self.handle, ctypes.byref(graph), lam_of(lam), variant, ctypes.byref(o),
+                                           st, _ptr(labels_out), ctypes.byref(res)))
+        elif init is None and constraint is None:
             _check(lib.lcc_cluster(self.handle, ctypes.byref(graph), lam_of(lam), variant, ctypes.byref(o), st,
                                    _ptr(labels_out), ctypes.byref(res)))
         else:
