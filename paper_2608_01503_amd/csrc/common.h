@@ -108,7 +108,7 @@ struct Ctrl {
   int64_t refine_U, refine_m;
   int64_t lmalt_best;
   int64_t bucket_edges[NBUCKET];  // sum of degrees per bucket (level being prepared)
-  int64_t pairs[NBUCKET];         // distinct (vertex, other cluster) pairs enumerated, per bucket (accumulated)
+  int64_t enum_bytes[NBUCKET];    // algorithmic bytes of the enumeration launches, per bucket (accumulated)
 };
 
 enum : uint32_t {
@@ -412,7 +412,7 @@ struct LMBuffers {
   int32_t* freelist;
   uint32_t* arena; // 2 * nnz (key, value) slots for the global-memory hash
   void* scan_temp;
-  int64_t* pairs;  // per-bucket counters of enumerated (vertex, cluster) pairs, or null
+  int64_t* enum_bytes;  // per-bucket algorithmic bytes of the enumeration launches (diagnostics), or null
   Tagged* tg;      // free-id marks and single-pass scan state
 };
 

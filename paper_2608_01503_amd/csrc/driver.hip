@@ -360,9 +360,9 @@ void prof_resolve(lcc_ctx* c, const Ctrl* h) {
     c->ev_pool.push_back(r.b);
   }
   c->prof_recs.clear();
-  // device-counted part of the enumeration bytes: one 8-byte cluster-weight read per distinct pair
+  // the enumeration launches count their algorithmic bytes on the device
   for (int k = 0; k < NBUCKET; ++k)
-    if ((c->prof_mask >> (PF_ENUM_B0 + k)) & 1) c->prof_bytes[PF_ENUM_B0 + k] += 8.0 * (double)h->pairs[k];
+    if ((c->prof_mask >> (PF_ENUM_B0 + k)) & 1) c->prof_bytes[PF_ENUM_B0 + k] += (double)h->enum_bytes[k];
 }
 
 template <typename T>
@@ -509,7 +509,7 @@ struct Run {
     B.C = w.C; B.Cout = w.Cout; B.W = w.W; B.vs = w.vs; B.keep = w.keep; B.empty = w.empty;
     B.scan_a = w.scan_a; B.scan_b = w.scan_b; B.freelist = w.freelist; B.arena = (uint32_t*)w.k0;
     B.scan_temp = w.scan_temp;
-    B.pairs = &w.ctrl->pairs[0];
+    B.enum_bytes = &w.ctrl->enum_bytes[0];
     B.tg = &w.tg;
     return B;
   }

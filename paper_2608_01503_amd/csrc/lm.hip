@@ -153,29 +153,30 @@ __device__ __forceinline__ Verdict decide(int64_t scur, int64_t sbest, int32_t c
   return {cand ? d : D_NONE, cand ? delta : 0, cand};
 }
 
-// Per-block counters flushed with one global atomic each.
-struct BlockCounters {
-  unsigned long long ncand;
-  unsigned long long own;
-  unsigned long long pairs;
-};
-
-__device__ __forceinline__ void counters_init(BlockCounters* bc) {
-  if (threadIdx.x == 0) { bc->ncand = 0; bc->own = 0; bc->pairs = 0; }
-  __syncthreads();
-}
 // this workgroup's stripe of the counter partials (see NSTRIPE)
 __device__ __forceinline__ unsigned long long* stripe(int64_t* S, int ct) {
   return (unsigned long long*)&S[(int64_t)(blockIdx.x & (NSTRIPE - 1)) * STRIPE_W + ct];
 }
-// counter ids < 0 are not counted
-__device__ __forceinline__ void counters_flush(BlockCounters* bc, int64_t* S, int ct_ncand, int ct_own,
-                                               int ct_pairs = -1) {
-  __syncthreads();
+
+// Per-thread counter partials: each thread adds into registers, and the workgroup reduces them once at its end
+// (one stripe atomic per counter), instead of an LDS atomic per vertex on one shared address.
+struct VtxAcc {
+  int64_t ncand = 0;
+  int64_t own = 0;
+  int64_t bytes = 0;
+};
+// every thread of the workgroup (BS threads) calls this once, at the end of the kernel; counter ids < 0 are
+// not counted
+template <int BS>
+__device__ __forceinline__ void acc_flush(const VtxAcc& a, int64_t* S, int ct_ncand, int ct_own = -1,
+                                          int ct_bytes = -1) {
+  const int64_t c = ct_ncand >= 0 ? sum_reduce<BS>(a.ncand) : 0;
+  const int64_t o = ct_own >= 0 ? sum_reduce<BS>(a.own) : 0;
+  const int64_t b = ct_bytes >= 0 ? sum_reduce<BS>(a.bytes) : 0;
   if (threadIdx.x == 0) {
-    if (bc->ncand && ct_ncand >= 0) atomicAdd(stripe(S, ct_ncand), bc->ncand);
-    if (bc->own && ct_own >= 0) atomicAdd(stripe(S, ct_own), bc->own);
-    if (bc->pairs && ct_pairs >= 0) atomicAdd(stripe(S, ct_pairs), bc->pairs);
+    if (c) atomicAdd(stripe(S, ct_ncand), (unsigned long long)c);
+    if (o) atomicAdd(stripe(S, ct_own), (unsigned long long)o);
+    if (b) atomicAdd(stripe(S, ct_bytes), (unsigned long long)b);
   }
 }
 
@@ -236,7 +237,7 @@ __device__ __forceinline__ void fold_block(int64_t* S, const FoldDst& f) {
 
 __device__ __forceinline__ void finish_vertex(int32_t v, int32_t cv, int64_t wv, int64_t own, int64_t sbest,
                                               int32_t cbest, const Score& sc, const int64_t* W, uint32_t pa,
-                                              uint32_t pb, int strict, VState* vs, BlockCounters* bc,
+                                              uint32_t pb, int strict, VState* vs, VtxAcc& va,
                                               int64_t* ownv) {
   int64_t scur = sc.q * own - sc.p * wv * (W[cv] - wv);
   Verdict vd = decide(scur, sbest, cbest, pa, pb, strict);
@@ -245,10 +246,14 @@ __device__ __forceinline__ void finish_vertex(int32_t v, int32_t cv, int64_t wv,
   o.d = vd.d;
   o.delta = vd.delta;
   vs[v] = o;
-  if (vd.cand) atomicAdd(&bc->ncand, 1ull);
-  if (own) atomicAdd(&bc->own, (unsigned long long)own);
+  va.ncand += vd.cand ? 1 : 0;
+  va.own += own;
   if (ownv) ownv[v] = own;
 }
+
+// Algorithmic bytes of the enumeration (diagnostics): a vertex's row (index, weight and the neighbour's
+// cluster: 12 bytes per entry), its own state (56 bytes) and one cluster weight per other cluster (8 bytes each).
+__device__ __forceinline__ int64_t enum_bytes(int64_t deg, int64_t np) { return 12 * deg + 56 + 8 * np; }
 
 __device__ __forceinline__ uint32_t hslot(int32_t c, int bits) {
   return ((uint32_t)c * 2654435761u) >> (32 - bits);
@@ -555,8 +560,7 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64_t cnt, DevGraph g, ScoreSrc ss,
                                                       uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot,
                                                       int pass, int64_t* S) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   const int gl = threadIdx.x % G;
   for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
        gid += (int64_t)gridDim.x * (BLOCK / G)) {
@@ -566,17 +570,16 @@ __global__ __launch_bounds__(BLOCK) void k_single_grp(const int32_t* list, int64
     Best r = best_init();
     single_row<G <= 16 ? 1 : U>(g, sc, g.off[v], g.off[v + 1], gl, G, wv, r, ss.cons, ss.con(v));
     best_reduce<G>(r);
-    if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
+    if (gl == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, va, ss.ownv);
   }
-  counters_flush(&bc, S, CT_NCAND, -1);
+  acc_flush<BLOCK>(va, S, CT_NCAND, -1);
 }
 
 template <int G>
 __global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t cnt, DevGraph g, ScoreSrc ss,
                                                   uint32_t pa, uint32_t pb, VState* vs, LMSlot* slot, int pass,
                                                   int64_t* S) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
     const int64_t wv = g.vw[v];
@@ -584,10 +587,10 @@ __global__ __launch_bounds__(G) void k_single_blk(const int32_t* list, int64_t c
     Best r = best_init();
     single_row(g, sc, g.off[v], g.off[v + 1], threadIdx.x, G, wv, r, ss.cons, ss.con(v));
     best_reduce<G>(r);
-    if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, &bc, ss.ownv);
+    if (threadIdx.x == 0) finish_vertex(v, v, wv, 0, r.s, r.c, sc, g.vw, pa, pb, 0, vs, va, ss.ownv);
     __syncthreads();
   }
-  counters_flush(&bc, S, CT_NCAND, -1);
+  acc_flush<G>(va, S, CT_NCAND, -1);
 }
 
 // Hub chunk of the singleton pass: partial argmax per chunk.
@@ -638,8 +641,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
                                                     const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
                                                     uint32_t pb, int strict, VState* vs, LMSlot* slot, int pass,
                                                     int64_t* S, int ct_own, int ct_pairs) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   if (slot && slot->skip[pass]) return;
   const int gl = threadIdx.x % G;
   for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
@@ -663,13 +665,16 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
     if (leader && c != cv) {
       bs = sc.q * acc - sc.p * wv * W[c];
       bcl = c;
-      atomicAdd(&bc.pairs, 1ull);
+      va.bytes += 8;
     }
     argmax_reduce<G>(bs, bcl);
     own = sum_reduce<G>(own);
-    if (gl == 0) finish_vertex(v, cv, wv, own, bs, bcl, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
+    if (gl == 0) {
+      finish_vertex(v, cv, wv, own, bs, bcl, sc, W, pa, pb, strict, vs, va, ss.ownv);
+      va.bytes += enum_bytes(d, 0);
+    }
   }
-  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
+  acc_flush<BLOCK>(va, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
 
 // Orders a wavefront's own LDS accesses around a phase change of its private table: every LDS operation of
@@ -691,8 +696,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
                                                      int pass, int64_t* S, int ct_own, int ct_pairs) {
   __shared__ int32_t hk[BLOCK / WAVE][SLOTS];
   __shared__ uint32_t hv[BLOCK / WAVE][SLOTS];
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   if (slot && slot->skip[pass]) return;
   const int wv = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
   int32_t* tk = hk[wv];
@@ -715,12 +719,12 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
     r.own += own_reg;
     best_reduce<WAVE>(r);
     if (lane == 0) {
-      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
-      if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
+      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, va, ss.ownv);
+      va.bytes += enum_bytes(e - b, r.np);
     }
     wave_lds_sync();  // the scan's reads are done before the next vertex clears the table
   }
-  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
+  acc_flush<BLOCK>(va, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
 
 // One workgroup of BS threads per vertex sharing an LDS hash of capacity pow2ceil(2 d) <= SLOTS.
@@ -732,8 +736,7 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
                                                  int64_t dhi = INT64_MAX) {
   __shared__ int32_t hk[SLOTS];
   __shared__ uint32_t hv[SLOTS];
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   if (slot && slot->skip[pass]) return;
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
@@ -753,12 +756,12 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
     r.own += own_reg;
     best_reduce<BS>(r);
     if (threadIdx.x == 0) {
-      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, &bc, ss.ownv);
-      if (r.np) atomicAdd(&bc.pairs, (unsigned long long)r.np);
+      finish_vertex(v, cv, wvt, r.own, r.s, r.c, sc, W, pa, pb, strict, vs, va, ss.ownv);
+      va.bytes += enum_bytes(e - b, r.np);
     }
     __syncthreads();
   }
-  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
+  acc_flush<BS>(va, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
 }
 
 // Hubs: global-memory hash of 2 d 64-bit slots (cluster << 32 | weight sum) at slot offset 2 off[v] of the
@@ -861,17 +864,18 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_hub_scan(const int32_t* hubs, con
   np_ = sum_reduce<HUB_BLOCK>(np_);
   if (threadIdx.x == 0) {
     ps[blockIdx.x] = bs; pc[blockIdx.x] = bcl; pown[blockIdx.x] = own;
-    if (ct_pairs >= 0 && np_) atomicAdd(stripe(S, ct_pairs), (unsigned long long)np_);
+    if (ct_pairs >= 0 && np_) atomicAdd(stripe(S, ct_pairs), (unsigned long long)(8 * np_));
   }
 }
 
-// Combine the chunks of each hub (pown may be null: singleton pass).
+// Combine the chunks of each hub (pown may be null: singleton pass).  off (the level's offsets) and ct_bytes
+// (a counter id, or -1) count the hub rows' algorithmic bytes.
 __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64_t n7, const int64_t* vw,
                             const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb, int strict,
                             const int64_t* ps, const int32_t* pc, const int64_t* pown, VState* vs,
-                            LMSlot* slot, int pass, int64_t* S, int ct_own) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+                            LMSlot* slot, int pass, int64_t* S, int ct_own, const int64_t* off = nullptr,
+                            int ct_bytes = -1) {
+  VtxAcc va;
   if (slot && slot->skip[pass]) return;
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n7) {
@@ -883,9 +887,10 @@ __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64
       if (pown) own += pown[ch];
     }
     int32_t cv = C ? C[v] : v;
-    finish_vertex(v, cv, vw[v], own, bs, bcl, ss.at(v), C ? W : vw, pa, pb, strict, vs, &bc, ss.ownv);
+    finish_vertex(v, cv, vw[v], own, bs, bcl, ss.at(v), C ? W : vw, pa, pb, strict, vs, va, ss.ownv);
+    if (off) va.bytes += enum_bytes(off[v + 1] - off[v], 0);
   }
-  counters_flush(&bc, S, slot ? CT_NCAND : -1, ct_own);
+  acc_flush<BLOCK>(va, S, slot ? CT_NCAND : -1, ct_own, ct_bytes);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -966,8 +971,7 @@ template <int G>
 __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
                                                   ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass,
                                                   int64_t* S) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   if (slot->skip[pass]) return;
   const int gl = threadIdx.x % G;
   for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
@@ -982,19 +986,18 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
       if (gl == 0) {
         bool k = me.delta + acc >= 0;
         keep[v] = k;
-        if (k) atomicAdd(&bc.ncand, 1ull);
+        if (k) va.ncand += 1;
       }
     }
   }
-  counters_flush(&bc, S, CT_NM, -1);
+  acc_flush<BLOCK>(va, S, CT_NM, -1);
 }
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
                                                ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass,
                                                int64_t* S) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   if (slot->skip[pass]) return;
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
@@ -1008,10 +1011,10 @@ __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt,
     if (threadIdx.x == 0) {
       bool k = me.delta + acc >= 0;
       keep[v] = k;
-      if (k) atomicAdd(&bc.ncand, 1ull);
+      if (k) va.ncand += 1;
     }
   }
-  counters_flush(&bc, S, CT_NM, -1);
+  acc_flush<BS>(va, S, CT_NM, -1);
 }
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
@@ -1032,8 +1035,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_ab_hub(const int32_t* hubs, const
 
 __global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs, int64_t* hacc, uint8_t* keep,
                                LMSlot* slot, int pass, int64_t* S) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   if (slot->skip[pass]) return;
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n7) {
@@ -1042,17 +1044,16 @@ __global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs
     bool kp = me.d != D_NONE && me.delta + hacc[k] >= 0;
     keep[v] = kp;
     hacc[k] = 0;
-    if (kp) atomicAdd(&bc.ncand, 1ull);
+    if (kp) va.ncand += 1;
   }
-  counters_flush(&bc, S, CT_NM, -1);
+  acc_flush<BLOCK>(va, S, CT_NM, -1);
 }
 
 // Ablations of the symmetry breaking (Table 2): every candidate kept (mode 1), or the minimum label heuristic
 // in odd passes (mode 2: kept only when moving to a lower cluster id or to a new singleton).
 __global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, int mode, int pass, uint8_t* keep,
                             LMSlot* slot, int64_t* S) {
-  __shared__ BlockCounters bc;
-  counters_init(&bc);
+  VtxAcc va;
   if (slot->skip[pass]) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = list[i];
@@ -1060,9 +1061,9 @@ __global__ void k_keep_rule(const int32_t* list, int64_t cnt, const VState* vs, 
     bool k = s.d != D_NONE;
     if (k && mode == 2 && (pass & 1)) k = s.d == D_EMPTY || s.d < s.c;
     keep[v] = k;
-    if (k) atomicAdd(&bc.ncand, 1ull);
+    if (k) va.ncand += 1;
   }
-  counters_flush(&bc, S, CT_NM, -1);
+  acc_flush<BLOCK>(va, S, CT_NM, -1);
 }
 
 // ---------------------------------------------------------------------------------------------------------
@@ -1571,14 +1572,16 @@ __global__ void k_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, C
     if (off[v + 1] < off[v]) atomicOr(&ctrl->err_bits, ERRB_INVALID);
 }
 
-// Exact symmetry: every entry (v, u) with u > v must find (u, v) of the same weight in row u (binary search,
-// rows ascending), and the entries with u > v must be exactly as many as those with u < v.  The first
-// condition maps the upper entries one-to-one onto lower entries of equal weight (rows hold no duplicate);
-// with equal counts that map is onto, so every lower entry has its reverse too.  A row that is not ascending
-// is reported as unsorted first, whatever the search finds in it.
+// Exact symmetry: every entry (v, u) with u < v must find (u, v) of the same weight in row u (binary search,
+// rows ascending), and the entries with u < v must be exactly as many as those with u > v.  The first
+// condition maps these entries one-to-one onto entries (u, v) with v > u of equal weight (rows hold no
+// duplicate); with equal counts that map is onto, so every entry has its reverse.  The searches go into the row
+// of the smaller id: where high-degree vertices have small ids (R-MAT) they land in a few long rows whose upper
+// search levels stay in cache.  A row that is not ascending is reported as unsorted first, whatever the search
+// finds in it.
 struct EdgeCheck {
   uint32_t err = 0;
-  int64_t balance = 0;  // upper entries minus lower entries
+  int64_t balance = 0;  // entries towards a smaller id minus entries towards a larger one
   int64_t ws = 0;
 };
 
@@ -1599,10 +1602,10 @@ __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t
   if (u == v) ec.err |= ERRB_SELF_LOOP;
   if (j > rb && g.idx[j - 1] >= u) ec.err |= ERRB_UNSORTED;
   if (wt <= 0) ec.err |= ERRB_WEIGHT;
-  if (u > v) {
+  if (u < v) {
     ++ec.balance;
     if (!has_reverse(g, u, v, wt)) ec.err |= ERRB_NOT_SYMMETRIC;
-  } else if (u < v) {
+  } else if (u > v) {
     --ec.balance;
   }
 }
@@ -1898,15 +1901,15 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
     fold(S, {{CT_NCAND, &slot->nL[pass]}}, st, pending);
     return;
   }
-  int64_t* P = strict ? nullptr : bufs.pairs;  // distinct-pair counters (diagnostics), per bucket
+  int64_t* P = strict ? nullptr : bufs.enum_bytes;  // algorithmic-byte counters (diagnostics), per bucket
   const int co = own_sum ? CT_OWN : -1;
   auto cp = [&](int k) { return P ? CT_PAIRS + k : -1; };
-  auto eb = [&](int k) { return 12.0 * (double)b.edges[k] + 56.0 * (double)b.count[k]; };
+  // the launches count their algorithmic bytes on the device; they join the timing tallies when the call ends
 #define LCC_ENUM(k, launch)                      \
   if (b.count[k]) {                              \
     prof_begin(PF_ENUM_B0 + k, st);              \
     launch;                                      \
-    prof_end(PF_ENUM_B0 + k, eb(k), st);         \
+    prof_end(PF_ENUM_B0 + k, 0.0, st);           \
   }
   LCC_ENUM(0, (k_enum_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(0))))
   LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(1))))
@@ -1917,7 +1920,7 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   // bucket 6: rows up to 4096 on 512 threads and an 8192-slot table; when a tuning raises the bucket's bound,
   // longer rows on 1024 threads and a 16384-slot table (a second launch over the bucket)
   LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), -1, LDS_SLOTS_B6 / 2)))
-  if (b.count[6] && b.hub_deg > LDS_SLOTS_B6 / 2) {  // the bucket's bytes are counted with the first launch
+  if (b.count[6] && b.hub_deg > LDS_SLOTS_B6 / 2) {
     prof_begin(PF_ENUM_B0 + 6, st);
     k_enum_blk<1024, LDS_SLOTS_B6X><<<vtx_blocks(b, b.count[6], 4), 1024, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), LDS_SLOTS_B6 / 2, INT64_MAX);
     prof_end(PF_ENUM_B0 + 6, 0.0, st);
@@ -1930,8 +1933,8 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
     k_hub_scan<<<nc, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, C, W, sc, bufs.arena, hs.ps, hs.pc, hs.pown, slot, pass,
                                          S, cp(7));
     k_hub_final<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g.vw, C, W, sc, pa, pb, strict, hs.ps,
-                                               hs.pc, hs.pown, vs, slot, pass, S, co);
-    prof_end(PF_ENUM_B0 + 7, eb(7), st);
+                                               hs.pc, hs.pown, vs, slot, pass, S, co, g.off, cp(7));
+    prof_end(PF_ENUM_B0 + 7, 0.0, st);
   }
   fold(S, {{CT_NCAND, slot ? &slot->nL[pass] : nullptr}, {CT_OWN, own_sum}, {CT_PAIRS + 0, P ? P + 0 : nullptr},
            {CT_PAIRS + 1, P ? P + 1 : nullptr}, {CT_PAIRS + 2, P ? P + 2 : nullptr}, {CT_PAIRS + 3, P ? P + 3 : nullptr},

@@ -61,12 +61,53 @@ def run_oracle(g, variant, lam, vw_mode, vw=None, opts_kw=None, init=None, const
     return O.cluster(g, variant, lam=lam, vw_mode=vw_mode, vw=vw, opts=o, init=init, constraint=constraint)
 
 
+def fp64_report(g, labels, lam, vw_mode, vw=None):
+    """Eq. 1 and the Newman-Girvan modularity recomputed in FP64 from the labels alone (no integer score form):
+    lambdaCC = I - lambda (sum_c W_c^2 - sum_v w(v)^2) with I the internal ordered edge weight, and
+    Q = sum_c [I_c / W - gamma (W_c / W)^2].  Returns (lambdaCC, its scale, Q or None, Q's scale); a scale is
+    the sum of the magnitudes of the terms, the yardstick of the rounding error near zero."""
+    w = g.w.astype(np.float64) if g.w is not None else np.ones(len(g.idx))
+    src = np.repeat(np.arange(g.n), np.diff(g.off))
+    if vw_mode == O.VW_WEIGHTED_DEGREE:
+        vwf = np.bincount(src, weights=w, minlength=g.n)
+    elif vw_mode == O.VW_UNIT:
+        vwf = np.ones(g.n)
+    else:
+        vwf = np.asarray(vw, dtype=np.float64)
+    lab = np.asarray(labels, dtype=np.int64)
+    same = lab[src] == lab[g.idx]
+    I = float(w[same].sum())
+    Wc = np.bincount(lab, weights=vwf, minlength=int(lab.max()) + 1 if g.n else 1)
+    W = float(vwf.sum())
+    lamf = lam[0] / (lam[1] * (W if lam[2] else 1.0))
+    sW2, sw2 = float((Wc * Wc).sum()), float((vwf * vwf).sum())
+    obj = I - lamf * (sW2 - sw2)
+    scale = I + lamf * (sW2 + sw2)
+    Q = Qs = None
+    if vw_mode == O.VW_WEIGHTED_DEGREE and lam[2] and W > 0:
+        gamma = lam[0] / lam[1]
+        Q = I / W - gamma * sW2 / (W * W)
+        Qs = I / W + gamma * sW2 / (W * W)
+    return obj, scale, Q, Qs
+
+
+def assert_fp64_report(g, labels, res, lam, vw_mode, vw=None, rel=1e-12):
+    """The FP64 fields of a result agree with the independent FP64 recompute to `rel` (relative to the scale)."""
+    obj, scale, Q, Qs = fp64_report(g, labels, lam, vw_mode, vw)
+    assert abs(res.objective - obj) <= rel * max(scale, 1e-300), (res.objective, obj, scale)
+    if Q is None:
+        assert np.isnan(res.modularity)
+    else:
+        assert abs(res.modularity - Q) <= rel * Qs, (res.modularity, Q)
+
+
 def assert_parity(g, variant, lam, vw_mode, vw=None, opts_kw=None, **kw):
     ref = run_oracle(g, variant, lam, vw_mode, vw, opts_kw, init=kw.get("init"), constraint=kw.get("constraint"))
     lab, res = run_gpu(g, variant, lam, vw_mode, vw, opts_kw, **kw)
     assert ref.status == 0
     assert np.array_equal(lab, ref.labels), f"labels differ ({(lab != ref.labels).sum()} of {g.n})"
     assert res.N == ref.N and res.obj_den == ref.q
+    assert_fp64_report(g, lab, res, lam, vw_mode, vw)
     assert res.num_clusters == ref.num_clusters and res.levels == ref.levels and res.flags == ref.flags
     if res.trace is not None:
         assert res.trace.shape == ref.trace.shape, (res.trace.shape, ref.trace.shape)
