@@ -8,8 +8,11 @@ labels plus the exact objective: setup and validation, every local-move pass of 
 uncoarsening, contraction and projection.  value = directed CSR entries (2m) per second, the paper's
 processing rate (Sec. VII).
 
-Prints one JSON line.  The CPU baseline is the oracle (single-threaded, exact) timed on a bounded sample of
-the same workload (the same generator at a smaller scale).
+Prints one JSON line.  The CPU baseline is the oracle (single-threaded, exact, pinned to one host core) timed on
+a bounded sample of the same workload (the same generator at a smaller scale).  With the default `--legs all`
+the line also carries the batched form (4,096 kNN graphs in one fused call against 4,096 plain calls) and the
+served form (a Poisson request stream at 0.8 of the FIFO server's saturated rate: continuous-batching server
+against one-at-a-time plain calls), each with p50/p99 latency and edges/s.
 """
 from __future__ import annotations
 
@@ -111,7 +114,8 @@ def write_counter_summary(run_dir: str, family: str, workload_name: str):
     h = hashlib.sha256()
     for f in COUNTER_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    step = f"python -u bench.py --workload {workload_name} --steps 1 --warmup 0 --no-cpu-baseline --family {family}"
+    step = (f"python -u bench.py --workload {workload_name} --steps 1 --warmup 0 --no-cpu-baseline --legs none "
+            f"--family {family}")
     cmds = [f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/fetch -o run -- {step}",
             f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {run_dir}/write -o run -- {step}",
             f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {run_dir}/cal_fetch -o run -- python -u bench.py --copy-calibration",
@@ -136,6 +140,83 @@ def write_counter_summary(run_dir: str, family: str, workload_name: str):
         o.write(f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}\n")
         o.write(f"sources: {' '.join(COUNTER_SOURCES)}\n")
         o.write(f"sources_sha256: {h.hexdigest()}\n")
+    print(open(out).read())
+
+
+def write_counter_table(run_dir: str, workload_name: str):
+    """Every kernel's HBM traffic on one pipeline step: the FETCH_SIZE and WRITE_SIZE runs under run_dir (fetch/,
+    write/; `bench.py --workload W --steps 1 --warmup 0 --no-cpu-baseline --legs none --family enum_b5`), each
+    scaled by what the counter reads for the plain 1 GiB device copy (cal_fetch/, cal_write/), and the average
+    duration of each kernel from the kernel-trace run of the same command (trace/) -> counted HBM GB/s and its
+    fraction of the 8 TB/s peak.  Writes profiles/counters_all_<workload>.txt.  Runs on the host."""
+    import csv
+    import glob
+    import re
+    from collections import defaultdict
+
+    def csv_rows(sub, pat):
+        f = glob.glob(os.path.join(run_dir, sub, "**", pat), recursive=True)
+        if not f:
+            raise SystemExit(f"no {pat} under {os.path.join(run_dir, sub)}")
+        return list(csv.DictReader(open(f[0])))
+
+    def short(name):
+        name = name.replace("lcc::", "").replace("(anonymous namespace)::", "")
+        name = re.sub(r"^void ", "", name)
+        depth, out = 0, []
+        for ch in name:
+            if ch == "(" and depth == 0:
+                break
+            depth += ch == "<"
+            depth -= ch == ">"
+            out.append(ch)
+        return "".join(out)
+
+    def per_kernel(sub):
+        acc = defaultdict(list)
+        for r in csv_rows(sub, "*counter_collection.csv"):
+            acc[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        return acc
+
+    def scale(sub):
+        v = max(float(r["Counter_Value"]) for r in csv_rows(sub, "*counter_collection.csv")
+                if "copy" in r["Kernel_Name"].lower())
+        return (1 << 30) / (v * 1024.0)
+
+    fs, ws = scale("cal_fetch"), scale("cal_write")
+    fk, wk = per_kernel("fetch"), per_kernel("write")
+    dur = {}
+    for r in csv_rows("trace", "*kernel_stats.csv"):
+        dur[short(r["Name"])] = float(r["AverageNs"])
+    lines = []
+    for k in fk:
+        if k not in wk or not fk[k] or "copy" in k.lower():
+            continue
+        fb = sum(fk[k]) / len(fk[k]) * 1024 * fs
+        wb = sum(wk[k]) / len(wk[k]) * 1024 * ws
+        d = dur.get(k)
+        gbs = (fb + wb) / d if d else None  # bytes per ns = GB/s
+        lines.append((len(fk[k]) * ((fb + wb)), k, len(fk[k]), fb, wb, d, gbs))
+    lines.sort(reverse=True)
+    step = f"python -u bench.py --workload {workload_name} --steps 1 --warmup 0 --no-cpu-baseline --legs none --family enum_b5"
+    out = os.path.join(ROOT, "profiles", f"counters_all_{workload_name}.txt")
+    with open(out, "w") as o:
+        o.write(f"# HBM traffic per kernel, one pipeline step of workload {workload_name} (each counter scaled by what it\n"
+                "# reads for a plain 1 GiB device copy; duration = average of the kernel-trace run of the same command)\n")
+        for sub, extra in [("fetch", "--pmc FETCH_SIZE"), ("write", "--pmc WRITE_SIZE"),
+                           ("trace", "--kernel-trace --stats")]:
+            o.write(f"#   rocprofv3 {extra} --output-format csv -d {run_dir}/{sub} -o run -- {step}\n")
+        for sub, extra in [("cal_fetch", "--pmc FETCH_SIZE"), ("cal_write", "--pmc WRITE_SIZE")]:
+            o.write(f"#   rocprofv3 {extra} --output-format csv -d {run_dir}/{sub} -o run -- python -u bench.py "
+                    "--copy-calibration\n")
+        o.write(f"#   python bench.py --counter-table {run_dir} --workload {workload_name}\n")
+        o.write(f"# fetch scale {fs:.4f}, write scale {ws:.4f}; fraction = counted GB/s / {HBM_PEAK_GBS:.0f}\n#\n")
+        o.write("# dispatches  fetch_MB  write_MB  avg_us  counted_GB/s  frac  kernel   (MB per dispatch)\n")
+        for _, k, nd, fb, wb, d, gbs in lines:
+            if (fb + wb) * nd < 1e6:
+                continue
+            o.write(f"{nd:10d} {fb / 1e6:9.2f} {wb / 1e6:9.2f} {d / 1e3 if d else float('nan'):7.1f} "
+                    f"{gbs if gbs else float('nan'):12.1f} {gbs / HBM_PEAK_GBS if gbs else float('nan'):5.3f}  {k}\n")
     print(open(out).read())
 
 
@@ -244,7 +325,7 @@ def bench_knn_batch(args):
     ctx.cluster_batch(graphs, lam, var, opts=opts, labels_out=outs)
     torch.cuda.synchronize()
     walls = []
-    for _ in range(max(1, args.steps)):
+    for _ in range(max(1, args.steps if args.workload == "knn" else 3)):
         tf = time.perf_counter()
         _, fres = ctx.cluster_batch(graphs, lam, var, opts=opts, labels_out=outs)
         torch.cuda.synchronize()
@@ -253,6 +334,16 @@ def bench_knn_batch(args):
     same = all(a.N == b.N and a.num_clusters == b.num_clusters for a, b in zip(plain_res, fres)) and \
         all(torch.equal(plain_labels[i], outs[i]) for i in range(len(plain_labels)))
     pct = lambda x, q: float(np.percentile(np.asarray(x), q))
+    leg = {"workload": f"{len(graphs)} kNN graphs (k=15, 50-D Gaussian mixtures), pLouvain+ modularity",
+           "graphs": len(graphs), "nnz": nnz, "generation_s": gen_s,
+           "batched": {"wall_s": fused_wall, "p50_latency_s": fused_wall, "p99_latency_s": fused_wall,
+                       "edges_per_s": nnz / fused_wall},
+           "plain": {"wall_s": plain_wall, "p50_latency_s": pct(done, 50), "p99_latency_s": pct(done, 99),
+                     "p50_call_s": pct(dur, 50), "p99_call_s": pct(dur, 99), "edges_per_s": nnz / plain_wall},
+           "results_identical": bool(same)}
+    if not args.workload == "knn":
+        ctx.close()
+        return leg
     out = {
         "metric": METRIC, "value": nnz / fused_wall, "unit": "edges/s", "n_gpus": 1, "steps": len(walls),
         "warmup": 1, "ms_per_step": fused_wall * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -272,7 +363,7 @@ def bench_knn_batch(args):
     ctx.close()
 
 
-def bench_serve(args):
+def bench_serve(args, loads=(0.5, 0.8, 0.95)):
     """Served form: a Poisson request stream (SBM, R-MAT scales 12-20, kNN; modularity or CPM 1/10, 1/20,
     1/50; pLouvain+ or pLeiden) against the continuous-batching server and against a FIFO server that runs one
     request at a time with plain lcc_cluster calls, at 0.5, 0.8 and 0.95 of the FIFO server's saturated
@@ -324,7 +415,7 @@ def bench_serve(args):
     rng = np.random.default_rng(6)
     pct = lambda x, q: float(np.percentile(np.asarray(x), q))
     runs = []
-    for load in (0.5, 0.8, 0.95):
+    for load in loads:
         qps = load * qps_sat
         arr = np.cumsum(rng.exponential(1.0 / qps, size=len(items)))
         # FIFO: one request at a time, in arrival order
@@ -384,6 +475,13 @@ def bench_serve(args):
               file=sys.stderr, flush=True)
     srv.close()
     hi = runs[-1]
+    if args.workload != "serve":
+        srv_ctx.close()
+        ctx.close()
+        return {"workload": "Poisson request stream (SBM, R-MAT scales 12-20, kNN; modularity or CPM; pLouvain+ "
+                            "or pLeiden), continuous-batching server vs a FIFO server of plain calls",
+                "requests": len(items), "warm_up_requests": args.serve_warm, "fifo_saturated_qps": qps_sat,
+                "runs": runs}
     out = {
         "metric": METRIC, "value": hi["server"]["edges_per_s"], "unit": "edges/s", "n_gpus": 1,
         "steps": len(items), "warmup": args.serve_warm, "ms_per_step": None, "higher_is_better": True,
@@ -399,18 +497,37 @@ def bench_serve(args):
     ctx.close()
 
 
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scale: int):
-    """The oracle, as it stands, on R-MAT of a smaller scale (same generator and parameters)."""
+    """The oracle, as it stands, on a bounded sample of the benchmarked workload: the same R-MAT generator and
+    parameters at a smaller scale, pinned to one host core (the oracle is single-threaded)."""
     import graphgen as gg
     import oracle as O
     g = gg.rmat(scale, 16, 0.57, 0.19, 0.19, 2)
-    t = time.perf_counter()
-    r = O.cluster(g, O.PLOUVAIN, lam=(1, 1, True), vw_mode=O.VW_WEIGHTED_DEGREE)
-    dt = time.perf_counter() - t
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    try:
+        t = time.perf_counter()
+        r = O.cluster(g, O.PLOUVAIN, lam=(1, 1, True), vw_mode=O.VW_WEIGHTED_DEGREE)
+        dt = time.perf_counter() - t
+    finally:
+        os.sched_setaffinity(0, allowed)
     assert r.status == 0
     return {"value": g.nnz / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"R-MAT scale {scale} (n={g.n}, nnz={g.nnz}), same generator and parameters, "
-                      f"pLouvain+ modularity, one single-threaded run of {dt:.1f} s"}
+            "sample": f"R-MAT scale {scale} (n={g.n}, nnz={g.nnz}), same generator and parameters as the "
+                      f"benchmarked scale-22 graph, pLouvain+ modularity, one run of {dt:.1f} s pinned to host core "
+                      f"{core}",
+            "host_cores": os.cpu_count(), "host_cores_allowed": len(allowed), "host_cpu": host_cpu_model()}
 
 
 def main():
@@ -426,12 +543,18 @@ def main():
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="run the library's autotuner before timing (auto: on for the kNN batch, off for single "
                          "graphs, whose committed counter profiles are taken with the default tuning)")
+    ap.add_argument("--legs", choices=["all", "none"], default="all",
+                    help="with the single-graph workload: also run the batched (kNN batch) and served legs and add "
+                         "their latency figures to the line")
     ap.add_argument("--serve-count", type=int, default=240, help="measured requests of the served workload")
     ap.add_argument("--serve-warm", type=int, default=24, help="warm-up requests of the served workload")
     ap.add_argument("--trace-summary", metavar="DIR",
                     help="only summarise the rocprofv3 kernel-trace run under DIR into profiles/")
     ap.add_argument("--counter-summary", metavar="DIR",
                     help="only summarise the rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR into profiles/")
+    ap.add_argument("--counter-table", metavar="DIR",
+                    help="only summarise the FETCH_SIZE/WRITE_SIZE and kernel-trace runs under DIR into a per-kernel "
+                         "traffic table under profiles/")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (counter calibration for HBM traffic)")
     args = ap.parse_args()
@@ -440,6 +563,9 @@ def main():
         return
     if args.counter_summary:
         write_counter_summary(args.counter_summary, args.family, args.workload)
+        return
+    if args.counter_table:
+        write_counter_table(args.counter_table, args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU path is not built",
@@ -553,8 +679,19 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args.cpu_scale),
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
+    if args.legs == "all" and args.workload == "rmat22":
+        del graph, off, idx, w, labels
+        torch.cuda.empty_cache()
+        print("# batched leg", file=sys.stderr, flush=True)
+        out["batched_vs_plain"] = bench_knn_batch(args)
+        print("# served leg", file=sys.stderr, flush=True)
+        out["served_vs_fifo"] = bench_serve(args, loads=(0.8,))
+        out["not_timed"] = {
+            "rmat26": "R-MAT scale 26 with pLeiden CPM 1/20 is timed by `bench.py --workload rmat26` (about 50 s per "
+                      "call at the 64-level guard plus about a minute of host-side graph generation), outside this "
+                      "line's time budget"}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -1572,40 +1572,42 @@ __global__ void k_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, C
     if (off[v + 1] < off[v]) atomicOr(&ctrl->err_bits, ERRB_INVALID);
 }
 
-// Exact symmetry: every entry (v, u) with u < v must find (u, v) of the same weight in row u (binary search,
-// rows ascending), and the entries with u < v must be exactly as many as those with u > v.  The first
-// condition maps these entries one-to-one onto entries (u, v) with v > u of equal weight (rows hold no
-// duplicate); with equal counts that map is onto, so every entry has its reverse.  The searches go into the row
-// of the smaller id: where high-degree vertices have small ids (R-MAT) they land in a few long rows whose upper
-// search levels stay in cache.  A row that is not ascending is reported as unsorted first, whatever the search
-// finds in it.
+// Exact symmetry.  Rank vertices by (row length, id).  Every entry (v, u) whose target u ranks below v must find
+// (u, v) of the same weight in row u (binary search, rows ascending), and these entries must be exactly as many
+// as those whose target ranks above.  The first condition maps them one-to-one onto entries (u, v) whose target
+// v ranks above u (rows hold no duplicate); with equal counts that map is onto, so every entry has its reverse.
+// Each search runs in the shorter row of its pair: a cache line or two, never a long row.  A row that is not
+// ascending is reported as unsorted first, whatever the search finds in it.
 struct EdgeCheck {
   uint32_t err = 0;
-  int64_t balance = 0;  // entries towards a smaller id minus entries towards a larger one
+  int64_t balance = 0;  // entries towards a lower-ranked vertex minus entries towards a higher-ranked one
   int64_t ws = 0;
 };
 
-__device__ __forceinline__ bool has_reverse(const DevGraph& g, int32_t u, int32_t v, int32_t wt) {
-  int64_t lo = g.off[u], hi = g.off[u + 1];
-  while (lo < hi) {  // first position of row u holding an id >= v
+__device__ __forceinline__ bool found_in_row(const DevGraph& g, int64_t lo, int64_t end, int32_t v, int32_t wt) {
+  int64_t hi = end;
+  while (lo < hi) {  // first position holding an id >= v
     const int64_t mid = lo + ((hi - lo) >> 1);
     if (g.idx[mid] < v) lo = mid + 1; else hi = mid;
   }
-  return lo < g.off[u + 1] && g.idx[lo] == v && g.w[lo] == wt;
+  return lo < end && g.idx[lo] == v && g.w[lo] == wt;
 }
 
-__device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t j, int64_t rb, EdgeCheck& ec) {
+// entry j = (v, u) of row v, which starts at rb and holds dv entries
+__device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t j, int64_t rb, int64_t dv,
+                                           EdgeCheck& ec) {
   int32_t u = g.idx[j];
   int32_t wt = g.w[j];
   ec.ws += wt;
   if (u < 0 || u >= g.n) { ec.err |= ERRB_INVALID; return; }
-  if (u == v) ec.err |= ERRB_SELF_LOOP;
+  if (u == v) { ec.err |= ERRB_SELF_LOOP; return; }
   if (j > rb && g.idx[j - 1] >= u) ec.err |= ERRB_UNSORTED;
   if (wt <= 0) ec.err |= ERRB_WEIGHT;
-  if (u < v) {
+  const int64_t bu = g.off[u], eu = g.off[u + 1], du = eu - bu;
+  if (du < dv || (du == dv && u < v)) {
     ++ec.balance;
-    if (!has_reverse(g, u, v, wt)) ec.err |= ERRB_NOT_SYMMETRIC;
-  } else if (u > v) {
+    if (!found_in_row(g, bu, eu, v, wt)) ec.err |= ERRB_NOT_SYMMETRIC;
+  } else {
     --ec.balance;
   }
 }
@@ -1651,7 +1653,7 @@ __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int
     const int32_t v = list[gid];
     const int64_t rb = g.off[v], re = g.off[v + 1];
     const int64_t ws0 = ec.ws;
-    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, ec);
+    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, re - rb, ec);
     int64_t ws = sum_reduce<G>(ec.ws - ws0);
     if (gl == 0) {
       vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
@@ -1670,7 +1672,7 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list,
     const int32_t v = list[vi];
     const int64_t rb = g.off[v], re = g.off[v + 1];
     const int64_t ws0 = ec.ws;
-    for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, ec);
+    for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, re - rb, ec);
     int64_t ws = sum_reduce<BIG_BLOCK>(ec.ws - ws0);
     if (threadIdx.x == 0) {
       vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
@@ -1690,7 +1692,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_validate_hub(const int32_t* hubs,
   const int64_t j0 = rb + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   EdgeCheck ec;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) check_edge(g, v, j, rb, ec);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) check_edge(g, v, j, rb, g.off[v + 1] - rb, ec);
   int64_t ws = sum_reduce<HUB_BLOCK>(ec.ws);
   if (threadIdx.x == 0 && ws) atomicAdd((unsigned long long*)&hsum[k], (unsigned long long)ws);
   flush_check(ec, threadIdx.x == 0 ? ws : 0, ctrl);
