@@ -160,6 +160,20 @@ def random_gnp(n: int, p: float, seed: int, w_max: int = 1) -> Graph:
     return from_pairs(n, pairs, wts, name=f"gnp{n}")
 
 
+def reweight(g: Graph, total: int, seed: int) -> Graph:
+    """Same edges as ``g``, new symmetric integer weights uniform in [1, 2 m] scaled so that the sum of all
+    CSR entries comes to about ``total`` (and never above it); for tests of large weight totals."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.off))
+    up = rows < g.idx
+    pairs = np.stack([rows[up], g.idx[up].astype(np.int64)], axis=1)
+    m = len(pairs)
+    raw = rng.integers(1, 2 * m + 1, size=m).astype(np.float64)
+    w = np.maximum(1, np.floor(raw * (total / 2) / raw.sum())).astype(np.int64)
+    assert 2 * int(w.sum()) <= total and int(w.max()) < 2 ** 31
+    return from_pairs(g.n, pairs, w, name=g.name + "-heavy")
+
+
 # Named workloads ---------------------------------------------------------------------------------
 
 def config1_sbm() -> Graph:

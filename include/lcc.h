@@ -36,8 +36,8 @@ typedef enum {
   LCC_ERR_WEIGHT = -5,        /* an edge weight <= 0 or a given vertex weight < 0 */
   LCC_ERR_LAMBDA = -6,        /* lambda outside [0, 1] or undefined (zero denominator / zero total weight) */
   LCC_ERR_OVERFLOW = -7,      /* exactness bound violated: total edge weight >= 2^32, a given vertex weight
-                                 >= 2^31, or
-                                 q * W_E + p * W^2 >= 2^60 for lambda = p / q in lowest terms */
+                                 >= 2^31, or q * W_E + p * W^2 >= 2^62 for lambda = p / q in lowest terms
+                                 (modularity: 2 W^2 < 2^62, i.e. W below about 1.5e9) */
   LCC_ERR_OOM = -8,           /* the allocator returned NULL */
   LCC_ERR_DEVICE = -9,        /* a HIP runtime call failed */
   LCC_ERR_BUSY = -10,         /* server: admission refused (footprint exceeds the free budget) */

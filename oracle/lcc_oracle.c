@@ -150,9 +150,9 @@ int orc_setup(int64_t n, const int64_t* off, const int32_t* idx, const int32_t* 
   uint64_t p = (uint64_t)P, q = (uint64_t)Q;
   if (p == 0) q = 1;
   else { uint64_t d = gcd_u64(p, q); p /= d; q /= d; }
-  /* every score, delta and objective of the method stays below 2^61 in magnitude under this bound */
-  if (p > 0 && W >= ((i128)1 << 30)) return ORC_ERR_OVERFLOW;
-  if ((i128)q * WE + (i128)p * W * W >= ((i128)1 << 60)) return ORC_ERR_OVERFLOW;
+  /* admission bound of the library (every score and objective numerator of the method stays below 2^62 in
+   * magnitude); the oracle itself computes in 128 bits throughout */
+  if ((i128)q * WE + (i128)p * W * W >= ((i128)1 << 62)) return ORC_ERR_OVERFLOW;
   pq[0] = p; pq[1] = q;
   return ORC_OK;
 }

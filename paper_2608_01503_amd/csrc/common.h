@@ -222,16 +222,16 @@ struct LdsAgg {
   // flush, returning this thread's share of the change of the sum of squares of out: each atomic returns the
   // value it added to, so the shares of all flushes add up to the exact change (sum of (old + v)^2 - old^2)
   __device__ __forceinline__ int64_t flush_sq(int64_t* out) {
-    int64_t d = 0;
+    uint64_t d = 0;  // modulo 2^64: the shares of all threads add up to a value that fits
     for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
       int32_t k = keys[s];
       if (k >= 0 && vals[s]) {
         const int64_t v = (int64_t)vals[s];
         const int64_t old = (int64_t)atomicAdd((unsigned long long*)&out[k], vals[s]);
-        d += 2 * old * v + v * v;
+        d += (uint64_t)(2 * old * v + v * v);
       }
     }
-    return d;
+    return (int64_t)d;
   }
 };
 

@@ -976,9 +976,8 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   uint64_t p = (uint64_t)P, q = (uint64_t)Q;
   if (p == 0) q = 1;
   else { uint64_t d = gcd64(p, q); p /= d; q /= d; }
-  if (p > 0 && W >= ((unsigned __int128)1 << 30)) fail(LCC_ERR_OVERFLOW, "q W_E + p W^2 >= 2^60");
-  if ((unsigned __int128)q * WE + (unsigned __int128)p * W * W >= ((unsigned __int128)1 << 60))
-    fail(LCC_ERR_OVERFLOW, "q W_E + p W^2 >= 2^60");
+  if ((unsigned __int128)q * WE + (unsigned __int128)p * W * W >= ((unsigned __int128)1 << 62))
+    fail(LCC_ERR_OVERFLOW, "q W_E + p W^2 >= 2^62");
   R.p = (int64_t)p;
   R.q = (int64_t)q;
   R.sc.p = R.p;
@@ -1001,9 +1000,8 @@ lcc_status graph_score(lcc_lambda lam, unsigned __int128 W, unsigned __int128 WE
   uint64_t p = (uint64_t)P, q = (uint64_t)Q;
   if (p == 0) q = 1;
   else { uint64_t d = gcd64(p, q); p /= d; q /= d; }
-  if ((p > 0 && W >= ((unsigned __int128)1 << 30)) ||
-      (unsigned __int128)q * WE + (unsigned __int128)p * W * W >= ((unsigned __int128)1 << 60)) {
-    *why = "q W_E + p W^2 >= 2^60";
+  if ((unsigned __int128)q * WE + (unsigned __int128)p * W * W >= ((unsigned __int128)1 << 62)) {
+    *why = "q W_E + p W^2 >= 2^62";
     return LCC_ERR_OVERFLOW;
   }
   out->p = (int64_t)p;

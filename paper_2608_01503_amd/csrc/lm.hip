@@ -4,8 +4,12 @@
 //   a(v,c) = sum of w(u,v) over neighbours u with C[u] = c        W_c = sum of w(u) over cluster c
 //   S(v,c) = q a(v,c) - p w(v) W_c            (c != C[v])         S_cur = q a(v,C[v]) - p w(v) (W_C[v] - w(v))
 //   N(C)   = q I(C) - p (sum_c W_c^2 - sum_v w(v)^2)              (lambdaCC = N / q, Eq. 1)
-// The host guarantees q W_E + p W^2 < 2^60, so every score, delta and objective fits in int64; the
-// temperature test multiplies by the rational phi and is done in 128 bits.
+// The host guarantees q W_E + p W^2 < 2^62, so every score, every objective numerator and every sum of
+// afterburner adjustments is below 2^62 (2^63 for the adjustment sums) in magnitude and fits in int64, a delta
+// (a difference of two scores) below 2^63.  What can reach 2^64 -- the difference of two deltas in the tie test,
+// a delta plus its adjustments -- is formed in 128 bits, as is the temperature test (a rational phi times a
+// score).  Sums whose final value fits but whose partial sums need not (the change of the sum of squared
+// cluster weights) are accumulated modulo 2^64, which leaves the final value exact.
 //
 // Work decomposition per degree bucket (see common.h): groups of G lanes (G = 4..32, one neighbour per lane,
 // neighbour clusters aggregated by register shuffles), one wavefront per vertex with an LDS open-addressing
@@ -900,8 +904,8 @@ __global__ void k_hub_final(const int32_t* hubs, const int32_t* chunk_off, int64
 // ---------------------------------------------------------------------------------------------------------
 // u and v are graph-local ids (the level id minus the graph's first id in a union of graphs).
 __device__ __forceinline__ bool before(int32_t u, int64_t du, int32_t v, int64_t dv, int64_t tie) {
-  int64_t diff = du - dv;
-  int64_t ad = diff < 0 ? -diff : diff;
+  const __int128 diff = (__int128)du - dv;  // two deltas below 2^63 each: their difference needs 65 bits
+  const __int128 ad = diff < 0 ? -diff : diff;
   if (ad <= tie) return fmix64((uint64_t)(uint32_t)u) < fmix64((uint64_t)(uint32_t)v);
   return diff > 0;
 }
@@ -984,7 +988,7 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
       int64_t acc = ab_row<G <= 16 ? 1 : U>(g, vs, ss.at(v), ss.base(v), g.off[v], g.off[v + 1], gl, G, v, me, g.vw[v]);
       acc = sum_reduce<G>(acc);
       if (gl == 0) {
-        bool k = me.delta + acc >= 0;
+        bool k = (__int128)me.delta + acc >= 0;
         keep[v] = k;
         if (k) va.ncand += 1;
       }
@@ -1009,7 +1013,7 @@ __global__ __launch_bounds__(BS) void k_ab_blk(const int32_t* list, int64_t cnt,
     int64_t acc = ab_row(g, vs, ss.at(v), ss.base(v), g.off[v], g.off[v + 1], threadIdx.x, BS, v, me, g.vw[v]);
     acc = sum_reduce<BS>(acc);
     if (threadIdx.x == 0) {
-      bool k = me.delta + acc >= 0;
+      bool k = (__int128)me.delta + acc >= 0;
       keep[v] = k;
       if (k) va.ncand += 1;
     }
@@ -1041,7 +1045,7 @@ __global__ void k_ab_hub_final(const int32_t* hubs, int64_t n7, const VState* vs
   if (k < n7) {
     int32_t v = hubs[k];
     VState me = vs[v];
-    bool kp = me.d != D_NONE && me.delta + hacc[k] >= 0;
+    bool kp = me.d != D_NONE && (__int128)me.delta + hacc[k] >= 0;
     keep[v] = kp;
     hacc[k] = 0;
     if (kp) va.ncand += 1;
@@ -1125,19 +1129,19 @@ struct AggList {
   // resets the list count.
   __device__ __forceinline__ int64_t flush(int64_t* out, bool sq) {
     const int n = *nused;
-    int64_t d = 0;
+    uint64_t d = 0;  // modulo 2^64: the changes of all workgroups add up to a value that fits
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       const int s = used[i];
       const int32_t k = keys[s];
       const unsigned long long v = vals[s];
       if (v) {
         const int64_t old = (int64_t)atomicAdd((unsigned long long*)&out[k], v);
-        if (sq) d += 2 * old * (int64_t)v + (int64_t)v * (int64_t)v;
+        if (sq) d += (uint64_t)(2 * old * (int64_t)v + (int64_t)v * (int64_t)v);  // modulo 2^64
       }
       keys[s] = -1;
       vals[s] = 0;
     }
-    return d;
+    return (int64_t)d;
   }
 };
 
@@ -1147,7 +1151,7 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
                                                  const int64_t* vw, int32_t* C, int64_t* W, uint8_t* empty,
                                                  LMSlot* slot, int pass, int64_t* S, int track_sq) {
   if (slot && slot->skip[pass]) return;
-  int64_t dsq = 0;
+  uint64_t dsq = 0;  // modulo 2^64 (see AggList::flush)
   __shared__ int32_t ak[AGG_SLOTS];
   __shared__ unsigned long long av[AGG_SLOTS];
   __shared__ uint16_t au[AGG_SLOTS / 2];
@@ -1189,19 +1193,19 @@ __global__ __launch_bounds__(BLOCK) void k_apply(int64_t n, const uint8_t* keep,
     }
     used += (int)sum_reduce<BLOCK>(claims);  // its barriers also complete this tile's table updates
     if (used > AGG_FLUSH_AT) {
-      dsq += agg.flush(W, track_sq);
+      dsq += (uint64_t)agg.flush(W, track_sq);
       __syncthreads();
       if (threadIdx.x == 0) an = 0;
       __syncthreads();
       used = 0;
     }
   }
-  if (used) dsq += agg.flush(W, track_sq);
+  if (used) dsq += (uint64_t)agg.flush(W, track_sq);
   __syncthreads();
   if (threadIdx.x == 0 && ne && slot) slot->n_empty = 1;  // consumers only test it against zero
   if (track_sq) {
-    dsq = sum_reduce<BLOCK>(dsq);
-    if (threadIdx.x == 0 && dsq) atomicAdd(stripe(S, CT_SQ), (unsigned long long)dsq);
+    const int64_t tot = sum_reduce<BLOCK>((int64_t)dsq);
+    if (threadIdx.x == 0 && tot) atomicAdd(stripe(S, CT_SQ), (unsigned long long)tot);
   }
 }
 

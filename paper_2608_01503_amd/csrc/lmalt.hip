@@ -158,7 +158,8 @@ __global__ void k_gain(const int32_t* list, int64_t k, const VState* vs, const i
     const int32_t v = list[i];
     const VState me = vs[v];
     const int64_t fB = me.d == D_EMPTY ? 0 : F[4 * i + 2];
-    gain[i] = me.delta + sc.q * adj[i] - sc.p * vw[v] * (fB - F[4 * i + 3]);
+    // half the exact objective change of the move (below 2^62): its terms are summed modulo 2^64
+    gain[i] = (int64_t)((uint64_t)me.delta + (uint64_t)(sc.q * adj[i]) - (uint64_t)(sc.p * vw[v] * (fB - F[4 * i + 3])));
   }
 }
 

@@ -127,6 +127,8 @@ def test_error_statuses_match_oracle():
         (G(3, [0, 1, 3, 4], [1, 0, 2, 1], [2 ** 31 - 1] * 4), MOD),       # total edge weight >= 2^32
         (G(3, [0, 0, 0, 0], [], []), MOD),                        # modularity with no edges: W = 0
         (G(4, [0, 1, 2, 3, 4], [2, 3, 1, 0], [1, 1, 1, 1]), MOD), # as many upper as lower entries, no reverses
+        (G(2, [0, 1, 2], [1, 0], [759250125] * 2), MOD),         # q W_E + p W^2 = 8 x^2 just above 2^62
+        (G(2, [0, 1, 2], [1, 0], [2 ** 30] * 2), MOD),           # (the bound before it was raised)
     ]
     for g, (lam, mode) in cases:
         ref = O.cluster(g, O.PLOUVAIN, lam=lam, vw_mode=mode)
@@ -158,6 +160,29 @@ def test_symmetry_check_is_exact(where):
         bad2 = gg.Graph(n=g.n, off=g.off, idx=idx, w=g.w)
         assert O.cluster(bad2, O.PLOUVAIN, lam=MOD[0], vw_mode=MOD[1]).status == -2
         assert _status_gpu(bad2, *MOD) == -2
+
+
+HEAVY = [("rmat12", lambda: gg.rmat(12, seed=11), O.PLOUVAIN),
+         ("hubs", lambda: U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=4), O.PLEIDEN_PLUS),
+         ("lattice", lambda: gg.lattice(40, 40, seed=7), O.PLEIDEN),
+         ("sbm", lambda: gg.sbm(8, 120, 0.2, 0.01, seed=3), O.LOUVAIN)]
+
+
+@pytest.mark.parametrize("name,make,variant", HEAVY, ids=[h[0] for h in HEAVY])
+def test_modularity_with_weight_total_above_2_30(name, make, variant):
+    """Weight totals between 2^30 and the 2^62 bound (W about 1.45e9): scores, deltas, gains and objective
+    numerators then run up to about 2^62, where only 128-bit tests and modulo-2^64 sums stay exact."""
+    g = gg.reweight(make(), 1_450_000_000, seed=17)
+    W = int(g.w.astype(np.int64).sum())
+    assert 2 ** 30 < W and W * W + W * W < 2 ** 62
+    U.assert_parity(g, variant, *MOD)
+
+
+def test_largest_admitted_pair():
+    g = gg.Graph(n=2, off=np.array([0, 1, 2], np.int64), idx=np.array([1, 0], np.int32),
+                 w=np.array([759250124] * 2, np.int32))
+    ref, res = U.assert_parity(g, O.PLOUVAIN, *MOD)
+    assert res.N == 2 * 759250124 ** 2
 
 
 def test_deterministic_repeat():

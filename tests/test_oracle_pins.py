@@ -85,6 +85,47 @@ def test_setup_rejects_invalid_graphs():
     assert O.setup(ok, O.VW_GIVEN, (1, 20, False), -vbig)[0] == -5                 # negative vertex weight
 
 
+def test_setup_exactness_bound_is_2_62():
+    """Two vertices joined by one edge of weight x under modularity: W_E = W = 2x and lambda = 1/(2x), so
+    q W_E + p W^2 = 8 x^2, which stays below 2^62 exactly up to x = floor(sqrt(2^59 - 1))."""
+    x_max = int(np.floor(np.sqrt(2.0 ** 59)))
+    while 8 * (x_max + 1) ** 2 < 2 ** 62:
+        x_max += 1
+    while 8 * x_max ** 2 >= 2 ** 62:
+        x_max -= 1
+    assert x_max == 759250124
+    for x, want in ((x_max, 0), (x_max + 1, -7), (2 ** 30, -7)):
+        g = _g(2, [0, 1, 2], [1, 0], [x, x])
+        st, vw, p, q = O.setup(g)
+        assert st == want, (x, st)
+        if st == 0:
+            assert (p, q) == (1, 2 * x) and q * 2 * x + p * (2 * x) ** 2 == 8 * x * x < 2 ** 62
+            r = O.cluster(g, O.PLOUVAIN)
+            # joining the pair: internal weight 2x, (sum W_c^2 - sum w^2) = 2 x^2 -> N = 2x * 2x - 2x^2
+            assert r.status == 0 and defs.same_partition(r.labels, [0, 0]) and r.N == 2 * x * x
+
+
+def test_heavy_weights_above_2_30_stay_exact():
+    """Modularity with a weight total between 2^30 and the 2^62 bound (about 1.5e9): the oracle's objective
+    matches Eq. 1 in exact rationals and the textbook modularity, and the two heavy cliques are found."""
+    g = gg.reweight(defs_two_cliques(6), 1_450_000_000, seed=5)
+    vw, p, q = resolved(g)
+    W = int(vw.sum())
+    assert 2 ** 30 < W <= 1_450_000_000 and q * W + p * W * W < 2 ** 62
+    D = defs.Dense(g, vw)
+    rng = random.Random(3)
+    for _ in range(20):
+        C = [rng.randrange(4) for _ in range(g.n)]
+        assert Fraction(O.objective(g, vw, p, q, C), q) == D.lambdacc(C, Fraction(p, q))
+    for variant in VARIANTS:
+        r = O.cluster(g, variant)
+        assert r.status == 0
+        assert Fraction(r.N, r.q) == D.lambdacc(list(r.labels), Fraction(p, q))
+        Q = (r.N - p * int(np.sum(vw.astype(object) ** 2))) / (q * W)
+        assert abs(Q - defs.textbook_modularity(g, r.labels)) < 1e-12
+        assert defs.same_partition(r.labels, [0] * 6 + [1] * 6)
+
+
 def test_setup_lambda_reduced():
     g = defs_two_cliques(4)
     st, vw, p, q = O.setup(g, O.VW_WEIGHTED_DEGREE, (1, 1, True))
