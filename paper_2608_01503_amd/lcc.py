@@ -61,6 +61,9 @@ class lcc_options(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+_OPTION_FIELDS = {f[0] for f in lcc_options._fields_} - {"n_phi", "phi_num", "phi_den", "phi_until", "eps_num",
+                                                           "eps_den", "reserved"}
+
 LCC_SYM_AFTERBURNER, LCC_SYM_NONE, LCC_SYM_MLH = 0, 1, 2
 
 
@@ -174,8 +177,10 @@ def lcc_default_options(**kw) -> lcc_options:
                 o.phi_num[j], o.phi_den[j], o.phi_until[j] = a, b, u
         elif k == "eps":
             o.eps_num, o.eps_den = val
-        else:
+        elif k in _OPTION_FIELDS:
             setattr(o, k, val)
+        else:
+            raise TypeError(f"unknown option {k!r}")
     return o
 
 

@@ -1,36 +1,83 @@
-"""R-MAT scale 26 with pLeiden CPM 1/20 at full size (n = 67.1M, nnz = 2.1e9).  The oracle would need days
-at this size (44 s at scale 18, growing about 9x per factor 4 in size, and it keeps every level's graph), so
-this run is checked by what holds at any size: the labels are compact, the objective the library reports
-equals an independent recompute of Eq. 1 from the labels (exact int64), it is positive (the all-singleton
-start scores 0 and the best-so-far is kept), and, when the run converged before the level cap, every cluster
-is connected (Sec. II-B, Theorem 1), found by min-label propagation over intra-cluster edges.
-Opt-in (LCC_FULL_SCALE=1): a few minutes on one MI355X, most of it generating the graph on the host."""
+"""R-MAT scale 26 with pLeiden CPM 1/20 at full size (n = 67.1M, nnz = 2.1e9).
+
+Two checks share one generated graph:
+  * bit-exact parity for the first two levels against the oracle's stored result
+    (tests/golden/rmat26_pleiden_cpm20_2levels.json, written by tests/golden/make_golden.py, which calls only
+    the oracle; about an hour of CPU): the local moves of levels 0 and 1 with LocalMoveAlt, the refinement and
+    the contraction between them -- labels (SHA-256), objective, cluster and level counts, flags and every
+    per-pass / per-level trace record;
+  * the complete run (up to the level cap), checked by what holds at any size: the labels are compact, the
+    reported objective equals an independent recompute of Eq. 1 from the labels (exact int64), it is positive
+    (the all-singleton start scores 0 and the best-so-far is kept), and, when the run converged before the
+    level cap, every cluster is connected (Sec. II-B, Theorem 1), found by min-label propagation over
+    intra-cluster edges.
+About 90 s on one MI355X, most of it generating and hashing the graph on the host (about 45 GB of host
+memory); LCC_FULL_SCALE=0 skips it."""
 from __future__ import annotations
 
+import hashlib
+import json
 import os
+import threading
 
+import numpy as np
 import pytest
 
 import graphgen as gg
 
 pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("LCC_FULL_SCALE") != "1",
-                                 reason="full-size R-MAT scale 26 run: set LCC_FULL_SCALE=1")]
+              pytest.mark.skipif(os.environ.get("LCC_FULL_SCALE") == "0",
+                                 reason="full-size R-MAT scale 26 run skipped (LCC_FULL_SCALE=0)")]
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rmat26_pleiden_cpm20_2levels.json")
 
 
-def test_rmat26_pleiden_cpm_properties():
+@pytest.fixture(scope="module")
+def rmat26():
+    """The graph on the device, plus the SHA-256 of its host CSR (hashed on a thread while the GPU runs)."""
     import torch
     import paper_2608_01503_amd as L
     g = gg.config3b_rmat()
+    print(f"rmat26: generated n={g.n} nnz={g.nnz}", flush=True)
     dev = torch.device("cuda:0")
     off = torch.from_numpy(g.off).to(dev)
     idx = torch.from_numpy(g.idx).to(dev)
     w = torch.from_numpy(g.w).to(dev)
-    del g
-    n = off.numel() - 1
-    print(f"rmat26: n={n} nnz={idx.numel()}", flush=True)
+    digest = {}
+    hasher = threading.Thread(target=lambda: digest.setdefault("sha", g.digest()))
+    hasher.start()
+    graph = L.make_graph(off, idx, w, None, L.LCC_VW_UNIT)
+    yield dict(off=off, idx=idx, w=w, graph=graph, digest=digest, hasher=hasher)
+    hasher.join()
+
+
+def test_rmat26_pleiden_cpm_two_levels_against_golden(rmat26):
+    import torch
+    import paper_2608_01503_amd as L
+    ref = json.load(open(GOLDEN))
     ctx = L.Context(0, allocator="hip")
-    lab, res = ctx.cluster(L.make_graph(off, idx, w, None, L.LCC_VW_UNIT), (1, 20, False), L.LCC_PLEIDEN)
+    opts = L.lcc_default_options(**ref["opts"])
+    lab, res = ctx.cluster(rmat26["graph"], tuple(ref["lam"]), ref["variant"], opts, trace_capacity=1 << 14)
+    torch.cuda.synchronize()
+    ctx.close()
+    lab = np.ascontiguousarray(lab.cpu().numpy())
+    print(f"rmat26 two levels: clusters={res.num_clusters} levels={res.levels} flags={res.flags}", flush=True)
+    rmat26["hasher"].join()
+    assert rmat26["digest"]["sha"] == ref["graph_sha256"]
+    assert hashlib.sha256(lab.tobytes()).hexdigest() == ref["labels_sha256"]
+    assert res.N == int(ref["N"]) and res.obj_den == ref["q"]
+    assert (res.num_clusters, res.levels, res.flags) == (ref["num_clusters"], ref["levels"], ref["flags"])
+    assert res.trace.tolist() == ref["trace"]
+
+
+def test_rmat26_pleiden_cpm_properties(rmat26):
+    import torch
+    import paper_2608_01503_amd as L
+    off, idx, w = rmat26["off"], rmat26["idx"], rmat26["w"]
+    dev = off.device
+    n = off.numel() - 1
+    ctx = L.Context(0, allocator="hip")
+    lab, res = ctx.cluster(rmat26["graph"], (1, 20, False), L.LCC_PLEIDEN)
     torch.cuda.synchronize()
     ctx.close()
     print(f"rmat26: clusters={res.num_clusters} levels={res.levels} flags={res.flags}", flush=True)
@@ -40,7 +87,6 @@ def test_rmat26_pleiden_cpm_properties():
     # Eq. 1 with w(v) = 1, lambda = 1/20: N = 20 I - (sum_c W_c^2 - n), I over ordered intra-cluster entries
     src = torch.repeat_interleave(torch.arange(n, device=dev), off[1:] - off[:-1])
     dst = idx.long()
-    del idx
     same = lab[src] == lab[dst]
     I = int(w[same].long().sum())
     Wc = torch.bincount(lab, minlength=k)
