@@ -19,6 +19,7 @@ import hashlib
 import json
 import os
 import threading
+import time
 
 import numpy as np
 import pytest
@@ -37,8 +38,9 @@ def rmat26():
     """The graph on the device, plus the SHA-256 of its host CSR (hashed on a thread while the GPU runs)."""
     import torch
     import paper_2608_01503_amd as L
+    t = time.time()
     g = gg.config3b_rmat()
-    print(f"rmat26: generated n={g.n} nnz={g.nnz}", flush=True)
+    print(f"rmat26: generated n={g.n} nnz={g.nnz} in {time.time() - t:.1f} s", flush=True)
     dev = torch.device("cuda:0")
     off = torch.from_numpy(g.off).to(dev)
     idx = torch.from_numpy(g.idx).to(dev)
@@ -57,11 +59,13 @@ def test_rmat26_pleiden_cpm_two_levels_against_golden(rmat26):
     ref = json.load(open(GOLDEN))
     ctx = L.Context(0, allocator="hip")
     opts = L.lcc_default_options(**ref["opts"])
+    t = time.time()
     lab, res = ctx.cluster(rmat26["graph"], tuple(ref["lam"]), ref["variant"], opts, trace_capacity=1 << 14)
     torch.cuda.synchronize()
     ctx.close()
     lab = np.ascontiguousarray(lab.cpu().numpy())
-    print(f"rmat26 two levels: clusters={res.num_clusters} levels={res.levels} flags={res.flags}", flush=True)
+    print(f"rmat26 two levels: clusters={res.num_clusters} levels={res.levels} flags={res.flags} "
+          f"{time.time() - t:.1f} s", flush=True)
     rmat26["hasher"].join()
     assert rmat26["digest"]["sha"] == ref["graph_sha256"]
     assert hashlib.sha256(lab.tobytes()).hexdigest() == ref["labels_sha256"]
@@ -77,10 +81,12 @@ def test_rmat26_pleiden_cpm_properties(rmat26):
     dev = off.device
     n = off.numel() - 1
     ctx = L.Context(0, allocator="hip")
+    t = time.time()
     lab, res = ctx.cluster(rmat26["graph"], (1, 20, False), L.LCC_PLEIDEN)
     torch.cuda.synchronize()
     ctx.close()
-    print(f"rmat26: clusters={res.num_clusters} levels={res.levels} flags={res.flags}", flush=True)
+    print(f"rmat26: clusters={res.num_clusters} levels={res.levels} flags={res.flags} {time.time() - t:.1f} s",
+          flush=True)
     lab = lab.long()
     k = res.num_clusters
     assert int(lab.min()) == 0 and int(lab.max()) == k - 1 and torch.unique(lab).numel() == k
