@@ -156,8 +156,11 @@ lcc_status lcc_destroy(lcc_ctx* ctx);
 /* Fill *opts with the paper's settings (see lcc_options). */
 void lcc_default_options(lcc_options* opts);
 
-/* Upper bound of the device bytes one lcc_cluster call on a graph of n vertices and nnz entries may hold
- * at once (workspace + coarse levels); used for admission control. */
+/* Device bytes one lcc_cluster call on a graph of n vertices and nnz entries holds at most (workspace +
+ * coarse levels) when its coarsening is geometric: every coarse level of pLouvain+ is kept for the
+ * uncoarsening, so a coarsening that removes few vertices per level holds more (the call then grows its
+ * level pool through the allocator); Louvain, pLeiden and pLeiden+ hold at most two levels at a time.  Used
+ * for admission control (the server also counts what its slots actually hold). */
 lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size_t* bytes);
 
 /* Cluster one graph (Alg. 1 or Alg. 5 with the setup of Sec. II).  labels_out: n int32, in the same memory
@@ -250,13 +253,20 @@ lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lam
                         int64_t count, const lcc_options* opts, void* stream, int32_t trials, lcc_tuning* best,
                         double* best_ms);
 
-/* Continuous-batching server over one context (its device and allocator).  The server runs 8 execution
- * slots, each with its own context and HIP stream, so admitted jobs run concurrently on the GPU.  A free slot
- * admits the oldest queued job whose footprint (lcc_workspace_bytes) fits the unreserved part of hbm_budget
- * (a job passed over 4 times blocks further overtaking); if that job is a Louvain / Louvain+ request of at
- * most 2^22 entries, the slot also takes the other queued such requests with the same options (up to 256
- * requests, 2^25 entries) and runs them as one fused lcc_cluster_batch call.  Results are identical to plain
- * lcc_cluster calls.
+/* Continuous-batching server over one context (its device and allocator).  The server runs 4 execution
+ * slots (one per hardware queue HIP gives a process by default; the environment variable LCC_SERVER_SLOTS,
+ * 1-16, overrides it), each with its own context and HIP stream, so admitted jobs run concurrently on the
+ * GPU.  A free slot admits the oldest queued job whose footprint (lcc_workspace_bytes) fits the unreserved
+ * part of hbm_budget (a job passed over 4 times blocks further overtaking); if that job is a Louvain /
+ * Louvain+ request of at most 2^22 entries, the slot also takes the other queued such requests with the same
+ * options (up to 256 requests, 2^25 entries) and runs them as one fused lcc_cluster_batch call.  Results are
+ * identical to plain lcc_cluster calls.
+ * Device memory: every slot allocates through ctx's allocator, and the bytes the slots hold (workspaces and
+ * coarse levels, also while idle) plus the footprints reserved for running jobs never exceed hbm_budget.  An
+ * idle slot keeps its workspace for the next job unless it holds more than hbm_budget / slots or a queued
+ * job needs the memory.  A job whose coarse levels outgrow its footprint while other jobs hold memory is
+ * refused the extra memory and rerun alone, once every other slot is idle and empty; it fails with
+ * LCC_ERR_OOM only if it does not fit hbm_budget even then.
  *   lcc_server_create  hbm_budget > 0 bytes; the server keeps ctx's device and allocator (ctx must outlive it)
  *   lcc_submit         copies the graph (host or device memory) before returning and queues the job; returns
  *                      LCC_ERR_BUSY when the job's footprint alone exceeds hbm_budget; *ticket identifies it

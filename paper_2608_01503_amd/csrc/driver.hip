@@ -239,7 +239,10 @@ struct lcc_ctx {
     if (freef) freef(p, user);
     else (void)hipFree(p);
   }
-  void ensure_ws(int64_t n, int64_t nnz) {
+  // The context's own work is drained when a call returns (every call ends with a stream synchronisation), so
+  // growing the workspace waits for nothing but the new workspace's initialisation on the call's stream: no
+  // device-wide synchronisation that would also wait for other contexts' streams.
+  void ensure_ws(int64_t n, int64_t nnz, hipStream_t st) {
     if (arena) {  // carved from the scratch array for exactly this graph (the caller checked the size)
       WS tmp{};
       const size_t need = carve(tmp, nullptr, n, nnz);
@@ -257,7 +260,7 @@ struct lcc_ctx {
     int64_t nn = std::max(n, ws_n), ne = std::max(nnz, ws_nnz);
     WS tmp{};
     size_t need = carve(tmp, nullptr, nn, ne);
-    if (ws_base) { (void)hipDeviceSynchronize(); dfree(ws_base); ws_base = nullptr; }
+    if (ws_base) { dfree(ws_base); ws_base = nullptr; }
     // until the new workspace is in place the context has none: a failed allocation must not leave the sizes
     // of the freed one behind for the next call
     ws_n = ws_nnz = -1;
@@ -266,11 +269,11 @@ struct lcc_ctx {
     ws_base = (char*)dalloc(need);
     ws_bytes = need;
     carve(w, ws_base, nn, ne);
-    hip_check(hipMemset(w.tg.held, 0, (size_t)w.tg.held_cap * sizeof(uint32_t)), "workspace");
-    hip_check(hipMemset(w.tg.status, 0, (size_t)w.tg.status_cap * sizeof(unsigned long long)), "workspace");
-    hip_check(hipMemset(w.tg.ticket, 0, sizeof(uint32_t)), "workspace");
-    hip_check(hipMemset(w.stripes, 0, (size_t)NSTRIPE * STRIPE_W * sizeof(int64_t)), "workspace");
-    hip_check(hipDeviceSynchronize(), "workspace");
+    hip_check(hipMemsetAsync(w.tg.held, 0, (size_t)w.tg.held_cap * sizeof(uint32_t), st), "workspace");
+    hip_check(hipMemsetAsync(w.tg.status, 0, (size_t)w.tg.status_cap * sizeof(unsigned long long), st), "workspace");
+    hip_check(hipMemsetAsync(w.tg.ticket, 0, sizeof(uint32_t), st), "workspace");
+    hip_check(hipMemsetAsync(w.stripes, 0, (size_t)NSTRIPE * STRIPE_W * sizeof(int64_t), st), "workspace");
+    hip_check(hipStreamSynchronize(st), "workspace");
     // tags are result-neutral; LCC_TAG_BASE starts their sequence elsewhere (tests use it to reach the
     // wrap-around, which otherwise takes billions of passes)
     if (const char* tb = getenv("LCC_TAG_BASE")) w.tg.last = (uint32_t)strtoul(tb, nullptr, 10);
@@ -296,7 +299,9 @@ struct lcc_ctx {
       ++pool.cur;
       pool.off = 0;
     }
-    size_t cap = std::max(bytes, std::max((size_t)64 << 20, level_bytes(ws_n, ws_nnz)));
+    // chunks of one input-sized level: two hold the coarse levels of a geometric coarsening, the bound that
+    // lcc_workspace_bytes reports
+    size_t cap = std::max(bytes, level_bytes(ws_n, ws_nnz));
     pool.chunks.push_back({(char*)dalloc(cap), cap});
     pool.cur = pool.chunks.size() - 1;
     pool.off = bytes;
@@ -1045,9 +1050,13 @@ void check_graph_args(const lcc_graph* g) {
 }
 
 // Footprint bound of one call (workspace + coarse levels), the admission figure of lcc_workspace_bytes.
-size_t call_bytes(int64_t n, int64_t nnz) {
+// Louvain and pLouvain+ keep coarse levels in pool chunks of one input-sized level: two hold a geometric
+// coarsening (pLouvain+ keeps every level, so a slow coarsening holds more).  pLeiden and pLeiden+ keep two
+// alternating level buffers plus the refinement's and the alternate move's transient scratch: three chunks.
+size_t call_bytes(int64_t n, int64_t nnz, lcc_variant variant) {
   WS tmp{};
-  return carve(tmp, nullptr, n, nnz) + 2 * level_bytes(n, nnz);
+  const size_t levels = (variant == LCC_PLEIDEN || variant == LCC_PLEIDEN_PLUS) ? 3 : 2;
+  return carve(tmp, nullptr, n, nnz) + levels * level_bytes(n, nnz);
 }
 
 // Puts a context into no-allocation mode for one call and restores its own workspace afterwards.
@@ -1082,7 +1091,7 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
     fail(LCC_ERR_INVALID, "a constraint clustering applies to Louvain variants without initial labels");
   std::unique_lock<std::mutex> call_lock;  // no-allocation calls on one device share its scratch array
   if (noalloc) {
-    const size_t need = call_bytes(g->n, g->nnz);
+    const size_t need = call_bytes(g->n, g->nnz, variant);
     if (need > NOALLOC_BYTES)
       fail(LCC_ERR_INVALID, "graph too large for the no-allocation scratch: lcc_workspace_bytes = " +
                                 std::to_string(need) + " > " + std::to_string(NOALLOC_BYTES));
@@ -1115,7 +1124,7 @@ lcc_status cluster_impl(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, lcc_va
       for (auto& e : c->prof_open) if (e) { c->ev_pool.push_back(e); e = nullptr; }
     }
   } prof_guard(ctx);
-  ctx->ensure_ws(g->n, g->nnz);
+  ctx->ensure_ws(g->n, g->nnz, st);
   if (noalloc) {  // the array keeps the previous call's contents: clear what must start at zero
     WS& w = ctx->w;
     zero_bytes(w.tg.held, (size_t)w.tg.held_cap * sizeof(uint32_t), st);
@@ -1305,7 +1314,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     for (int64_t i = 0; i < G; ++i) fill_result(&res[i], 0, 0, s0[i].p, s0[i].q, 0, 0, false, 1, 0);
     return LCC_OK;
   }
-  ctx->ensure_ws(n, nnz);
+  ctx->ensure_ws(n, nnz, st);
   ctx->pool_reset();
   // on every exit, also a failure half-way: the stream is drained before the level pool is handed out again
   struct PoolGuard {
@@ -1539,8 +1548,7 @@ lcc_status lcc_workspace_bytes(int64_t n, int64_t nnz, lcc_variant variant, size
   return guarded([&]() -> lcc_status {
     if (!bytes || n < 0 || nnz < 0) fail(LCC_ERR_INVALID, "bad arguments");
     if (variant < LCC_LOUVAIN || variant > LCC_PLEIDEN_PLUS) fail(LCC_ERR_INVALID, "unknown variant");
-    // coarse levels: bounded by twice the input (geometric coarsening); the pool grows beyond on demand
-    *bytes = call_bytes(n, nnz);
+    *bytes = call_bytes(n, nnz, variant);
     return LCC_OK;
   });
 }
@@ -1709,7 +1717,7 @@ lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const
     hipStream_t st = (hipStream_t)stream;
     Run R(ctx, st);
     default_opts(&R.o);
-    ctx->ensure_ws(g->n, g->nnz);
+    ctx->ensure_ws(g->n, g->nnz, st);
     ctx->pool_reset();
     // on every exit, also a failure half-way: the stream is drained before the level pool is handed out again
   struct PoolGuard {
@@ -1811,6 +1819,22 @@ lcc_status lcc_cluster_init_internal(lcc_ctx* ctx, const lcc_graph* g, lcc_lambd
 }
 
 int lcc_ctx_device_internal(const lcc_ctx* ctx) { return ctx->device; }
+
+// Returns the context's workspace and level pool to its allocator (the next call allocates them again).  No
+// call of the context may be running; its last call drained its stream before returning.
+void lcc_ctx_release_internal(lcc_ctx* ctx) {
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  ctx->dfree(ctx->ws_base);
+  ctx->ws_base = nullptr;
+  ctx->ws_bytes = 0;
+  ctx->ws_n = ctx->ws_nnz = -1;
+  ctx->w = WS{};
+  for (auto& c : ctx->pool.chunks) ctx->dfree(c.p);
+  ctx->pool.chunks.clear();
+  ctx->pool.cur = 0;
+  ctx->pool.off = 0;
+}
 void lcc_ctx_allocator_internal(const lcc_ctx* ctx, lcc_alloc_fn* a, lcc_free_fn* f, void** user) {
   *a = ctx->alloc;
   *f = ctx->freef;

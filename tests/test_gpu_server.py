@@ -2,6 +2,7 @@
 whatever else is in flight, including fused groups of small Louvain requests and invalid requests."""
 from __future__ import annotations
 
+import threading
 import time
 
 import numpy as np
@@ -97,4 +98,101 @@ def test_server_invalid_request_in_fused_group():
             srv2.submit(U.host_graph(good[0], O.VW_WEIGHTED_DEGREE), (1, 1, True), L.LCC_PLOUVAIN)
         finally:
             srv2.close()
+    ctx.close()
+
+
+class CountingAllocator:
+    """torch's caching allocator, counting what is outstanding and its peak (called from the slot threads)."""
+
+    def __init__(self):
+        self.live = {}
+        self.peak = 0
+        self.lock = threading.Lock()
+
+    def alloc(self, nbytes):
+        import torch
+        p = torch.cuda.caching_allocator_alloc(nbytes, 0)
+        with self.lock:
+            self.live[p] = nbytes
+            self.peak = max(self.peak, sum(self.live.values()))
+        return p
+
+    def free(self, p):
+        import torch
+        with self.lock:
+            self.live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+
+def _footprint(g, variant):
+    import ctypes
+    import paper_2608_01503_amd as L
+    fp = ctypes.c_size_t(0)
+    assert L.load().lcc_workspace_bytes(g.n, g.nnz, variant, ctypes.byref(fp)) == 0
+    return fp.value
+
+
+def test_server_holds_device_memory_within_the_budget():
+    """Large and small jobs mixed under a budget of about two large footprints: every byte the slots hold,
+    idle ones included, is counted, so the allocator never has more outstanding than the budget, and every
+    result equals the same request run alone."""
+    import paper_2608_01503_amd as L
+    large = [gg.rmat(14, seed=30 + k) for k in range(3)] + [gg.lattice(150, 150, seed=k) for k in range(2)]
+    small = [gg.random_gnp(300 + 40 * k, 0.02, 50 + k, w_max=3) for k in range(24)]
+    budget = 2 * max(_footprint(g, L.LCC_PLOUVAIN) for g in large) + (8 << 20)
+    a = CountingAllocator()
+    ctx = L.Context(0, allocator=(a.alloc, a.free))
+    srv = L.Server(ctx, budget)
+    tickets, meta = {}, {}
+    jobs = [(g, L.LCC_PLOUVAIN) for g in large] + [(g, L.LCC_LOUVAIN) for g in small]
+    jobs += [(large[0], L.LCC_PLEIDEN), (large[3], L.LCC_PLEIDEN_PLUS)]
+    order = np.random.default_rng(1).permutation(len(jobs))
+    for i in order:
+        g, v = jobs[i]
+        t = srv.submit(U.host_graph(g, O.VW_WEIGHTED_DEGREE), (1, 1, True), v)
+        tickets[t] = g.n
+        meta[t] = (g, v)
+    done = _drain(srv, tickets)
+    srv.close()
+    assert a.peak <= budget, (a.peak, budget)
+    assert not a.live  # every slot context returned its memory when the server closed
+    for t, r in done.items():
+        g, v = meta[t]
+        assert not isinstance(r, Exception), r
+        alone, ares = U.run_gpu(g, v, (1, 1, True), O.VW_WEIGHTED_DEGREE, trace=False)
+        assert np.array_equal(r[0], alone) and r[1].N == ares.N, (g.name, v)
+    ctx.close()
+
+
+def test_server_refuses_a_job_that_outgrows_the_budget_alone():
+    """A budget equal to a job's footprint estimate while the job needs more (Louvain+ keeps every coarse level,
+    and a slow coarsening keeps more than two input-sized levels): the job is refused the memory, rerun alone,
+    refused again and reported as LCC_ERR_OOM; the server then runs the next job normally."""
+    import paper_2608_01503_amd as L
+    # an 80 x 80 unit-weight grid under CPM 2/3: each level merges few vertices, 13 levels of similar size
+    cands = [(gg.lattice(80, 80, 0.0, 1, seed=2), (2, 3, False)), (gg.lattice(80, 80, 0.0, 1, seed=2), (3, 4, False))]
+    a = CountingAllocator()
+    pick = None
+    for g, lam in cands:
+        probe = L.Context(0, allocator=(a.alloc, a.free))
+        a.peak = 0
+        probe.cluster(U.host_graph(g, O.VW_UNIT), lam, L.LCC_PLOUVAIN)
+        probe.close()
+        if a.peak > _footprint(g, L.LCC_PLOUVAIN):
+            pick = (g, lam)
+            break
+    if pick is None:
+        pytest.skip("every candidate's coarse levels fit the footprint estimate")
+    g, lam = pick
+    ctx = L.Context(0, allocator=(a.alloc, a.free))
+    srv = L.Server(ctx, _footprint(g, L.LCC_PLOUVAIN))
+    t = srv.submit(U.host_graph(g, O.VW_UNIT), lam, L.LCC_PLOUVAIN)
+    done = _drain(srv, {t: g.n})
+    assert isinstance(done[t], L.LccError) and done[t].status == -8
+    small = gg.random_gnp(200, 0.03, 9)
+    t2 = srv.submit(U.host_graph(small, O.VW_WEIGHTED_DEGREE), (1, 1, True), L.LCC_PLOUVAIN)
+    r = _drain(srv, {t2: small.n})[t2]
+    ref = O.cluster(small, O.PLOUVAIN, lam=(1, 1, True), vw_mode=O.VW_WEIGHTED_DEGREE)
+    assert not isinstance(r, Exception) and np.array_equal(r[0], ref.labels)
+    srv.close()
     ctx.close()
