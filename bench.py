@@ -321,7 +321,7 @@ def bench_knn_batch(args):
         plain_res.append(r)
     torch.cuda.synchronize()
     plain_wall = time.perf_counter() - tp
-    plain_labels = [o.clone() for o in outs[:8]]
+    plain_labels = torch.cat(outs)  # every graph's labels from its plain call
     done = np.cumsum(dur)
     # fused: one warm-up call (union workspace), then the timed call
     ctx.cluster_batch(graphs, lam, var, opts=opts, labels_out=outs)
@@ -333,8 +333,9 @@ def bench_knn_batch(args):
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - tf)
     fused_wall = float(np.median(walls))
+    # every graph: labels, exact objective and cluster count of the fused call equal its plain call's
     same = all(a.N == b.N and a.num_clusters == b.num_clusters for a, b in zip(plain_res, fres)) and \
-        all(torch.equal(plain_labels[i], outs[i]) for i in range(len(plain_labels)))
+        torch.equal(plain_labels, torch.cat(outs))
     pct = lambda x, q: float(np.percentile(np.asarray(x), q))
     leg = {"workload": f"{len(graphs)} kNN graphs (k=15, 50-D Gaussian mixtures), pLouvain+ modularity",
            "graphs": len(graphs), "nnz": nnz, "generation_s": gen_s,
@@ -342,7 +343,7 @@ def bench_knn_batch(args):
                        "edges_per_s": nnz / fused_wall},
            "plain": {"wall_s": plain_wall, "p50_latency_s": pct(done, 50), "p99_latency_s": pct(done, 99),
                      "p50_call_s": pct(dur, 50), "p99_call_s": pct(dur, 99), "edges_per_s": nnz / plain_wall},
-           "results_identical": bool(same)}
+           "results_identical": bool(same), "graphs_compared": len(graphs)}
     if not args.workload == "knn":
         ctx.close()
         return leg
@@ -359,7 +360,7 @@ def bench_knn_batch(args):
         "plain": {"wall_s": plain_wall, "p50_latency_s": pct(done, 50), "p99_latency_s": pct(done, 99),
                   "p50_call_s": pct(dur, 50), "p99_call_s": pct(dur, 99), "edges_per_s": nnz / plain_wall},
         "speedup_wall": plain_wall / fused_wall,
-        "results_identical": bool(same),
+        "results_identical": bool(same), "graphs_compared": len(graphs),
     }
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -421,15 +422,16 @@ def bench_serve(args, loads=(0.5, 0.8, 0.95)):
         qps = load * qps_sat
         arr = np.cumsum(rng.exponential(1.0 / qps, size=len(items)))
         # FIFO: one request at a time, in arrival order
-        fifo_lat, fifo_N = [], []
+        fifo_lat, fifo_N, fifo_lab = [], [], []
         start = time.perf_counter()
         for (g, gr, lam, v), ta in zip(items, arr):
             now = time.perf_counter() - start
             if now < ta:
                 time.sleep(ta - now)
-            _, r = ctx.cluster(gr, lam, v, opts)
+            lab, r = ctx.cluster(gr, lam, v, opts)
             fifo_lat.append(time.perf_counter() - start - ta)
             fifo_N.append(r.N)
+            fifo_lab.append(lab)
             if len(fifo_lat) % 50 == 0:
                 print(f"# load {load} fifo: {len(fifo_lat)} requests done", file=sys.stderr, flush=True)
         fifo_span = time.perf_counter() - start
@@ -437,6 +439,7 @@ def bench_serve(args, loads=(0.5, 0.8, 0.95)):
         tickets = [None] * len(items)
         done_at = [None] * len(items)
         srv_N = [None] * len(items)
+        srv_lab = [None] * len(items)
         start = time.perf_counter()
 
         def submitter():
@@ -457,6 +460,7 @@ def bench_serve(args, loads=(0.5, 0.8, 0.95)):
                 if r is not None:
                     done_at[k] = time.perf_counter() - start
                     srv_N[k] = r[1].N
+                    srv_lab[k] = r[0]
                     left.discard(k)
                     if len(left) % 50 == 0:
                         print(f"# load {load} server: {len(left)} requests left", file=sys.stderr, flush=True)
@@ -471,7 +475,10 @@ def bench_serve(args, loads=(0.5, 0.8, 0.95)):
                               "edges_per_s": sum(it[0].nnz for it in items) / fifo_span},
                      "server": {"p50_s": pct(srv_lat[w0:], 50), "p99_s": pct(srv_lat[w0:], 99),
                                 "edges_per_s": sum(it[0].nnz for it in items) / srv_span},
-                     "results_identical": fifo_N == srv_N, "measured_requests": len(items) - w0,
+                     # every request: labels and exact objective from the server equal its plain call's
+                     "results_identical": fifo_N == srv_N and all(
+                         np.array_equal(np.asarray(a), np.asarray(b)) for a, b in zip(fifo_lab, srv_lab)),
+                     "measured_requests": len(items) - w0,
                      "measured_edges": edges})
         print(f"# load {load}: fifo p99 {runs[-1]['fifo']['p99_s']:.4f} s, server p99 {runs[-1]['server']['p99_s']:.4f} s",
               file=sys.stderr, flush=True)

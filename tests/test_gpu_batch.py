@@ -105,7 +105,7 @@ def test_knn_generator_device_matches_host():
 
 def test_fused_knn_batch_full_size_sample():
     """48 graphs of the batched kNN workload at their full sizes (500..50,000 vertices) in one fused call:
-    every graph equals its own plain call, and a sample (the largest included) equals the oracle."""
+    every graph equals its own plain call, and every third graph (the largest included) equals the oracle."""
     import torch
     import paper_2608_01503_amd as L
     dev = torch.device("cuda:0")
@@ -123,7 +123,7 @@ def test_fused_knn_batch_full_size_sample():
         torch.cuda.synchronize()
         assert torch.equal(lab, labs[i]) and res.N == ress[i].N and res.levels == ress[i].levels, i
     big = max(range(len(graphs)), key=lambda i: graphs[i].n)
-    for i in sorted({big, 0, 7, 19, 33}):
+    for i in sorted({big} | set(range(0, len(graphs), 3))):
         off, idx, w = keep[i]
         g = gg.Graph(n=graphs[i].n, off=off.cpu().numpy(), idx=idx.cpu().numpy(), w=w.cpu().numpy())
         ref = O.cluster(g, O.PLOUVAIN, lam=(1, 1, True), vw_mode=O.VW_WEIGHTED_DEGREE)
