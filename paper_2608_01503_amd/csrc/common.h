@@ -286,9 +286,18 @@ void offsets32_to_64(const int32_t* in, int64_t* out, int64_t n1, hipStream_t st
 void launch_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* ctrl, hipStream_t st);
 // Union levels: vw_mode per graph (gmode[gid[v]]) when gmode is not null; rowsum (if not null) receives
 // every vertex's weighted degree.
+// Buffers of the exact symmetry check: nnz (key, value) pairs twice (sort ping-pong) and radix_temp_bytes(nnz)
+// of temp; k0 == null skips the check.
+struct SymBuffers {
+  uint64_t* k0 = nullptr;
+  uint32_t* v0 = nullptr;
+  uint64_t* k1 = nullptr;
+  uint32_t* v1 = nullptr;
+  void* temp = nullptr;
+};
 void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, const int64_t* vw_given,
-                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st, const int32_t* gid = nullptr,
-                          const int8_t* gmode = nullptr, int64_t* rowsum = nullptr);
+                          int64_t* vw_out, Ctrl* ctrl, hipStream_t st, const SymBuffers& sb,
+                          const int32_t* gid = nullptr, const int8_t* gmode = nullptr, int64_t* rowsum = nullptr);
 // Degree buckets of the vertices of a level; with gid/gact only the vertices whose graph has gact set.
 void launch_buckets(const int64_t* off, int64_t n, int32_t* list, Ctrl* ctrl, const BucketBounds& bb, hipStream_t st,
                     const int32_t* gid = nullptr, const uint8_t* gact = nullptr);

@@ -957,10 +957,17 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
-  launch_validate_rows(L.g, L.b, (int)g->vw_mode, vwg, w.vw0, w.ctrl, st);
+  const auto sym_mark = ctx->pool_mark();  // the symmetry check's sort scratch is released below
+  SymBuffers sb;
+  if (R.o.validate) {
+    sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
+    sb.temp = ctx->pool_take(radix_temp_bytes(nnz));
+  }
+  launch_validate_rows(L.g, L.b, (int)g->vw_mode, vwg, w.vw0, w.ctrl, st, sb);
   launch_vertex_sums(w.vw0, n, w.ctrl, st);
   if (init_labels) k_labels_in_range<<<grid1(n), BLOCK, 0, st>>>(init_labels, n, w.ctrl);
   R.read_ctrl("validate rows");
+  ctx->pool_release(sym_mark);
   const Ctrl& c = *ctx->h_ctrl;
   uint32_t e = c.err_bits;
   if (!R.o.validate) e &= ERRB_INVALID | ERRB_VW_TOO_BIG;  // structural faults that would break the kernels
@@ -968,7 +975,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
   if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
   if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
-  if ((e & ERRB_NOT_SYMMETRIC) || (R.o.validate && c.count0 != 0)) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
+  if (e & ERRB_NOT_SYMMETRIC) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
   if (c.sum_we >= ((uint64_t)1 << 32)) fail(LCC_ERR_OVERFLOW, "total edge weight >= 2^32");
   if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
   L.sum_w2 = (int64_t)c.sum_w2;
@@ -1406,7 +1413,13 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
-  launch_validate_rows(L.g, L.b, LCC_VW_UNIT, any_given ? w.in_vwg : nullptr, w.vw0, w.ctrl, st, w.gid0, gmode,
+  const auto sym_mark = ctx->pool_mark();  // the symmetry check's sort scratch is released below
+  SymBuffers sb;
+  if (R.o.validate) {
+    sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
+    sb.temp = ctx->pool_take(radix_temp_bytes(nnz));
+  }
+  launch_validate_rows(L.g, L.b, LCC_VW_UNIT, any_given ? w.in_vwg : nullptr, w.vw0, w.ctrl, st, sb, w.gid0, gmode,
                        w.t64b);
   launch_seg_sum(w.vw0, 0, L.vbase, G, gW, st);
   launch_seg_sum(w.t64b, 0, L.vbase, G, gW + G, st);
@@ -1415,6 +1428,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   std::vector<int64_t> hW((size_t)(3 * G));
   hip_check(hipMemcpyAsync(hW.data(), gW, sizeof(int64_t) * 3 * G, hipMemcpyDeviceToHost, st), "graph sums");
   R.read_ctrl("validate rows");
+  ctx->pool_release(sym_mark);
   const Ctrl& c = *ctx->h_ctrl;
   uint32_t e = c.err_bits;
   if (!R.o.validate) e &= ERRB_INVALID | ERRB_VW_TOO_BIG;
@@ -1422,8 +1436,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
   if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
   if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
-  if ((e & ERRB_NOT_SYMMETRIC) || (R.o.validate && c.count0 != 0))
-    fail(LCC_ERR_NOT_SYMMETRIC, "a graph of the batch is not symmetric");
+  if (e & ERRB_NOT_SYMMETRIC) fail(LCC_ERR_NOT_SYMMETRIC, "a graph of the batch is not symmetric");
   if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
   std::vector<Score> sc((size_t)G);
   for (int64_t i = 0; i < G; ++i) {
