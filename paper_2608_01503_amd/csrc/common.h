@@ -286,15 +286,20 @@ void offsets32_to_64(const int32_t* in, int64_t* out, int64_t n1, hipStream_t st
 void launch_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* ctrl, hipStream_t st);
 // Union levels: vw_mode per graph (gmode[gid[v]]) when gmode is not null; rowsum (if not null) receives
 // every vertex's weighted degree.
-// Buffers of the exact symmetry check: nnz (key, value) pairs twice (sort ping-pong) and radix_temp_bytes(nnz)
-// of temp; k0 == null skips the check.
+// The exact symmetry check: by search (search = true; the balance lands in ctrl->count0 and must be 0), or by
+// transposition (k0 set: nnz (key, value) pairs twice for the sort's ping-pong and radix_temp_bytes(nnz) of
+// temp), or none.
 struct SymBuffers {
+  bool search = false;
   uint64_t* k0 = nullptr;
   uint32_t* v0 = nullptr;
   uint64_t* k1 = nullptr;
   uint32_t* v1 = nullptr;
   void* temp = nullptr;
 };
+// Graphs (of a union: its largest graph) up to this many entries are checked by search: the rows a search
+// visits stay in cache.  Larger ones by transposition.
+constexpr int64_t SYM_SEARCH_MAX_NNZ = (int64_t)1 << 23;
 void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, const int64_t* vw_given,
                           int64_t* vw_out, Ctrl* ctrl, hipStream_t st, const SymBuffers& sb,
                           const int32_t* gid = nullptr, const int8_t* gmode = nullptr, int64_t* rowsum = nullptr);

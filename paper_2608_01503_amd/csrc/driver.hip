@@ -959,7 +959,9 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   }
   const auto sym_mark = ctx->pool_mark();  // the symmetry check's sort scratch is released below
   SymBuffers sb;
-  if (R.o.validate) {
+  if (R.o.validate && nnz <= SYM_SEARCH_MAX_NNZ) {
+    sb.search = true;
+  } else if (R.o.validate) {
     sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
     sb.temp = ctx->pool_take(radix_temp_bytes(nnz));
   }
@@ -975,7 +977,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
   if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
   if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
-  if (e & ERRB_NOT_SYMMETRIC) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
+  if ((e & ERRB_NOT_SYMMETRIC) || (sb.search && c.count0 != 0)) fail(LCC_ERR_NOT_SYMMETRIC, "the graph is not symmetric");
   if (c.sum_we >= ((uint64_t)1 << 32)) fail(LCC_ERR_OVERFLOW, "total edge weight >= 2^32");
   if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
   L.sum_w2 = (int64_t)c.sum_w2;
@@ -1415,7 +1417,11 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   }
   const auto sym_mark = ctx->pool_mark();  // the symmetry check's sort scratch is released below
   SymBuffers sb;
-  if (R.o.validate) {
+  int64_t max_nnz = 0;
+  for (int64_t i = 0; i < G; ++i) max_nnz = std::max(max_nnz, gs[i].nnz);
+  if (R.o.validate && max_nnz <= SYM_SEARCH_MAX_NNZ) {
+    sb.search = true;  // every graph's rows are local: the searches stay in cache
+  } else if (R.o.validate) {
     sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
     sb.temp = ctx->pool_take(radix_temp_bytes(nnz));
   }
@@ -1436,7 +1442,8 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   if (e & ERRB_SELF_LOOP) fail(LCC_ERR_SELF_LOOP, "a row contains its own vertex");
   if (e & ERRB_UNSORTED) fail(LCC_ERR_UNSORTED, "a row is not strictly ascending");
   if (e & ERRB_WEIGHT) fail(LCC_ERR_WEIGHT, "an edge weight <= 0 or a vertex weight < 0");
-  if (e & ERRB_NOT_SYMMETRIC) fail(LCC_ERR_NOT_SYMMETRIC, "a graph of the batch is not symmetric");
+  if ((e & ERRB_NOT_SYMMETRIC) || (sb.search && c.count0 != 0))
+    fail(LCC_ERR_NOT_SYMMETRIC, "a graph of the batch is not symmetric");
   if (e & ERRB_VW_TOO_BIG) fail(LCC_ERR_OVERFLOW, "a vertex weight >= 2^31");
   std::vector<Score> sc((size_t)G);
   for (int64_t i = 0; i < G; ++i) {

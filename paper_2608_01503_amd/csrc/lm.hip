@@ -1576,18 +1576,37 @@ __global__ void k_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, C
     if (off[v + 1] < off[v]) atomicOr(&ctrl->err_bits, ERRB_INVALID);
 }
 
-// Exact symmetry.  Every entry j = (v, u, w) of row v is also written as the key (u << 32 | v) with value w.
-// A stable sort of these pairs by u alone keeps, for each u, the entries in the order of their rows v, so the
-// sorted sequence is the transposed CSR in canonical order; the graph is symmetric iff it equals the CSR
-// itself entry by entry (k_sym_compare).  A row that is not ascending is reported as unsorted first.
+// Exact symmetry, two ways (the driver picks one per call; both give the same verdict):
+//  - by transposition: every entry j = (v, u, w) of row v is also written as the key (u << 32 | v) with value
+//    w.  A stable sort of these pairs by u alone keeps, for each u, the entries in the order of their rows v,
+//    so the sorted sequence is the transposed CSR in canonical order; the graph is symmetric iff it equals the
+//    CSR itself entry by entry (k_sym_compare).  Cost: a few streaming passes, whatever the layout.
+//  - by search (keys == null, search set): vertices are ranked by (row length, id); every entry (v, u) whose
+//    target u ranks below v must find (u, v) of the same weight in row u (binary search, rows ascending), and
+//    these entries must be exactly as many as those whose target ranks above.  The first condition maps them
+//    one-to-one onto entries (u, v) whose target v ranks above u (rows hold no duplicate); with equal counts
+//    that map is onto, so every entry has its reverse.  Each search runs in the shorter row of its pair: cheap
+//    when the rows a search visits are in cache (graphs of a few million entries, or a union of such graphs),
+//    line-miss bound otherwise.
+// A row that is not ascending is reported as unsorted first.
 struct EdgeCheck {
   uint32_t err = 0;
+  int64_t balance = 0;  // entries towards a lower-ranked vertex minus entries towards a higher-ranked one
   int64_t ws = 0;
 };
 
-// entry j = (v, u) of row v, which starts at rb
-__device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t j, int64_t rb, EdgeCheck& ec,
-                                           uint64_t* keys, uint32_t* vals) {
+__device__ __forceinline__ bool found_in_row(const DevGraph& g, int64_t lo, int64_t end, int32_t v, int32_t wt) {
+  int64_t hi = end;
+  while (lo < hi) {  // first position holding an id >= v
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (g.idx[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo < end && g.idx[lo] == v && g.w[lo] == wt;
+}
+
+// entry j = (v, u) of row v, which starts at rb and holds dv entries
+__device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t j, int64_t rb, int64_t dv,
+                                           EdgeCheck& ec, uint64_t* keys, uint32_t* vals, bool search) {
   int32_t u = g.idx[j];
   int32_t wt = g.w[j];
   ec.ws += wt;
@@ -1599,6 +1618,14 @@ __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t
   if (u == v) { ec.err |= ERRB_SELF_LOOP; return; }
   if (j > rb && g.idx[j - 1] >= u) ec.err |= ERRB_UNSORTED;
   if (wt <= 0) ec.err |= ERRB_WEIGHT;
+  if (!search) return;
+  const int64_t bu = g.off[u], eu = g.off[u + 1], du = eu - bu;
+  if (du < dv || (du == dv && u < v)) {
+    ++ec.balance;
+    if (!found_in_row(g, bu, eu, v, wt)) ec.err |= ERRB_NOT_SYMMETRIC;
+  } else {
+    --ec.balance;
+  }
 }
 
 // The sorted (u << 32 | v, w) pairs against the CSR: position j must hold (row of j, idx[j], w[j]), that is
@@ -1637,15 +1664,19 @@ __device__ __forceinline__ int64_t vertex_weight(int vw_mode, int64_t ws, const 
 
 __device__ __forceinline__ void flush_check(EdgeCheck ec, int64_t wsum, Ctrl* ctrl) {
   // block-wide: every thread calls this
+  const int64_t bal = sum_reduce<BLOCK>(ec.balance);
   wsum = sum_reduce<BLOCK>(wsum);
   if (ec.err) atomicOr(&ctrl->err_bits, ec.err);
-  if (threadIdx.x == 0 && wsum) atomicAdd((unsigned long long*)&ctrl->sum_we, (unsigned long long)wsum);
+  if (threadIdx.x == 0) {
+    if (bal) atomicAdd((unsigned long long*)&ctrl->count0, (unsigned long long)bal);
+    if (wsum) atomicAdd((unsigned long long*)&ctrl->sum_we, (unsigned long long)wsum);
+  }
 }
 
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int64_t cnt, DevGraph g, VwSrc vm,
                                                         const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl,
-                                                        uint64_t* keys, uint32_t* vals) {
+                                                        uint64_t* keys, uint32_t* vals, bool search) {
   const int gl = threadIdx.x % G;
   EdgeCheck ec;
   int64_t wsum = 0;
@@ -1654,7 +1685,7 @@ __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int
     const int32_t v = list[gid];
     const int64_t rb = g.off[v], re = g.off[v + 1];
     const int64_t ws0 = ec.ws;
-    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, ec, keys, vals);
+    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, re - rb, ec, keys, vals, search);
     int64_t ws = sum_reduce<G>(ec.ws - ws0);
     if (gl == 0) {
       vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
@@ -1667,14 +1698,14 @@ __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int
 
 __global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list, int64_t cnt, DevGraph g, VwSrc vm,
                                                             const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl,
-                                                            uint64_t* keys, uint32_t* vals) {
+                                                            uint64_t* keys, uint32_t* vals, bool search) {
   EdgeCheck ec;
   int64_t wsum = 0;
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
     const int64_t rb = g.off[v], re = g.off[v + 1];
     const int64_t ws0 = ec.ws;
-    for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, ec, keys, vals);
+    for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, re - rb, ec, keys, vals, search);
     int64_t ws = sum_reduce<BIG_BLOCK>(ec.ws - ws0);
     if (threadIdx.x == 0) {
       vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
@@ -1688,14 +1719,14 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list,
 // hubs: chunk sums of the weighted degree land in hsum[k] (zeroed beforehand)
 __global__ __launch_bounds__(HUB_BLOCK) void k_validate_hub(const int32_t* hubs, const int32_t* chunk_off,
                                                             int64_t n7, DevGraph g, int64_t* hsum, Ctrl* ctrl,
-                                                            uint64_t* keys, uint32_t* vals) {
+                                                            uint64_t* keys, uint32_t* vals, bool search) {
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
   const int64_t rb = g.off[v];
   const int64_t j0 = rb + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   EdgeCheck ec;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) check_edge(g, v, j, rb, ec, keys, vals);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) check_edge(g, v, j, rb, g.off[v + 1] - rb, ec, keys, vals, search);
   int64_t ws = sum_reduce<HUB_BLOCK>(ec.ws);
   if (threadIdx.x == 0 && ws) atomicAdd((unsigned long long*)&hsum[k], (unsigned long long)ws);
   flush_check(ec, threadIdx.x == 0 ? ws : 0, ctrl);
@@ -1797,17 +1828,17 @@ void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, cons
   const VwSrc vm{vw_mode, gid, gmode, rowsum};
   uint64_t* keys = sb.k0;
   uint32_t* vals = sb.v0;
-  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vm, vw_given, vw_out, ctrl, keys, vals);
-  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vm, vw_given, vw_out, ctrl, keys, vals);
-  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vm, vw_given, vw_out, ctrl, keys, vals);
-  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vm, vw_given, vw_out, ctrl, keys, vals);
+  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
+  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
+  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
+  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
   int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_validate_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vm, vw_given, vw_out, ctrl, keys, vals);
-  if (b.count[6]) k_validate_blk<<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vm, vw_given, vw_out, ctrl, keys, vals);
+  if (nw) k_validate_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
+  if (b.count[6]) k_validate_blk<<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
   if (b.count[7]) {
     const int32_t* hubs = L + b.off[7];
     fill_i64(b.hub_acc, 0, b.count[7], st);
-    k_validate_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, b.hub_acc, ctrl, keys, vals);
+    k_validate_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, b.hub_acc, ctrl, keys, vals, sb.search);
     k_validate_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vm, vw_given, b.hub_acc, vw_out, ctrl);
   }
   if (keys && g.nnz > 0) {  // symmetry: the pairs sorted by their target, then compared with the CSR

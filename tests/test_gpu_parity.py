@@ -162,6 +162,31 @@ def test_symmetry_check_is_exact(where):
         assert _status_gpu(bad2, *MOD) == -2
 
 
+def test_symmetry_check_by_transposition():
+    """Graphs above 2^23 entries are checked by transposing (stable sort by target, then an entry-by-entry
+    comparison with the CSR) instead of searching: one weight changed on one side, one entry moved to another
+    neighbour, or one reverse entry of a hub edge missing are each NOT_SYMMETRIC, as in the oracle, and the
+    unmodified graph passes."""
+    g = gg.rmat(19, seed=3)
+    assert g.nnz > 2 ** 23
+    assert _status_gpu(g, *MOD) == 0
+    deg = np.diff(g.off)
+    hub = int(np.argmax(deg))
+    mid = int(np.nonzero((deg > 32) & (deg <= 128))[0][7])
+    w = g.w.copy()
+    w[g.off[mid] + 3] += 1
+    bad = gg.Graph(n=g.n, off=g.off, idx=g.idx, w=w)
+    assert O.setup(bad)[0] == -2 and _status_gpu(bad, *MOD) == -2
+    # the last entry of the hub's row moved to a larger id whose row has no entry for the hub
+    idx = g.idx.copy()
+    j = g.off[hub + 1] - 1
+    u = next(x for x in range(int(idx[j]) + 1, g.n)
+             if x != hub and hub not in g.idx[g.off[x]:g.off[x + 1]])
+    idx[j] = u
+    bad2 = gg.Graph(n=g.n, off=g.off, idx=idx, w=g.w)
+    assert O.setup(bad2)[0] == -2 and _status_gpu(bad2, *MOD) == -2
+
+
 HEAVY = [("rmat12", lambda: gg.rmat(12, seed=11), O.PLOUVAIN),
          ("hubs", lambda: U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=4), O.PLEIDEN_PLUS),
          ("lattice", lambda: gg.lattice(40, 40, seed=7), O.PLEIDEN),
