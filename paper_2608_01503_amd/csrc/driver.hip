@@ -210,6 +210,7 @@ struct lcc_ctx {
   Arena* arena = nullptr;       // set for the duration of a no-allocation call
   Ctrl* h_ctrl = nullptr;       // pinned mirror
   LMSlot* h_slots = nullptr;    // pinned mirror
+  int32_t* h_count = nullptr;   // pinned: a label count copied back beside another read
   std::mutex mu;
   // kernel timing (diagnostics)
   uint64_t prof_mask = 0;
@@ -568,6 +569,13 @@ struct Run {
     return ctx->h_slots[s];
   }
 
+  // w.rank = the label rank of `labels`; their count lands in *ctx->h_count at the next synchronisation (no
+  // synchronisation of its own: it rides on the next read)
+  void rank_labels(const int32_t* labels, int64_t n) {
+    launch_label_rank(labels, n, w.used, w.rank, w.scan_temp, st);
+    hip_check(hipMemcpyAsync(ctx->h_count, w.rank + n, sizeof(int32_t), hipMemcpyDeviceToHost, st), "count");
+  }
+
   int64_t count_labels(const int32_t* labels, int64_t n) {
     launch_label_rank(labels, n, w.used, w.rank, w.scan_temp, st);
     int32_t nc = 0;
@@ -685,8 +693,9 @@ struct Run {
     for (;;) {
       int s = local_move_level(l, !(l == 0 && init), 0);
       Level& L = lv[l];
-      int64_t nc = count_labels(L.C, L.g.n);
+      rank_labels(L.C, L.g.n);
       LMSlot S = read_slot(s);
+      const int64_t nc = *ctx->h_count;
       rec(2, l, 0, 0, L.g.n, L.g.nnz, nc, S.Nbest);
       if (nc == L.g.n) break;
       if (l + 1 >= o.max_levels) { flags |= LCC_FLAG_LEVEL_CAP; break; }
@@ -699,8 +708,9 @@ struct Run {
       launch_project(lv[k + 1].C, L.map, L.g.n, L.C, st);
       if (plus) {
         int s = local_move_level(k, false, 1);
-        int64_t nc = count_labels(L.C, L.g.n);
+        rank_labels(L.C, L.g.n);
         LMSlot S = read_slot(s);
+        const int64_t nc = *ctx->h_count;
         rec(2, k, 1, 0, L.g.n, L.g.nnz, nc, S.Nbest);
       }
     }
@@ -783,6 +793,7 @@ struct Run {
       const int64_t n = L.g.n;
       int s = local_move_level(l, singleton, 0);
       singleton = false;
+      rank_labels(L.C, n);  // the count of C_l, unless the alternate move below changes it
       LMSlot S = read_slot(s);
       int64_t N = S.Nbest;
       if (S.Nbest == S.N0) {
@@ -799,12 +810,13 @@ struct Run {
         copy_i32(L.C, w.C, n, st);
         launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         launch_objective(L.g, L.b, w.C, w.W, w.ctrl, st);
+        rank_labels(L.C, n);
         read_ctrl("lmalt");  // the stream is done with the scratch
         ctx->pool_release(mark);
         N = q * ctx->h_ctrl->obj_I - p * (ctx->h_ctrl->obj_SW2 - L.sum_w2);
         rec(3, l, 0, 0, ctx->h_ctrl->lmalt_k, ctx->h_ctrl->lmalt_best_k, N, 0);
       }
-      int64_t nc = count_labels(L.C, n);
+      const int64_t nc = *ctx->h_count;
       rec(2, l, 0, 0, n, L.g.nnz, nc, N);
       if (nc == n) break;
       if (l + 1 >= o.max_levels) { flags |= LCC_FLAG_LEVEL_CAP; break; }
@@ -817,8 +829,9 @@ struct Run {
                st);
         ctx->pool_release(mk);
       }
-      int64_t nR = count_labels(R, n);
+      rank_labels(R, n);
       read_ctrl("refine");
+      const int64_t nR = *ctx->h_count;
       if (ctx->h_ctrl->err_bits & ERRB_INTERNAL) fail(LCC_ERR_DEVICE, "refinement produced a parent cycle");
       rec(4, l, 0, 0, nR, (int64_t)refine_calls, ctx->h_ctrl->refine_U, ctx->h_ctrl->refine_m);
       ++refine_calls;
@@ -830,7 +843,7 @@ struct Run {
       contract(l, R, nR);
       // Downsample: C_{l+1}[x] = compact(C_l)[C_l[v]] for any v in x
       Level& L2 = lv[l];
-      count_labels(L2.C, n);  // w.rank = compaction of C_l
+      launch_label_rank(L2.C, n, w.used, w.rank, w.scan_temp, st);  // w.rank = compaction of C_l
       launch_downsample(L2.C, w.rank, L2.map, n, lv[l + 1].C, st);
       ++l;
     }
@@ -840,8 +853,9 @@ struct Run {
       launch_project(lv[k + 1].C, L.map, L.g.n, L.C, st);
       if (plus) {
         int s = local_move_level(k, false, 1);
-        int64_t nc = count_labels(L.C, L.g.n);
+        rank_labels(L.C, L.g.n);
         LMSlot S = read_slot(s);
+        const int64_t nc = *ctx->h_count;
         rec(2, k, 1, 0, L.g.n, L.g.nnz, nc, S.Nbest);
       }
     }
@@ -1532,7 +1546,10 @@ lcc_status lcc_create(int device, lcc_alloc_fn alloc, lcc_free_fn free_fn, void*
     c->freef = free_fn;
     c->user = user;
     if (hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_slots, sizeof(LMSlot) * NSLOT) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_slots, sizeof(LMSlot) * NSLOT) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_count, 64) != hipSuccess) {
+      if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
+      if (c->h_slots) (void)hipHostFree(c->h_slots);
       delete c;
       fail(LCC_ERR_DEVICE, "pinned host allocation failed");
     }
@@ -1553,6 +1570,7 @@ lcc_status lcc_destroy(lcc_ctx* ctx) {
       ctx->pool.chunks.clear();
       if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
       if (ctx->h_slots) (void)hipHostFree(ctx->h_slots);
+      if (ctx->h_count) (void)hipHostFree(ctx->h_count);
       for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     }
     delete ctx;
