@@ -89,6 +89,7 @@ struct LMSlot {
   int64_t n_empty;              // movers to a new singleton in the current pass
   int64_t Nbest;                // objective numerator of C_out
   int64_t N0;                   // objective numerator of the starting clustering
+  int64_t nlab;                 // distinct labels of the clustering the driver ranked after the call
 };
 
 // Scalars shared by the driver and the kernels.
@@ -109,6 +110,7 @@ struct Ctrl {
   int64_t lmalt_best;
   int64_t bucket_edges[NBUCKET];  // sum of degrees per bucket (level being prepared)
   int64_t enum_bytes[NBUCKET];    // algorithmic bytes of the enumeration launches, per bucket (accumulated)
+  int64_t nlab;                   // distinct labels of the clustering the driver ranked last
 };
 
 enum : uint32_t {
@@ -275,6 +277,7 @@ size_t radix_temp_bytes(int64_t m);
 int radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int64_t m, const int* shifts,
                      int npass, void* temp, hipStream_t st);
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+void store_count(const int32_t* src, int64_t* dst, hipStream_t st);  // *dst = *src on the device
 void fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
 void fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 void zero_bytes(void* p, size_t bytes, hipStream_t st);  // a fill kernel, safe inside captured graphs
@@ -298,8 +301,10 @@ struct SymBuffers {
   void* temp = nullptr;
 };
 // Graphs (of a union: its largest graph) up to this many entries are checked by search: the rows a search
-// visits stay in cache.  Larger ones by transposition.
+// visits stay in cache.  So are graphs of at most SYM_SEARCH_MAX_AVG_DEG entries per row (half an entry per
+// row searches, one short row each, against four sort passes over every entry).  Others by transposition.
 constexpr int64_t SYM_SEARCH_MAX_NNZ = (int64_t)1 << 23;
+constexpr int64_t SYM_SEARCH_MAX_AVG_DEG = 8;
 void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, const int64_t* vw_given,
                           int64_t* vw_out, Ctrl* ctrl, hipStream_t st, const SymBuffers& sb,
                           const int32_t* gid = nullptr, const int8_t* gmode = nullptr, int64_t* rowsum = nullptr);

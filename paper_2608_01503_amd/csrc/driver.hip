@@ -210,7 +210,6 @@ struct lcc_ctx {
   Arena* arena = nullptr;       // set for the duration of a no-allocation call
   Ctrl* h_ctrl = nullptr;       // pinned mirror
   LMSlot* h_slots = nullptr;    // pinned mirror
-  int32_t* h_count = nullptr;   // pinned: a label count copied back beside another read
   std::mutex mu;
   // kernel timing (diagnostics)
   uint64_t prof_mask = 0;
@@ -569,11 +568,11 @@ struct Run {
     return ctx->h_slots[s];
   }
 
-  // w.rank = the label rank of `labels`; their count lands in *ctx->h_count at the next synchronisation (no
-  // synchronisation of its own: it rides on the next read)
-  void rank_labels(const int32_t* labels, int64_t n) {
+  // w.rank = the label rank of `labels`; their count is stored on the device at *dst (a field of a slot or of
+  // the control block), so it comes back with the next read of that block: no copy or synchronisation of its own
+  void rank_labels(const int32_t* labels, int64_t n, int64_t* dst) {
     launch_label_rank(labels, n, w.used, w.rank, w.scan_temp, st);
-    hip_check(hipMemcpyAsync(ctx->h_count, w.rank + n, sizeof(int32_t), hipMemcpyDeviceToHost, st), "count");
+    store_count(w.rank + n, dst, st);
   }
 
   int64_t count_labels(const int32_t* labels, int64_t n) {
@@ -693,9 +692,9 @@ struct Run {
     for (;;) {
       int s = local_move_level(l, !(l == 0 && init), 0);
       Level& L = lv[l];
-      rank_labels(L.C, L.g.n);
+      rank_labels(L.C, L.g.n, &w.slots[s].nlab);
       LMSlot S = read_slot(s);
-      const int64_t nc = *ctx->h_count;
+      const int64_t nc = S.nlab;
       rec(2, l, 0, 0, L.g.n, L.g.nnz, nc, S.Nbest);
       if (nc == L.g.n) break;
       if (l + 1 >= o.max_levels) { flags |= LCC_FLAG_LEVEL_CAP; break; }
@@ -708,9 +707,9 @@ struct Run {
       launch_project(lv[k + 1].C, L.map, L.g.n, L.C, st);
       if (plus) {
         int s = local_move_level(k, false, 1);
-        rank_labels(L.C, L.g.n);
+        rank_labels(L.C, L.g.n, &w.slots[s].nlab);
         LMSlot S = read_slot(s);
-        const int64_t nc = *ctx->h_count;
+        const int64_t nc = S.nlab;
         rec(2, k, 1, 0, L.g.n, L.g.nnz, nc, S.Nbest);
       }
     }
@@ -793,8 +792,9 @@ struct Run {
       const int64_t n = L.g.n;
       int s = local_move_level(l, singleton, 0);
       singleton = false;
-      rank_labels(L.C, n);  // the count of C_l, unless the alternate move below changes it
+      rank_labels(L.C, n, &w.slots[s].nlab);  // the count of C_l, unless the alternate move below changes it
       LMSlot S = read_slot(s);
+      int64_t nc = S.nlab;
       int64_t N = S.Nbest;
       if (S.Nbest == S.N0) {
         // C_l unchanged by the local move: the alternate local move (Sec. V-A) from C_l
@@ -810,13 +810,13 @@ struct Run {
         copy_i32(L.C, w.C, n, st);
         launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
         launch_objective(L.g, L.b, w.C, w.W, w.ctrl, st);
-        rank_labels(L.C, n);
+        rank_labels(L.C, n, &w.ctrl->nlab);
         read_ctrl("lmalt");  // the stream is done with the scratch
+        nc = ctx->h_ctrl->nlab;
         ctx->pool_release(mark);
         N = q * ctx->h_ctrl->obj_I - p * (ctx->h_ctrl->obj_SW2 - L.sum_w2);
         rec(3, l, 0, 0, ctx->h_ctrl->lmalt_k, ctx->h_ctrl->lmalt_best_k, N, 0);
       }
-      const int64_t nc = *ctx->h_count;
       rec(2, l, 0, 0, n, L.g.nnz, nc, N);
       if (nc == n) break;
       if (l + 1 >= o.max_levels) { flags |= LCC_FLAG_LEVEL_CAP; break; }
@@ -829,9 +829,9 @@ struct Run {
                st);
         ctx->pool_release(mk);
       }
-      rank_labels(R, n);
+      rank_labels(R, n, &w.ctrl->nlab);
       read_ctrl("refine");
-      const int64_t nR = *ctx->h_count;
+      const int64_t nR = ctx->h_ctrl->nlab;
       if (ctx->h_ctrl->err_bits & ERRB_INTERNAL) fail(LCC_ERR_DEVICE, "refinement produced a parent cycle");
       rec(4, l, 0, 0, nR, (int64_t)refine_calls, ctx->h_ctrl->refine_U, ctx->h_ctrl->refine_m);
       ++refine_calls;
@@ -853,9 +853,9 @@ struct Run {
       launch_project(lv[k + 1].C, L.map, L.g.n, L.C, st);
       if (plus) {
         int s = local_move_level(k, false, 1);
-        rank_labels(L.C, L.g.n);
+        rank_labels(L.C, L.g.n, &w.slots[s].nlab);
         LMSlot S = read_slot(s);
-        const int64_t nc = *ctx->h_count;
+        const int64_t nc = S.nlab;
         rec(2, k, 1, 0, L.g.n, L.g.nnz, nc, S.Nbest);
       }
     }
@@ -973,7 +973,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
   }
   const auto sym_mark = ctx->pool_mark();  // the symmetry check's sort scratch is released below
   SymBuffers sb;
-  if (R.o.validate && nnz <= SYM_SEARCH_MAX_NNZ) {
+  if (R.o.validate && (nnz <= SYM_SEARCH_MAX_NNZ || nnz <= SYM_SEARCH_MAX_AVG_DEG * n)) {
     sb.search = true;
   } else if (R.o.validate) {
     sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
@@ -1433,7 +1433,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   SymBuffers sb;
   int64_t max_nnz = 0;
   for (int64_t i = 0; i < G; ++i) max_nnz = std::max(max_nnz, gs[i].nnz);
-  if (R.o.validate && max_nnz <= SYM_SEARCH_MAX_NNZ) {
+  if (R.o.validate && (max_nnz <= SYM_SEARCH_MAX_NNZ || nnz <= SYM_SEARCH_MAX_AVG_DEG * n)) {
     sb.search = true;  // every graph's rows are local: the searches stay in cache
   } else if (R.o.validate) {
     sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
@@ -1546,8 +1546,7 @@ lcc_status lcc_create(int device, lcc_alloc_fn alloc, lcc_free_fn free_fn, void*
     c->freef = free_fn;
     c->user = user;
     if (hipHostMalloc((void**)&c->h_ctrl, sizeof(Ctrl)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_slots, sizeof(LMSlot) * NSLOT) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_count, 64) != hipSuccess) {
+        hipHostMalloc((void**)&c->h_slots, sizeof(LMSlot) * NSLOT) != hipSuccess) {
       if (c->h_ctrl) (void)hipHostFree(c->h_ctrl);
       if (c->h_slots) (void)hipHostFree(c->h_slots);
       delete c;
@@ -1570,7 +1569,6 @@ lcc_status lcc_destroy(lcc_ctx* ctx) {
       ctx->pool.chunks.clear();
       if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
       if (ctx->h_slots) (void)hipHostFree(ctx->h_slots);
-      if (ctx->h_count) (void)hipHostFree(ctx->h_count);
       for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     }
     delete ctx;

@@ -360,6 +360,10 @@ int radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int
   return (npass & 1) ? 1 : 0;
 }
 
+__global__ void k_store_count(const int32_t* src, int64_t* dst) { *dst = *src; }
+
+void store_count(const int32_t* src, int64_t* dst, hipStream_t st) { k_store_count<<<1, 1, 0, st>>>(src, dst); }
+
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
   if (n > 0) k_fill<int32_t><<<grid_for(n), BLOCK, 0, st>>>(p, v, n);
 }
