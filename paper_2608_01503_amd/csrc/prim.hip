@@ -164,52 +164,73 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint64_t* keys, int6
 
 // Stable scatter.  Items of a tile are taken in rounds of 256 (one per thread, in index order); within a
 // round, a lane's rank among same-digit items is the number of lower lanes of its wavefront with the same
-// digit (ballot match over the 8 digit bits) plus the counts of the earlier wavefronts of the round.
+// digit (ballot match over the 8 digit bits) plus the counts of the earlier wavefronts of the round.  Each
+// item first goes to its place in the tile sorted by digit, in LDS; the sorted tile is then written out with
+// consecutive threads on consecutive positions of each digit's run, so the stores coalesce instead of
+// scattering every round's items over 256 digit runs.
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint64_t* kin, const uint32_t* vin, int64_t m,
-                                                         int shift, const uint32_t* offs, int64_t ntiles,
-                                                         uint64_t* kout, uint32_t* vout) {
-  __shared__ uint32_t base[256];
+                                                         int shift, const uint32_t* hist, const uint32_t* offs,
+                                                         int64_t ntiles, uint64_t* kout, uint32_t* vout) {
+  __shared__ uint64_t tk[RADIX_TILE];
+  __shared__ uint32_t tv[RADIX_TILE];
+  __shared__ uint32_t lbase[256];  // first position of each digit in the sorted tile
+  __shared__ uint32_t lrun[256];   // next free position of each digit in the sorted tile
+  __shared__ uint32_t gbase[256];  // first global position of this tile's items of each digit
   __shared__ uint32_t wcnt[BLOCK / WAVE][256];
   const int tid = threadIdx.x, wv = tid / WAVE, lane = tid & (WAVE - 1);
-  base[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
   const int64_t t0 = (int64_t)blockIdx.x * RADIX_TILE;
+  gbase[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+  {  // the tile's digit counts (from the histogram pass), exclusive-scanned over the digits
+    uint32_t tot = 0;
+    const uint32_t c = hist[(int64_t)tid * ntiles + blockIdx.x];
+    const uint32_t ex = block_excl_scan<uint32_t>(c, &tot);
+    lbase[tid] = ex;
+    lrun[tid] = ex;
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-  for (int r = 0; r < RADIX_TILE / BLOCK; ++r) {
-    if (t0 + r * BLOCK >= m) break;  // block-uniform
+  const int items = (int)min<int64_t>(RADIX_TILE, m - t0);
+  for (int r = 0; r * BLOCK < items; ++r) {  // block-uniform
 #pragma unroll
     for (int k = 0; k < BLOCK / WAVE; ++k) wcnt[k][tid] = 0;
     __syncthreads();
-    int64_t i = t0 + r * BLOCK + tid;
-    bool valid = i < m;
-    uint64_t key = valid ? kin[i] : 0;
-    uint32_t val = valid ? vin[i] : 0;
-    uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const int li = r * BLOCK + tid;
+    const bool valid = li < items;
+    const uint64_t key = valid ? kin[t0 + li] : 0;
+    const uint32_t val = valid ? vin[t0 + li] : 0;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
     uint64_t mask = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       uint64_t bal = __ballot((d >> b) & 1u);
       mask &= ((d >> b) & 1u) ? bal : ~bal;
     }
-    uint32_t prank = (uint32_t)__popcll(mask & lt);
+    const uint32_t prank = (uint32_t)__popcll(mask & lt);
     if (valid && prank == 0) wcnt[wv][d] = (uint32_t)__popcll(mask);
     __syncthreads();
     {
-      uint32_t run = base[tid];
+      uint32_t run = lrun[tid];
 #pragma unroll
       for (int k = 0; k < BLOCK / WAVE; ++k) {
         uint32_t c = wcnt[k][tid];
         wcnt[k][tid] = run;
         run += c;
       }
-      base[tid] = run;
+      lrun[tid] = run;
     }
     __syncthreads();
     if (valid) {
-      uint32_t dst = wcnt[wv][d] + prank;
-      kout[dst] = key;
-      vout[dst] = val;
+      const uint32_t pos = wcnt[wv][d] + prank;
+      tk[pos] = key;
+      tv[pos] = val;
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int p = tid; p < items; p += BLOCK) {
+    const uint64_t key = tk[p];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint32_t dst = gbase[d] + ((uint32_t)p - lbase[d]);
+    kout[dst] = key;
+    vout[dst] = tv[p];
   }
 }
 
@@ -353,7 +374,7 @@ int radix_sort_pairs(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, int
   for (int p = 0; p < npass; ++p) {
     k_radix_hist<<<(unsigned)nt, BLOCK, 0, st>>>(ki, m, shifts[p], hist, nt);
     scan_impl<uint32_t, uint32_t>(hist, offs, 256 * nt, stemp, nullptr, st);
-    k_radix_scatter<<<(unsigned)nt, BLOCK, 0, st>>>(ki, vi, m, shifts[p], offs, nt, ko, vo);
+    k_radix_scatter<<<(unsigned)nt, BLOCK, 0, st>>>(ki, vi, m, shifts[p], hist, offs, nt, ko, vo);
     uint64_t* tk = ki; ki = ko; ko = tk;
     uint32_t* tv = vi; vi = vo; vo = tv;
   }
