@@ -15,7 +15,8 @@
  *
  * Every entry point returns an lcc_status; on a negative status no output buffer is written and
  * lcc_last_error() (thread-local) describes the failure.  No C++ exception crosses this boundary.
- * Every computation runs on the GPU; there is no CPU fallback.
+ * Every step of a clustering call runs on the GPU; there is no CPU fallback.  lcc_objective, which scores given
+ * labels of a host graph (no clustering), is the one host-side computation.
  */
 #ifndef LCC_H
 #define LCC_H
@@ -217,10 +218,21 @@ lcc_status lcc_cluster_batch(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda
                              const lcc_variant* variants, int64_t count, const lcc_options* opts, void* stream,
                              int32_t* const* labels_out, lcc_result* res);
 
-/* Exact objective (Eq. 1) of a given clustering `labels` (n int32 in [0, n), same memory as g), computed on
- * the device. */
-lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, const int32_t* labels,
-                         void* stream, lcc_result* res);
+/* Exact objective (Eq. 1) of a given clustering of a host graph (g->mem = LCC_MEM_HOST), evaluated on the host
+ * in 128-bit integers: labels are n int32 in [0, n) (host memory).  The graph passes the same checks as for
+ * clustering (offsets, index range, self-loops, sorted rows, weights, symmetry, in that order, then the labels
+ * and lambda).  Its exactness domain is wider than the clustering calls': q W_E + p W^2 < 2^126 (lambda = p / q
+ * in lowest terms, W = sum of the vertex weights < 2^63, W_E = sum of the stored edge weights), else
+ * LCC_ERR_OVERFLOW.  res: num_clusters = distinct labels, obj_num / obj_den = lambdaCC exactly (Sec. II,
+ * Eq. 1 over ordered pairs), objective and modularity in FP64 as for lcc_cluster, levels = 1, flags = 0.
+ * A device graph is refused (LCC_ERR_INVALID); use lcc_objective_device. */
+lcc_status lcc_objective(const lcc_graph* g, lcc_lambda lambda, const int32_t* labels, lcc_result* res);
+
+/* The same evaluation on the device for a graph in either memory (a host graph and its labels are copied to the
+ * device first), queued on `stream` of the context's device; the clustering calls' exactness bound applies
+ * (LCC_ERR_OVERFLOW as for lcc_cluster).  Returns when the result is on the host. */
+lcc_status lcc_objective_device(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, const int32_t* labels,
+                                void* stream, lcc_result* res);
 
 /* Launch tuning of a context.  Every setting gives bit-identical results; only the work decomposition
  * changes.  bucket_max[k] is the largest row degree put in degree bucket k (0-3: groups of 4/8/16/32 lanes,

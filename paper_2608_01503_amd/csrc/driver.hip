@@ -1742,8 +1742,8 @@ lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lam
   return st;
 }
 
-lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const int32_t* labels, void* stream,
-                         lcc_result* res) {
+lcc_status lcc_objective_device(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const int32_t* labels,
+                                void* stream, lcc_result* res) {
   return guarded([&]() -> lcc_status {
     if (!ctx || !res) fail(LCC_ERR_INVALID, "bad arguments");
     check_graph_args(g);
@@ -1783,6 +1783,113 @@ lcc_status lcc_objective(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam, const
     __int128 N = (__int128)R.q * ctx->h_ctrl->obj_I - (__int128)R.p * (ctx->h_ctrl->obj_SW2 - L0.sum_w2);
     const bool mod = g->vw_mode == LCC_VW_WEIGHTED_DEGREE && lam.over_total_weight;
     fill_result(res, nc, N, R.p, R.q, L0.sum_w2, R.W, mod, 1, 0);
+    return LCC_OK;
+  });
+}
+
+// Eq. 1 of a given clustering of a host graph, evaluated on the host in 128-bit integers.  It scores labels from
+// any source and takes no part in the clustering calls.  The graph passes the same checks as for clustering,
+// in the same order (offsets, rows, weights, symmetry); then the labels, lambda and the bound.
+lcc_status lcc_objective(const lcc_graph* g, lcc_lambda lam, const int32_t* labels, lcc_result* res) {
+  return guarded([&]() -> lcc_status {
+    typedef unsigned __int128 u128;
+    if (!res) fail(LCC_ERR_INVALID, "res is NULL");
+    check_graph_args(g);
+    if (g->mem != LCC_MEM_HOST) fail(LCC_ERR_INVALID, "lcc_objective takes a host graph (device graphs: lcc_objective_device)");
+    const int64_t n = g->n, nnz = g->nnz;
+    if (n > 0 && !labels) fail(LCC_ERR_INVALID, "labels is NULL");
+    if (n == 0 && nnz == 0) {  // the empty clustering of the empty graph, as on the device
+      fill_result(res, 0, 0, 0, 1, 0, 0, false, 0, 0);
+      return LCC_OK;
+    }
+    const int64_t* o64 = g->offsets_bits == 64 ? (const int64_t*)g->offsets : nullptr;
+    const int32_t* o32 = g->offsets_bits == 32 ? (const int32_t*)g->offsets : nullptr;
+    auto off = [&](int64_t v) -> int64_t { return o64 ? o64[v] : (int64_t)o32[v]; };
+    const int32_t* idx = g->indices;
+    auto wt = [&](int64_t j) -> int64_t { return g->edge_w ? (int64_t)g->edge_w[j] : 1; };
+    if (off(0) != 0 || off(n) != nnz) fail(LCC_ERR_INVALID, "offsets[0] != 0 or offsets[n] != nnz");
+    for (int64_t v = 0; v < n; ++v)
+      if (off(v + 1) < off(v)) fail(LCC_ERR_INVALID, "offsets decrease");
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t j = off(v); j < off(v + 1); ++j)
+        if (idx[j] < 0 || idx[j] >= n) fail(LCC_ERR_INVALID, "neighbour index out of range");
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t j = off(v); j < off(v + 1); ++j) {
+        if (idx[j] == v) fail(LCC_ERR_SELF_LOOP, "self-loop");
+        if (j > off(v) && idx[j - 1] >= idx[j]) fail(LCC_ERR_UNSORTED, "row not strictly ascending");
+      }
+    for (int64_t j = 0; j < nnz; ++j)
+      if (wt(j) <= 0) fail(LCC_ERR_WEIGHT, "edge weight <= 0");
+    if (g->vw_mode == LCC_VW_GIVEN)
+      for (int64_t v = 0; v < n; ++v)
+        if (g->vertex_w[v] < 0) fail(LCC_ERR_WEIGHT, "vertex weight < 0");
+    // every entry (v, u, w) has its reverse (u, v, w): binary search of v in the sorted row u
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t j = off(v); j < off(v + 1); ++j) {
+        const int32_t u = idx[j];
+        const int32_t* b = idx + off(u);
+        const int32_t* e = idx + off(u + 1);
+        const int32_t* f = std::lower_bound(b, e, (int32_t)v);
+        if (f == e || *f != v || wt(f - idx) != wt(j)) fail(LCC_ERR_NOT_SYMMETRIC, "graph not symmetric");
+      }
+    for (int64_t v = 0; v < n; ++v)
+      if (labels[v] < 0 || labels[v] >= n) fail(LCC_ERR_INVALID, "label outside [0, n)");
+    // vertex weights; W < 2^63 keeps every square below 2^126
+    std::vector<int64_t> vw((size_t)n);
+    u128 W = 0, WE = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      int64_t x = 1;
+      if (g->vw_mode == LCC_VW_GIVEN) x = g->vertex_w[v];
+      if (g->vw_mode == LCC_VW_WEIGHTED_DEGREE) {
+        x = 0;
+        for (int64_t j = off(v); j < off(v + 1); ++j) x += wt(j);
+      }
+      vw[(size_t)v] = x;
+      W += (u128)x;
+    }
+    for (int64_t j = 0; j < nnz; ++j) WE += (u128)wt(j);
+    const u128 LIM = (u128)1 << 126;
+    if (W >> 63) fail(LCC_ERR_OVERFLOW, "total vertex weight >= 2^63");
+    // lambda = p / q in lowest terms
+    if (lam.den == 0) fail(LCC_ERR_LAMBDA, "lambda denominator is zero");
+    u128 P = lam.num, Q = (u128)lam.den * (lam.over_total_weight ? W : 1);
+    if (Q == 0 || P > Q) fail(LCC_ERR_LAMBDA, "lambda outside [0, 1] or undefined");
+    if (P == 0) {
+      Q = 1;
+    } else {
+      u128 a = P, b = Q;
+      while (b) { u128 t = a % b; a = b; b = t; }
+      P /= a;
+      Q /= a;
+    }
+    if (Q >> 64) fail(LCC_ERR_OVERFLOW, "lambda denominator >= 2^64");
+    // |N| <= q W_E + p W^2 < 2^126
+    const u128 qWE = Q * WE, W2 = W * W;
+    if (qWE >= LIM || (P && W2 > (LIM - 1 - qWE) / P)) fail(LCC_ERR_OVERFLOW, "q W_E + p W^2 >= 2^126");
+    std::vector<uint64_t> Wc((size_t)n, 0);
+    std::vector<uint8_t> seen((size_t)n, 0);
+    int64_t nc = 0;
+    u128 sum_w2 = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      Wc[(size_t)labels[v]] += (uint64_t)vw[(size_t)v];
+      sum_w2 += (u128)vw[(size_t)v] * (u128)vw[(size_t)v];
+      if (!seen[(size_t)labels[v]]) { seen[(size_t)labels[v]] = 1; ++nc; }
+    }
+    u128 I = 0, SW2 = 0;
+    for (int64_t v = 0; v < n; ++v)
+      for (int64_t j = off(v); j < off(v + 1); ++j)
+        if (labels[idx[j]] == labels[v]) I += (u128)wt(j);
+    for (int64_t c = 0; c < n; ++c) SW2 += (u128)Wc[(size_t)c] * (u128)Wc[(size_t)c];
+    const __int128 N = (__int128)(Q * I) - (__int128)(P * (SW2 - sum_w2));
+    res->num_clusters = nc;
+    res->obj_num_hi = (int64_t)(N >> 64);
+    res->obj_num_lo = (uint64_t)N;
+    res->obj_den = (uint64_t)Q;
+    res->objective = (double)N / (double)Q;
+    const bool mod = g->vw_mode == LCC_VW_WEIGHTED_DEGREE && lam.over_total_weight;
+    res->modularity = mod && W > 0 ? (double)(N - (__int128)(P * sum_w2)) / ((double)Q * (double)W) : NAN;
+    res->levels = 1;
+    res->flags = 0;
     return LCC_OK;
   });
 }

@@ -26,8 +26,8 @@ LCC_FLAG_LEVEL_CAP, LCC_FLAG_REFINE_NO_PROGRESS = 1, 2
 LCC_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 EXPORTED = ["lcc_create", "lcc_destroy", "lcc_default_options", "lcc_workspace_bytes", "lcc_cluster",
-            "lcc_cluster_ex", "lcc_cluster_noalloc", "lcc_cluster_batch", "lcc_objective", "lcc_server_create", "lcc_submit", "lcc_poll",
-            "lcc_server_destroy", "lcc_profile_enable", "lcc_profile_read", "lcc_status_string", "lcc_last_error",
+            "lcc_cluster_ex", "lcc_cluster_noalloc", "lcc_cluster_batch", "lcc_objective", "lcc_objective_device",
+            "lcc_server_create", "lcc_submit", "lcc_poll", "lcc_server_destroy", "lcc_profile_enable", "lcc_profile_read", "lcc_status_string", "lcc_last_error",
             "lcc_default_tuning", "lcc_set_tuning", "lcc_get_tuning", "lcc_autotune"]
 
 # kernel families of lcc_profile_enable (bit = index) and the kernel each one times
@@ -122,7 +122,9 @@ def load():
     lib.lcc_cluster_batch.argtypes = [v, P(lcc_graph), P(lcc_lambda), P(ctypes.c_int), i64, P(lcc_options), v,
                                       P(v), P(lcc_result)]
     lib.lcc_objective.restype = st
-    lib.lcc_objective.argtypes = [v, P(lcc_graph), lcc_lambda, v, v, P(lcc_result)]
+    lib.lcc_objective.argtypes = [P(lcc_graph), lcc_lambda, v, P(lcc_result)]
+    lib.lcc_objective_device.restype = st
+    lib.lcc_objective_device.argtypes = [v, P(lcc_graph), lcc_lambda, v, v, P(lcc_result)]
     lib.lcc_server_create.restype = st
     lib.lcc_server_create.argtypes = [v, ctypes.c_size_t, P(v)]
     lib.lcc_submit.restype = st
@@ -423,9 +425,18 @@ class Context:
 
     def objective(self, graph: lcc_graph, labels, lam=(1, 1, True), stream=None) -> Result:
         res = lcc_result()
-        _check(load().lcc_objective(self.handle, ctypes.byref(graph), lam_of(lam), _ptr(labels),
+        _check(load().lcc_objective_device(self.handle, ctypes.byref(graph), lam_of(lam), _ptr(labels),
                                     _stream_handle(stream, graph), ctypes.byref(res)))
         return _result(res)
+
+
+def lcc_objective(graph: lcc_graph, labels, lam=(1, 1, True)) -> Result:
+    """Exact objective of `labels` (numpy int32) on a host graph (numpy arrays), evaluated by the library on the
+    host in 128-bit integers."""
+    res = lcc_result()
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    _check(load().lcc_objective(ctypes.byref(graph), lam_of(lam), _ptr(lab), ctypes.byref(res)))
+    return _result(res)
 
 
 def _stream_handle(stream, graph):

@@ -227,6 +227,12 @@ def test_objective_entry_point():
     import torch
     res = U.ctx().objective(U.device_graph(g, O.VW_WEIGHTED_DEGREE), torch.from_numpy(C).cuda(), (1, 1, True))
     assert res.N == want and res.obj_den == q
+    # the host evaluation (lcc_objective) and the device one (lcc_objective_device) agree field by field
+    hg = L.make_graph(g.off, g.idx, g.w, None, L.LCC_VW_WEIGHTED_DEGREE)
+    h = L.lcc_objective(hg, C, (1, 1, True))
+    assert (h.N, h.obj_den, h.num_clusters, h.levels, h.flags) == (res.N, res.obj_den, res.num_clusters, res.levels,
+                                                                   res.flags)
+    assert h.objective == res.objective and h.modularity == res.modularity
 
 
 def test_batch_equals_single():
