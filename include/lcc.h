@@ -241,13 +241,15 @@ lcc_status lcc_objective_device(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam
  * chunks).  The default bounds are {4, 8, 16, 32, 128, 1024, 4096}; a bucket's kernels serve rows up to
  * {4, 8, 16, 32, 128, 1024, 8192}, so a tuning may set the bounds anywhere up to these capacities
  * (non-decreasing in k, >= 0); equal neighbouring bounds leave a bucket empty.  grid_cap (64..65536, default 2048) bounds the
- * workgroups of the persistent per-vertex launches.  lcc_set_tuning returns LCC_ERR_INVALID for a setting
+ * workgroups of the persistent per-vertex launches.  hash_shift (0..2, default 0) sizes the LDS hash of a row
+ * of degree d in buckets 4-6 at 2^hash_shift times the smallest power of two >= 2 d slots (a lower load
+ * factor, fewer probe collisions), capped at the bucket's table.  lcc_set_tuning returns LCC_ERR_INVALID for a setting
  * outside these limits and leaves the context unchanged; the tuning applies to later calls on the context
  * (and to the execution slots of servers created afterwards). */
 typedef struct {
   int64_t bucket_max[7];
   int32_t grid_cap;
-  int32_t reserved;  /* 0 */
+  int32_t hash_shift;
 } lcc_tuning;
 
 void lcc_default_tuning(lcc_tuning* t);
@@ -255,7 +257,8 @@ lcc_status lcc_set_tuning(lcc_ctx* ctx, const lcc_tuning* t);
 lcc_status lcc_get_tuning(lcc_ctx* ctx, lcc_tuning* t);
 
 /* Autotuner: times a fixed list of candidate tunings (three grid caps with the current bounds, then bucket
- * layouts that move rows to larger-capacity buckets with the best cap) on the given graphs, `trials` timed
+ * layouts that move rows to larger-capacity buckets with the best cap, then hash_shift 0, 1 and 2 with the best
+ * layout) on the given graphs, `trials` timed
  * runs each after one warm-up run (the fastest run counts), and keeps the fastest tuning on the context.
  * Each run is one lcc_cluster_batch call over the graphs (lcc_cluster when count == 1) on `stream`; graphs,
  * lambdas, variants and opts are as for lcc_cluster_batch, and labels are written to scratch the tuner owns.

@@ -137,6 +137,7 @@ struct Buckets {
   const int32_t* list = nullptr;
   int32_t grid_cap = 2048;  // workgroups of the persistent per-vertex launches (a result-neutral tuning)
   int64_t hub_deg = 4096;   // rows longer than this are in the hub bucket (its lower bound, exclusive)
+  int32_t hash_shift = 0;   // LDS hash of a row of degree d: pow2ceil(2 d) << hash_shift slots, capped (a tuning)
   int64_t count[NBUCKET] = {};
   int64_t off[NBUCKET + 1] = {};
   // hub (last bucket) vertices are processed in fixed-size edge chunks: chunk range of hub k is

@@ -505,6 +505,7 @@ struct Run {
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc; b.stripes = w.stripes;
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
+    b.hash_shift = ctx->tune.hash_shift;
     if (!into) L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
     if (b.count[NBUCKET - 1]) launch_hub_chunks(list + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, hub_off, w.scan_temp, st);
   }
@@ -968,6 +969,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc; b.stripes = w.stripes;
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
+    b.hash_shift = ctx->tune.hash_shift;
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
@@ -1426,6 +1428,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     b.hub_ps = w.hub_ps; b.hub_pc = w.hub_pc; b.hub_pown = w.hub_pown; b.hub_acc = w.hub_acc; b.stripes = w.stripes;
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
+    b.hash_shift = ctx->tune.hash_shift;
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
@@ -1631,7 +1634,7 @@ lcc_status lcc_set_tuning(lcc_ctx* ctx, const lcc_tuning* t) {
       if (k > 0 && t->bucket_max[k] < t->bucket_max[k - 1]) fail(LCC_ERR_INVALID, "bucket bounds must not decrease");
     }
     if (t->grid_cap < 64 || t->grid_cap > 65536) fail(LCC_ERR_INVALID, "grid_cap outside [64, 65536]");
-    if (t->reserved != 0) fail(LCC_ERR_INVALID, "reserved must be 0");
+    if (t->hash_shift < 0 || t->hash_shift > 2) fail(LCC_ERR_INVALID, "hash_shift outside [0, 2]");
     std::lock_guard<std::mutex> lock(ctx->mu);
     ctx->tune = *t;
     return LCC_OK;
@@ -1724,6 +1727,14 @@ lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lam
         t.bucket_max[k] = lay[k];
       }
       if (same) continue;
+      double ms = run(t);
+      if (ms < win_ms) { win_ms = ms; win = t; }
+    }
+    cur = win;
+    for (int32_t hs = 0; hs <= 2; ++hs) {  // LDS hash sizes with the best layout
+      if (hs == cur.hash_shift) continue;
+      lcc_tuning t = cur;
+      t.hash_shift = hs;
       double ms = run(t);
       if (ms < win_ms) { win_ms = ms; win = t; }
     }

@@ -269,6 +269,16 @@ __device__ __forceinline__ int ceil_log2(int64_t x) {
   return b;
 }
 
+// log2 of the LDS hash capacity for a row of degree d: pow2ceil(2 d) << shift slots (at least 2), at most the
+// kernel's table of `slots`; the bucket bounds keep 2 d <= slots, so the load factor never exceeds 1/2
+__device__ __forceinline__ int table_bits(int64_t d, int shift, int slots) {
+  int bits = ceil_log2(2 * d);
+  if (bits < 1) bits = 1;
+  bits += shift;
+  const int cap = ceil_log2(slots);
+  return bits < cap ? bits : cap;
+}
+
 __device__ __forceinline__ int find_chunk_owner(const int32_t* chunk_off, int64_t n7, int64_t blk) {
   int64_t lo = 0, hi = n7;
   while (hi - lo > 1) {
@@ -697,7 +707,8 @@ template <int SLOTS>
 __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_t cnt, DevGraph g,
                                                      const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
                                                      uint32_t pb, int strict, VState* vs, LMSlot* slot,
-                                                     int pass, int64_t* S, int ct_own, int ct_pairs) {
+                                                     int pass, int64_t* S, int ct_own, int ct_pairs,
+                                                     int hshift) {
   __shared__ int32_t hk[BLOCK / WAVE][SLOTS];
   __shared__ uint32_t hv[BLOCK / WAVE][SLOTS];
   VtxAcc va;
@@ -711,8 +722,7 @@ __global__ __launch_bounds__(BLOCK) void k_enum_wave(const int32_t* list, int64_
     const int64_t b = g.off[v], e = g.off[v + 1];
     const int32_t cv = C[v];
     const int64_t wvt = g.vw[v];
-    int bits = ceil_log2(2 * (e - b));
-    if (bits < 1) bits = 1;
+    const int bits = table_bits(e - b, hshift, SLOTS);
     for (int sl = lane; sl < (1 << bits); sl += WAVE) { tk[sl] = -1; tv[sl] = 0; }
     wave_lds_sync();
     const int64_t own_reg = insert_row(g, C, b, e, lane, WAVE, cv, tk, tv, bits, ss.cons, ss.con(v));
@@ -736,8 +746,8 @@ template <int BS, int SLOTS>
 __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
                                                  const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb,
                                                  int strict, VState* vs, LMSlot* slot, int pass,
-                                                 int64_t* S, int ct_own, int ct_pairs, int64_t dlo = -1,
-                                                 int64_t dhi = INT64_MAX) {
+                                                 int64_t* S, int ct_own, int ct_pairs, int hshift,
+                                                 int64_t dlo = -1, int64_t dhi = INT64_MAX) {
   __shared__ int32_t hk[SLOTS];
   __shared__ uint32_t hv[SLOTS];
   VtxAcc va;
@@ -748,8 +758,7 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
     if (e - b <= dlo || e - b > dhi) continue;  // rows of the other launch over this bucket (uniform)
     const int32_t cv = C[v];
     const int64_t wvt = g.vw[v];
-    int bits = ceil_log2(2 * (e - b));
-    if (bits < 1) bits = 1;
+    const int bits = table_bits(e - b, hshift, SLOTS);
     for (int sl = threadIdx.x; sl < (1 << bits); sl += BS) { hk[sl] = -1; hv[sl] = 0; }
     __syncthreads();
     const int64_t own_reg = insert_row(g, C, b, e, threadIdx.x, BS, cv, hk, hv, bits, ss.cons, ss.con(v));
@@ -1963,14 +1972,14 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(1))))
   LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(2))))
   LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(3))))
-  LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(4))))
-  LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(5))))
+  LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(4), b.hash_shift)))
+  LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(5), b.hash_shift)))
   // bucket 6: rows up to 4096 on 512 threads and an 8192-slot table; when a tuning raises the bucket's bound,
   // longer rows on 1024 threads and a 16384-slot table (a second launch over the bucket)
-  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), -1, LDS_SLOTS_B6 / 2)))
+  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), b.hash_shift, -1, LDS_SLOTS_B6 / 2)))
   if (b.count[6] && b.hub_deg > LDS_SLOTS_B6 / 2) {
     prof_begin(PF_ENUM_B0 + 6, st);
-    k_enum_blk<1024, LDS_SLOTS_B6X><<<vtx_blocks(b, b.count[6], 4), 1024, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), LDS_SLOTS_B6 / 2, INT64_MAX);
+    k_enum_blk<1024, LDS_SLOTS_B6X><<<vtx_blocks(b, b.count[6], 4), 1024, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), b.hash_shift, LDS_SLOTS_B6 / 2, INT64_MAX);
     prof_end(PF_ENUM_B0 + 6, 0.0, st);
   }
 #undef LCC_ENUM

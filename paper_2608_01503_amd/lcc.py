@@ -68,7 +68,7 @@ LCC_SYM_AFTERBURNER, LCC_SYM_NONE, LCC_SYM_MLH = 0, 1, 2
 
 
 class lcc_tuning(ctypes.Structure):
-    _fields_ = [("bucket_max", ctypes.c_int64 * 7), ("grid_cap", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("bucket_max", ctypes.c_int64 * 7), ("grid_cap", ctypes.c_int32), ("hash_shift", ctypes.c_int32)]
 
 
 class lcc_kernel_stat(ctypes.Structure):
@@ -186,7 +186,7 @@ def lcc_default_options(**kw) -> lcc_options:
     return o
 
 
-def lcc_default_tuning(bucket_max=None, grid_cap=None) -> lcc_tuning:
+def lcc_default_tuning(bucket_max=None, grid_cap=None, hash_shift=None) -> lcc_tuning:
     """The default launch tuning, with the given fields replaced (bucket_max: 7 bounds)."""
     t = lcc_tuning()
     load().lcc_default_tuning(ctypes.byref(t))
@@ -195,11 +195,14 @@ def lcc_default_tuning(bucket_max=None, grid_cap=None) -> lcc_tuning:
             t.bucket_max[k] = int(b)
     if grid_cap is not None:
         t.grid_cap = int(grid_cap)
+    if hash_shift is not None:
+        t.hash_shift = int(hash_shift)
     return t
 
 
 def tuning_dict(t: lcc_tuning) -> dict:
-    return {"bucket_max": [int(x) for x in t.bucket_max], "grid_cap": int(t.grid_cap)}
+    return {"bucket_max": [int(x) for x in t.bucket_max], "grid_cap": int(t.grid_cap),
+            "hash_shift": int(t.hash_shift)}
 
 
 def lcc_workspace_bytes(n: int, nnz: int, variant: int = LCC_PLOUVAIN) -> int:

@@ -1,4 +1,4 @@
-"""Launch tuning is result-neutral: every bucket layout and grid cap gives bit-identical labels, objective and
+"""Launch tuning is result-neutral: every bucket layout, grid cap and hash size gives bit-identical labels, objective and
 per-pass trace (plain calls and fused batches), and the autotuner only picks among such settings."""
 from __future__ import annotations
 
@@ -18,6 +18,8 @@ TUNINGS = [
     dict(bucket_max=[0, 8, 8, 32, 32, 1024, 1024], grid_cap=65536),
     dict(bucket_max=[4, 4, 4, 4, 128, 128, 128]),         # no 8/16/32-lane groups, no workgroup hashes
     dict(bucket_max=[4, 8, 16, 32, 128, 1024, 8192]),     # rows 4097-8192 on the 16384-slot workgroups
+    dict(hash_shift=1),                                   # LDS hashes at twice the capacity
+    dict(bucket_max=[4, 8, 16, 32, 128, 1024, 8192], hash_shift=2),  # 4 times, capped at every table
 ]
 
 CASES = [
@@ -80,7 +82,7 @@ def test_set_tuning_rejects_out_of_range_settings():
            dict(bucket_max=[4, 8, 16, 32, 128, 1024, 8193]),
            dict(bucket_max=[4, 8, 6, 32, 128, 1024, 4096]),      # decreasing
            dict(bucket_max=[-1, 8, 16, 32, 128, 1024, 4096]),
-           dict(grid_cap=32), dict(grid_cap=70000)]
+           dict(grid_cap=32), dict(grid_cap=70000), dict(hash_shift=-1), dict(hash_shift=3)]
     for t in bad:
         with pytest.raises(L.LccError) as e:
             ctx.set_tuning(L.lcc_default_tuning(**t))
@@ -100,6 +102,7 @@ def test_autotune_keeps_a_valid_tuning_and_results():
     assert t == L.tuning_dict(ctx.get_tuning())
     caps = [4, 8, 16, 32, 128, 1024, 8192]
     assert all(0 <= b <= c for b, c in zip(t["bucket_max"], caps)) and 64 <= t["grid_cap"] <= 65536
+    assert 0 <= t["hash_shift"] <= 2
     after, ares = ctx.cluster(graph, (1, 1, True), L.LCC_PLOUVAIN)
     assert np.array_equal(before.cpu().numpy(), after.cpu().numpy()) and ares.N == bres.N
     # a batch of graphs
