@@ -207,10 +207,12 @@ lcc_status lcc_cluster_ex(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, l
 
 /* Cluster `count` independent graphs (each with its own lambda, vertex-weight mode and variant) in one call.
  * Results are identical to `count` separate lcc_cluster calls.  labels_out[i] and res[i] as for lcc_cluster.
- * When every graph uses LCC_LOUVAIN or LCC_PLOUVAIN (and opts->trace is NULL), the graphs are processed
- * together (host graphs are first copied to the device): their CSRs are concatenated into one union graph and every
- * kernel launch of a level covers all graphs still coarsening (Alg. 1 applied to the union, with each graph's
- * own lambda, objective, best-so-far state and level count).  Otherwise the graphs run one after another.
+ * When every graph uses a variant of one family -- LCC_LOUVAIN / LCC_PLOUVAIN, or LCC_PLEIDEN / LCC_PLEIDEN_PLUS --
+ * and opts->trace is NULL, the graphs are processed together (host graphs are first copied to the device): their
+ * CSRs are concatenated into one union graph and every kernel launch of a level covers all graphs still
+ * coarsening (Alg. 1 or Alg. 5 applied to the union, with each graph's own lambda, objective, best-so-far
+ * state, alternate local move, refinement stream, no-progress retries and level count).  Otherwise the graphs
+ * run one after another.
  * The workspace is sized for the union (sum of n, sum of nnz).  On a failure the status of the first problem
  * found is returned and no result is written; in the fused form structural faults of any graph (CSR layout,
  * symmetry, weights) are reported before lambda and bound problems, which are checked per graph in order. */
@@ -272,9 +274,10 @@ lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lam
  * slots (one per hardware queue HIP gives a process by default; the environment variable LCC_SERVER_SLOTS,
  * 1-16, overrides it), each with its own context and HIP stream, so admitted jobs run concurrently on the
  * GPU.  A free slot admits the oldest queued job whose footprint (lcc_workspace_bytes) fits the unreserved
- * part of hbm_budget (a job passed over 4 times blocks further overtaking); if that job is a Louvain /
- * Louvain+ request of at most 2^22 entries, the slot also takes the other queued such requests with the same
- * options (up to 256 requests, 2^25 entries) and runs them as one fused lcc_cluster_batch call.  Results are
+ * part of hbm_budget (a job passed over 4 times blocks further overtaking); if that job is a request of at most
+ * 2^22 entries, the slot also takes the other queued such requests of its family (Louvain / Louvain+, or pLeiden
+ * / pLeiden+) with the same options (up to 256 requests, 2^25 entries) and runs them as one fused
+ * lcc_cluster_batch call.  Results are
  * identical to plain lcc_cluster calls.
  * Device memory: every slot allocates through ctx's allocator, and the bytes the slots hold (workspaces and
  * coarse levels, also while idle) plus the footprints reserved for running jobs never exceed hbm_budget.  An

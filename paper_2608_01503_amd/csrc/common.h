@@ -452,13 +452,15 @@ void local_move(const DevGraph& g, const Buckets& b, const LMParams& prm, bool s
                 LMSlot* slot, Ctrl* ctrl, hipStream_t st);
 // Destinations without the temperature rule (candidate iff the move strictly improves): used by
 // LocalMoveAlt.  Fills bufs.vs and bufs.keep (keep = non-node-optimal).
-void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
+void launch_destinations_strict(const DevGraph& g, const Buckets& b, const ScoreSrc& ss, LMBuffers& bufs,
                                 LMSlot* slot, hipStream_t st);
 void launch_cluster_weights(const int32_t* C, const int64_t* vw, int64_t n, int64_t* W, hipStream_t st);
 // Exact objective pieces of clustering C: ctrl->obj_I and ctrl->obj_SW2 (W must hold C's cluster weights).
 void launch_objective(const DevGraph& g, const Buckets& b, const int32_t* C, const int64_t* W,
                       Ctrl* ctrl, hipStream_t st);
-void launch_apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, LMSlot* slot, hipStream_t st);
+// sg: a union of graphs (free ids per graph), or empty
+void launch_apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, const SegLM& sg, LMSlot* slot,
+                            hipStream_t st);
 
 // contract.hip
 // used flags of labels -> rank (compact map) : rank[c] for c in [0, n), count at rank[n].
@@ -487,8 +489,12 @@ void launch_coarse_write(const uint64_t* keys, const uint32_t* vals, const uint8
 void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int32_t* fine_C, hipStream_t st,
                     const int32_t* gid = nullptr, const int32_t* vbase_f = nullptr,
                     const int32_t* vbase_c = nullptr);
+// Cc[map[v]] = rankB[B[v]] where map[v] >= 0.  In a union (gid set): the graph-local rank, rebased from graph
+// gid[v]'s fine id range (vbase_f) to its coarse one (vbase_c); for a graph with keep[k] set (its coarse level
+// repeats the fine one) B[v] itself, rebased.
 void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,
-                       hipStream_t st);
+                       hipStream_t st, const int32_t* gid = nullptr, const int32_t* vbase_f = nullptr,
+                       const int32_t* vbase_c = nullptr, const uint8_t* keep = nullptr);
 
 // refine.hip: pLeidenR (Alg. 6)
 struct RefineBuffers {
@@ -517,12 +523,42 @@ void segsort_pairs(uint64_t* kin, uint32_t* vin, uint64_t* kout, uint32_t* vout,
                    int64_t nseg, int low_bits, void* scan_temp, const std::function<void*(size_t)>& take,
                    hipStream_t st);
 
-void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t* B, uint64_t seed, uint64_t t,
-            int32_t* R, RefineBuffers& rb, Ctrl* ctrl, const std::function<void*(size_t)>& take, hipStream_t st);
+// What the refinement of a vertex depends on besides the graph: the scoring parameters, the random stream s_t
+// of the refinement call and the vertex id that enters the hashes.  For one graph these are `s`, `st` and v;
+// in a union of graphs (gid set) they are those of the vertex's own graph, with graph-local ids, so every graph
+// is refined exactly as alone, and graphs with act[k] == 0 are left unrefined (none of their vertices is in U).
+struct RefSrc {
+  Score s{};
+  uint64_t st = 0;
+  const int32_t* gid = nullptr;
+  const int32_t* vbase = nullptr;
+  const Score* tab = nullptr;     // [G]
+  const uint64_t* stt = nullptr;  // [G]
+  const uint8_t* act = nullptr;   // [G]
+  __device__ __forceinline__ Score sc(int32_t v) const { return gid ? tab[gid[v]] : s; }
+  __device__ __forceinline__ uint64_t seed(int32_t v) const { return gid ? stt[gid[v]] : st; }
+  __device__ __forceinline__ uint32_t fseed(int32_t v) const { return (uint32_t)(seed(v) >> 32); }
+  __device__ __forceinline__ uint32_t loc(int32_t v) const {
+    return gid ? (uint32_t)(v - vbase[gid[v]]) : (uint32_t)v;
+  }
+  __device__ __forceinline__ bool on(int32_t v) const { return !act || act[gid[v]]; }
+};
+
+void refine(const DevGraph& g, const Buckets& b, const RefSrc& rs, const int32_t* B, int32_t* R, RefineBuffers& rb,
+            Ctrl* ctrl, const std::function<void*(size_t)>& take, hipStream_t st);
 
 // lmalt.hip: LocalMoveAlt (Sec. V-A)
-// Returns false (nothing done) when the mover count is 2^30 or more.
+// A union of graphs: only the graphs with act[k] set take the move, each with its own scoring parameters, its
+// own committed prefix (best_k[k], device) and its own free ids (sg).
+struct AltSeg {
+  ScoreSrc ss;
+  const uint8_t* act = nullptr;  // [G]
+  int64_t* best_k = nullptr;     // [G]
+  SegLM sg;
+};
+// Returns false (nothing done) when the mover count is 2^30 or more.  seg: a union of graphs (null: one graph).
 bool lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs, LMSlot* slot, Ctrl* ctrl,
-           int32_t* list, int64_t* gain, const std::function<void*(size_t)>& take, hipStream_t st);
+           int32_t* list, int64_t* gain, const std::function<void*(size_t)>& take, hipStream_t st,
+           const AltSeg* seg = nullptr);
 
 }  // namespace lcc

@@ -255,9 +255,19 @@ __global__ void k_project(const int32_t* coarse_C, const int32_t* map, int64_t n
   }
 }
 
-__global__ void k_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    if (map[v] >= 0) Cc[map[v]] = rankB[B[v]];
+__global__ void k_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,
+                             const int32_t* gid, const int32_t* vbase_f, const int32_t* vbase_c,
+                             const uint8_t* keep) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = map[v];
+    if (x < 0) continue;
+    if (!gid) {
+      Cc[x] = rankB[B[v]];
+    } else {
+      const int32_t k = gid[v], bf = vbase_f[k];
+      Cc[x] = (keep && keep[k] ? B[v] - bf : rankB[B[v]] - rankB[bf]) + vbase_c[k];
+    }
+  }
 }
 
 }  // namespace
@@ -335,8 +345,9 @@ void launch_project(const int32_t* coarse_C, const int32_t* map, int64_t n, int3
 }
 
 void launch_downsample(const int32_t* B, const int32_t* rankB, const int32_t* map, int64_t n, int32_t* Cc,
-                       hipStream_t st) {
-  k_downsample<<<grid_for(n), BLOCK, 0, st>>>(B, rankB, map, n, Cc);
+                       hipStream_t st, const int32_t* gid, const int32_t* vbase_f, const int32_t* vbase_c,
+                       const uint8_t* keep) {
+  k_downsample<<<grid_for(n), BLOCK, 0, st>>>(B, rankB, map, n, Cc, gid, vbase_f, vbase_c, keep);
 }
 
 }  // namespace lcc

@@ -585,11 +585,21 @@ struct Run {
   }
 
   // Union: number of distinct labels of every graph of level L (labels of graph k lie in its own id range).
-  std::vector<int64_t> count_labels_seg(const int32_t* labels, const Level& L) {
+  // With nb / n0: also every graph's best and starting objective of the last local move (one synchronisation).
+  std::vector<int64_t> count_labels_seg(const int32_t* labels, const Level& L, std::vector<int64_t>* nb = nullptr,
+                                        std::vector<int64_t>* n0 = nullptr) {
     launch_label_rank(labels, L.g.n, w.used, w.rank, w.scan_temp, st);
     launch_rebase(w.rank, L.vbase, G, gtmp, st);
     std::vector<int32_t> h((size_t)G + 1);
     hip_check(hipMemcpyAsync(h.data(), gtmp, (size_t)(G + 1) * 4, hipMemcpyDeviceToHost, st), "counts");
+    if (nb) {
+      nb->resize((size_t)G);
+      hip_check(hipMemcpyAsync(nb->data(), gNbest, (size_t)G * 8, hipMemcpyDeviceToHost, st), "best");
+    }
+    if (n0) {
+      n0->resize((size_t)G);
+      hip_check(hipMemcpyAsync(n0->data(), gN0, (size_t)G * 8, hipMemcpyDeviceToHost, st), "start");
+    }
     sync("counts");
     std::vector<int64_t> nc((size_t)G);
     for (int64_t k = 0; k < G; ++k) nc[k] = h[k + 1] - h[k];
@@ -826,8 +836,10 @@ struct Run {
       RefineBuffers rb = rbufs();
       {
         const auto mk = ctx->pool_mark();  // the refinement's sort scratch is released right after
-        refine(L.g, L.b, sc, L.C, o.seed, refine_calls, R, rb, w.ctrl, [&](size_t by) { return ctx->pool_take(by); },
-               st);
+        RefSrc rs;
+        rs.s = sc;
+        rs.st = seed_stream(o.seed, refine_calls);
+        refine(L.g, L.b, rs, L.C, R, rb, w.ctrl, [&](size_t by) { return ctx->pool_take(by); }, st);
         ctx->pool_release(mk);
       }
       rank_labels(R, n, &w.ctrl->nlab);
@@ -861,6 +873,140 @@ struct Run {
       }
     }
     return top;
+  }
+
+  // ---------------------------------------------------------------------------------------------------
+  // Alg. 5 on a union of graphs.  Every graph follows its own sequence: the alternate local move where its
+  // local move left C_l unchanged, its own refinement stream (s_t with t = its own refinement count) and
+  // termination.  A graph whose refinement makes no progress repeats its level: its part of the next union
+  // level is the same graph (the contraction by singletons is the identity) and starts from the same C_l; that
+  // union level is not one of its own levels.  On the way back (pLeiden+), union level l's local move covers the
+  // graphs with top[k] > l whose level l -> l+1 was a real contraction.
+  // ---------------------------------------------------------------------------------------------------
+  int leiden_seg(const std::vector<uint8_t>& plus, std::vector<int>& top, std::vector<int>& levels,
+                 std::vector<uint32_t>& gflags) {
+    std::vector<uint8_t> cont((size_t)G), alt((size_t)G), rep((size_t)G);
+    std::vector<int> own((size_t)G, 0), noprog((size_t)G, 0);  // the graph's own level; no-progress retries
+    std::vector<uint64_t> calls((size_t)G, 0), hst((size_t)G);
+    std::vector<std::vector<uint8_t>> repeated;  // repeated[l][k]: union level l -> l+1 repeats graph k's level
+    for (int64_t k = 0; k < G; ++k) cont[k] = lv[0].hvb[k + 1] > lv[0].hvb[k];
+    uint64_t* d_st = take<uint64_t>(ctx, G);
+    uint8_t* d_alt = take<uint8_t>(ctx, G);
+    uint8_t* d_rep = take<uint8_t>(ctx, G);
+    int64_t* d_bestk = take<int64_t>(ctx, G);
+    int l = 0;
+    for (;;) {
+      const int64_t n = lv[l].g.n;
+      local_move_level(l, l == 0, 0);
+      std::vector<int64_t> nb, n0;
+      std::vector<int64_t> nc = count_labels_seg(lv[l].C, lv[l], &nb, &n0);
+      // C_l unchanged by the local move: the alternate local move (Sec. V-A), for those graphs together
+      bool any_alt = false;
+      for (int64_t k = 0; k < G; ++k) {
+        alt[k] = cont[k] && nb[k] == n0[k];
+        any_alt = any_alt || alt[k];
+      }
+      if (any_alt) {
+        Level& L = lv[l];
+        hip_check(hipMemcpyAsync(d_alt, alt.data(), (size_t)G, hipMemcpyHostToDevice, st), "alternate graphs");
+        LMBuffers B = bufs();
+        copy_i32(w.C, L.C, n, st);
+        launch_cluster_weights(w.C, L.g.vw, n, w.W, st);
+        if (nslot >= NSLOT) fail(LCC_ERR_INVALID, "too many local-move calls");
+        int s2 = nslot++;
+        AltSeg as;
+        as.ss.tab = d_score; as.ss.gid = L.gid; as.ss.vbase = L.vbase;
+        as.act = d_alt;
+        as.best_k = d_bestk;
+        as.sg = lm_params(L).seg;
+        const auto mark = ctx->pool_mark();
+        if (!lmalt(L.g, L.b, sc, B, w.slots + s2, w.ctrl, w.alt_list, w.alt_gain,
+                   [this](size_t bytes) { return ctx->pool_take(bytes); }, st, &as))
+          fail(LCC_ERR_INVALID, "alternate local move with 2^30 or more movers is not supported");
+        copy_i32(L.C, w.C, n, st);
+        nc = count_labels_seg(L.C, L);  // the stream is done with the scratch
+        ctx->pool_release(mark);
+      }
+      bool any = false;
+      for (int64_t k = 0; k < G; ++k) {
+        if (!cont[k]) continue;
+        const int64_t nk = lv[l].hvb[k + 1] - lv[l].hvb[k];
+        if (nc[k] == nk) {
+          top[k] = l; cont[k] = 0;
+        } else if (own[k] + 1 >= o.max_levels) {
+          top[k] = l; gflags[k] |= LCC_FLAG_LEVEL_CAP; cont[k] = 0;
+        } else {
+          any = true;
+        }
+      }
+      if (!any) break;
+      // refinement of the continuing graphs, each with its own stream
+      for (int64_t k = 0; k < G; ++k) hst[k] = seed_stream(o.seed, calls[k]);
+      hip_check(hipMemcpyAsync(d_st, hst.data(), (size_t)G * 8, hipMemcpyHostToDevice, st), "streams");
+      hip_check(hipMemcpyAsync(gact, cont.data(), (size_t)G, hipMemcpyHostToDevice, st), "active graphs");
+      int32_t* R = w.in_labels;
+      {
+        Level& L = lv[l];
+        RefineBuffers rb = rbufs();
+        RefSrc rs;
+        rs.gid = L.gid; rs.vbase = L.vbase; rs.tab = d_score; rs.stt = d_st; rs.act = gact;
+        const auto mk = ctx->pool_mark();
+        refine(L.g, L.b, rs, L.C, R, rb, w.ctrl, [&](size_t by) { return ctx->pool_take(by); }, st);
+        ctx->pool_release(mk);
+      }
+      // the control block comes back with the counts' synchronisation
+      hip_check(hipMemcpyAsync(ctx->h_ctrl, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st), "refine");
+      std::vector<int64_t> nR = count_labels_seg(R, lv[l]);
+      if (ctx->h_ctrl->err_bits & ERRB_INTERNAL) fail(LCC_ERR_DEVICE, "refinement produced a parent cycle");
+      any = false;
+      for (int64_t k = 0; k < G; ++k) {
+        rep[k] = 0;
+        if (!cont[k]) continue;
+        ++calls[k];
+        const int64_t nk = lv[l].hvb[k + 1] - lv[l].hvb[k];
+        if (nR[k] == nk) {
+          if (++noprog[k] >= 3) {
+            gflags[k] |= LCC_FLAG_REFINE_NO_PROGRESS; top[k] = l; cont[k] = 0;
+            continue;
+          }
+          rep[k] = 1;  // the same level again with the next refinement stream
+        } else {
+          noprog[k] = 0;
+        }
+        any = true;
+      }
+      if (!any) break;
+      hip_check(hipMemcpyAsync(gact, cont.data(), (size_t)G, hipMemcpyHostToDevice, st), "active graphs");
+      hip_check(hipMemcpyAsync(d_rep, rep.data(), (size_t)G, hipMemcpyHostToDevice, st), "repeated graphs");
+      if (lv.size() + 1 > lv.capacity()) fail(LCC_ERR_INVALID, "internal: too many union levels");
+      contract(l, R, 0, gact);
+      // Downsample: C_{l+1}[x] = graph-local compact(C_l)[C_l[v]] for any v in x; a repeated graph keeps C_l
+      Level& L2 = lv[l];
+      launch_label_rank(L2.C, n, w.used, w.rank, w.scan_temp, st, L2.gid, gact);
+      launch_downsample(L2.C, w.rank, L2.map, n, lv[l + 1].C, st, L2.gid, L2.vbase, lv[l + 1].vbase, d_rep);
+      for (int64_t k = 0; k < G; ++k)
+        if (cont[k] && !rep[k]) ++own[k];
+      repeated.push_back(rep);
+      ++l;
+    }
+    const int T = l;
+    for (int64_t k = 0; k < G; ++k) levels[k] = own[k] + 1;
+    std::vector<uint8_t> act((size_t)G);
+    for (int j = T - 1; j >= 0; --j) {
+      Level& L = lv[j];
+      launch_project(lv[j + 1].C, L.map, L.g.n, L.C, st, L.gid, L.vbase, lv[j + 1].vbase);
+      bool any = false;
+      for (int64_t k = 0; k < G; ++k) {
+        act[k] = top[k] > j && plus[k] && !repeated[(size_t)j][k];
+        any = any || act[k];
+      }
+      if (!any) continue;
+      hip_check(hipMemcpyAsync(gact, act.data(), (size_t)G, hipMemcpyHostToDevice, st), "active graphs");
+      Buckets only;
+      prepare(L, take<int32_t>(ctx, L.g.n), take<int32_t>(ctx, L.g.n + 1), gact, &only);
+      local_move_level(j, false, 1, &only);
+    }
+    return T;
   }
 
   void emit_pass_records() {
@@ -1299,11 +1445,15 @@ __global__ void k_write_labels_seg(const int32_t* C, const int32_t* rank, const 
   }
 }
 
+bool leiden_family(lcc_variant v) { return v == LCC_PLEIDEN || v == LCC_PLEIDEN_PLUS; }
+
+// graphs of one family (Louvain / Louvain+ or pLeiden / pLeiden+), untraced, whose union fits 32-bit ids
 bool fusable(const lcc_graph* gs, const lcc_variant* variants, int64_t count, const lcc_options* opts) {
   if (count < 2 || (opts && opts->trace)) return false;
   int64_t n = 0, e = 0;
   for (int64_t i = 0; i < count; ++i) {
-    if (variants[i] != LCC_LOUVAIN && variants[i] != LCC_PLOUVAIN) return false;
+    if (variants[i] < LCC_LOUVAIN || variants[i] > LCC_PLEIDEN_PLUS) return false;
+    if (leiden_family(variants[i]) != leiden_family(variants[0])) return false;
     n += gs[i].n;
     e += gs[i].nnz;
   }
@@ -1352,7 +1502,9 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   } guard{ctx, st};
   WS& w = R.w;
   R.G = G;
-  R.lv.reserve((size_t)R.o.max_levels + 2);
+  const bool leiden = leiden_family(variants[0]);
+  // a Leiden graph may repeat each of its levels twice (no-progress retries): up to 3 union levels per level
+  R.lv.reserve((size_t)(leiden ? 3 : 1) * R.o.max_levels + 2);
   // per-graph device arrays
   R.d_score = take<Score>(ctx, G);
   R.gI = take<int64_t>(ctx, (MAX_PASSES + 1) * G);
@@ -1471,10 +1623,15 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
   hip_check(hipMemcpyAsync(R.d_score, sc.data(), sizeof(Score) * G, hipMemcpyHostToDevice, st), "scores");
   // the method
   std::vector<uint8_t> plus((size_t)G);
-  for (int64_t i = 0; i < G; ++i) plus[i] = variants[i] == LCC_PLOUVAIN;
-  std::vector<int> top((size_t)G, 0);
+  for (int64_t i = 0; i < G; ++i) plus[i] = variants[i] == LCC_PLOUVAIN || variants[i] == LCC_PLEIDEN_PLUS;
+  std::vector<int> top((size_t)G, 0), levels((size_t)G, 1);
   std::vector<uint32_t> gflags((size_t)G, 0);
-  R.louvain_seg(plus, top, gflags);
+  if (leiden) {
+    R.leiden_seg(plus, top, levels, gflags);
+  } else {
+    R.louvain_seg(plus, top, gflags);
+    for (int64_t i = 0; i < G; ++i) levels[i] = top[i] + 1;
+  }
   // per-graph compact labels and exact objective (Eq. 1) on level 0
   Level& F = R.lv[0];
   launch_label_rank(F.C, n, w.used, w.rank, w.scan_temp, st);
@@ -1502,7 +1659,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     }
     const __int128 N = (__int128)sc[i].q * ho[i] - (__int128)sc[i].p * (ho[G + i] - hW[2 * G + i]);
     const bool mod = gs[i].vw_mode == LCC_VW_WEIGHTED_DEGREE && lams[i].over_total_weight;
-    fill_result(&res[i], hr[i + 1] - hr[i], N, sc[i].p, sc[i].q, hW[2 * G + i], (uint64_t)hW[i], mod, top[i] + 1,
+    fill_result(&res[i], hr[i + 1] - hr[i], N, sc[i].p, sc[i].q, hW[2 * G + i], (uint64_t)hW[i], mod, levels[i],
                 gflags[i]);
   }
   return LCC_OK;

@@ -2181,18 +2181,17 @@ uint32_t next_tag(Tagged& t, hipStream_t st) {
   return x;
 }
 
-void launch_apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, LMSlot* slot, hipStream_t st) {
-  apply_and_empty(g, b, bufs, SegLM{}, slot, 0, false, st);
+void launch_apply_and_empty(const DevGraph& g, const Buckets& b, LMBuffers& bufs, const SegLM& sg, LMSlot* slot,
+                            hipStream_t st) {
+  apply_and_empty(g, b, bufs, sg, slot, 0, false, st);
 }
 
-void launch_destinations_strict(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs,
+void launch_destinations_strict(const DevGraph& g, const Buckets& b, const ScoreSrc& ss, LMBuffers& bufs,
                                 LMSlot* slot, hipStream_t st) {
   const HubScratch hs = hub_scratch(b);
   if (b.count[7])
     k_hub_clear<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(L_hubs(b), b.hub_chunk_off, b.count[7], g.off,
                                                              bufs.arena, nullptr, -1);
-  ScoreSrc ss;
-  ss.s = sc;
   launch_destinations(g, b, ss, 0, 1, 1, false, bufs, slot, 0, nullptr, hs, st);
 }
 

@@ -28,9 +28,10 @@ inline unsigned grid_for(int64_t n) {
   return (unsigned)g;
 }
 
-__global__ void k_mover_flags(int64_t n, const VState* vs, uint8_t* mv) {
+// movers: vertices that are not node optimal (in a union, only those of the graphs with act set)
+__global__ void k_mover_flags(int64_t n, const VState* vs, uint8_t* mv, const int32_t* gid, const uint8_t* act) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    mv[v] = vs[v].d != D_NONE;
+    mv[v] = vs[v].d != D_NONE && (!act || act[gid[v]]);
 }
 
 __global__ void k_mover_list(int64_t n, const uint8_t* mv, const int32_t* pos, int32_t* list) {
@@ -152,11 +153,12 @@ __global__ void k_alt_query(const uint64_t* key, const uint32_t* val, const uint
     if (key[p] != NO_KEY && !(key[p] & 1)) F[val[p]] = S[p] - base[H[p] + head[p] - 1];
 }
 
-__global__ void k_gain(const int32_t* list, int64_t k, const VState* vs, const int64_t* vw, Score sc,
+__global__ void k_gain(const int32_t* list, int64_t k, const VState* vs, const int64_t* vw, ScoreSrc ss,
                        const int64_t* adj, const int64_t* F, int64_t* gain) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = list[i];
     const VState me = vs[v];
+    const Score sc = ss.at(v);
     const int64_t fB = me.d == D_EMPTY ? 0 : F[4 * i + 2];
     // half the exact objective change of the move (below 2^62): its terms are summed modulo 2^64
     gain[i] = (int64_t)((uint64_t)me.delta + (uint64_t)(sc.q * adj[i]) - (uint64_t)(sc.p * vw[v] * (fB - F[4 * i + 3])));
@@ -189,6 +191,51 @@ __global__ __launch_bounds__(BP_BLOCK) void k_best_prefix(const int64_t* S, int6
   }
 }
 
+// Union: the same per graph.  Graph k's movers are list positions [pos[vbase[k]], pos[vbase[k + 1]]) (pos is
+// the exclusive scan of the mover flags), so its running sums are differences of S; they are formed modulo 2^64
+// (exact: every graph's own running sums are below 2^63).  One workgroup per graph (grid-stride over graphs);
+// best_k[k] = the length of graph k's committed prefix.
+__global__ __launch_bounds__(BP_BLOCK) void k_best_prefix_seg(const int64_t* S, const int32_t* pos,
+                                                              const int32_t* vbase, int64_t G, const uint8_t* act,
+                                                              int64_t* best_k) {
+  __shared__ int64_t sv[BP_BLOCK / WAVE], si[BP_BLOCK / WAVE];
+  for (int64_t gk = blockIdx.x; gk < G; gk += gridDim.x) {
+    if (!act[gk]) {
+      if (threadIdx.x == 0) best_k[gk] = 0;
+      continue;  // uniform over the workgroup
+    }
+    const int64_t i0 = pos[vbase[gk]], i1 = pos[vbase[gk + 1]];
+    const uint64_t base = (uint64_t)S[i0];
+    int64_t bv = 0, bi = INT64_MAX;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += BP_BLOCK) {
+      const int64_t r = (int64_t)((uint64_t)S[i + 1] - base);
+      if (r > bv || (r == bv && r > 0 && i < bi)) { bv = r; bi = i; }
+    }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const int64_t ov = __shfl_xor(bv, o, WAVE), oi = __shfl_xor(bi, o, WAVE);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    if (lane == 0) { sv[wv] = bv; si[wv] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < BP_BLOCK / WAVE; ++w)
+        if (sv[w] > bv || (sv[w] == bv && si[w] < bi)) { bv = sv[w]; bi = si[w]; }
+      best_k[gk] = bv > 0 ? bi + 1 - i0 : 0;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_commit_prefix_seg(int64_t n, uint8_t* keep, const int32_t* pos, const int32_t* gid,
+                                    const int32_t* vbase, const int64_t* best_k) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k = gid[v];
+    keep[v] = keep[v] && pos[v] - pos[vbase[k]] < best_k[k];
+  }
+}
+
 __global__ void k_commit_prefix(int64_t n, uint8_t* keep, const int32_t* pos, const Ctrl* ctrl) {
   const int64_t kb = ctrl->lmalt_best_k;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -210,11 +257,15 @@ __global__ void k_set_counts(Ctrl* ctrl, int64_t k) {
 // scratch that stays valid until the call's stream has finished (sized by the mover count).  Returns false
 // (nothing changed) when there are 2^30 movers or more.
 bool lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs, LMSlot* slot, Ctrl* ctrl,
-           int32_t* list, int64_t* gain, const std::function<void*(size_t)>& take, hipStream_t st) {
+           int32_t* list, int64_t* gain, const std::function<void*(size_t)>& take, hipStream_t st,
+           const AltSeg* seg) {
   const int64_t n = g.n;
+  ScoreSrc ss;
+  ss.s = sc;
+  if (seg) ss = seg->ss;
   zero_bytes(slot, sizeof(LMSlot), st);
-  launch_destinations_strict(g, b, sc, bufs, slot, st);
-  k_mover_flags<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.vs, bufs.keep);
+  launch_destinations_strict(g, b, ss, bufs, slot, st);
+  k_mover_flags<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.vs, bufs.keep, seg ? ss.gid : nullptr, seg ? seg->act : nullptr);
   scan_u8_i32(bufs.keep, bufs.scan_a, n, bufs.scan_temp, nullptr, st);
   int32_t k32 = 0;
   hipMemcpyAsync(&k32, bufs.scan_a + n, sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -263,11 +314,18 @@ bool lmalt(const DevGraph& g, const Buckets& b, const Score& sc, LMBuffers& bufs
   scan_u8_i32(head, H, m, stemp, nullptr, st);
   k_alt_base<<<grid_for(m), BLOCK, 0, st>>>(head, H, S, m, base);
   k_alt_query<<<grid_for(m), BLOCK, 0, st>>>(ks, vs_, head, H, S, base, m, F);
-  k_gain<<<grid_for(k), BLOCK, 0, st>>>(list, k, bufs.vs, g.vw, sc, adj, F, gain);
+  k_gain<<<grid_for(k), BLOCK, 0, st>>>(list, k, bufs.vs, g.vw, ss, adj, F, gain);
   scan_i64_i64(gain, S2, k, stemp, st);
-  k_best_prefix<<<1, BP_BLOCK, 0, st>>>(S2, k, ctrl);
-  k_commit_prefix<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, ctrl);
-  launch_apply_and_empty(g, b, bufs, slot, st);
+  if (seg) {
+    const int64_t G = seg->sg.G;
+    k_best_prefix_seg<<<(unsigned)std::min<int64_t>(G, 4096), BP_BLOCK, 0, st>>>(S2, bufs.scan_a, ss.vbase, G, seg->act,
+                                                                                 seg->best_k);
+    k_commit_prefix_seg<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, ss.gid, ss.vbase, seg->best_k);
+  } else {
+    k_best_prefix<<<1, BP_BLOCK, 0, st>>>(S2, k, ctrl);
+    k_commit_prefix<<<grid_for(n), BLOCK, 0, st>>>(n, bufs.keep, bufs.scan_a, ctrl);
+  }
+  launch_apply_and_empty(g, b, bufs, seg ? seg->sg : SegLM{}, slot, st);
   return true;
 }
 

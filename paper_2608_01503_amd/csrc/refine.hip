@@ -49,15 +49,15 @@ __device__ __forceinline__ int64_t gsum(int64_t x) {
   return x;
 }
 
-__device__ __forceinline__ uint64_t fkey(int32_t v, uint32_t fseed, const uint8_t* flip) {
-  uint64_t f = fmix32((uint32_t)v ^ fseed);
+__device__ __forceinline__ uint64_t fkey(int32_t v, const RefSrc& rs, const uint8_t* flip) {
+  uint64_t f = fmix32(rs.loc(v) ^ rs.fseed(v));
   return flip && flip[v] ? (uint64_t)(2 * K32 - 1) - f : f;
 }
 
 // a(v, B[v] \ v) and membership of U
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_aB_grp(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* B,
-                                                  const int64_t* WB, Score sc, int64_t* aB, uint8_t* inU,
+                                                  const int64_t* WB, RefSrc rs, int64_t* aB, uint8_t* inU,
                                                   int64_t* nU) {
   __shared__ unsigned long long cu;  // |U| of this workgroup, one global atomic at the end
   if (threadIdx.x == 0) cu = 0;
@@ -74,7 +74,8 @@ __global__ __launch_bounds__(BLOCK) void k_aB_grp(const int32_t* list, int64_t c
     if (gl == 0) {
       aB[v] = s;
       int64_t wv = g.vw[v];
-      bool u = sc.q * s - sc.p * wv * (WB[bv] - wv) >= 0;
+      const Score sc = rs.sc(v);
+      bool u = rs.on(v) && sc.q * s - sc.p * wv * (WB[bv] - wv) >= 0;
       inU[v] = u;
       if (u) atomicAdd(&cu, 1ull);
     }
@@ -103,14 +104,15 @@ __global__ void k_hub_zero64(const int32_t* hubs, int64_t n7, int64_t* a) {
 }
 
 __global__ void k_hub_inU(const int32_t* hubs, int64_t n7, DevGraph g, const int32_t* B, const int64_t* WB,
-                          Score sc, const int64_t* aB, uint8_t* inU, int64_t* nU) {
+                          RefSrc rs, const int64_t* aB, uint8_t* inU, int64_t* nU) {
   __shared__ unsigned long long cu;
   if (threadIdx.x == 0) cu = 0;
   __syncthreads();
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n7; k += (int64_t)gridDim.x * blockDim.x) {
     int32_t v = hubs[k];
     int64_t wv = g.vw[v];
-    bool u = sc.q * aB[v] - sc.p * wv * (WB[B[v]] - wv) >= 0;
+    const Score sc = rs.sc(v);
+    bool u = rs.on(v) && sc.q * aB[v] - sc.p * wv * (WB[B[v]] - wv) >= 0;
     inU[v] = u;
     if (u) atomicAdd(&cu, 1ull);
   }
@@ -127,7 +129,7 @@ __device__ __forceinline__ bool qualifies(const DevGraph& g, const int32_t* B, c
 // Random candidate edge for rows of up to whole-wavefront groups: count, pick, locate (two sweeps).
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_choose_grp(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* B,
-                                                      const uint8_t* inU, Score sc, uint64_t st, int32_t* H) {
+                                                      const uint8_t* inU, RefSrc rs, int32_t* H) {
   const int gl = threadIdx.x % G;
   // the loop bound is the same for every lane of the workgroup: the ballots below see whole wavefronts
   for (int64_t gbase0 = (int64_t)blockIdx.x * (BLOCK / G); gbase0 < cnt; gbase0 += (int64_t)gridDim.x * (BLOCK / G)) {
@@ -138,6 +140,7 @@ __global__ __launch_bounds__(BLOCK) void k_choose_grp(const int32_t* list, int64
   const int64_t j0 = active ? g.off[v] : 0, j1 = active ? g.off[v + 1] : 0;
   const int32_t bv = active ? B[v] : 0;
   const int64_t wv = active ? g.vw[v] : 0;
+  const Score sc = rs.sc(v);
   // uniform trip count over the wavefront
   int64_t d = vin ? j1 - j0 : 0, dmax = d;
 #pragma unroll
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(BLOCK) void k_choose_grp(const int32_t* list, int64
   }
   int64_t target = -1;  // index among qualifying neighbours, or -1 for v itself
   if (vin) {
-    uint64_t r = fmix64(st ^ ((uint64_t)(uint32_t)v << 1)) % (uint64_t)(total + 1);
+    uint64_t r = fmix64(rs.seed(v) ^ ((uint64_t)rs.loc(v) << 1)) % (uint64_t)(total + 1);
     if ((int64_t)r != below) target = (int64_t)r < below ? (int64_t)r : (int64_t)r - 1;
   }
   int64_t seen = 0;
@@ -186,13 +189,14 @@ __global__ __launch_bounds__(BLOCK) void k_choose_grp(const int32_t* list, int64
 // hubs: per-chunk (qualifying count << 32 | qualifying count below v)
 __global__ __launch_bounds__(HUB_BLOCK) void k_choose_hub_count(const int32_t* hubs, const int32_t* chunk_off,
                                                                 int64_t n7, DevGraph g, const int32_t* B,
-                                                                const uint8_t* inU, Score sc, int64_t* pc) {
+                                                                const uint8_t* inU, RefSrc rs, int64_t* pc) {
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
   int64_t c = 0, cb = 0;
   if (inU[v]) {
     const int32_t bv = B[v];
     const int64_t wv = g.vw[v];
+    const Score sc = rs.sc(v);
     const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK_EDGES;
     const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK_EDGES);
     for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK)
@@ -215,7 +219,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_choose_hub_count(const int32_t* h
 
 // per hub: pick r, find the chunk holding the target; tgt[k] = chunk << 32 | rank in chunk, or -1
 __global__ void k_choose_hub_pick(const int32_t* hubs, const int32_t* chunk_off, int64_t n7, const uint8_t* inU,
-                                  uint64_t st, const int64_t* pc, int64_t* tgt, int32_t* H) {
+                                  RefSrc rs, const int64_t* pc, int64_t* tgt, int32_t* H) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n7) return;
   int32_t v = hubs[k];
@@ -226,7 +230,7 @@ __global__ void k_choose_hub_pick(const int32_t* hubs, const int32_t* chunk_off,
     total += pc[c] >> 32;
     below += pc[c] & 0xFFFFFFFF;
   }
-  uint64_t r = fmix64(st ^ ((uint64_t)(uint32_t)v << 1)) % (uint64_t)(total + 1);
+  uint64_t r = fmix64(rs.seed(v) ^ ((uint64_t)rs.loc(v) << 1)) % (uint64_t)(total + 1);
   if ((int64_t)r == below) { H[v] = v; return; }
   int64_t t = (int64_t)r < below ? (int64_t)r : (int64_t)r - 1;
   for (int32_t c = chunk_off[k]; c < chunk_off[k + 1]; ++c) {
@@ -238,7 +242,7 @@ __global__ void k_choose_hub_pick(const int32_t* hubs, const int32_t* chunk_off,
 
 // per hub with a target: one workgroup scans the chunk in order
 __global__ __launch_bounds__(HUB_BLOCK) void k_choose_hub_find(const int32_t* hubs, int64_t n7, DevGraph g,
-                                                               const int32_t* B, const uint8_t* inU, Score sc,
+                                                               const int32_t* B, const uint8_t* inU, RefSrc rs,
                                                                const int64_t* tgt, int32_t* H) {
   const int64_t k = blockIdx.x;
   const int64_t tg = tgt[k];
@@ -246,6 +250,7 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_choose_hub_find(const int32_t* hu
   const int32_t v = hubs[k];
   const int32_t bv = B[v];
   const int64_t wv = g.vw[v];
+  const Score sc = rs.sc(v);
   const int64_t j0 = g.off[v] + (tg >> 32) * HUB_CHUNK_EDGES;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK_EDGES);
   const int64_t want = tg & 0xFFFFFFFF;
@@ -267,10 +272,10 @@ __global__ __launch_bounds__(HUB_BLOCK) void k_choose_hub_find(const int32_t* hu
   }
 }
 
-__global__ void k_parents(int64_t n, const int32_t* H, uint32_t fseed, int32_t* par, uint8_t* has_child) {
+__global__ void k_parents(int64_t n, const int32_t* H, RefSrc rs, int32_t* par, uint8_t* has_child) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     int32_t h = H[v];
-    bool keep = h != (int32_t)v && fmix32((uint32_t)h ^ fseed) < fmix32((uint32_t)v ^ fseed);
+    bool keep = h != (int32_t)v && fkey(h, rs, nullptr) < fkey((int32_t)v, rs, nullptr);
     par[v] = keep ? h : (int32_t)v;
     if (keep) has_child[h] = 1;
   }
@@ -281,10 +286,10 @@ __global__ void k_flip(int64_t n, const int32_t* par, const uint8_t* has_child, 
     flip[v] = par[v] == (int32_t)v && !has_child[v];
 }
 
-__global__ void k_reparent(int64_t n, const int32_t* H, uint32_t fseed, const uint8_t* flip, int32_t* par) {
+__global__ void k_reparent(int64_t n, const int32_t* H, RefSrc rs, const uint8_t* flip, int32_t* par) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     int32_t h = H[v];
-    if (flip[v] && h != (int32_t)v && fkey(h, fseed, flip) < fkey((int32_t)v, fseed, flip)) par[v] = h;
+    if (flip[v] && h != (int32_t)v && fkey(h, rs, flip) < fkey((int32_t)v, rs, flip)) par[v] = h;
   }
 }
 
@@ -313,11 +318,11 @@ __global__ void k_tree_sizes(int64_t n, const int32_t* root, const int32_t* tsz,
 }
 
 __global__ void k_tree_keys(int64_t n, const uint8_t* member, const int64_t* tpos, const int32_t* root,
-                            uint32_t fseed, const uint8_t* flip, uint64_t* keys, uint32_t* vals) {
+                            RefSrc rs, const uint8_t* flip, uint64_t* keys, uint32_t* vals) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     if (!member[v]) continue;
     const int64_t p = tpos[v];
-    keys[p] = ((uint64_t)(uint32_t)root[v] << 33) | fkey((int32_t)v, fseed, flip);
+    keys[p] = ((uint64_t)(uint32_t)root[v] << 33) | fkey((int32_t)v, rs, flip);
     vals[p] = (uint32_t)v;
   }
 }
@@ -325,7 +330,7 @@ __global__ void k_tree_keys(int64_t n, const uint8_t* member, const int64_t* tpo
 // a(v, X_{<v}): edges to earlier vertices of the same tree
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_aX_grp(const int32_t* list, int64_t cnt, DevGraph g, const uint8_t* member,
-                                                  const int32_t* root, uint32_t fseed, const uint8_t* flip,
+                                                  const int32_t* root, RefSrc rs, const uint8_t* flip,
                                                   int64_t* aX) {
   const int gl = threadIdx.x % G;
   for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
@@ -333,11 +338,11 @@ __global__ __launch_bounds__(BLOCK) void k_aX_grp(const int32_t* list, int64_t c
     const int32_t v = list[gid];
     if (!member[v]) continue;  // uniform within the group
     const int32_t rv = root[v];
-    const uint64_t fv = fkey(v, fseed, flip);
+    const uint64_t fv = fkey(v, rs, flip);
     int64_t s = 0;
     for (int64_t j = g.off[v] + gl; j < g.off[v + 1]; j += G) {
       int32_t u = g.idx[j];
-      if (root[u] == rv && fkey(u, fseed, flip) < fv) s += g.w[j];
+      if (root[u] == rv && fkey(u, rs, flip) < fv) s += g.w[j];
     }
     s = gsum<G>(s);
     if (gl == 0) aX[v] = s;
@@ -346,18 +351,18 @@ __global__ __launch_bounds__(BLOCK) void k_aX_grp(const int32_t* list, int64_t c
 
 __global__ __launch_bounds__(HUB_BLOCK) void k_aX_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
                                                       DevGraph g, const uint8_t* member, const int32_t* root,
-                                                      uint32_t fseed, const uint8_t* flip, int64_t* aX) {
+                                                      RefSrc rs, const uint8_t* flip, int64_t* aX) {
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
   if (!member[v]) return;
   const int32_t rv = root[v];
-  const uint64_t fv = fkey(v, fseed, flip);
+  const uint64_t fv = fkey(v, rs, flip);
   const int64_t j0 = g.off[v] + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK_EDGES;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK_EDGES);
   int64_t s = 0;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) {
     int32_t u = g.idx[j];
-    if (root[u] == rv && fkey(u, fseed, flip) < fv) s += g.w[j];
+    if (root[u] == rv && fkey(u, rs, flip) < fv) s += g.w[j];
   }
   s = gsum<WAVE>(s);
   if ((threadIdx.x & (WAVE - 1)) == 0 && s) atomicAdd((unsigned long long*)&aX[v], (unsigned long long)s);
@@ -375,13 +380,14 @@ __global__ void k_sorted_terms(int64_t m, const uint32_t* sv, const int64_t* vw,
 
 __global__ void k_validity(int64_t m, const uint32_t* sv, const int32_t* root, const int32_t* pos_of,
                            const int64_t* pw, const int64_t* pc, const int64_t* aX, const int64_t* vw,
-                           const int32_t* B, const int64_t* WB, Score sc, int32_t* fail) {
+                           const int32_t* B, const int64_t* WB, RefSrc rs, int32_t* fail) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
     int32_t v = (int32_t)sv[i];
     int32_t r = root[v];
     int64_t s = pos_of[r];
     int64_t wX = pw[i] - pw[s];
     int64_t cut = pc[i] - pc[s];
+    const Score sc = rs.sc(r);
     int64_t c1 = sc.q * aX[v] - sc.p * vw[v] * wX;
     int64_t c2 = sc.q * cut - sc.p * wX * (WB[B[r]] - wX);
     if (c1 < 0 || c2 < 0) atomicMin(&fail[r], (int32_t)i);
@@ -402,45 +408,43 @@ __global__ void k_set_i64(int64_t* p, int64_t v) {
 
 }  // namespace
 
-void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t* B, uint64_t seed, uint64_t t,
-            int32_t* R, RefineBuffers& rb, Ctrl* ctrl, const std::function<void*(size_t)>& take, hipStream_t st) {
+void refine(const DevGraph& g, const Buckets& b, const RefSrc& rs, const int32_t* B, int32_t* R, RefineBuffers& rb,
+            Ctrl* ctrl, const std::function<void*(size_t)>& take, hipStream_t st) {
   const int64_t n = g.n;
   const int32_t* L = b.list;
-  const uint64_t s_t = seed_stream(seed, t);
-  const uint32_t fseed = (uint32_t)(s_t >> 32);
   // constraint-cluster weights and U
   launch_cluster_weights(B, g.vw, n, rb.WB, st);
   k_set_i64<<<1, 1, 0, st>>>(&ctrl->refine_U, 0);
-  if (b.count[0]) k_aB_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
-  if (b.count[1]) k_aB_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
-  if (b.count[2]) k_aB_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
-  if (b.count[3]) k_aB_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[0]) k_aB_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.WB, rs, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[1]) k_aB_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.WB, rs, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[2]) k_aB_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.WB, rs, rb.aB, rb.inU, &ctrl->refine_U);
+  if (b.count[3]) k_aB_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.WB, rs, rb.aB, rb.inU, &ctrl->refine_U);
   int64_t nw = b.count[4] + b.count[5] + b.count[6];
-  if (nw) k_aB_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+  if (nw) k_aB_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.WB, rs, rb.aB, rb.inU, &ctrl->refine_U);
   const int32_t* hubs = L + b.off[7];
   const int64_t n7 = b.count[7];
   if (n7) {
     k_hub_zero64<<<grid_for(n7), BLOCK, 0, st>>>(hubs, n7, rb.aB);
     k_aB_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, B, rb.aB);
-    k_hub_inU<<<grid_for(n7), BLOCK, 0, st>>>(hubs, n7, g, B, rb.WB, sc, rb.aB, rb.inU, &ctrl->refine_U);
+    k_hub_inU<<<grid_for(n7), BLOCK, 0, st>>>(hubs, n7, g, B, rb.WB, rs, rb.aB, rb.inU, &ctrl->refine_U);
   }
   // random candidate edge
-  if (b.count[0]) k_choose_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.inU, sc, s_t, rb.H);
-  if (b.count[1]) k_choose_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.inU, sc, s_t, rb.H);
-  if (b.count[2]) k_choose_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.inU, sc, s_t, rb.H);
-  if (b.count[3]) k_choose_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.inU, sc, s_t, rb.H);
-  if (nw) k_choose_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.inU, sc, s_t, rb.H);
+  if (b.count[0]) k_choose_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, B, rb.inU, rs, rb.H);
+  if (b.count[1]) k_choose_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, B, rb.inU, rs, rb.H);
+  if (b.count[2]) k_choose_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, B, rb.inU, rs, rb.H);
+  if (b.count[3]) k_choose_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, B, rb.inU, rs, rb.H);
+  if (nw) k_choose_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, B, rb.inU, rs, rb.H);
   if (n7) {
-    k_choose_hub_count<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, B, rb.inU, sc, b.hub_ps);
-    k_choose_hub_pick<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, rb.inU, s_t, b.hub_ps, b.hub_acc, rb.H);
-    k_choose_hub_find<<<(unsigned)n7, HUB_BLOCK, 0, st>>>(hubs, n7, g, B, rb.inU, sc, b.hub_acc, rb.H);
+    k_choose_hub_count<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, B, rb.inU, rs, b.hub_ps);
+    k_choose_hub_pick<<<grid_for(n7), BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, rb.inU, rs, b.hub_ps, b.hub_acc, rb.H);
+    k_choose_hub_find<<<(unsigned)n7, HUB_BLOCK, 0, st>>>(hubs, n7, g, B, rb.inU, rs, b.hub_acc, rb.H);
     fill_i64(b.hub_acc, 0, n7, st);  // the per-hub accumulator is expected zero by the afterburner
   }
   // parents, singleton-tree fix, roots
   fill_u8(rb.has_child, 0, n, st);
-  k_parents<<<grid_for(n), BLOCK, 0, st>>>(n, rb.H, fseed, rb.par, rb.has_child);
+  k_parents<<<grid_for(n), BLOCK, 0, st>>>(n, rb.H, rs, rb.par, rb.has_child);
   k_flip<<<grid_for(n), BLOCK, 0, st>>>(n, rb.par, rb.has_child, rb.flip);
-  k_reparent<<<grid_for(n), BLOCK, 0, st>>>(n, rb.H, fseed, rb.flip, rb.par);
+  k_reparent<<<grid_for(n), BLOCK, 0, st>>>(n, rb.H, rs, rb.flip, rb.par);
   fill_i32(rb.tsz, 0, n, st);
   k_roots<<<grid_for(n), BLOCK, 0, st>>>(n, rb.par, rb.root, rb.tsz, ctrl);
   k_members<<<grid_for(n), BLOCK, 0, st>>>(n, rb.root, rb.tsz, rb.member);
@@ -459,21 +463,21 @@ void refine(const DevGraph& g, const Buckets& b, const Score& sc, const int32_t*
   fill_i32(rb.fail, INT32_MAX, n, st);
   if (m > 0) {
     launch_group_place(rb.root, nullptr, rb.member, n, toff, n, cursor, tpos, st);
-    k_tree_keys<<<grid_for(n), BLOCK, 0, st>>>(n, rb.member, tpos, rb.root, fseed, rb.flip, rb.k0, rb.v0);
+    k_tree_keys<<<grid_for(n), BLOCK, 0, st>>>(n, rb.member, tpos, rb.root, rs, rb.flip, rb.k0, rb.v0);
     segsort_pairs(rb.k0, rb.v0, rb.k1, rb.v1, m, toff, n, 33, rb.scan_temp, take, st);
     const uint32_t* sv = rb.v1;
     // a(v, X_{<v}) for tree members
     fill_i64(rb.aX, 0, n, st);
-    if (b.count[0]) k_aX_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (b.count[1]) k_aX_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (b.count[2]) k_aX_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (b.count[3]) k_aX_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (nw) k_aX_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, rb.member, rb.root, fseed, rb.flip, rb.aX);
-    if (n7) k_aX_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, rb.member, rb.root, fseed, rb.flip, rb.aX);
+    if (b.count[0]) k_aX_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, rb.member, rb.root, rs, rb.flip, rb.aX);
+    if (b.count[1]) k_aX_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, rb.member, rb.root, rs, rb.flip, rb.aX);
+    if (b.count[2]) k_aX_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, rb.member, rb.root, rs, rb.flip, rb.aX);
+    if (b.count[3]) k_aX_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, rb.member, rb.root, rs, rb.flip, rb.aX);
+    if (nw) k_aX_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, rb.member, rb.root, rs, rb.flip, rb.aX);
+    if (n7) k_aX_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, n7, g, rb.member, rb.root, rs, rb.flip, rb.aX);
     k_sorted_terms<<<grid_for(m), BLOCK, 0, st>>>(m, sv, g.vw, rb.aB, rb.aX, rb.tmp64a, rb.tmp64b, rb.pos_of);
     scan_i64_i64(rb.tmp64a, rb.pw, m, rb.scan_temp, st);
     scan_i64_i64(rb.tmp64b, rb.pc, m, rb.scan_temp, st);
-    k_validity<<<grid_for(m), BLOCK, 0, st>>>(m, sv, rb.root, rb.pos_of, rb.pw, rb.pc, rb.aX, g.vw, B, rb.WB, sc,
+    k_validity<<<grid_for(m), BLOCK, 0, st>>>(m, sv, rb.root, rb.pos_of, rb.pw, rb.pc, rb.aX, g.vw, B, rb.WB, rs,
                                               rb.fail);
   }
   k_commit<<<grid_for(n), BLOCK, 0, st>>>(n, rb.member, rb.root, rb.pos_of, rb.fail, R);

@@ -5,9 +5,9 @@
 // A submitted job is copied to host memory and queued.  A free slot admits the oldest queued job whose
 // device footprint (lcc_workspace_bytes) fits the unreserved part of the HBM budget; a job that does not fit
 // yet is passed over by smaller ones at most a few times before it holds the next free slot, so a large
-// request cannot starve.  When the admitted job is a small Louvain / Louvain+ request, the slot also takes
-// the other queued small Louvain requests with the same options that fit the budget and runs them all as one
-// fused batch (lcc_cluster_batch: one union graph per kernel launch), so a burst of small requests costs
+// request cannot starve.  When the admitted job is a small request, the slot also takes the other queued small
+// requests of its family (Louvain / Louvain+, or pLeiden / pLeiden+) with the same options that fit the budget
+// and runs them all as one fused batch (lcc_cluster_batch: one union graph per kernel launch), so a burst of small requests costs
 // about one request's launches.  A finished slot releases its reservations at once and the next job joins
 // without waiting for the others.  Results are bit-identical to a plain lcc_cluster call.
 //
@@ -163,14 +163,14 @@ struct lcc_server {
     return nullptr;
   }
 
-  static bool fusable(const Job& j) {
-    return (j.variant == LCC_LOUVAIN || j.variant == LCC_PLOUVAIN) && j.nnz <= FUSE_NNZ;
-  }
+  static bool fusable(const Job& j) { return j.nnz <= FUSE_NNZ; }
+  // one fused group holds one family: Louvain / Louvain+ or pLeiden / pLeiden+
+  static bool leiden(const Job& j) { return j.variant == LCC_PLEIDEN || j.variant == LCC_PLEIDEN_PLUS; }
   static bool same_opts(const Job& a, const Job& b) {
     return a.has_opts == b.has_opts && (!a.has_opts || memcmp(&a.opts, &b.opts, sizeof(lcc_options)) == 0);
   }
 
-  // The admitted job plus the queued small Louvain jobs that can join it (caller holds mu).
+  // The admitted job plus the queued small jobs of its family that can join it (caller holds mu).
   std::vector<std::shared_ptr<Job>> pick_group(int k) {
     std::vector<std::shared_ptr<Job>> grp;
     auto head = pick(k);
@@ -181,7 +181,8 @@ struct lcc_server {
     for (size_t i = 0; i < queue.size() && grp.size() < FUSE_MAX;) {
       auto& j = queue[i];
       const size_t rest = total_charge() - charge(k);
-      if (fusable(*j) && !j->alone && same_opts(*head, *j) && total + j->nnz <= FUSE_TOTAL_NNZ &&
+      if (fusable(*j) && !j->alone && leiden(*j) == leiden(*head) && same_opts(*head, *j) &&
+          total + j->nnz <= FUSE_TOTAL_NNZ &&
           rest + std::max(held[k], reserve[k] + j->footprint) <= budget) {
         reserve[k] += j->footprint;
         total += j->nnz;

@@ -135,3 +135,52 @@ def test_fused_batch_with_ablation_options():
             [(gg.random_gnp(900, 0.006, 60, w_max=5), O.LOUVAIN, *CPM20, None)]
     for sym in (1, 2):
         _batch(items, opts_kw=dict(phases=((0, 1, 6),), symmetry=sym))
+
+
+def _empty(n):
+    return gg.Graph(n=n, off=np.zeros(n + 1, np.int64), idx=np.zeros(0, np.int32), w=np.zeros(0, np.int32))
+
+
+def test_fused_pleiden_mixed_graphs():
+    """pLeiden and pLeiden+ graphs in one fused call: alternate local moves (Sec. V-A) on some graphs and not on
+    others at the same level, refinements that make no progress (those graphs repeat their level while the
+    others go on; a two-vertex graph stops with the no-progress flag), empty graphs, hubs and per-graph
+    lambdas and vertex weights."""
+    rng = np.random.default_rng(5)
+    items = [
+        (gg.random_gnp(400, 0.01, 100, w_max=3), O.PLEIDEN, *CPM20, None),
+        (gg.random_gnp(400, 0.01, 102, w_max=3), O.PLEIDEN_PLUS, *CPM20, None),
+        (gg.rmat(11, seed=40), O.PLEIDEN, (1, 10, False), O.VW_UNIT, None),
+        (gg.lattice(40, 40, seed=52), O.PLEIDEN_PLUS, *CPM20, None),
+        (gg.config1_sbm(), O.PLEIDEN_PLUS, *MOD, None),
+        (gg.knn_graph(800, 8, 5, 2), O.PLEIDEN, *MOD, None),
+        (gg.from_pairs(2, [(0, 1)]), O.PLEIDEN, *CPM20, None),
+        (_empty(0), O.PLEIDEN, *CPM20, None),
+        (_empty(5), O.PLEIDEN_PLUS, *CPM20, None),
+        (U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=4), O.PLEIDEN_PLUS, *CPM20, None),
+        (gg.rmat(12, 16, seed=21), O.PLEIDEN, *CPM3, None),
+    ]
+    g9 = gg.random_gnp(800, 0.01, 5, w_max=9)
+    items.append((g9, O.PLEIDEN, (1, 400, False), O.VW_GIVEN, rng.integers(0, 20, size=g9.n)))
+    ress = _batch(items, offsets32=(0, 6))
+    assert ress[6].flags & 2  # the two-vertex graph: no progress in three refinements
+
+
+def test_fused_pleiden_many_small_graphs_and_options():
+    rng = np.random.default_rng(17)
+    items = []
+    for k in range(96):
+        n = int(np.exp(rng.uniform(np.log(20), np.log(2500))))
+        g = gg.random_gnp(n, min(0.5, 6.0 / n), 2000 + k, w_max=int(rng.integers(1, 30)))
+        obj = [MOD, CPM20, CPM3][k % 3]
+        items.append((g, O.PLEIDEN_PLUS if k % 2 else O.PLEIDEN, *obj, None))
+    _batch(items)
+    for kw in [dict(max_levels=3), dict(seed=7), dict(pass_limit=2, phases=((1, 2, 2),))]:
+        _batch(items[:40], opts_kw=kw)
+
+
+def test_mixed_families_run_one_by_one():
+    """A batch with both families is not fused; the results are still every graph's own."""
+    items = [(gg.random_gnp(300, 0.02, 70, w_max=3), O.PLOUVAIN, *MOD, None),
+             (gg.random_gnp(300, 0.02, 71, w_max=3), O.PLEIDEN, *CPM20, None)]
+    _batch(items)
