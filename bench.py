@@ -294,8 +294,10 @@ def bench_knn_batch(args):
     nv = sum(gr.n for gr in graphs)
     ctx = L.Context(0)
     opts = L.lcc_default_options()
+    variant, vname = {"plouvain": (L.LCC_PLOUVAIN, "pLouvain+"), "pleiden": (L.LCC_PLEIDEN, "pLeiden"),
+                      "pleiden_plus": (L.LCC_PLEIDEN_PLUS, "pLeiden+")}[args.knn_variant]
     lam = [(1, 1, True)] * len(graphs)
-    var = [L.LCC_PLOUVAIN] * len(graphs)
+    var = [variant] * len(graphs)
     outs = [torch.empty(gr.n, dtype=torch.int32, device=dev) for gr in graphs]
     # launch tuning from the autotuner on every 16th graph (one fused batch per candidate); both the plain
     # and the fused runs below use it
@@ -309,14 +311,14 @@ def bench_knn_batch(args):
         print(f"# autotuned on {len(sample)} graphs in {tune_s:.1f} s: {tuning}", file=sys.stderr, flush=True)
     # plain: one call per graph (warm the workspace on the largest graph first)
     big = max(range(len(graphs)), key=lambda i: graphs[i].nnz)
-    ctx.cluster(graphs[big], (1, 1, True), L.LCC_PLOUVAIN, opts, labels_out=outs[big])
+    ctx.cluster(graphs[big], (1, 1, True), variant, opts, labels_out=outs[big])
     torch.cuda.synchronize()
     dur = []
     plain_res = []
     tp = time.perf_counter()
     for i, gr in enumerate(graphs):
         a = time.perf_counter()
-        _, r = ctx.cluster(gr, (1, 1, True), L.LCC_PLOUVAIN, opts, labels_out=outs[i])
+        _, r = ctx.cluster(gr, (1, 1, True), variant, opts, labels_out=outs[i])
         dur.append(time.perf_counter() - a)
         plain_res.append(r)
     torch.cuda.synchronize()
@@ -337,7 +339,7 @@ def bench_knn_batch(args):
     same = all(a.N == b.N and a.num_clusters == b.num_clusters for a, b in zip(plain_res, fres)) and \
         torch.equal(plain_labels, torch.cat(outs))
     pct = lambda x, q: float(np.percentile(np.asarray(x), q))
-    leg = {"workload": f"{len(graphs)} kNN graphs (k=15, 50-D Gaussian mixtures), pLouvain+ modularity",
+    leg = {"workload": f"{len(graphs)} kNN graphs (k=15, 50-D Gaussian mixtures), {vname} modularity",
            "graphs": len(graphs), "nnz": nnz, "generation_s": gen_s,
            "batched": {"wall_s": fused_wall, "p50_latency_s": fused_wall, "p99_latency_s": fused_wall,
                        "edges_per_s": nnz / fused_wall},
@@ -352,7 +354,7 @@ def bench_knn_batch(args):
         "warmup": 1, "ms_per_step": fused_wall * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"{len(graphs)} kNN graphs (k=15, 50-D Gaussian mixtures with 5-40 components, "
-                               f"n log-uniform in [500, 50000]), pLouvain+ modularity, one fused batch call",
+                               f"n log-uniform in [500, 50000]), {vname} modularity, one fused batch call",
                    "graphs": len(graphs), "vertices": nv, "nnz": nnz, "generation_s": gen_s,
                    "tuning": tuning, "autotune_s": tune_s},
         "batched": {"wall_s": fused_wall, "p50_latency_s": fused_wall, "p99_latency_s": fused_wall,
@@ -609,6 +611,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--family", default="auto", help="kernel family timed live for the roofline")
     ap.add_argument("--knn-count", type=int, default=4096, help="graphs of the kNN batch workload")
+    ap.add_argument("--knn-variant", choices=["plouvain", "pleiden", "pleiden_plus"], default="plouvain",
+                    help="method of the kNN batch workload (the batched configuration is pLouvain+)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="run the library's autotuner before timing (auto: on for the kNN batch, off for single "
                          "graphs, whose committed counter profiles are taken with the default tuning)")

@@ -223,8 +223,8 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint64_t* kin, co
       tk[pos] = key;
       tv[pos] = val;
     }
+    __syncthreads();  // every wavefront has read its offsets before the next round clears them
   }
-  __syncthreads();
   for (int p = tid; p < items; p += BLOCK) {
     const uint64_t key = tk[p];
     const uint32_t d = (uint32_t)(key >> shift) & 255u;
