@@ -234,7 +234,13 @@ def write_trace_summary(run_dir: str, workload_name: str, steps: int, warmup: in
         raise SystemExit(f"no kernel_stats.csv under {run_dir}")
     rows = list(csv.DictReader(open(f[0])))
     calls = steps + warmup
-    _, _, _, _, desc = workload(workload_name, generate=False)
+    knn = workload_name.startswith("knn")
+    if knn:  # the fused calls of `--workload knn --knn-plain off` (one untimed + steps timed); library kernels only
+        rows = [r for r in rows if "lcc::" in r["Name"]]
+        desc = (f"fused lcc_cluster_batch call over the batched kNN workload ({workload_name}), library kernels "
+                "only (the graph generation's torch kernels are left out)")
+    else:
+        _, _, _, _, desc = workload(workload_name, generate=False)
 
     def short(name):
         name = name.replace("lcc::", "").replace("(anonymous namespace)::", "")
@@ -253,13 +259,19 @@ def write_trace_summary(run_dir: str, workload_name: str, steps: int, warmup: in
     out = os.path.join(ROOT, "profiles", f"kernels_{workload_name}.txt")
     with open(out, "w") as o:
         o.write(f"# Kernel time per clustering call: {desc}\n")
-        o.write(f"# commands ({calls} clustering calls: {warmup} warm-up + {steps} timed, plus one objective check; "
-                "figures below are per clustering call):\n")
-        o.write(f"#   rocprofv3 --kernel-trace --stats --output-format csv -d {run_dir} -o run -- python -u bench.py "
-                f"--workload {workload_name} --steps {steps} --warmup {warmup} --no-cpu-baseline --family {family}\n")
+        o.write(f"# commands ({calls} clustering calls: {warmup} warm-up + {steps} timed"
+                f"{'' if knn else ', plus one objective check'}; figures below are per clustering call):\n")
+        if knn:  # knn (pLouvain+) or knn_<variant>
+            kv = f" --knn-variant {workload_name[4:]}" if len(workload_name) > 3 else ""
+            o.write(f"#   rocprofv3 --kernel-trace --stats --output-format csv -d {run_dir} -o run -- python -u bench.py "
+                    f"--workload knn --steps {steps} --knn-plain off --autotune off{kv}\n")
+        else:
+            o.write(f"#   rocprofv3 --kernel-trace --stats --output-format csv -d {run_dir} -o run -- python -u bench.py "
+                    f"--workload {workload_name} --steps {steps} --warmup {warmup} --no-cpu-baseline --family {family}\n")
         o.write(f"#   python bench.py --trace-summary {run_dir} --workload {workload_name} --steps {steps} "
                 f"--warmup {warmup} --family {family}\n")
-        o.write(f"# total kernel time per call: {total:.2f} ms\n#\n")
+        o.write(f"# total kernel time per call: {total:.2f} ms, {sum(int(r['Calls']) for r in rows) / calls:.0f} "
+                "launches per call\n#\n")
         o.write("# ms/call  calls/call  avg_us  max_us  kernel\n")
         for r in rows:
             ms = float(r["TotalDurationNs"]) / calls / 1e6
@@ -309,22 +321,24 @@ def bench_knn_batch(args):
         tune_s = time.perf_counter() - ta
         tuning = L.tuning_dict(best)
         print(f"# autotuned on {len(sample)} graphs in {tune_s:.1f} s: {tuning}", file=sys.stderr, flush=True)
-    # plain: one call per graph (warm the workspace on the largest graph first)
-    big = max(range(len(graphs)), key=lambda i: graphs[i].nnz)
-    ctx.cluster(graphs[big], (1, 1, True), variant, opts, labels_out=outs[big])
-    torch.cuda.synchronize()
-    dur = []
-    plain_res = []
-    tp = time.perf_counter()
-    for i, gr in enumerate(graphs):
-        a = time.perf_counter()
-        _, r = ctx.cluster(gr, (1, 1, True), variant, opts, labels_out=outs[i])
-        dur.append(time.perf_counter() - a)
-        plain_res.append(r)
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - tp
-    plain_labels = torch.cat(outs)  # every graph's labels from its plain call
-    done = np.cumsum(dur)
+    # plain: one call per graph (warm the workspace on the largest graph first); --knn-plain off skips them
+    # (a profile of the fused call alone)
+    dur, plain_res, plain_wall, plain_labels = [], [], float("nan"), None
+    if args.knn_plain == "on":
+        big = max(range(len(graphs)), key=lambda i: graphs[i].nnz)
+        ctx.cluster(graphs[big], (1, 1, True), variant, opts, labels_out=outs[big])
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for i, gr in enumerate(graphs):
+            a = time.perf_counter()
+            _, r = ctx.cluster(gr, (1, 1, True), variant, opts, labels_out=outs[i])
+            dur.append(time.perf_counter() - a)
+            plain_res.append(r)
+        torch.cuda.synchronize()
+        plain_wall = time.perf_counter() - tp
+        plain_labels = torch.cat(outs)  # every graph's labels from its plain call
+    done = np.cumsum(dur) if dur else [float("nan")]
+    dur = dur or [float("nan")]
     # fused: one warm-up call (union workspace), then the timed call
     ctx.cluster_batch(graphs, lam, var, opts=opts, labels_out=outs)
     torch.cuda.synchronize()
@@ -336,8 +350,9 @@ def bench_knn_batch(args):
         walls.append(time.perf_counter() - tf)
     fused_wall = float(np.median(walls))
     # every graph: labels, exact objective and cluster count of the fused call equal its plain call's
-    same = all(a.N == b.N and a.num_clusters == b.num_clusters for a, b in zip(plain_res, fres)) and \
-        torch.equal(plain_labels, torch.cat(outs))
+    same = None if plain_labels is None else (
+        all(a.N == b.N and a.num_clusters == b.num_clusters for a, b in zip(plain_res, fres)) and
+        torch.equal(plain_labels, torch.cat(outs)))
     pct = lambda x, q: float(np.percentile(np.asarray(x), q))
     leg = {"workload": f"{len(graphs)} kNN graphs (k=15, 50-D Gaussian mixtures), {vname} modularity",
            "graphs": len(graphs), "nnz": nnz, "generation_s": gen_s,
@@ -345,7 +360,7 @@ def bench_knn_batch(args):
                        "edges_per_s": nnz / fused_wall},
            "plain": {"wall_s": plain_wall, "p50_latency_s": pct(done, 50), "p99_latency_s": pct(done, 99),
                      "p50_call_s": pct(dur, 50), "p99_call_s": pct(dur, 99), "edges_per_s": nnz / plain_wall},
-           "results_identical": bool(same), "graphs_compared": len(graphs)}
+           "results_identical": same, "graphs_compared": len(graphs) if same is not None else 0}
     if not args.workload == "knn":
         ctx.close()
         return leg
@@ -362,7 +377,7 @@ def bench_knn_batch(args):
         "plain": {"wall_s": plain_wall, "p50_latency_s": pct(done, 50), "p99_latency_s": pct(done, 99),
                   "p50_call_s": pct(dur, 50), "p99_call_s": pct(dur, 99), "edges_per_s": nnz / plain_wall},
         "speedup_wall": plain_wall / fused_wall,
-        "results_identical": bool(same), "graphs_compared": len(graphs),
+        "results_identical": same, "graphs_compared": len(graphs) if same is not None else 0,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -611,6 +626,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--family", default="auto", help="kernel family timed live for the roofline")
     ap.add_argument("--knn-count", type=int, default=4096, help="graphs of the kNN batch workload")
+    ap.add_argument("--knn-plain", choices=["on", "off"], default="on",
+                    help="also run the kNN batch as plain calls (off: the fused call alone, for profiling)")
     ap.add_argument("--knn-variant", choices=["plouvain", "pleiden", "pleiden_plus"], default="plouvain",
                     help="method of the kNN batch workload (the batched configuration is pLouvain+)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
@@ -746,7 +763,7 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "nnz": g.nnz, "clusters": res.num_clusters if res else None,
-                   "modularity": res.modularity if res else None, "levels": res.levels if res else None,
+                   "modularity": res.modularity if res and res.modularity == res.modularity else None, "levels": res.levels if res else None,
                    "flags": res.flags if res else None, "objective_consistent": objective_consistent,
                    "tuning": tuning},
         "roofline": roofline,
