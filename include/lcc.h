@@ -240,7 +240,7 @@ lcc_status lcc_objective_device(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lam
  * changes.  bucket_max[k] is the largest row degree put in degree bucket k (0-3: groups of 4/8/16/32 lanes,
  * 4: a wavefront with a 256-slot LDS hash, 5 and 6: workgroups with 2048- and 8192-slot LDS hashes, 6's rows
  * above 4096 on workgroups with a 16384-slot hash; rows above bucket_max[6] go to the hub path of 2048-edge
- * chunks).  The default bounds are {4, 8, 16, 32, 128, 1024, 4096}; a bucket's kernels serve rows up to
+ * chunks).  The default bounds are {4, 8, 16, 32, 128, 1024, 8192}; a bucket's kernels serve rows up to
  * {4, 8, 16, 32, 128, 1024, 8192}, so a tuning may set the bounds anywhere up to these capacities
  * (non-decreasing in k, >= 0); equal neighbouring bounds leave a bucket empty.  grid_cap (64..65536, default 2048) bounds the
  * workgroups of the persistent per-vertex launches.  hash_shift (0..2, default 0) sizes the LDS hash of a row

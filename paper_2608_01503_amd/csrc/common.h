@@ -39,12 +39,14 @@ constexpr int32_t D_EMPTY = -2;  // destination = a new singleton cluster
 // count of its group, half the slots of its LDS hash); a tuning may set lower bounds, never higher ones, and
 // every setting gives the same results.
 constexpr int64_t BUCKET_CAP[NBUCKET - 1] = {4, 8, 16, 32, 128, 1024, 8192};
-// default bounds (bucket 6 rows above 4096 are a tuning choice: they help graphs with many such rows)
-constexpr int64_t BUCKET_DEFAULT[NBUCKET - 1] = {4, 8, 16, 32, 128, 1024, 4096};
+// default bounds: every row up to 8192 entries is aggregated in LDS (bucket 6's rows above B6_SPLIT take the
+// 16384-slot table), longer ones in the hub chunks
+constexpr int64_t BUCKET_DEFAULT[NBUCKET - 1] = {4, 8, 16, 32, 128, 1024, 8192};
 constexpr int LDS_SLOTS_B4 = 256;
 constexpr int LDS_SLOTS_B5 = 2048;
 constexpr int LDS_SLOTS_B6 = 8192;    // bucket 6 rows up to 4096 (512 threads)
 constexpr int LDS_SLOTS_B6X = 16384;  // bucket 6 rows 4097-8192 (1024 threads, 128 KB of LDS)
+constexpr int64_t B6_SPLIT = LDS_SLOTS_B6 / 2;  // bucket 6 rows above this take the 16384-slot table
 
 struct BucketBounds {
   int64_t max[NBUCKET - 1];  // upper degree bound of buckets 0..6; bucket 7 takes the rest
@@ -99,6 +101,8 @@ struct Ctrl {
   int64_t bucket_count[NBUCKET];
   int64_t bucket_off[NBUCKET + 1];
   int64_t bucket_cursor[NBUCKET];
+  int64_t bucket6_hi;           // rows of bucket 6 longer than B6_SPLIT (placed at the end of its list)
+  int64_t bucket6_cursor_hi;
   uint64_t sum_we;              // total edge weight W_E
   uint64_t sum_w;               // total vertex weight W
   uint64_t sum_w2;              // sum of w(v)^2
@@ -137,6 +141,7 @@ struct Buckets {
   const int32_t* list = nullptr;
   int32_t grid_cap = 2048;  // workgroups of the persistent per-vertex launches (a result-neutral tuning)
   int64_t hub_deg = 4096;   // rows longer than this are in the hub bucket (its lower bound, exclusive)
+  int64_t count6_hi = 0;    // the last count6_hi rows of bucket 6's list are longer than B6_SPLIT
   int32_t hash_shift = 0;   // LDS hash of a row of degree d: pow2ceil(2 d) << hash_shift slots, capped (a tuning)
   int64_t count[NBUCKET] = {};
   int64_t off[NBUCKET + 1] = {};

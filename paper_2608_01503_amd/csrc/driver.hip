@@ -394,6 +394,7 @@ __global__ void k_reset_level_counters(Ctrl* c) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int b = 0; b < NBUCKET; ++b) { c->bucket_count[b] = 0; c->bucket_cursor[b] = 0; c->bucket_edges[b] = 0; }
   c->count3 = 0;
+  c->bucket6_hi = 0;
   c->sum_w = 0;
   c->sum_w2 = 0;
 }
@@ -506,6 +507,7 @@ struct Run {
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     b.hash_shift = ctx->tune.hash_shift;
+    b.count6_hi = ctx->h_ctrl->bucket6_hi;
     if (!into) L.sum_w2 = (int64_t)ctx->h_ctrl->sum_w2;
     if (b.count[NBUCKET - 1]) launch_hub_chunks(list + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, hub_off, w.scan_temp, st);
   }
@@ -1116,6 +1118,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     b.hash_shift = ctx->tune.hash_shift;
+    b.count6_hi = ctx->h_ctrl->bucket6_hi;
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
@@ -1581,6 +1584,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     b.grid_cap = ctx->tune.grid_cap;
     b.hub_deg = ctx->tune.bucket_max[NBUCKET - 2];
     b.hash_shift = ctx->tune.hash_shift;
+    b.count6_hi = ctx->h_ctrl->bucket6_hi;
     if (b.count[NBUCKET - 1])
       launch_hub_chunks(w.list0 + b.off[NBUCKET - 1], b.count[NBUCKET - 1], L.g.off, w.hub_cnt, w.hub_off0, w.scan_temp, st);
   }
@@ -1867,14 +1871,14 @@ lcc_status lcc_autotune(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lam
     cur = win;
     // bucket layouts: each moves one class of rows to a bucket of larger capacity
     static const int64_t layouts[][NBUCKET - 1] = {
-        {4, 8, 16, 32, 128, 1024, 4096},   // the default
-        {0, 8, 16, 32, 128, 1024, 4096},   // no 4-lane groups
-        {4, 8, 16, 16, 128, 1024, 4096},   // no 32-lane groups: degrees 17-32 to a wavefront
-        {4, 8, 16, 32, 64, 1024, 4096},    // wavefront hash only up to degree 64
-        {4, 8, 16, 32, 128, 512, 4096},    // the 8192-slot workgroups from degree 513
+        {4, 8, 16, 32, 128, 1024, 8192},   // the default
+        {0, 8, 16, 32, 128, 1024, 8192},   // no 4-lane groups
+        {4, 8, 16, 16, 128, 1024, 8192},   // no 32-lane groups: degrees 17-32 to a wavefront
+        {4, 8, 16, 32, 64, 1024, 8192},    // wavefront hash only up to degree 64
+        {4, 8, 16, 32, 128, 512, 8192},    // the 8192-slot workgroups from degree 513
+        {4, 8, 16, 32, 128, 1024, 4096},   // no 16384-slot workgroups: hub chunks from degree 4097
         {4, 8, 16, 32, 128, 1024, 2048},   // hub chunks from degree 2049
         {4, 8, 16, 32, 128, 1024, 1024},   // no 8192-slot workgroups: hub chunks from degree 1025
-        {4, 8, 16, 32, 128, 1024, 8192},   // rows up to 8192 in LDS (16384-slot workgroups above 4096)
     };
     for (const auto& lay : layouts) {
       lcc_tuning t = cur;

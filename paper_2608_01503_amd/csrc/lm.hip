@@ -746,8 +746,7 @@ template <int BS, int SLOTS>
 __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cnt, DevGraph g, const int32_t* C,
                                                  const int64_t* W, ScoreSrc ss, uint32_t pa, uint32_t pb,
                                                  int strict, VState* vs, LMSlot* slot, int pass,
-                                                 int64_t* S, int ct_own, int ct_pairs, int hshift,
-                                                 int64_t dlo = -1, int64_t dhi = INT64_MAX) {
+                                                 int64_t* S, int ct_own, int ct_pairs, int hshift) {
   __shared__ int32_t hk[SLOTS];
   __shared__ uint32_t hv[SLOTS];
   VtxAcc va;
@@ -755,7 +754,6 @@ __global__ __launch_bounds__(BS) void k_enum_blk(const int32_t* list, int64_t cn
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
     const int64_t b = g.off[v], e = g.off[v + 1];
-    if (e - b <= dlo || e - b > dhi) continue;  // rows of the other launch over this bucket (uniform)
     const int32_t cv = C[v];
     const int64_t wvt = g.vw[v];
     const int bits = table_bits(e - b, hshift, SLOTS);
@@ -1502,9 +1500,9 @@ __global__ void k_zero_i64(int64_t* p) {
 __global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl, const int32_t* gid, const uint8_t* gact,
                                BucketBounds bb) {
   __shared__ unsigned long long cnt[NBUCKET], edg[NBUCKET];
-  __shared__ unsigned long long chunks;
+  __shared__ unsigned long long chunks, hi6;
   if (threadIdx.x < NBUCKET) { cnt[threadIdx.x] = 0; edg[threadIdx.x] = 0; }
-  if (threadIdx.x == 0) chunks = 0;
+  if (threadIdx.x == 0) { chunks = 0; hi6 = 0; }
   __syncthreads();
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     if (gact && !gact[gid[v]]) continue;
@@ -1513,8 +1511,10 @@ __global__ void k_bucket_count(const int64_t* off, int64_t n, Ctrl* ctrl, const 
     atomicAdd(&cnt[b], 1ull);
     if (d) atomicAdd(&edg[b], (unsigned long long)d);
     if (b == NBUCKET - 1) atomicAdd(&chunks, (unsigned long long)cdiv(d, HUB_CHUNK));
+    if (b == NBUCKET - 2 && d > B6_SPLIT) atomicAdd(&hi6, 1ull);
   }
   __syncthreads();
+  if (threadIdx.x == 0 && hi6) atomicAdd((unsigned long long*)&ctrl->bucket6_hi, hi6);
   if (threadIdx.x < NBUCKET && cnt[threadIdx.x])
     atomicAdd((unsigned long long*)&ctrl->bucket_count[threadIdx.x], cnt[threadIdx.x]);
   if (threadIdx.x < NBUCKET && edg[threadIdx.x])
@@ -1531,31 +1531,42 @@ __global__ void k_bucket_offsets(Ctrl* ctrl) {
     s += ctrl->bucket_count[b];
   }
   ctrl->bucket_off[NBUCKET] = s;
+  ctrl->bucket6_cursor_hi = ctrl->bucket_off[NBUCKET - 1] - ctrl->bucket6_hi;
 }
 
 // Bucket lists: per workgroup tile, LDS counts per bucket, one global atomic per bucket, positions inside
-// the tile from LDS atomics (the order inside a bucket does not affect any result).
+// the tile from LDS atomics (the order inside a bucket does not affect any result).  Rows of bucket 6 longer
+// than B6_SPLIT go to the end of its list (a list of their own, index NBUCKET here), so the two table sizes of
+// that bucket each walk only their own rows.
 __global__ __launch_bounds__(BLOCK) void k_bucket_scatter(const int64_t* off, int64_t n, int32_t* list,
                                                           Ctrl* ctrl, const int32_t* gid, const uint8_t* gact,
                                                           BucketBounds bb) {
-  __shared__ uint32_t cnt[NBUCKET];
-  __shared__ int64_t base[NBUCKET];
+  __shared__ uint32_t cnt[NBUCKET + 1];
+  __shared__ int64_t base[NBUCKET + 1];
   constexpr int T = 4 * BLOCK;
   for (int64_t t0 = (int64_t)blockIdx.x * T; t0 < n; t0 += (int64_t)gridDim.x * T) {
-    if (threadIdx.x < NBUCKET) cnt[threadIdx.x] = 0;
+    if (threadIdx.x <= NBUCKET) cnt[threadIdx.x] = 0;
     __syncthreads();
     int b[4];
     uint32_t r[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       int64_t v = t0 + k * BLOCK + threadIdx.x;
-      b[k] = (v < n && (!gact || gact[gid[v]])) ? bucket_of(off[v + 1] - off[v], bb) : -1;
+      b[k] = -1;
+      if (v < n && (!gact || gact[gid[v]])) {
+        const int64_t d = off[v + 1] - off[v];
+        b[k] = bucket_of(d, bb);
+        if (b[k] == NBUCKET - 2 && d > B6_SPLIT) b[k] = NBUCKET;
+      }
       if (b[k] >= 0) r[k] = atomicAdd(&cnt[b[k]], 1u);
     }
     __syncthreads();
     if (threadIdx.x < NBUCKET && cnt[threadIdx.x])
       base[threadIdx.x] = (int64_t)atomicAdd((unsigned long long*)&ctrl->bucket_cursor[threadIdx.x],
                                              (unsigned long long)cnt[threadIdx.x]);
+    if (threadIdx.x == NBUCKET && cnt[NBUCKET])
+      base[NBUCKET] = (int64_t)atomicAdd((unsigned long long*)&ctrl->bucket6_cursor_hi,
+                                         (unsigned long long)cnt[NBUCKET]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -1974,12 +1985,17 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
   LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(3))))
   LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(4), b.hash_shift)))
   LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(5), b.hash_shift)))
-  // bucket 6: rows up to 4096 on 512 threads and an 8192-slot table; when a tuning raises the bucket's bound,
-  // longer rows on 1024 threads and a 16384-slot table (a second launch over the bucket)
-  LCC_ENUM(6, (k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, b.count[6], 4), 512, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), b.hash_shift, -1, LDS_SLOTS_B6 / 2)))
-  if (b.count[6] && b.hub_deg > LDS_SLOTS_B6 / 2) {
+  // bucket 6: rows up to B6_SPLIT on 512 threads and an 8192-slot table; when a tuning raises the bucket's
+  // bound, the longer rows (the tail of the bucket's list) on 1024 threads and a 16384-slot table
+  const int64_t n6 = b.count[6] - b.count6_hi;
+  if (n6) {
     prof_begin(PF_ENUM_B0 + 6, st);
-    k_enum_blk<1024, LDS_SLOTS_B6X><<<vtx_blocks(b, b.count[6], 4), 1024, 0, st>>>(L + b.off[6], b.count[6], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), b.hash_shift, LDS_SLOTS_B6 / 2, INT64_MAX);
+    k_enum_blk<512, LDS_SLOTS_B6><<<vtx_blocks(b, n6, 4), 512, 0, st>>>(L + b.off[6], n6, g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), b.hash_shift);
+    prof_end(PF_ENUM_B0 + 6, 0.0, st);
+  }
+  if (b.count6_hi) {
+    prof_begin(PF_ENUM_B0 + 6, st);
+    k_enum_blk<1024, LDS_SLOTS_B6X><<<vtx_blocks(b, b.count6_hi, 4), 1024, 0, st>>>(L + b.off[6] + n6, b.count6_hi, g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(6), b.hash_shift);
     prof_end(PF_ENUM_B0 + 6, 0.0, st);
   }
 #undef LCC_ENUM

@@ -41,6 +41,6 @@ def test_host_only_entry_points():
     assert lcc.lcc_workspace_bytes(1000, 10000) > 0
     assert lcc.lcc_status_string(-2) == "graph not symmetric"
     t = lcc.lcc_default_tuning()
-    assert lcc.tuning_dict(t) == {"bucket_max": [4, 8, 16, 32, 128, 1024, 4096], "grid_cap": 2048, "hash_shift": 0}
+    assert lcc.tuning_dict(t) == {"bucket_max": [4, 8, 16, 32, 128, 1024, 8192], "grid_cap": 2048, "hash_shift": 0}
     assert lcc.tuning_dict(lcc.lcc_default_tuning(hash_shift=2))["hash_shift"] == 2
     assert lcc.tuning_dict(lcc.lcc_default_tuning(grid_cap=512))["grid_cap"] == 512

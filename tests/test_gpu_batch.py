@@ -157,7 +157,7 @@ def test_fused_pleiden_mixed_graphs():
         (gg.from_pairs(2, [(0, 1)]), O.PLEIDEN, *CPM20, None),
         (_empty(0), O.PLEIDEN, *CPM20, None),
         (_empty(5), O.PLEIDEN_PLUS, *CPM20, None),
-        (U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=4), O.PLEIDEN_PLUS, *CPM20, None),
+        (U.hub_graph(n=12000, hub_deg=(9000, 6000, 1500), seed=4), O.PLEIDEN_PLUS, *CPM20, None),
         (gg.rmat(12, 16, seed=21), O.PLEIDEN, *CPM3, None),
     ]
     g9 = gg.random_gnp(800, 0.01, 5, w_max=9)

@@ -40,7 +40,9 @@ def test_random_graphs(variant, obj):
 def test_hubs_every_bucket(variant):
     g = U.hub_graph()
     d = np.diff(g.off)
-    assert d.max() > 4096 and ((d > 1024) & (d <= 4096)).any() and ((d > 128) & (d <= 1024)).any()
+    # hub chunks (above 8192), the 16384- and 8192-slot workgroup tables, the 2048-slot one
+    assert d.max() > 8192 and ((d > 4096) & (d <= 8192)).any() and ((d > 1024) & (d <= 4096)).any()
+    assert ((d > 128) & (d <= 1024)).any()
     U.assert_parity(g, variant, *MOD)
     U.assert_parity(g, variant, *CPM20)
 
@@ -141,7 +143,7 @@ def test_symmetry_check_is_exact(where):
     """One entry's weight changed (or one reverse entry moved to another neighbour) in a hub row, a mid-degree
     row or a short row: the device check compares every entry with its reverse, so each is NOT_SYMMETRIC, as
     in the oracle; the unmodified graph passes."""
-    g = U.hub_graph(n=6000, hub_deg=(5000, 2000, 700), seed=12)
+    g = U.hub_graph(n=12000, hub_deg=(9000, 2000, 700), seed=12)  # row 0 in the hub chunks
     deg = np.diff(g.off)
     v = {"hub": 0, "wave": int(np.nonzero((deg > 32) & (deg <= 128))[0][0]),
          "group": int(np.nonzero((deg > 1) & (deg <= 4))[0][0])}[where]
@@ -188,7 +190,7 @@ def test_symmetry_check_by_transposition():
 
 
 HEAVY = [("rmat12", lambda: gg.rmat(12, seed=11), O.PLOUVAIN),
-         ("hubs", lambda: U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=4), O.PLEIDEN_PLUS),
+         ("hubs", lambda: U.hub_graph(n=12000, hub_deg=(9000, 6000, 1500), seed=4), O.PLEIDEN_PLUS),
          ("lattice", lambda: gg.lattice(40, 40, seed=7), O.PLEIDEN),
          ("sbm", lambda: gg.sbm(8, 120, 0.2, 0.01, seed=3), O.LOUVAIN)]
 
@@ -316,7 +318,7 @@ def test_tag_wraparound(monkeypatch, base):
     import paper_2608_01503_amd as L
     monkeypatch.setenv("LCC_TAG_BASE", str(base))
     ctx = L.Context(0)  # a fresh context: the variable is read when its workspace is allocated
-    for g, v, lam, mode in [(U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=8), L.LCC_PLEIDEN_PLUS,
+    for g, v, lam, mode in [(U.hub_graph(n=12000, hub_deg=(9000, 6000, 1500), seed=8), L.LCC_PLEIDEN_PLUS,
                              (1, 20, False), L.LCC_VW_UNIT),
                             (gg.random_gnp(3000, 0.004, 77, w_max=4), L.LCC_PLOUVAIN, (1, 1, True),
                              L.LCC_VW_WEIGHTED_DEGREE)]:

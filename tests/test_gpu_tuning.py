@@ -24,7 +24,7 @@ TUNINGS = [
 
 CASES = [
     ("hubs", lambda: U.hub_graph(), O.PLOUVAIN, (1, 1, True), O.VW_WEIGHTED_DEGREE),
-    ("hubs-leiden", lambda: U.hub_graph(n=6000, hub_deg=(5000, 3000, 1500), seed=4), O.PLEIDEN_PLUS,
+    ("hubs-leiden", lambda: U.hub_graph(n=12000, hub_deg=(9000, 6000, 1500), seed=4), O.PLEIDEN_PLUS,
      (1, 20, False), O.VW_UNIT),
     ("lattice", lambda: gg.lattice(48, 48, seed=7), O.PLEIDEN, (1, 20, False), O.VW_UNIT),
     ("rmat12", lambda: gg.rmat(12, seed=11), O.PLOUVAIN, (1, 1, True), O.VW_WEIGHTED_DEGREE),
@@ -60,7 +60,7 @@ def test_fused_batch_under_tunings():
     import torch
     import paper_2608_01503_amd as L
     graphs = [gg.random_gnp(300 + 97 * k, 0.03, 70 + k, w_max=5) for k in range(12)]
-    graphs.append(U.hub_graph(n=12000, hub_deg=(6000, 3000, 1500), seed=12))
+    graphs.append(U.hub_graph(n=12000, hub_deg=(9000, 3000, 1500), seed=12))
     dev = [U.device_graph(g, O.VW_WEIGHTED_DEGREE) for g in graphs]
     lams = [(1, 1, True)] * len(graphs)
     var = [L.LCC_PLOUVAIN] * len(graphs)
