@@ -568,6 +568,8 @@ def bench_largest(args):
     launches, kms, kbytes = prof[family]
     achieved = (kbytes / 1e9) / (kms / 1e3) if kms > 0 else 0.0
     out = {"workload": "R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), pLeiden, CPM lambda=1/20",
+           "role": "the largest configuration that fits one GPU; measured here with one timed call because a call "
+                   "takes about 50 s, so the line's steps and warm-up calls stay on the R-MAT scale 22 workload",
            "n": n, "nnz": nnz, "calls": 1, "warmup": "one call stopped after 3 levels", "s_per_call": sec, "edges_per_s": nnz / sec,
            "levels": res.levels, "flags": res.flags, "clusters": res.num_clusters,
            "objective_consistent": bool(chk.N == res.N and chk.num_clusters == res.num_clusters),

@@ -35,7 +35,8 @@ PROFILE_FAMILIES = ["enum_b0", "enum_b1", "enum_b2", "enum_b3", "enum_b4", "enum
                     "single", "afterburner"]
 FAMILY_KERNELS = {"enum_b0": "k_enum_grp<4>", "enum_b1": "k_enum_grp<8>", "enum_b2": "k_enum_grp<16>",
                   "enum_b3": "k_enum_grp<32>", "enum_b4": "k_enum_wave<256>", "enum_b5": "k_enum_blk<128, 2048>",
-                  "enum_b6": "k_enum_blk<512, 8192>", "enum_b7": "k_hub_insert+k_hub_scan+k_hub_final",
+                  "enum_b6": "k_enum_blk<512, 8192>+k_enum_blk<1024, 16384>",
+                  "enum_b7": "k_hub_insert+k_hub_scan+k_hub_final",
                   "single": "k_single_*"}
 
 
