@@ -300,11 +300,14 @@ void launch_validate_offsets(const int64_t* off, int64_t n, int64_t nnz, Ctrl* c
 // temp), or none.
 struct SymBuffers {
   bool search = false;
-  uint64_t* k0 = nullptr;
+  uint64_t* k0 = nullptr;  // transposition (k0 set): nnz / 2 pairs in each of (k0, v0) and (k1, v1)
   uint32_t* v0 = nullptr;
   uint64_t* k1 = nullptr;
   uint32_t* v1 = nullptr;
-  void* temp = nullptr;
+  void* temp = nullptr;       // the sort's scratch
+  int32_t* lo = nullptr;      // n: entries of each row towards lower ids
+  int64_t* lbase = nullptr;   // n + 1: their exclusive scan
+  void* scan_temp = nullptr;
 };
 // Graphs (of a union: its largest graph) up to this many entries are checked by search: the rows a search
 // visits stay in cache.  So are graphs of at most SYM_SEARCH_MAX_AVG_DEG entries per row (half an entry per

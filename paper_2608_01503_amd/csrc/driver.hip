@@ -1128,6 +1128,7 @@ void setup(Run& R, const lcc_graph* g, lcc_lambda lam, const int32_t* init_label
     sb.search = true;
   } else if (R.o.validate) {
     sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
+    sb.lo = w.cnt; sb.lbase = w.seg0; sb.scan_temp = w.scan_temp;
     sb.temp = ctx->pool_take(radix_temp_bytes(nnz));
   }
   launch_validate_rows(L.g, L.b, (int)g->vw_mode, vwg, w.vw0, w.ctrl, st, sb);
@@ -1596,6 +1597,7 @@ lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lamb
     sb.search = true;  // every graph's rows are local: the searches stay in cache
   } else if (R.o.validate) {
     sb.k0 = w.k0; sb.v0 = w.v0; sb.k1 = w.k1; sb.v1 = w.v1;
+    sb.lo = w.cnt; sb.lbase = w.seg0; sb.scan_temp = w.scan_temp;
     sb.temp = ctx->pool_take(radix_temp_bytes(nnz));
   }
   launch_validate_rows(L.g, L.b, LCC_VW_UNIT, any_given ? w.in_vwg : nullptr, w.vw0, w.ctrl, st, sb, w.gid0, gmode,

@@ -1613,6 +1613,7 @@ struct EdgeCheck {
   uint32_t err = 0;
   int64_t balance = 0;  // entries towards a lower-ranked vertex minus entries towards a higher-ranked one
   int64_t ws = 0;
+  int64_t lower = 0;    // entries towards a lower vertex id
 };
 
 __device__ __forceinline__ bool found_in_row(const DevGraph& g, int64_t lo, int64_t end, int32_t v, int32_t wt) {
@@ -1626,14 +1627,11 @@ __device__ __forceinline__ bool found_in_row(const DevGraph& g, int64_t lo, int6
 
 // entry j = (v, u) of row v, which starts at rb and holds dv entries
 __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t j, int64_t rb, int64_t dv,
-                                           EdgeCheck& ec, uint64_t* keys, uint32_t* vals, bool search) {
+                                           EdgeCheck& ec, bool search) {
   int32_t u = g.idx[j];
   int32_t wt = g.w[j];
   ec.ws += wt;
-  if (keys) {
-    keys[j] = ((uint64_t)(uint32_t)u << 32) | (uint32_t)v;
-    vals[j] = (uint32_t)wt;
-  }
+  ec.lower += u < v;
   if (u < 0 || u >= g.n) { ec.err |= ERRB_INVALID; return; }
   if (u == v) { ec.err |= ERRB_SELF_LOOP; return; }
   if (j > rb && g.idx[j - 1] >= u) ec.err |= ERRB_UNSORTED;
@@ -1648,17 +1646,59 @@ __device__ __forceinline__ void check_edge(const DevGraph& g, int32_t v, int64_t
   }
 }
 
-// The sorted (u << 32 | v, w) pairs against the CSR: position j must hold (row of j, idx[j], w[j]), that is
-// off[u] <= j < off[u + 1], v == idx[j] and the weights equal.  Entry-parallel and coalesced (u grows with j,
-// so the offset reads stay in cache).
-__global__ __launch_bounds__(BLOCK) void k_sym_compare(DevGraph g, const uint64_t* ks, const uint32_t* vs,
-                                                       Ctrl* ctrl) {
+// Symmetry by transposition of the upper half.  Row v's entries towards higher ids (the upper entries; a
+// suffix of the ascending row, after its lo[v] lower entries) are written as pairs (u << 32 | v, w), packed
+// in entry order: entry j goes to j - lbase[v] - lo[v], lbase = exclusive scan of lo.  Sorted stably by u,
+// the pairs of target u list their sources ascending, so a symmetric graph gives exactly row u's lower part:
+// position p must hold u with lbase[u] <= p < lbase[u] + lo[u], the source at idx[off[u] + p - lbase[u]] and the
+// same weight, and there must be as many lower entries as upper ones (nnz / 2 each).  Positions map to distinct
+// lower entries, so equal counts make the pairing a bijection.
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_sym_emit_grp(const int32_t* list, int64_t cnt, DevGraph g,
+                                                        const int32_t* lo, const int64_t* lbase, uint64_t* keys,
+                                                        uint32_t* vals) {
+  const int gl = threadIdx.x % G;
+  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
+       gid += (int64_t)gridDim.x * (BLOCK / G)) {
+    const int32_t v = list[gid];
+    const int64_t rb = g.off[v], re = g.off[v + 1];
+    const int64_t shift = lbase[v] + lo[v];
+    for (int64_t j = rb + lo[v] + gl; j < re; j += G) {
+      keys[j - shift] = ((uint64_t)(uint32_t)g.idx[j] << 32) | (uint32_t)v;
+      vals[j - shift] = (uint32_t)g.w[j];
+    }
+  }
+}
+
+// hub rows: each chunk writes the upper entries of its own edge range
+__global__ __launch_bounds__(HUB_BLOCK) void k_sym_emit_hub(const int32_t* hubs, const int32_t* chunk_off, int64_t n7,
+                                                            DevGraph g, const int32_t* lo, const int64_t* lbase,
+                                                            uint64_t* keys, uint32_t* vals) {
+  const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
+  const int32_t v = hubs[k];
+  const int64_t rb = g.off[v];
+  const int64_t j0 = max(rb + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK, rb + lo[v]);
+  const int64_t j1 = min(g.off[v + 1], rb + (int64_t)(blockIdx.x - chunk_off[k] + 1) * HUB_CHUNK);
+  const int64_t shift = lbase[v] + lo[v];
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) {
+    keys[j - shift] = ((uint64_t)(uint32_t)g.idx[j] << 32) | (uint32_t)v;
+    vals[j - shift] = (uint32_t)g.w[j];
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sym_compare(DevGraph g, const uint64_t* ks, const uint32_t* vs, int64_t m,
+                                                       const int32_t* lo, const int64_t* lbase, Ctrl* ctrl) {
   bool bad = false;
-  for (int64_t j = (int64_t)blockIdx.x * BLOCK + threadIdx.x; j < g.nnz; j += (int64_t)gridDim.x * BLOCK) {
-    const uint64_t key = ks[j];
+  if (blockIdx.x == 0 && threadIdx.x == 0) bad = g.nnz != 2 * m || lbase[g.n] != m;
+  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < m; p += (int64_t)gridDim.x * BLOCK) {
+    const uint64_t key = ks[p];
     const int64_t u = (int64_t)(key >> 32);
     const int32_t v = (int32_t)(uint32_t)key;
-    bad |= u >= g.n || j < g.off[u] || j >= g.off[u + 1] || v != g.idx[j] || vs[j] != (uint32_t)g.w[j];
+    if (u >= g.n) { bad = true; continue; }
+    const int64_t r = p - lbase[u];
+    if (r < 0 || r >= lo[u]) { bad = true; continue; }
+    const int64_t j = g.off[u] + r;
+    bad |= v != g.idx[j] || vs[p] != (uint32_t)g.w[j];
   }
   if (bad) atomicOr(&ctrl->err_bits, ERRB_NOT_SYMMETRIC);
 }
@@ -1696,7 +1736,7 @@ __device__ __forceinline__ void flush_check(EdgeCheck ec, int64_t wsum, Ctrl* ct
 template <int G>
 __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int64_t cnt, DevGraph g, VwSrc vm,
                                                         const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl,
-                                                        uint64_t* keys, uint32_t* vals, bool search) {
+                                                        int32_t* lo, bool search) {
   const int gl = threadIdx.x % G;
   EdgeCheck ec;
   int64_t wsum = 0;
@@ -1704,10 +1744,12 @@ __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int
        gid += (int64_t)gridDim.x * (BLOCK / G)) {
     const int32_t v = list[gid];
     const int64_t rb = g.off[v], re = g.off[v + 1];
-    const int64_t ws0 = ec.ws;
-    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, re - rb, ec, keys, vals, search);
+    const int64_t ws0 = ec.ws, lo0 = ec.lower;
+    for (int64_t j = rb + gl; j < re; j += G) check_edge(g, v, j, rb, re - rb, ec, search);
     int64_t ws = sum_reduce<G>(ec.ws - ws0);
+    const int64_t nlo = lo ? sum_reduce<G>(ec.lower - lo0) : 0;
     if (gl == 0) {
+      if (lo) lo[v] = (int32_t)nlo;
       vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
       if (vm.rowsum) vm.rowsum[v] = ws;
       wsum += ws;
@@ -1718,16 +1760,18 @@ __global__ __launch_bounds__(BLOCK) void k_validate_grp(const int32_t* list, int
 
 __global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list, int64_t cnt, DevGraph g, VwSrc vm,
                                                             const int64_t* vw_given, int64_t* vw_out, Ctrl* ctrl,
-                                                            uint64_t* keys, uint32_t* vals, bool search) {
+                                                            int32_t* lo, bool search) {
   EdgeCheck ec;
   int64_t wsum = 0;
   for (int64_t vi = blockIdx.x; vi < cnt; vi += gridDim.x) {
     const int32_t v = list[vi];
     const int64_t rb = g.off[v], re = g.off[v + 1];
-    const int64_t ws0 = ec.ws;
-    for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, re - rb, ec, keys, vals, search);
+    const int64_t ws0 = ec.ws, lo0 = ec.lower;
+    for (int64_t j = rb + threadIdx.x; j < re; j += BIG_BLOCK) check_edge(g, v, j, rb, re - rb, ec, search);
     int64_t ws = sum_reduce<BIG_BLOCK>(ec.ws - ws0);
+    const int64_t nlo = lo ? sum_reduce<BIG_BLOCK>(ec.lower - lo0) : 0;
     if (threadIdx.x == 0) {
+      if (lo) lo[v] = (int32_t)nlo;
       vw_out[v] = vertex_weight(vm.at(v), ws, vw_given, v, ec.err);
       if (vm.rowsum) vm.rowsum[v] = ws;
       wsum += ws;
@@ -1739,16 +1783,20 @@ __global__ __launch_bounds__(BIG_BLOCK) void k_validate_blk(const int32_t* list,
 // hubs: chunk sums of the weighted degree land in hsum[k] (zeroed beforehand)
 __global__ __launch_bounds__(HUB_BLOCK) void k_validate_hub(const int32_t* hubs, const int32_t* chunk_off,
                                                             int64_t n7, DevGraph g, int64_t* hsum, Ctrl* ctrl,
-                                                            uint64_t* keys, uint32_t* vals, bool search) {
+                                                            int32_t* lo, bool search) {
   const int k = find_chunk_owner(chunk_off, n7, blockIdx.x);
   const int32_t v = hubs[k];
   const int64_t rb = g.off[v];
   const int64_t j0 = rb + (int64_t)(blockIdx.x - chunk_off[k]) * HUB_CHUNK;
   const int64_t j1 = min(g.off[v + 1], j0 + HUB_CHUNK);
   EdgeCheck ec;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) check_edge(g, v, j, rb, g.off[v + 1] - rb, ec, keys, vals, search);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += HUB_BLOCK) check_edge(g, v, j, rb, g.off[v + 1] - rb, ec, search);
   int64_t ws = sum_reduce<HUB_BLOCK>(ec.ws);
   if (threadIdx.x == 0 && ws) atomicAdd((unsigned long long*)&hsum[k], (unsigned long long)ws);
+  if (lo) {  // lo of a hub is zeroed beforehand; its chunks add their counts
+    const int64_t nlo = sum_reduce<HUB_BLOCK>(ec.lower);
+    if (threadIdx.x == 0 && nlo) atomicAdd(&lo[v], (int32_t)nlo);
+  }
   flush_check(ec, threadIdx.x == 0 ? ws : 0, ctrl);
 }
 
@@ -1846,30 +1894,40 @@ void launch_validate_rows(const DevGraph& g, const Buckets& b, int vw_mode, cons
                           const int8_t* gmode, int64_t* rowsum) {
   const int32_t* L = b.list;
   const VwSrc vm{vw_mode, gid, gmode, rowsum};
-  uint64_t* keys = sb.k0;
-  uint32_t* vals = sb.v0;
-  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
-  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
-  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
-  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
-  int64_t nw = b.count[4] + b.count[5];
-  if (nw) k_validate_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
-  if (b.count[6]) k_validate_blk<<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vm, vw_given, vw_out, ctrl, keys, vals, sb.search);
+  const bool tr = sb.k0 && g.nnz > 0;  // symmetry by transposition: the rows' lower counts first
+  int32_t* lo = tr ? sb.lo : nullptr;
+  const int64_t nw = b.count[4] + b.count[5];
+  const int32_t* hubs = L + b.off[7];
+  if (tr && b.count[7]) fill_i32(lo, 0, g.n, st);  // hub rows add their chunks' counts
+  if (b.count[0]) k_validate_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vm, vw_given, vw_out, ctrl, lo, sb.search);
+  if (b.count[1]) k_validate_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vm, vw_given, vw_out, ctrl, lo, sb.search);
+  if (b.count[2]) k_validate_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vm, vw_given, vw_out, ctrl, lo, sb.search);
+  if (b.count[3]) k_validate_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vm, vw_given, vw_out, ctrl, lo, sb.search);
+  if (nw) k_validate_grp<64><<<grp_blocks(b, nw, 64), BLOCK, 0, st>>>(L + b.off[4], nw, g, vm, vw_given, vw_out, ctrl, lo, sb.search);
+  if (b.count[6]) k_validate_blk<<<vtx_blocks(b, b.count[6]), BIG_BLOCK, 0, st>>>(L + b.off[6], b.count[6], g, vm, vw_given, vw_out, ctrl, lo, sb.search);
   if (b.count[7]) {
-    const int32_t* hubs = L + b.off[7];
     fill_i64(b.hub_acc, 0, b.count[7], st);
-    k_validate_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, b.hub_acc, ctrl, keys, vals, sb.search);
+    k_validate_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, b.hub_acc, ctrl, lo, sb.search);
     k_validate_hub_final<<<grid_for(b.count[7]), BLOCK, 0, st>>>(hubs, b.count[7], vm, vw_given, b.hub_acc, vw_out, ctrl);
   }
-  if (keys && g.nnz > 0) {  // symmetry: the pairs sorted by their target, then compared with the CSR
+  if (tr) {  // the upper entries packed, sorted by their target and compared with the rows' lower parts
+    scan_i32_i64(lo, sb.lbase, g.n, sb.scan_temp, st);
+    const int64_t m = g.nnz / 2;
+    const int32_t* lc = lo;
+    if (b.count[0]) k_sym_emit_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, lc, sb.lbase, sb.k0, sb.v0);
+    if (b.count[1]) k_sym_emit_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, lc, sb.lbase, sb.k0, sb.v0);
+    if (b.count[2]) k_sym_emit_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, lc, sb.lbase, sb.k0, sb.v0);
+    if (b.count[3]) k_sym_emit_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, lc, sb.lbase, sb.k0, sb.v0);
+    if (nw + b.count[6]) k_sym_emit_grp<64><<<grp_blocks(b, nw + b.count[6], 64), BLOCK, 0, st>>>(L + b.off[4], nw + b.count[6], g, lc, sb.lbase, sb.k0, sb.v0);
+    if (b.count[7]) k_sym_emit_hub<<<(unsigned)b.hub_chunks, HUB_BLOCK, 0, st>>>(hubs, b.hub_chunk_off, b.count[7], g, lc, sb.lbase, sb.k0, sb.v0);
     int bits = 1;
     while (((int64_t)1 << bits) < g.n) ++bits;
     int shifts[4];
     const int npass = (bits + 7) / 8;
     for (int k = 0; k < npass; ++k) shifts[k] = 32 + 8 * k;
-    const int which = radix_sort_pairs(sb.k0, sb.v0, sb.k1, sb.v1, g.nnz, shifts, npass, sb.temp, st);
-    k_sym_compare<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(g.nnz, BLOCK), 16384)), BLOCK, 0, st>>>(
-        g, which ? sb.k1 : sb.k0, which ? sb.v1 : sb.v0, ctrl);
+    const int which = m > 0 ? radix_sort_pairs(sb.k0, sb.v0, sb.k1, sb.v1, m, shifts, npass, sb.temp, st) : 0;
+    k_sym_compare<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(cdiv(m, BLOCK), 16384)), BLOCK, 0, st>>>(
+        g, which ? sb.k1 : sb.k0, which ? sb.v1 : sb.v0, m, lc, sb.lbase, ctrl);
   }
 }
 

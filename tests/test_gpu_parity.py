@@ -187,6 +187,32 @@ def test_symmetry_check_by_transposition():
     idx[j] = u
     bad2 = gg.Graph(n=g.n, off=g.off, idx=idx, w=g.w)
     assert O.setup(bad2)[0] == -2 and _status_gpu(bad2, *MOD) == -2
+    # the check transposes the entries towards higher ids and matches them with the entries towards lower ids:
+    # a lower entry's weight changed, a lower entry moved to another lower id, and the last lower entry of a row
+    # moved to a higher id (one lower entry fewer than upper ones) are each NOT_SYMMETRIC as well
+    rows = np.repeat(np.arange(g.n), deg)
+    lo = np.bincount(rows[g.idx < rows], minlength=g.n)
+
+    def gap_after(j, x0):  # the smallest id in (x0, idx[j + 1]) whose row lacks the row of j
+        r = int(rows[j])
+        return next((x for x in range(x0 + 1, int(g.idx[j + 1])) if x != r and r not in g.idx[g.off[x]:g.off[x + 1]]),
+                    None)
+
+    cand = np.nonzero((lo >= 3) & (deg - lo >= 2) & (deg <= 64))[0]
+    r = next(int(x) for x in cand if gap_after(g.off[x], int(g.idx[g.off[x]])) is not None
+             and gap_after(g.off[x] + lo[x] - 1, int(x)) is not None)
+    w = g.w.copy()
+    w[g.off[r]] += 1
+    assert _status_gpu(gg.Graph(n=g.n, off=g.off, idx=g.idx, w=w), *MOD) == -2
+    idx = g.idx.copy()
+    idx[g.off[r]] = gap_after(g.off[r], int(g.idx[g.off[r]]))
+    bad3 = gg.Graph(n=g.n, off=g.off, idx=idx, w=g.w)
+    assert O.setup(bad3)[0] == -2 and _status_gpu(bad3, *MOD) == -2
+    idx = g.idx.copy()
+    jl = g.off[r] + lo[r] - 1
+    idx[jl] = gap_after(jl, r)
+    bad4 = gg.Graph(n=g.n, off=g.off, idx=idx, w=g.w)
+    assert O.setup(bad4)[0] == -2 and _status_gpu(bad4, *MOD) == -2
 
 
 HEAVY = [("rmat12", lambda: gg.rmat(12, seed=11), O.PLOUVAIN),

@@ -133,8 +133,8 @@ def _footprint(g, variant):
 
 
 def test_server_holds_device_memory_within_the_budget():
-    """Large and small jobs mixed under a budget of about two large footprints: every byte the slots hold,
-    idle ones included, is counted, so the allocator never has more outstanding than the budget, and every
+    """Large and small jobs of both families mixed under a budget of about two large footprints: every byte the
+    slots hold, idle ones included, is counted, so the allocator never has more outstanding than the budget, and every
     result equals the same request run alone."""
     import paper_2608_01503_amd as L
     large = [gg.rmat(14, seed=30 + k) for k in range(3)] + [gg.lattice(150, 150, seed=k) for k in range(2)]
@@ -146,6 +146,7 @@ def test_server_holds_device_memory_within_the_budget():
     tickets, meta = {}, {}
     jobs = [(g, L.LCC_PLOUVAIN) for g in large] + [(g, L.LCC_LOUVAIN) for g in small]
     jobs += [(large[0], L.LCC_PLEIDEN), (large[3], L.LCC_PLEIDEN_PLUS)]
+    jobs += [(g, L.LCC_PLEIDEN if k % 2 else L.LCC_PLEIDEN_PLUS) for k, g in enumerate(small[:12])]  # fused groups
     order = np.random.default_rng(1).permutation(len(jobs))
     for i in order:
         g, v = jobs[i]
