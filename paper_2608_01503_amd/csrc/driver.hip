@@ -365,9 +365,12 @@ void prof_resolve(lcc_ctx* c, const Ctrl* h) {
     c->ev_pool.push_back(r.b);
   }
   c->prof_recs.clear();
-  // the enumeration launches count their algorithmic bytes on the device
-  for (int k = 0; k < NBUCKET; ++k)
-    if ((c->prof_mask >> (PF_ENUM_B0 + k)) & 1) c->prof_bytes[PF_ENUM_B0 + k] += (double)h->enum_bytes[k];
+  // the enumeration launches count their algorithmic bytes on the device; buckets 0-2 share one launch
+  // (family 0)
+  for (int k = 0; k < NBUCKET; ++k) {
+    const int f = PF_ENUM_B0 + (k < 3 ? 0 : k);
+    if ((c->prof_mask >> f) & 1) c->prof_bytes[f] += (double)h->enum_bytes[k];
+  }
 }
 
 template <typename T>

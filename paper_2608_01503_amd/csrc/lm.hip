@@ -649,17 +649,15 @@ __device__ __forceinline__ void pair_sweep(int32_t c, int32_t wt, bool has, int 
   }
 }
 
-// degree <= G: lane l holds neighbour l; clusters aggregated by an all-pairs sweep of the group.
+// degree <= G: lane l holds neighbour l; clusters aggregated by an all-pairs sweep of the group.  Workgroup
+// bid of nblk walks the list.
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t cnt, DevGraph g,
-                                                    const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
-                                                    uint32_t pb, int strict, VState* vs, LMSlot* slot, int pass,
-                                                    int64_t* S, int ct_own, int ct_pairs) {
-  VtxAcc va;
-  if (slot && slot->skip[pass]) return;
+__device__ __forceinline__ void enum_grp_blocks(const int32_t* list, int64_t cnt, unsigned bid, unsigned nblk,
+                                                const DevGraph& g, const int32_t* C, const int64_t* W,
+                                                const ScoreSrc& ss, uint32_t pa, uint32_t pb, int strict,
+                                                VState* vs, VtxAcc& va) {
   const int gl = threadIdx.x % G;
-  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
-       gid += (int64_t)gridDim.x * (BLOCK / G)) {
+  for (int64_t gid = (int64_t)bid * (BLOCK / G) + threadIdx.x / G; gid < cnt; gid += (int64_t)nblk * (BLOCK / G)) {
     const int32_t v = list[gid];
     const int64_t b = g.off[v];
     const int d = (int)(g.off[v + 1] - b);
@@ -688,7 +686,47 @@ __global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t
       va.bytes += enum_bytes(d, 0);
     }
   }
+}
+
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_enum_grp(const int32_t* list, int64_t cnt, DevGraph g,
+                                                    const int32_t* C, const int64_t* W, ScoreSrc ss, uint32_t pa,
+                                                    uint32_t pb, int strict, VState* vs, LMSlot* slot, int pass,
+                                                    int64_t* S, int ct_own, int ct_pairs) {
+  VtxAcc va;
+  if (slot && slot->skip[pass]) return;
+  enum_grp_blocks<G>(list, cnt, blockIdx.x, gridDim.x, g, C, W, ss, pa, pb, strict, vs, va);
   acc_flush<BLOCK>(va, S, slot ? CT_NCAND : -1, ct_own, ct_pairs);
+}
+
+// The sub-wave group buckets in one launch: the workgroups are split in ranges, one per bucket, so the buckets
+// run side by side instead of one launch after another (each with its own tail).
+constexpr int NGRP = 3;
+struct GrpSet {
+  const int32_t* list[NGRP];
+  int64_t cnt[NGRP];
+  unsigned nb[NGRP];  // workgroups of each bucket (0: none)
+};
+__device__ __forceinline__ int grp_set_bucket(const GrpSet& q, unsigned& bid) {
+  bid = blockIdx.x;
+  int k = 0;
+  while (k < NGRP - 1 && bid >= q.nb[k]) bid -= q.nb[k++];
+  return k;
+}
+
+// buckets 0-2: rows of at most 4, 8 and 16 entries (the 32-lane bucket keeps a launch of its own: merged
+// with it, the lattice and kNN graphs ran slower)
+__global__ __launch_bounds__(BLOCK) void k_enum_grps(GrpSet q, DevGraph g, const int32_t* C, const int64_t* W,
+                                                     ScoreSrc ss, uint32_t pa, uint32_t pb, int strict, VState* vs,
+                                                     LMSlot* slot, int pass, int64_t* S, int ct_own, int ct_pairs0) {
+  VtxAcc va;
+  if (slot && slot->skip[pass]) return;
+  unsigned bid;
+  const int k = grp_set_bucket(q, bid);  // uniform over the workgroup
+  if (k == 0) enum_grp_blocks<4>(q.list[0], q.cnt[0], bid, q.nb[0], g, C, W, ss, pa, pb, strict, vs, va);
+  else if (k == 1) enum_grp_blocks<8>(q.list[1], q.cnt[1], bid, q.nb[1], g, C, W, ss, pa, pb, strict, vs, va);
+  else enum_grp_blocks<16>(q.list[2], q.cnt[2], bid, q.nb[2], g, C, W, ss, pa, pb, strict, vs, va);
+  acc_flush<BLOCK>(va, S, slot ? CT_NCAND : -1, ct_own, ct_pairs0 >= 0 ? ct_pairs0 + k : -1);
 }
 
 // Orders a wavefront's own LDS accesses around a phase change of its private table: every LDS operation of
@@ -979,14 +1017,11 @@ __device__ __forceinline__ int64_t ab_row(const DevGraph& g, const VState* vs, c
 }
 
 template <int G>
-__global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
-                                                  ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass,
-                                                  int64_t* S) {
-  VtxAcc va;
-  if (slot->skip[pass]) return;
+__device__ __forceinline__ void ab_grp_blocks(const int32_t* list, int64_t cnt, unsigned bid, unsigned nblk,
+                                              const DevGraph& g, const VState* vs, const ScoreSrc& ss, uint8_t* keep,
+                                              VtxAcc& va) {
   const int gl = threadIdx.x % G;
-  for (int64_t gid = (int64_t)blockIdx.x * (BLOCK / G) + threadIdx.x / G; gid < cnt;
-       gid += (int64_t)gridDim.x * (BLOCK / G)) {
+  for (int64_t gid = (int64_t)bid * (BLOCK / G) + threadIdx.x / G; gid < cnt; gid += (int64_t)nblk * (BLOCK / G)) {
     const int32_t v = list[gid];
     const VState me = vs[v];
     if (me.d == D_NONE) {
@@ -1001,6 +1036,28 @@ __global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t c
       }
     }
   }
+}
+
+template <int G>
+__global__ __launch_bounds__(BLOCK) void k_ab_grp(const int32_t* list, int64_t cnt, DevGraph g, const VState* vs,
+                                                  ScoreSrc ss, uint8_t* keep, LMSlot* slot, int pass,
+                                                  int64_t* S) {
+  VtxAcc va;
+  if (slot->skip[pass]) return;
+  ab_grp_blocks<G>(list, cnt, blockIdx.x, gridDim.x, g, vs, ss, keep, va);
+  acc_flush<BLOCK>(va, S, CT_NM, -1);
+}
+
+// buckets 0-2 in one launch, as for the enumeration
+__global__ __launch_bounds__(BLOCK) void k_ab_grps(GrpSet q, DevGraph g, const VState* vs, ScoreSrc ss, uint8_t* keep,
+                                                   LMSlot* slot, int pass, int64_t* S) {
+  VtxAcc va;
+  if (slot->skip[pass]) return;
+  unsigned bid;
+  const int k = grp_set_bucket(q, bid);  // uniform over the workgroup
+  if (k == 0) ab_grp_blocks<4>(q.list[0], q.cnt[0], bid, q.nb[0], g, vs, ss, keep, va);
+  else if (k == 1) ab_grp_blocks<8>(q.list[1], q.cnt[1], bid, q.nb[1], g, vs, ss, keep, va);
+  else ab_grp_blocks<16>(q.list[2], q.cnt[2], bid, q.nb[2], g, vs, ss, keep, va);
   acc_flush<BLOCK>(va, S, CT_NM, -1);
 }
 
@@ -2037,9 +2094,21 @@ static void launch_destinations(const DevGraph& g, const Buckets& b, const Score
     launch;                                      \
     prof_end(PF_ENUM_B0 + k, 0.0, st);           \
   }
-  LCC_ENUM(0, (k_enum_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(0))))
-  LCC_ENUM(1, (k_enum_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(1))))
-  LCC_ENUM(2, (k_enum_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(2))))
+  {  // buckets 0-2 in one launch (its time is family 0's, its bytes those of the three buckets)
+    GrpSet q{};
+    unsigned nb = 0;
+    for (int k = 0; k < 3; ++k) {
+      q.list[k] = L + b.off[k];
+      q.cnt[k] = b.count[k];
+      q.nb[k] = b.count[k] ? grp_blocks(b, b.count[k], 4 << k) : 0;
+      nb += q.nb[k];
+    }
+    if (nb) {
+      prof_begin(PF_ENUM_B0, st);
+      k_enum_grps<<<nb, BLOCK, 0, st>>>(q, g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(0));
+      prof_end(PF_ENUM_B0, 0.0, st);
+    }
+  }
   LCC_ENUM(3, (k_enum_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(3))))
   LCC_ENUM(4, (k_enum_wave<LDS_SLOTS_B4><<<grp_blocks(b, b.count[4], WAVE), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(4), b.hash_shift)))
   LCC_ENUM(5, (k_enum_blk<128, LDS_SLOTS_B5><<<vtx_blocks(b, b.count[5]), 128, 0, st>>>(L + b.off[5], b.count[5], g, C, W, sc, pa, pb, strict, vs, slot, pass, S, co, cp(5), b.hash_shift)))
@@ -2089,9 +2158,17 @@ static void launch_afterburner(const DevGraph& g, const Buckets& b, const ScoreS
   const int32_t* L = b.list;
   const VState* vs = bufs.vs;
   uint8_t* keep = bufs.keep;
-  if (b.count[0]) k_ab_grp<4><<<grp_blocks(b, b.count[0], 4), BLOCK, 0, st>>>(L + b.off[0], b.count[0], g, vs, sc, keep, slot, pass, b.stripes);
-  if (b.count[1]) k_ab_grp<8><<<grp_blocks(b, b.count[1], 8), BLOCK, 0, st>>>(L + b.off[1], b.count[1], g, vs, sc, keep, slot, pass, b.stripes);
-  if (b.count[2]) k_ab_grp<16><<<grp_blocks(b, b.count[2], 16), BLOCK, 0, st>>>(L + b.off[2], b.count[2], g, vs, sc, keep, slot, pass, b.stripes);
+  {  // buckets 0-2 in one launch
+    GrpSet q{};
+    unsigned nb = 0;
+    for (int k = 0; k < 3; ++k) {
+      q.list[k] = L + b.off[k];
+      q.cnt[k] = b.count[k];
+      q.nb[k] = b.count[k] ? grp_blocks(b, b.count[k], 4 << k) : 0;
+      nb += q.nb[k];
+    }
+    if (nb) k_ab_grps<<<nb, BLOCK, 0, st>>>(q, g, vs, sc, keep, slot, pass, b.stripes);
+  }
   if (b.count[3]) k_ab_grp<32><<<grp_blocks(b, b.count[3], 32), BLOCK, 0, st>>>(L + b.off[3], b.count[3], g, vs, sc, keep, slot, pass, b.stripes);
   // degree 33-128 rows in half-wavefront groups (one pass of U = 4 loads covers them), longer ones per wavefront
   if (b.count[4]) k_ab_grp<32><<<grp_blocks(b, b.count[4], 32), BLOCK, 0, st>>>(L + b.off[4], b.count[4], g, vs, sc, keep, slot, pass, b.stripes);

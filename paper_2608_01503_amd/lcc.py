@@ -33,8 +33,9 @@ EXPORTED = ["lcc_create", "lcc_destroy", "lcc_default_options", "lcc_workspace_b
 # kernel families of lcc_profile_enable (bit = index) and the kernel each one times
 PROFILE_FAMILIES = ["enum_b0", "enum_b1", "enum_b2", "enum_b3", "enum_b4", "enum_b5", "enum_b6", "enum_b7",
                     "single", "afterburner"]
-FAMILY_KERNELS = {"enum_b0": "k_enum_grp<4>", "enum_b1": "k_enum_grp<8>", "enum_b2": "k_enum_grp<16>",
-                  "enum_b3": "k_enum_grp<32>", "enum_b4": "k_enum_wave<256>", "enum_b5": "k_enum_blk<128, 2048>",
+# (buckets 0-2 share one launch, timed as family enum_b0; enum_b1 and enum_b2 stay empty)
+FAMILY_KERNELS = {"enum_b0": "k_enum_grps", "enum_b3": "k_enum_grp<32>", "enum_b4": "k_enum_wave<256>",
+                  "enum_b5": "k_enum_blk<128, 2048>",
                   "enum_b6": "k_enum_blk<512, 8192>+k_enum_blk<1024, 16384>",
                   "enum_b7": "k_hub_insert+k_hub_scan+k_hub_final",
                   "single": "k_single_*"}
