@@ -267,7 +267,7 @@ def write_trace_summary(run_dir: str, workload_name: str, steps: int, warmup: in
                     f"--workload knn --steps {steps} --knn-plain off --autotune off{kv}\n")
         else:
             o.write(f"#   rocprofv3 --kernel-trace --stats --output-format csv -d {run_dir} -o run -- python -u bench.py "
-                    f"--workload {workload_name} --steps {steps} --warmup {warmup} --no-cpu-baseline --family {family}\n")
+                    f"--workload {workload_name} --steps {steps} --warmup {warmup} --no-cpu-baseline --legs none --family {family}\n")
         o.write(f"#   python bench.py --trace-summary {run_dir} --workload {workload_name} --steps {steps} "
                 f"--warmup {warmup} --family {family}\n")
         o.write(f"# total kernel time per call: {total:.2f} ms, {sum(int(r['Calls']) for r in rows) / calls:.0f} "
@@ -279,7 +279,52 @@ def write_trace_summary(run_dir: str, workload_name: str, steps: int, warmup: in
                 continue
             o.write(f"{ms:8.2f} {int(r['Calls']) / calls:9.1f} {float(r['AverageNs']) / 1e3:9.1f} "
                     f"{float(r['MaxNs']) / 1e3:9.1f}  {short(r['Name'])}\n")
+        if not knn:
+            write_level_split(run_dir, calls, sum(int(r["Calls"]) for r in rows), o)
     print(open(out).read())
+
+
+def write_level_split(run_dir: str, calls: int, launches: int, o):
+    """Kernel time per level of the last clustering call of a --kernel-trace run, from its kernel_trace.csv.
+    A call starts at its offset check (k_validate_offsets) and a level at its bucket build
+    (k_reset_level_counters); the input checks before level 0's buckets are the setup, and the last level
+    also holds the way back up (the projections, and the local moves of the Louvain+ / Leiden+ variants) and
+    the result.  Kernel time only: the gaps between kernels are not counted (under the tracer they are wider
+    than in an untraced run).  Skipped unless the trace holds exactly the `launches` of the stats file (a
+    trace left from another run)."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(run_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not f:
+        return
+    ks = []
+    with open(f[0]) as fh:
+        for r in csv.DictReader(fh):
+            ks.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    if len(ks) != launches:
+        return
+    ks.sort()
+    segs = []
+    for k in ks:
+        if "k_validate_offsets" in k[2]:
+            segs.append([])
+        if segs:
+            segs[-1].append(k)
+    if len(segs) < calls:
+        return
+    levels = [[]]
+    for k in segs[calls - 1]:
+        if "k_reset_level_counters" in k[2]:
+            levels.append([])
+        levels[-1].append(k)
+    o.write("#\n# kernel time per level, last call (from the same run's kernel_trace.csv; a level starts at its "
+            "bucket build;\n# the last level also holds the way back up and the result)\n")
+    o.write("# level  launches  kernel_ms  cum_ms\n")
+    cum = 0.0
+    for i, lv in enumerate(levels):
+        ms = sum(e - s for s, e, _ in lv) / 1e6
+        cum += ms
+        o.write(f"{'setup' if i == 0 else i - 1:>7} {len(lv):9d} {ms:10.2f} {cum:7.2f}\n")
 
 
 def bench_knn_batch(args):
