@@ -59,7 +59,7 @@ typedef enum { LCC_MEM_HOST = 0, LCC_MEM_DEVICE = 1 } lcc_mem;
 /* Undirected graph in symmetric CSR (Sec. IV: both (u,v) and (v,u) are stored).  Row v lists the neighbours
  * of v strictly ascending, without v itself.  Borrowed for the duration of a call.
  *   n            vertices, 0 <= n < 2^31
- *   nnz          stored (directed) entries = offsets[n]
+ *   nnz          stored (directed) entries = offsets[n], 0 <= nnz < 2^31
  *   offsets      n+1 entries, int32 (offsets_bits = 32) or int64 (offsets_bits = 64), offsets[0] = 0
  *   indices      nnz int32 neighbour ids
  *   edge_w       nnz int32 weights > 0, symmetric; NULL means every weight is 1
@@ -211,8 +211,8 @@ lcc_status lcc_cluster_ex(lcc_ctx* ctx, const lcc_graph* g, lcc_lambda lambda, l
  * and opts->trace is NULL, the graphs are processed together (host graphs are first copied to the device): their
  * CSRs are concatenated into one union graph and every kernel launch of a level covers all graphs still
  * coarsening (Alg. 1 or Alg. 5 applied to the union, with each graph's own lambda, objective, best-so-far
- * state, alternate local move, refinement stream, no-progress retries and level count).  Otherwise the graphs
- * run one after another.
+ * state, alternate local move, refinement stream, no-progress retries and level count), provided the union
+ * has fewer than 2^31 - 1 vertices and 2^31 - 1 entries.  Otherwise the graphs run one after another.
  * The workspace is sized for the union (sum of n, sum of nnz).  On a failure the status of the first problem
  * found is returned and no result is written; in the fused form structural faults of any graph (CSR layout,
  * symmetry, weights) are reported before lambda and bound problems, which are checked per graph in order. */

@@ -1216,9 +1216,9 @@ void fill_result(lcc_result* res, int64_t nc, __int128 N, int64_t p, int64_t q, 
 void check_graph_args(const lcc_graph* g) {
   if (!g) fail(LCC_ERR_INVALID, "graph is NULL");
   if (g->n < 0 || g->n > 2147483647LL) fail(LCC_ERR_INVALID, "n outside [0, 2^31)");
-  if (g->nnz < 0 || g->nnz > 2147483647LL * 2) fail(LCC_ERR_INVALID, "nnz outside [0, 2^32)");
+  // entry positions of the contraction (run starts, coarse entry ids) are 32-bit
+  if (g->nnz < 0 || g->nnz > 2147483647LL) fail(LCC_ERR_INVALID, "nnz outside [0, 2^31)");
   if (g->offsets_bits != 32 && g->offsets_bits != 64) fail(LCC_ERR_INVALID, "offsets_bits must be 32 or 64");
-  if (g->offsets_bits == 32 && g->nnz > 2147483647LL) fail(LCC_ERR_INVALID, "32-bit offsets with nnz >= 2^31");
   if (!g->offsets) fail(LCC_ERR_INVALID, "offsets is NULL");
   if (g->nnz > 0 && !g->indices) fail(LCC_ERR_INVALID, "indices is NULL");
   if (g->vw_mode != LCC_VW_GIVEN && g->vw_mode != LCC_VW_WEIGHTED_DEGREE && g->vw_mode != LCC_VW_UNIT)
@@ -1454,7 +1454,8 @@ __global__ void k_write_labels_seg(const int32_t* C, const int32_t* rank, const 
 
 bool leiden_family(lcc_variant v) { return v == LCC_PLEIDEN || v == LCC_PLEIDEN_PLUS; }
 
-// graphs of one family (Louvain / Louvain+ or pLeiden / pLeiden+), untraced, whose union fits 32-bit ids
+// graphs of one family (Louvain / Louvain+ or pLeiden / pLeiden+), untraced, whose union fits 32-bit vertex
+// ids and 32-bit entry positions
 bool fusable(const lcc_graph* gs, const lcc_variant* variants, int64_t count, const lcc_options* opts) {
   if (count < 2 || (opts && opts->trace)) return false;
   int64_t n = 0, e = 0;
@@ -1464,7 +1465,7 @@ bool fusable(const lcc_graph* gs, const lcc_variant* variants, int64_t count, co
     n += gs[i].n;
     e += gs[i].nnz;
   }
-  return n < 2147483647LL && e < ((int64_t)1 << 40);
+  return n < 2147483647LL && e < 2147483647LL;
 }
 
 lcc_status cluster_batch_fused(lcc_ctx* ctx, const lcc_graph* gs, const lcc_lambda* lams, const lcc_variant* variants,

@@ -404,6 +404,7 @@ lcc_status lcc_submit(lcc_server* s, const lcc_graph* g, lcc_lambda lambda, lcc_
                       const lcc_options* opts, uint64_t* ticket) {
   if (!s || !g || !ticket) return LCC_ERR_INVALID;
   if (g->n < 0 || g->nnz < 0 || !g->offsets || (g->nnz > 0 && !g->indices)) return LCC_ERR_INVALID;
+  if (g->n > 2147483647LL || g->nnz > 2147483647LL) return LCC_ERR_INVALID;  // the clustering call's limits
   if (g->offsets_bits != 32 && g->offsets_bits != 64) return LCC_ERR_INVALID;
   if (g->vw_mode == LCC_VW_GIVEN && g->n > 0 && !g->vertex_w) return LCC_ERR_INVALID;
   size_t fp = 0;

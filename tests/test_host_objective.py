@@ -153,3 +153,19 @@ def test_label_lambda_and_memory_errors():
     empty = host_graph(np.zeros(1), np.zeros(0), np.zeros(0))
     r = LL.lcc_objective(empty, np.zeros(0, np.int32))
     assert (r.num_clusters, r.N, r.obj_den) == (0, 0, 1)
+
+
+def test_size_limits_are_checked_before_the_arrays():
+    """n < 2^31 and nnz < 2^31 (the contraction keeps entry positions in 32 bits): a graph header outside them is
+    refused before any of its arrays is read (the arrays here hold far fewer entries than the header claims)."""
+    off = np.array([0, 1, 2], np.int64)
+    idx = np.array([1, 0], np.int32)
+    for n, nnz in ((2, 2 ** 31), (2, 2 ** 32 - 2), (2 ** 31, 2), (2, -1)):
+        g = LL.lcc_graph(n=n, nnz=nnz, offsets=off.ctypes.data, offsets_bits=64, indices=idx.ctypes.data,
+                         edge_w=None, vertex_w=None, vw_mode=LL.LCC_VW_UNIT, mem=LL.LCC_MEM_HOST)
+        with pytest.raises(LL.LccError) as e:
+            LL.lcc_objective(g, np.zeros(2, np.int32), (1, 20, False))
+        assert e.value.status == ERR_INVALID and "outside [0, 2^31)" in str(e.value)
+    ok = LL.lcc_graph(n=2, nnz=2, offsets=off.ctypes.data, offsets_bits=64, indices=idx.ctypes.data, edge_w=None,
+                      vertex_w=None, vw_mode=LL.LCC_VW_UNIT, mem=LL.LCC_MEM_HOST)
+    assert LL.lcc_objective(ok, np.zeros(2, np.int32), (1, 20, False)).num_clusters == 1
